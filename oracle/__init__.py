@@ -1,0 +1,256 @@
+"""ctypes front end of the FP64 CPU oracle (hydro_oracle.c, mlp_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the CPU
+baseline of the benchmark.  Nothing in the product package imports it.
+
+Inputs are the plain data objects of ``paper_2609_37859_amd.workloads``
+(Config, Mesh, EosTable, numpy arrays); this module only marshals them.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SOURCES = ["hydro_oracle.c", "mlp_oracle.c"]
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with gcc: FP64, round-to-nearest, no contraction, OpenMP."""
+    srcs = [os.path.join(_HERE, s) for s in _SOURCES if os.path.exists(os.path.join(_HERE, s))]
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+           "-Wall", "-o", tmp] + srcs + ["-lm"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("oracle build failed:\n" + r.stderr)
+    os.replace(tmp, _LIB_PATH)
+    if verbose:
+        print(" ".join(cmd))
+    return _LIB_PATH
+
+
+class _Cfg(C.Structure):
+    _fields_ = [("eos_kind", C.c_int), ("dual", C.c_int), ("grav_kind", C.c_int), ("n_lat", C.c_int),
+                ("gamma", C.c_double), ("eta1", C.c_double), ("eta2", C.c_double), ("cfl", C.c_double),
+                ("rho_floor", C.c_double), ("p_floor", C.c_double), ("e_floor", C.c_double),
+                ("merge_frac", C.c_double), ("gm_bh", C.c_double), ("r_soft", C.c_double), ("r_exc", C.c_double),
+                ("bh_x0", C.c_double * 3), ("v_frame", C.c_double * 3)]
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("bc", C.c_int * 3),
+                ("x0", C.c_double * 3), ("dx", C.c_double * 3), ("nblocks", C.c_int),
+                ("blk", C.POINTER(C.c_int))]
+
+
+class _Table(C.Structure):
+    _fields_ = [("nrho", C.c_int), ("nT", C.c_int), ("lr0", C.c_double), ("dlr", C.c_double),
+                ("lT0", C.c_double), ("dlT", C.c_double), ("lP", C.POINTER(C.c_double)),
+                ("le", C.POINTER(C.c_double)), ("lc2", C.POINTER(C.c_double))]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        _lib = C.CDLL(_LIB_PATH)
+        P = C.POINTER
+        d, i = C.c_double, C.c_int
+        _lib.orc_run_sync.argtypes = [P(_Cfg), P(_Mesh), P(_Table), P(d), P(d), i, P(d), P(d), d]
+        _lib.orc_run_sync.restype = i
+        _lib.orc_cfl.argtypes = [P(_Cfg), P(_Mesh), P(_Table), P(d), d, P(d)]
+        _lib.orc_cfl.restype = i
+        _lib.orc_lat_assign.argtypes = [P(_Cfg), P(_Mesh), P(d), P(i), P(d)]
+        _lib.orc_lat_assign.restype = i
+        _lib.orc_lat_window.argtypes = [P(_Cfg), P(_Mesh), P(_Table), P(d), P(d), P(i), d, d]
+        _lib.orc_lat_window.restype = C.c_int64
+        _lib.orc_eos_eval.argtypes = [P(_Cfg), P(_Table), C.c_int64, P(d), P(d), P(d), P(d)]
+        _lib.orc_eos_eval.restype = None
+        _lib.orc_table_invert.argtypes = [P(_Table), C.c_int64, P(d), P(d), P(i), P(d), P(d)]
+        _lib.orc_table_invert.restype = None
+        _lib.orc_hllc_flux.argtypes = [P(d), d, d, P(d), d, d, P(d)]
+        _lib.orc_hllc_flux.restype = None
+        _lib.orc_num_threads.argtypes = []
+        _lib.orc_num_threads.restype = i
+        if hasattr(_lib, "orc_mlp_forward"):
+            _lib.orc_mlp_forward.argtypes = [P(d), i, C.c_int64, P(d), P(d)]
+            _lib.orc_mlp_forward.restype = None
+            _lib.orc_mlp_loss_grad.argtypes = [P(d), i, C.c_int64, P(d), P(d), P(d)]
+            _lib.orc_mlp_loss_grad.restype = d
+            _lib.orc_mlp_adam.argtypes = [P(d), P(d), P(d), P(d), i, d, d, d, d, C.c_int64]
+            _lib.orc_mlp_adam.restype = None
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int))
+
+
+class _Keep:
+    """Holds the ctypes structs and the numpy buffers they point into."""
+
+    def __init__(self, cfg, mesh, table):
+        c = _Cfg()
+        for f, _ in _Cfg._fields_:
+            v = getattr(cfg, f)
+            if f in ("bh_x0", "v_frame"):
+                getattr(c, f)[:] = [float(x) for x in v]
+            else:
+                setattr(c, f, v)
+        self.cfg = c
+        self.mesh = None
+        if mesh is not None:
+            self.blk = np.ascontiguousarray(mesh.blk, dtype=np.int32)
+            m = _Mesh()
+            m.nx, m.ny, m.nz = mesh.nx, mesh.ny, mesh.nz
+            m.bc[:] = list(mesh.bc)
+            m.x0[:] = list(mesh.x0)
+            m.dx[:] = list(mesh.dx)
+            m.nblocks = mesh.nblocks
+            m.blk = _ip(self.blk)
+            self.mesh = m
+        self.table = None
+        if table is not None:
+            self.tarr = [np.ascontiguousarray(a, dtype=np.float64) for a in (table.lP, table.le, table.lc2)]
+            t = _Table()
+            t.nrho, t.nT = table.nrho, table.nT
+            t.lr0, t.dlr, t.lT0, t.dlT = table.lr0, table.dlr, table.lT0, table.dlT
+            t.lP, t.le, t.lc2 = (_dp(a) for a in self.tarr)
+            self.table = t
+
+    def tptr(self):
+        return C.byref(self.table) if self.table is not None else None
+
+
+def run_sync(cfg, mesh, U, nsteps, table=None, phi=None, dts=None, t0=0.0):
+    """Advance U (modified copy returned) by nsteps synchronous RK2 steps.
+    Returns (U, dts_used)."""
+    k = _Keep(cfg, mesh, table)
+    U = np.ascontiguousarray(U, dtype=np.float64).copy()
+    phi_a = None if phi is None else np.ascontiguousarray(phi, dtype=np.float64)
+    dt_in = None if dts is None else np.ascontiguousarray(dts, dtype=np.float64)
+    dt_out = np.zeros(nsteps)
+    rc = lib().orc_run_sync(C.byref(k.cfg), C.byref(k.mesh), k.tptr(), _dp(U),
+                            None if phi_a is None else _dp(phi_a), nsteps,
+                            None if dt_in is None else _dp(dt_in), _dp(dt_out), float(t0))
+    if rc != 0:
+        raise ValueError("oracle run_sync rejected its input")
+    return U, dt_out
+
+
+def cfl(cfg, mesh, U, table=None, t=0.0):
+    k = _Keep(cfg, mesh, table)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    out = np.zeros(mesh.nblocks)
+    if lib().orc_cfl(C.byref(k.cfg), C.byref(k.mesh), k.tptr(), _dp(U), float(t), _dp(out)) != 0:
+        raise ValueError("oracle cfl rejected its input")
+    return out
+
+
+def lat_assign(cfg, mesh, dt_block):
+    """Returns (levels int32[nblocks], Lmax, dt0)."""
+    k = _Keep(cfg, mesh, None)
+    dtb = np.ascontiguousarray(dt_block, dtype=np.float64)
+    lev = np.zeros(mesh.nblocks, dtype=np.int32)
+    dt0 = C.c_double(0.0)
+    L = lib().orc_lat_assign(C.byref(k.cfg), C.byref(k.mesh), _dp(dtb), _ip(lev), C.byref(dt0))
+    if L < 0:
+        raise ValueError("oracle lat_assign rejected its input")
+    return lev, L, dt0.value
+
+
+def lat_window(cfg, mesh, U, levels, dt0, table=None, phi=None, t0=0.0):
+    """One LAT window; returns (U_new, block_updates)."""
+    k = _Keep(cfg, mesh, table)
+    U = np.ascontiguousarray(U, dtype=np.float64).copy()
+    lev = np.ascontiguousarray(levels, dtype=np.int32)
+    phi_a = None if phi is None else np.ascontiguousarray(phi, dtype=np.float64)
+    n = lib().orc_lat_window(C.byref(k.cfg), C.byref(k.mesh), k.tptr(), _dp(U),
+                             None if phi_a is None else _dp(phi_a), _ip(lev), float(dt0), float(t0))
+    if n < 0:
+        raise ValueError("oracle lat_window rejected its input")
+    return U, int(n)
+
+
+def eos_eval(cfg, rho, U, table=None):
+    k = _Keep(cfg, None, table)
+    rho = np.ascontiguousarray(rho, dtype=np.float64).ravel()
+    U = np.ascontiguousarray(U, dtype=np.float64).ravel()
+    P = np.zeros_like(rho)
+    cs = np.zeros_like(rho)
+    lib().orc_eos_eval(C.byref(k.cfg), k.tptr(), rho.size, _dp(rho), _dp(U), _dp(P), _dp(cs))
+    return P, cs
+
+
+def table_invert(table, lr, le):
+    k = _Keep(_DummyCfg(), None, table)
+    lr = np.ascontiguousarray(lr, dtype=np.float64).ravel()
+    le = np.ascontiguousarray(le, dtype=np.float64).ravel()
+    j = np.zeros(lr.size, dtype=np.int32)
+    wT = np.zeros(lr.size)
+    lT = np.zeros(lr.size)
+    lib().orc_table_invert(k.tptr(), lr.size, _dp(lr), _dp(le), _ip(j), _dp(wT), _dp(lT))
+    return j, wT, lT
+
+
+def hllc_flux(wl, pl, cl, wr, pr, cr):
+    wl = np.ascontiguousarray(wl, dtype=np.float64)
+    wr = np.ascontiguousarray(wr, dtype=np.float64)
+    f = np.zeros(5)
+    lib().orc_hllc_flux(_dp(wl), pl, cl, _dp(wr), pr, cr, _dp(f))
+    return f
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+class _DummyCfg:
+    eos_kind = 1
+    dual = 0
+    grav_kind = 0
+    n_lat = 0
+    gamma = 5.0 / 3.0
+    eta1 = eta2 = cfl = rho_floor = p_floor = e_floor = merge_frac = gm_bh = r_soft = r_exc = 0.0
+    bh_x0 = v_frame = (0.0, 0.0, 0.0)
+
+
+# --- MLP (mlp_oracle.c) -----------------------------------------------------
+N_PARAMS = 64 * 2 + 64 + 64 * 64 + 64 + 64 + 1
+
+
+def mlp_forward(params, x, round_bf16=True):
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 2)
+    y = np.zeros(x.shape[0])
+    lib().orc_mlp_forward(_dp(p), int(round_bf16), x.shape[0], _dp(x), _dp(y))
+    return y
+
+
+def mlp_loss_grad(params, x, t, round_bf16=True):
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 2)
+    t = np.ascontiguousarray(t, dtype=np.float64).ravel()
+    g = np.zeros(N_PARAMS)
+    loss = lib().orc_mlp_loss_grad(_dp(p), int(round_bf16), x.shape[0], _dp(x), _dp(t), _dp(g))
+    return loss, g
+
+
+def mlp_adam(master, m, v, grad, step, lr, b1=0.9, b2=0.999, eps=1e-8):
+    for a in (master, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = np.ascontiguousarray(grad, dtype=np.float64)
+    lib().orc_mlp_adam(_dp(master), _dp(m), _dp(v), _dp(g), int(step), lr, b1, b2, eps, master.size)

@@ -1,0 +1,935 @@
+/*
+ * FP64 CPU oracle for the MeshBlock finite-volume update of
+ * "An End-to-End Numerical Framework for Tidal Disruption Events with AthenaK".
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline of the benchmark load this library.  The product path never does.
+ *
+ * It is deliberately plain: every RK stage copies each block into an explicit
+ * ghost-padded array, converts to primitives, computes every face flux and
+ * then updates every cell, in that order, in IEEE double precision with round
+ * to nearest and no floating-point contraction (built with -ffp-contract=off).
+ * It shares no code, header or table with the GPU library; the two meet only
+ * in the input data (mesh description, state, EOS table, potential).
+ *
+ * What each part follows:
+ *   - hydro scheme: RK2 + PLM + Riemann solver, floors        (Table 1)
+ *   - conserved-to-primitive + dual-energy switch             (Sec. Dual-energy evolution,
+ *                                                              eqs dual-econs, dual-primitive-switch)
+ *   - aux-energy flux and face velocity                        (eqs dual-flux, dual-face-velocity)
+ *   - compression source, ideal (analytic) and tabulated       (eqs dual-compression-continuous,
+ *                                                              dual-divv, dual-tabulated-compression)
+ *   - resynchronisation                                        (eq dual-sync)
+ *   - gravity source, centred momentum / flux-form energy      (eqs lat-grav-momentum, lat-grav-energy)
+ *   - softened point-mass potential and excision               (eq bh-softened-gravity)
+ *   - tabulated EOS in (log rho, log T), inverted in energy    (Sec. Tabulated EOS construction,
+ *                                                              eqs eos-table-range, eos-table-fields)
+ *   - LAT base step, factors, windows, ghost time
+ *     interpolation, reflux with gravity work                  (Sec. LAT method; eqs lat-base-dt,
+ *                                                              lat-factor, lat-flux-impulse,
+ *                                                              lat-mass-impulse-mismatch, lat-grav-reflux)
+ * The Riemann solver is HLLC (Toro, Riemann Solvers and Numerical Methods for
+ * Fluid Dynamics, 3rd ed., Sec. 10.4, with Davis wave-speed estimates); the
+ * PLM limiter is van Leer's harmonic mean; RK2 is Heun's (SSP) method.
+ *
+ * State layout: blocks are cubic (edge n), stored one after another, each as
+ * nv arrays of n^3 doubles with x fastest.  nv = 5 (rho, mx, my, mz, E) or 6
+ * (plus the auxiliary internal energy density A when dual energy is on).
+ */
+#define _GNU_SOURCE
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { IDN = 0, IM1 = 1, IM2 = 2, IM3 = 3, IEN = 4, IAX = 5 };
+
+typedef struct {
+  int eos_kind;   /* 0 ideal gas, 1 table */
+  int dual;       /* dual-energy on (1) / off (0) */
+  int grav_kind;  /* 0 none, 1 stored cell-centred potential, 2 softened point mass */
+  int n_lat;      /* largest LAT exponent N_LAT */
+  double gamma, eta1, eta2, cfl;
+  double rho_floor, p_floor, e_floor; /* e_floor: specific-energy floor, table EOS */
+  double merge_frac;
+  double gm_bh, r_soft, r_exc;
+  double bh_x0[3], v_frame[3];
+} orc_cfg;
+
+typedef struct {
+  int nx, ny, nz;  /* global cells */
+  int bc[3];       /* 0 periodic, 1 outflow (zero gradient) */
+  double x0[3], dx[3];
+  int nblocks;
+  const int *blk;  /* [nblocks][4] = n, ox, oy, oz (global cell origin) */
+} orc_mesh;
+
+typedef struct {
+  int nrho, nT;
+  double lr0, dlr, lT0, dlT; /* log10 axes: node i at lr0 + i*dlr */
+  const double *lP, *le, *lc2; /* [nrho][nT], T contiguous */
+} orc_table;
+
+/* ------------------------------------------------------------------ */
+/* mesh bookkeeping                                                    */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  const orc_cfg *cfg;
+  const orc_mesh *m;
+  const orc_table *tab;
+  int nv;
+  int lat, lx, ly, lz;
+  int *lmap;     /* lattice cell -> block */
+  size_t *off;   /* state offset of each block (doubles) */
+  size_t *poff;  /* potential offset of each block */
+  size_t *ioff;  /* impulse offset of each block */
+  size_t total, ptotal, itotal;
+} mesh_t;
+
+static void mesh_free(mesh_t *M) {
+  free(M->lmap); free(M->off); free(M->poff); free(M->ioff);
+  memset(M, 0, sizeof *M);
+}
+
+static int mesh_build(mesh_t *M, const orc_cfg *cfg, const orc_mesh *m, const orc_table *tab) {
+  memset(M, 0, sizeof *M);
+  M->cfg = cfg; M->m = m; M->tab = tab;
+  M->nv = cfg->dual ? 6 : 5;
+  if (m->nblocks <= 0) return -1;
+  int lat = 1 << 30;
+  for (int b = 0; b < m->nblocks; b++) if (m->blk[4 * b] < lat) lat = m->blk[4 * b];
+  if (lat < 2) return -1;
+  if (m->nx % lat || m->ny % lat || m->nz % lat) return -1;
+  M->lat = lat; M->lx = m->nx / lat; M->ly = m->ny / lat; M->lz = m->nz / lat;
+  size_t nl = (size_t)M->lx * M->ly * M->lz;
+  M->lmap = malloc(nl * sizeof(int));
+  M->off = malloc((m->nblocks + 1) * sizeof(size_t));
+  M->poff = malloc((m->nblocks + 1) * sizeof(size_t));
+  M->ioff = malloc((m->nblocks + 1) * sizeof(size_t));
+  for (size_t i = 0; i < nl; i++) M->lmap[i] = -1;
+  size_t o = 0, po = 0, io = 0;
+  for (int b = 0; b < m->nblocks; b++) {
+    int n = m->blk[4 * b], ox = m->blk[4 * b + 1], oy = m->blk[4 * b + 2], oz = m->blk[4 * b + 3];
+    if (n % lat || ox % lat || oy % lat || oz % lat) { mesh_free(M); return -1; }
+    if (ox < 0 || oy < 0 || oz < 0 || ox + n > m->nx || oy + n > m->ny || oz + n > m->nz) { mesh_free(M); return -1; }
+    for (int c = oz / lat; c < (oz + n) / lat; c++)
+      for (int bb = oy / lat; bb < (oy + n) / lat; bb++)
+        for (int a = ox / lat; a < (ox + n) / lat; a++) {
+          size_t li = ((size_t)c * M->ly + bb) * M->lx + a;
+          if (M->lmap[li] != -1) { mesh_free(M); return -1; }
+          M->lmap[li] = b;
+        }
+    M->off[b] = o; o += (size_t)M->nv * n * n * n;
+    M->poff[b] = po; po += (size_t)(n + 2) * (n + 2) * (n + 2);
+    M->ioff[b] = io; io += (size_t)6 * M->nv * n * n;
+  }
+  for (size_t i = 0; i < nl; i++) if (M->lmap[i] < 0) { mesh_free(M); return -1; }
+  M->off[m->nblocks] = o; M->poff[m->nblocks] = po; M->ioff[m->nblocks] = io;
+  M->total = o; M->ptotal = po; M->itotal = io;
+  return 0;
+}
+
+/* Apply the domain boundary to a global cell index; returns 0 when the index
+ * lies outside an outflow edge (then it is clamped onto the edge cell). */
+static int wrap_axis(int g, int N, int bc) {
+  if (bc == 0) { g %= N; if (g < 0) g += N; return g; }
+  if (g < 0) return 0;
+  if (g >= N) return N - 1;
+  return g;
+}
+
+/* global cell -> owning block and local index */
+static void locate(const mesh_t *M, int gx, int gy, int gz, int *b, int *i, int *j, int *k) {
+  const orc_mesh *m = M->m;
+  gx = wrap_axis(gx, m->nx, m->bc[0]);
+  gy = wrap_axis(gy, m->ny, m->bc[1]);
+  gz = wrap_axis(gz, m->nz, m->bc[2]);
+  int bb = M->lmap[((size_t)(gz / M->lat) * M->ly + gy / M->lat) * M->lx + gx / M->lat];
+  *b = bb;
+  *i = gx - m->blk[4 * bb + 1];
+  *j = gy - m->blk[4 * bb + 2];
+  *k = gz - m->blk[4 * bb + 3];
+}
+
+/* whether the neighbour across a face is a real cell (not beyond an outflow edge) */
+static int inside_axis(int g, int N, int bc) { return bc == 0 || (g >= 0 && g < N); }
+
+/* ------------------------------------------------------------------ */
+/* equation of state                                                   */
+/* ------------------------------------------------------------------ */
+
+/* internal-energy-density floor (Table 1 floors; table: rho * e_floor) */
+static double u_floor(const orc_cfg *c, double rho) {
+  if (c->eos_kind == 0) return c->p_floor / (c->gamma - 1.0);
+  return rho * c->e_floor;
+}
+
+static void table_rho_cell(const orc_table *T, double lr, int *i, double *w) {
+  double lrmax = T->lr0 + (T->nrho - 1) * T->dlr;
+  if (lr < T->lr0) lr = T->lr0;
+  if (lr > lrmax) lr = lrmax;
+  double x = (lr - T->lr0) / T->dlr;
+  int ii = (int)floor(x);
+  if (ii > T->nrho - 2) ii = T->nrho - 2;
+  if (ii < 0) ii = 0;
+  *i = ii; *w = x - ii;
+}
+
+/* value of a table field at density weight w between rows i, i+1, at T node j */
+static double tcol(const double *F, int nT, int i, double w, int j) {
+  return (1.0 - w) * F[(size_t)i * nT + j] + w * F[(size_t)(i + 1) * nT + j];
+}
+
+/* Inversion e -> T at fixed density.  The answer is defined as the largest T
+ * node j in [0, nT-2] whose interpolated log e does not exceed the target,
+ * after the target is clamped into the column's range; this is found by
+ * bisection.  Returns j and the in-cell weight wT. */
+static void table_invert(const orc_table *T, int i, double w, double le, int *jout, double *wT) {
+  int nT = T->nT;
+  double lo_v = tcol(T->le, nT, i, w, 0), hi_v = tcol(T->le, nT, i, w, nT - 1);
+  if (le < lo_v) le = lo_v;
+  if (le > hi_v) le = hi_v;
+  int lo = 0, hi = nT - 1;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) / 2;
+    if (tcol(T->le, nT, i, w, mid) <= le) lo = mid; else hi = mid;
+  }
+  double a = tcol(T->le, nT, i, w, lo), b = tcol(T->le, nT, i, w, lo + 1);
+  *jout = lo;
+  *wT = (le - a) / (b - a);
+}
+
+static double tbil(const double *F, int nT, int i, double w, int j, double wT) {
+  return (1.0 - wT) * tcol(F, nT, i, w, j) + wT * tcol(F, nT, i, w, j + 1);
+}
+
+/* (rho, U) -> pressure and adiabatic sound speed */
+static void eos_pc(const orc_cfg *c, const orc_table *T, double rho, double U, double *P, double *cs) {
+  if (c->eos_kind == 0) {
+    double Ue = U;
+    double uf = u_floor(c, rho);
+    if (Ue < uf) Ue = uf;
+    *P = (c->gamma - 1.0) * Ue;
+    *cs = sqrt(c->gamma * (*P) / rho);
+    return;
+  }
+  int i, j; double w, wT;
+  double Ue = U;
+  double uf = u_floor(c, rho);
+  if (Ue < uf) Ue = uf; /* keeps the logarithm defined; the inversion clamps into the table */
+  table_rho_cell(T, log10(rho), &i, &w);
+  table_invert(T, i, w, log10(Ue / rho), &j, &wT);
+  *P = pow(10.0, tbil(T->lP, T->nT, i, w, j, wT));
+  *cs = pow(10.0, 0.5 * tbil(T->lc2, T->nT, i, w, j, wT));
+}
+
+/* ------------------------------------------------------------------ */
+/* cell primitives and the Riemann problem                             */
+/* ------------------------------------------------------------------ */
+
+/* conserved -> (rho, vx, vy, vz, U_EOS[, A]) with the dual-energy switch */
+static void c2p(const orc_cfg *c, const double *q, double *w) {
+  double rho = q[IDN];
+  double vx = q[IM1] / rho, vy = q[IM2] / rho, vz = q[IM3] / rho;
+  double K = 0.5 * (q[IM1] * q[IM1] + q[IM2] * q[IM2] + q[IM3] * q[IM3]) / rho;
+  double Uc = q[IEN] - K;
+  double Ueos = Uc;
+  if (c->dual) {
+    if (!(Uc > 0.0 && Uc > c->eta1 * q[IEN])) Ueos = q[IAX];
+    w[5] = q[IAX];
+  }
+  w[0] = rho; w[1] = vx; w[2] = vy; w[3] = vz; w[4] = Ueos;
+}
+
+static double vanleer(double dm, double dp) {
+  double p = dm * dp;
+  return p > 0.0 ? 2.0 * p / (dm + dp) : 0.0;
+}
+
+/* HLLC flux for states rotated so that index 1 is the face normal.
+ * wl, wr: (rho, un, ut1, ut2, U, [A]); returns flux (rho, mn, mt1, mt2, E).
+ * Davis wave speeds; contact tie S_M = 0 takes the left star state. */
+static void hllc(const double *wl, double pl, double cl, const double *wr, double pr, double cr, double *f) {
+  double rl = wl[0], ul = wl[1], vl = wl[2], zl = wl[3];
+  double rr = wr[0], ur = wr[1], vr = wr[2], zr = wr[3];
+  double El = wl[4] + 0.5 * rl * (ul * ul + vl * vl + zl * zl);
+  double Er = wr[4] + 0.5 * rr * (ur * ur + vr * vr + zr * zr);
+  double sl = fmin(ul - cl, ur - cr);
+  double sr = fmax(ul + cl, ur + cr);
+  double fl[5] = {rl * ul, rl * ul * ul + pl, rl * ul * vl, rl * ul * zl, (El + pl) * ul};
+  double fr[5] = {rr * ur, rr * ur * ur + pr, rr * ur * vr, rr * ur * zr, (Er + pr) * ur};
+  if (sl >= 0.0) { memcpy(f, fl, sizeof fl); return; }
+  if (sr <= 0.0) { memcpy(f, fr, sizeof fr); return; }
+  double sm = (pr - pl + rl * ul * (sl - ul) - rr * ur * (sr - ur)) / (rl * (sl - ul) - rr * (sr - ur));
+  if (sm >= 0.0) {
+    double a = rl * (sl - ul) / (sl - sm);
+    double us[5] = {a, a * sm, a * vl, a * zl, a * (El / rl + (sm - ul) * (sm + pl / (rl * (sl - ul))))};
+    double u0[5] = {rl, rl * ul, rl * vl, rl * zl, El};
+    for (int v = 0; v < 5; v++) f[v] = fl[v] + sl * (us[v] - u0[v]);
+  } else {
+    double a = rr * (sr - ur) / (sr - sm);
+    double us[5] = {a, a * sm, a * vr, a * zr, a * (Er / rr + (sm - ur) * (sm + pr / (rr * (sr - ur))))};
+    double u0[5] = {rr, rr * ur, rr * vr, rr * zr, Er};
+    for (int v = 0; v < 5; v++) f[v] = fr[v] + sr * (us[v] - u0[v]);
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* gravity and excision geometry                                       */
+/* ------------------------------------------------------------------ */
+static double cell_x(const orc_mesh *m, int d, int g) { return m->x0[d] + (g + 0.5) * m->dx[d]; }
+
+static double bh_pos(const orc_cfg *c, int d, double t) { return c->bh_x0[d] - c->v_frame[d] * t; }
+
+/* softened point-mass potential at a cell centre (eq bh-softened-gravity) */
+static double phi_point(const orc_cfg *c, const orc_mesh *m, int gx, int gy, int gz, double t) {
+  double dx = cell_x(m, 0, gx) - bh_pos(c, 0, t);
+  double dy = cell_x(m, 1, gy) - bh_pos(c, 1, t);
+  double dz = cell_x(m, 2, gz) - bh_pos(c, 2, t);
+  return -c->gm_bh / sqrt(dx * dx + dy * dy + dz * dz + c->r_soft * c->r_soft);
+}
+
+static int excised(const orc_cfg *c, const orc_mesh *m, int gx, int gy, int gz, double t) {
+  if (c->grav_kind != 2 || !(c->r_exc > 0.0)) return 0;
+  double dx = cell_x(m, 0, gx) - bh_pos(c, 0, t);
+  double dy = cell_x(m, 1, gy) - bh_pos(c, 1, t);
+  double dz = cell_x(m, 2, gz) - bh_pos(c, 2, t);
+  return dx * dx + dy * dy + dz * dz < c->r_exc * c->r_exc;
+}
+
+/* potential at local cell (i,j,k) of block b, i,j,k in [-1, n] */
+static double phi_at(const mesh_t *M, const double *phi, int b, int i, int j, int k, double t) {
+  const orc_mesh *m = M->m;
+  int n = m->blk[4 * b];
+  if (M->cfg->grav_kind == 1) {
+    int np = n + 2;
+    return phi[M->poff[b] + ((size_t)(k + 1) * np + (j + 1)) * np + (i + 1)];
+  }
+  return phi_point(M->cfg, m, m->blk[4 * b + 1] + i, m->blk[4 * b + 2] + j, m->blk[4 * b + 3] + k, t);
+}
+
+/* ------------------------------------------------------------------ */
+/* one RK stage on one block                                           */
+/* ------------------------------------------------------------------ */
+#define PADX(n) ((n) + 4)
+static inline size_t pidx(int n, int i, int j, int k) { /* i,j,k in [-2, n+2) */
+  int np = n + 4;
+  return ((size_t)(k + 2) * np + (j + 2)) * np + (i + 2);
+}
+static inline size_t cidx(int n, int i, int j, int k) { return ((size_t)k * n + j) * n + i; }
+static inline size_t fidx(int n, int a, int b) { return (size_t)b * n + a; }
+
+/*
+ * Stage update of block b.
+ *   qpad  : stage-input conserved state with 2 ghost layers, [nv][(n+4)^3]
+ *   qbase : state at the start of the step (stage 2 only), [nv][n^3]
+ *   stage : 1 -> out = q + dt L(q);  2 -> out = 1/2 qbase + 1/2 (q + dt L(q))
+ *   t     : time at which the stage's right-hand side is evaluated
+ *   bflux : boundary-face fluxes [6 faces][nv][n^2] (face = 2*dir + side)
+ */
+static void block_stage(const mesh_t *M, const double *phi, int b, const double *qpad, const double *qbase,
+                        int stage, double dt, double t, double *out, double *bflux) {
+  const orc_cfg *c = M->cfg;
+  const orc_mesh *m = M->m;
+  const orc_table *T = M->tab;
+  const int nv = M->nv;
+  const int n = m->blk[4 * b];
+  const int o[3] = {m->blk[4 * b + 1], m->blk[4 * b + 2], m->blk[4 * b + 3]};
+  const size_t np3 = (size_t)PADX(n) * PADX(n) * PADX(n);
+  const size_t n3 = (size_t)n * n * n;
+  const size_t nf = (size_t)(n + 1) * n * n; /* faces per direction */
+
+  double *W = malloc(np3 * nv * sizeof(double));
+  double *F = malloc(3 * nf * (nv + 1) * sizeof(double)); /* fluxes + face velocity */
+  unsigned char *exm = calloc(np3, 1);
+
+  /* primitives on the padded block */
+  for (size_t p = 0; p < np3; p++) {
+    double q[6], w[6];
+    for (int v = 0; v < nv; v++) q[v] = qpad[v * np3 + p];
+    c2p(c, q, w);
+    for (int v = 0; v < nv; v++) W[v * np3 + p] = w[v];
+  }
+  if (c->grav_kind == 2 && c->r_exc > 0.0) {
+    for (int k = -2; k < n + 2; k++)
+      for (int j = -2; j < n + 2; j++)
+        for (int i = -2; i < n + 2; i++)
+          exm[pidx(n, i, j, k)] = (unsigned char)excised(c, m, o[0] + i, o[1] + j, o[2] + k, t);
+  }
+
+  /* face fluxes: direction d, face index a in [0, n] between cells a-1 and a */
+  for (int d = 0; d < 3; d++) {
+    int perm[3]; /* velocity components in (normal, t1, t2) order */
+    perm[0] = 1 + d; perm[1] = 1 + (d + 1) % 3; perm[2] = 1 + (d + 2) % 3;
+    for (int t2 = 0; t2 < n; t2++)
+      for (int t1 = 0; t1 < n; t1++)
+        for (int a = 0; a <= n; a++) {
+          size_t pc[4];
+          for (int s = 0; s < 4; s++) {
+            int ii[3];
+            ii[d] = a - 2 + s; ii[(d + 1) % 3] = t1; ii[(d + 2) % 3] = t2;
+            pc[s] = pidx(n, ii[0], ii[1], ii[2]);
+          }
+          /* PLM on each primitive: left state from cell a-1, right from a */
+          double wl[6], wr[6];
+          for (int v = 0; v < nv; v++) {
+            double q0 = W[v * np3 + pc[0]], q1 = W[v * np3 + pc[1]];
+            double q2 = W[v * np3 + pc[2]], q3 = W[v * np3 + pc[3]];
+            double sL = vanleer(q1 - q0, q2 - q1);
+            double sR = vanleer(q2 - q1, q3 - q2);
+            wl[v] = q1 + 0.5 * sL;
+            wr[v] = q2 - 0.5 * sR;
+          }
+          /* rotate to (rho, un, ut1, ut2, U, A) */
+          double rl[6], rr[6];
+          rl[0] = wl[0]; rr[0] = wr[0];
+          for (int s = 0; s < 3; s++) { rl[1 + s] = wl[perm[s]]; rr[1 + s] = wr[perm[s]]; }
+          rl[4] = wl[4]; rr[4] = wr[4];
+          double pl, cl, pr, cr;
+          eos_pc(c, T, rl[0], rl[4], &pl, &cl);
+          eos_pc(c, T, rr[0], rr[4], &pr, &cr);
+          double fr5[5];
+          hllc(rl, pl, cl, rr, pr, cr, fr5);
+          double fl[7];
+          fl[IDN] = fr5[0];
+          for (int s = 0; s < 3; s++) fl[perm[s]] = fr5[1 + s];
+          fl[IEN] = fr5[4];
+          /* upwind state by the sign of the mass flux; tie -> left */
+          const double *wu = fr5[0] >= 0.0 ? wl : wr;
+          if (c->dual) fl[IAX] = fr5[0] * (wu[5] / wu[0]);
+          double vf = fr5[0] / wu[0];
+          /* excision is a one-way sink: a face between an active and an
+           * excised cell keeps its flux unless the mass flux leaves the sink */
+          unsigned char eL = exm[pc[1]], eR = exm[pc[2]];
+          if (eL != eR) {
+            int into = eR ? (fr5[0] >= 0.0) : (fr5[0] <= 0.0);
+            if (!into) { for (int v = 0; v < nv; v++) fl[v] = 0.0; vf = 0.0; }
+          }
+          int ii[3];
+          ii[d] = a; ii[(d + 1) % 3] = t1; ii[(d + 2) % 3] = t2;
+          /* face array index: (a, t1, t2) with a fastest */
+          size_t fi = ((size_t)t2 * n + t1) * (n + 1) + a;
+          for (int v = 0; v < nv; v++) F[((size_t)d * (nv + 1) + v) * nf + fi] = fl[v];
+          F[((size_t)d * (nv + 1) + nv) * nf + fi] = vf;
+          (void)ii;
+        }
+  }
+
+  /* boundary-face fluxes for the LAT impulse (face = 2*d + side) */
+  if (bflux) {
+    for (int d = 0; d < 3; d++)
+      for (int side = 0; side < 2; side++) {
+        int a = side ? n : 0;
+        for (int t2 = 0; t2 < n; t2++)
+          for (int t1 = 0; t1 < n; t1++) {
+            size_t fi = ((size_t)t2 * n + t1) * (n + 1) + a;
+            /* face-cell index over the two transverse axes in increasing axis order */
+            int ax[3]; ax[(d + 1) % 3] = t1; ax[(d + 2) % 3] = t2;
+            int u0 = d == 0 ? ax[1] : ax[0];
+            int u1 = d == 2 ? ax[1] : ax[2];
+            for (int v = 0; v < nv; v++)
+              bflux[((size_t)(2 * d + side) * nv + v) * n * n + fidx(n, u0, u1)] =
+                  F[((size_t)d * (nv + 1) + v) * nf + fi];
+          }
+      }
+  }
+
+  /* cell update */
+  const double tau = stage == 1 ? dt : 0.5 * dt;
+  for (int k = 0; k < n; k++)
+    for (int j = 0; j < n; j++)
+      for (int i = 0; i < n; i++) {
+        int lc[3] = {i, j, k};
+        size_t p = pidx(n, i, j, k);
+        double rhs[6] = {0, 0, 0, 0, 0, 0};
+        double divv = 0.0;
+        for (int d = 0; d < 3; d++) {
+          int tt1 = lc[(d + 1) % 3], tt2 = lc[(d + 2) % 3];
+          size_t fm = ((size_t)tt2 * n + tt1) * (n + 1) + lc[d];
+          size_t fp = fm + 1;
+          for (int v = 0; v < nv; v++) {
+            const double *Fv = F + ((size_t)d * (nv + 1) + v) * nf;
+            rhs[v] -= (Fv[fp] - Fv[fm]) / m->dx[d];
+          }
+          const double *Vf = F + ((size_t)d * (nv + 1) + nv) * nf;
+          divv += (Vf[fp] - Vf[fm]) / m->dx[d];
+          if (c->grav_kind) {
+            int im[3] = {i, j, k}, ip[3] = {i, j, k};
+            im[d] -= 1; ip[d] += 1;
+            double pm = phi_at(M, phi, b, im[0], im[1], im[2], t);
+            double p0 = phi_at(M, phi, b, i, j, k, t);
+            double pp = phi_at(M, phi, b, ip[0], ip[1], ip[2], t);
+            double rho_i = qpad[IDN * np3 + p];
+            rhs[IM1 + d] -= rho_i * (pp - pm) / (2.0 * m->dx[d]);
+            const double *Fr = F + ((size_t)d * (nv + 1) + IDN) * nf;
+            rhs[IEN] -= (Fr[fp] * (pp - p0) + Fr[fm] * (p0 - pm)) / (2.0 * m->dx[d]);
+          }
+        }
+        double qn[6];
+        for (int v = 0; v < nv; v++) {
+          double qs = qpad[v * np3 + p] + dt * rhs[v];
+          qn[v] = stage == 1 ? qs : 0.5 * qbase[v * n3 + cidx(n, i, j, k)] + 0.5 * qs;
+        }
+        if (c->dual) {
+          /* compression of the auxiliary energy over this stage's time */
+          double rho_in = qpad[IDN * np3 + p];
+          if (c->eos_kind == 0) {
+            qn[IAX] = qn[IAX] * exp(-(c->gamma - 1.0) * divv * tau);
+          } else {
+            double Pa, ca;
+            /* eos_pc floors its energy argument before the table call */
+            eos_pc(c, T, rho_in, qn[IAX], &Pa, &ca);
+            qn[IAX] = qn[IAX] - Pa * divv * tau;
+          }
+          double uf = u_floor(c, qn[IDN] > c->rho_floor ? qn[IDN] : c->rho_floor);
+          if (qn[IAX] < uf) qn[IAX] = uf;
+        }
+        /* floors */
+        if (qn[IDN] < c->rho_floor) qn[IDN] = c->rho_floor;
+        {
+          double w[6];
+          c2p(c, qn, w);
+          double uf = u_floor(c, qn[IDN]);
+          if (w[4] < uf) {
+            qn[IEN] += uf - w[4];
+            if (c->dual && qn[IAX] < uf) qn[IAX] = uf;
+          }
+        }
+        /* resynchronisation against the stage-input total energy of the 7-point neighbourhood */
+        if (c->dual) {
+          double emax = qpad[IEN * np3 + p];
+          for (int d = 0; d < 3; d++) {
+            int im[3] = {i, j, k}, ip[3] = {i, j, k};
+            im[d] -= 1; ip[d] += 1;
+            double e1 = qpad[IEN * np3 + pidx(n, im[0], im[1], im[2])];
+            double e2 = qpad[IEN * np3 + pidx(n, ip[0], ip[1], ip[2])];
+            if (e1 > emax) emax = e1;
+            if (e2 > emax) emax = e2;
+          }
+          double K = 0.5 * (qn[IM1] * qn[IM1] + qn[IM2] * qn[IM2] + qn[IM3] * qn[IM3]) / qn[IDN];
+          double Uc = qn[IEN] - K;
+          if (Uc > 0.0 && Uc > c->eta2 * emax) qn[IAX] = Uc;
+        }
+        for (int v = 0; v < nv; v++) out[v * n3 + cidx(n, i, j, k)] = qn[v];
+      }
+  free(W); free(F); free(exm);
+}
+
+/* reset excised cells to the zero-momentum floor state */
+static void excise_reset(const mesh_t *M, int b, double *q, double t) {
+  const orc_cfg *c = M->cfg;
+  const orc_mesh *m = M->m;
+  if (c->grav_kind != 2 || !(c->r_exc > 0.0)) return;
+  int n = m->blk[4 * b];
+  size_t n3 = (size_t)n * n * n;
+  for (int k = 0; k < n; k++)
+    for (int j = 0; j < n; j++)
+      for (int i = 0; i < n; i++) {
+        if (!excised(c, m, m->blk[4 * b + 1] + i, m->blk[4 * b + 2] + j, m->blk[4 * b + 3] + k, t)) continue;
+        size_t p = cidx(n, i, j, k);
+        double uf = u_floor(c, c->rho_floor);
+        q[IDN * n3 + p] = c->rho_floor;
+        q[IM1 * n3 + p] = 0.0; q[IM2 * n3 + p] = 0.0; q[IM3 * n3 + p] = 0.0;
+        q[IEN * n3 + p] = uf;
+        if (c->dual) q[IAX * n3 + p] = uf;
+      }
+}
+
+/* ------------------------------------------------------------------ */
+/* CFL time step per block (eq lat-base-dt uses its minimum)           */
+/* ------------------------------------------------------------------ */
+int orc_cfl(const orc_cfg *cfg, const orc_mesh *m, const orc_table *tab, const double *U, double t, double *dt_block) {
+  mesh_t M;
+  if (mesh_build(&M, cfg, m, tab)) return -1;
+  int nb = m->nblocks;
+#pragma omp parallel for schedule(dynamic)
+  for (int b = 0; b < nb; b++) {
+    int n = m->blk[4 * b];
+    size_t n3 = (size_t)n * n * n;
+    const double *q = U + M.off[b];
+    double best = INFINITY;
+    for (int k = 0; k < n; k++)
+      for (int j = 0; j < n; j++)
+        for (int i = 0; i < n; i++) {
+          if (excised(cfg, m, m->blk[4 * b + 1] + i, m->blk[4 * b + 2] + j, m->blk[4 * b + 3] + k, t)) continue;
+          size_t p = cidx(n, i, j, k);
+          double qq[6], w[6];
+          for (int v = 0; v < M.nv; v++) qq[v] = q[v * n3 + p];
+          c2p(cfg, qq, w);
+          double P, cs;
+          eos_pc(cfg, tab, w[0], w[4], &P, &cs);
+          for (int d = 0; d < 3; d++) {
+            double s = m->dx[d] / (fabs(w[1 + d]) + cs);
+            if (s < best) best = s;
+          }
+        }
+    dt_block[b] = cfg->cfl * best;
+  }
+  mesh_free(&M);
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* LAT level assignment (eq lat-factor, bin merging, neighbour limit)  */
+/* ------------------------------------------------------------------ */
+
+/* blocks sharing a face, edge or corner (periodic wrap; nothing beyond outflow edges) */
+static int *adjacency(const mesh_t *M, int *deg_out_max) {
+  const orc_mesh *m = M->m;
+  int nb = m->nblocks, maxd = 64;
+  int *adj = malloc((size_t)nb * maxd * sizeof(int));
+  for (int b = 0; b < nb; b++) {
+    int cnt = 0;
+    int n = m->blk[4 * b], L = M->lat;
+    int o[3] = {m->blk[4 * b + 1], m->blk[4 * b + 2], m->blk[4 * b + 3]};
+    for (int cz = o[2] - L; cz < o[2] + n + L; cz += L)
+      for (int cy = o[1] - L; cy < o[1] + n + L; cy += L)
+        for (int cx = o[0] - L; cx < o[0] + n + L; cx += L) {
+          if (!inside_axis(cx, m->nx, m->bc[0]) || !inside_axis(cy, m->ny, m->bc[1]) ||
+              !inside_axis(cz, m->nz, m->bc[2]))
+            continue;
+          int nb2, i, j, k;
+          locate(M, cx, cy, cz, &nb2, &i, &j, &k);
+          if (nb2 == b) continue;
+          int seen = 0;
+          for (int s = 0; s < cnt; s++) if (adj[b * maxd + s] == nb2) seen = 1;
+          if (!seen && cnt < maxd - 1) adj[b * maxd + cnt++] = nb2;
+        }
+    adj[b * maxd + cnt] = -1;
+  }
+  *deg_out_max = maxd;
+  return adj;
+}
+
+/*
+ * dt_block -> levels.  exps[b] = min(N_LAT, floor(log2(dt_b / dt0))) is taken
+ * with ilogb (exact), bins are merged from the top while they hold fewer than
+ * merge_frac * N blocks, then neighbours are limited to one exponent apart by
+ * relaxation to the fixed point.  Output level = Lmax - exponent, so level 0
+ * is the coarsest (largest step) and Lmax the finest.  Returns Lmax.
+ */
+int orc_lat_assign(const orc_cfg *cfg, const orc_mesh *m, const double *dt_block, int *levels, double *dt0_out) {
+  mesh_t M;
+  if (mesh_build(&M, cfg, m, NULL)) return -1;
+  int nb = m->nblocks;
+  double dt0 = INFINITY;
+  for (int b = 0; b < nb; b++) if (dt_block[b] < dt0) dt0 = dt_block[b];
+  int *e = malloc(nb * sizeof(int));
+  for (int b = 0; b < nb; b++) {
+    double r = dt_block[b] / dt0;
+    int k = ilogb(r);
+    if (k > cfg->n_lat) k = cfg->n_lat;
+    if (k < 0) k = 0;
+    e[b] = k;
+  }
+  /* merge sparse top bins */
+  for (;;) {
+    int top = 0, cnt = 0;
+    for (int b = 0; b < nb; b++) if (e[b] > top) top = e[b];
+    if (top == 0) break;
+    for (int b = 0; b < nb; b++) if (e[b] == top) cnt++;
+    if ((double)cnt >= cfg->merge_frac * nb) break;
+    for (int b = 0; b < nb; b++) if (e[b] == top) e[b] = top - 1;
+  }
+  /* neighbour limit: e_b <= e_c + 1 for every neighbour c */
+  int maxd;
+  int *adj = adjacency(&M, &maxd);
+  for (int changed = 1; changed;) {
+    changed = 0;
+    for (int b = 0; b < nb; b++)
+      for (int s = 0; adj[b * maxd + s] >= 0; s++) {
+        int cN = adj[b * maxd + s];
+        if (e[b] > e[cN] + 1) { e[b] = e[cN] + 1; changed = 1; }
+      }
+  }
+  int Lmax = 0;
+  for (int b = 0; b < nb; b++) if (e[b] > Lmax) Lmax = e[b];
+  for (int b = 0; b < nb; b++) levels[b] = Lmax - e[b];
+  if (dt0_out) *dt0_out = dt0;
+  free(e); free(adj); mesh_free(&M);
+  return Lmax;
+}
+
+/* ------------------------------------------------------------------ */
+/* LAT window (and the synchronous step as its one-level special case) */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  mesh_t *M;
+  const double *phi;
+  double *Qend, *Qstart, *Q1, *Qnew, *imp, *bf1, *bf2;
+  int *f;      /* factor per block (in dt0 units) */
+} lat_t;
+
+/* conserved value of variable v at global cell of block nb, as seen at
+ * sub-cycle k by a reader with factor fb in phase ph (1 or 2) */
+static double ghost_value(const lat_t *L, int reader, int nbk, size_t cell, int v, int k, int ph) {
+  const mesh_t *M = L->M;
+  int n = M->m->blk[4 * nbk];
+  size_t n3 = (size_t)n * n * n;
+  size_t o = M->off[nbk] + v * n3 + cell;
+  int fb = L->f[reader], fn = L->f[nbk];
+  int act = (k % fn) == 0;
+  if (ph == 1) {
+    if (act) return L->Qend[o];
+    int t0 = k - k % fn;
+    double w = (double)(k - t0) / fn;
+    return (1.0 - w) * L->Qstart[o] + w * L->Qend[o];
+  }
+  if (act) {
+    if (fn <= fb) return L->Q1[o];
+    double w = (double)fb / fn;
+    return (1.0 - w) * L->Qend[o] + w * L->Q1[o];
+  }
+  int t0 = k - k % fn;
+  double w = (double)(k + fb - t0) / fn;
+  return (1.0 - w) * L->Qstart[o] + w * L->Qend[o];
+}
+
+static void fill_pad(const lat_t *L, int b, int k, int ph, double *qpad) {
+  const mesh_t *M = L->M;
+  const orc_mesh *m = M->m;
+  int n = m->blk[4 * b];
+  size_t np3 = (size_t)PADX(n) * PADX(n) * PADX(n);
+  for (int kk = -2; kk < n + 2; kk++)
+    for (int jj = -2; jj < n + 2; jj++)
+      for (int ii = -2; ii < n + 2; ii++) {
+        int nbk, li, lj, lk;
+        locate(M, m->blk[4 * b + 1] + ii, m->blk[4 * b + 2] + jj, m->blk[4 * b + 3] + kk, &nbk, &li, &lj, &lk);
+        int nn = m->blk[4 * nbk];
+        size_t cell = cidx(nn, li, lj, lk);
+        for (int v = 0; v < M->nv; v++) qpad[v * np3 + pidx(n, ii, jj, kk)] = ghost_value(L, b, nbk, cell, v, k, ph);
+      }
+}
+
+/* neighbour across face (d, side) of local face cell (u0,u1): returns block or -1 */
+static int face_neighbor(const mesh_t *M, int b, int d, int side, int u0, int u1, int *cell_nb, int *u0n, int *u1n,
+                         int *ci) {
+  const orc_mesh *m = M->m;
+  int n = m->blk[4 * b];
+  int loc[3];
+  if (d == 0) { loc[1] = u0; loc[2] = u1; }
+  if (d == 1) { loc[0] = u0; loc[2] = u1; }
+  if (d == 2) { loc[0] = u0; loc[1] = u1; }
+  loc[d] = side ? n - 1 : 0;
+  int g[3] = {m->blk[4 * b + 1] + loc[0], m->blk[4 * b + 2] + loc[1], m->blk[4 * b + 3] + loc[2]};
+  *ci = (int)cidx(n, loc[0], loc[1], loc[2]);
+  g[d] += side ? 1 : -1;
+  int N[3] = {m->nx, m->ny, m->nz};
+  if (!inside_axis(g[d], N[d], m->bc[d])) return -1;
+  int nbk, i, j, k;
+  locate(M, g[0], g[1], g[2], &nbk, &i, &j, &k);
+  int nn = m->blk[4 * nbk];
+  *cell_nb = (int)cidx(nn, i, j, k);
+  int ln[3] = {i, j, k};
+  *u0n = d == 0 ? ln[1] : ln[0];
+  *u1n = d == 2 ? ln[1] : ln[2];
+  return nbk;
+}
+
+/*
+ * One LAT window of f_max = 2^Lmax sub-cycles of dt0 (Lmax = max level).
+ * Block b with level l has factor f = 2^(Lmax - l).  Returns the number of
+ * block updates performed, or -1 on invalid input.
+ */
+int64_t orc_lat_window(const orc_cfg *cfg, const orc_mesh *m, const orc_table *tab, double *U, const double *phi,
+                       const int *levels, double dt0, double t0) {
+  mesh_t M;
+  if (mesh_build(&M, cfg, m, tab)) return -1;
+  int nb = m->nblocks, nv = M.nv;
+  int Lmax = 0;
+  for (int b = 0; b < nb; b++) {
+    if (levels[b] < 0 || levels[b] > 30) { mesh_free(&M); return -1; }
+    if (levels[b] > Lmax) Lmax = levels[b];
+  }
+  /* neighbour levels must differ by at most one */
+  {
+    int maxd;
+    int *adj = adjacency(&M, &maxd);
+    for (int b = 0; b < nb; b++)
+      for (int s = 0; adj[b * maxd + s] >= 0; s++)
+        if (abs(levels[b] - levels[adj[b * maxd + s]]) > 1) { free(adj); mesh_free(&M); return -1; }
+    free(adj);
+  }
+  lat_t L;
+  L.M = &M; L.phi = phi;
+  L.Qend = U;
+  L.Qstart = malloc(M.total * sizeof(double));
+  L.Q1 = malloc(M.total * sizeof(double));
+  L.Qnew = malloc(M.total * sizeof(double));
+  L.imp = calloc(M.itotal, sizeof(double));
+  L.bf1 = calloc(M.itotal, sizeof(double));
+  L.bf2 = calloc(M.itotal, sizeof(double));
+  L.f = malloc(nb * sizeof(int));
+  for (int b = 0; b < nb; b++) L.f[b] = 1 << (Lmax - levels[b]);
+  memcpy(L.Qstart, U, M.total * sizeof(double));
+  int fmax = 1 << Lmax;
+  int64_t updates = 0;
+  for (int k = 0; k < fmax; k++) {
+    double tk = t0 + k * dt0;
+    /* phase 1 */
+#pragma omp parallel for schedule(dynamic)
+    for (int b = 0; b < nb; b++) {
+      if (k % L.f[b]) continue;
+      int n = m->blk[4 * b];
+      size_t np3 = (size_t)PADX(n) * PADX(n) * PADX(n);
+      double *qpad = malloc(np3 * nv * sizeof(double));
+      fill_pad(&L, b, k, 1, qpad);
+      block_stage(&M, phi, b, qpad, NULL, 1, L.f[b] * dt0, tk, L.Q1 + M.off[b], L.bf1 + M.ioff[b]);
+      free(qpad);
+    }
+    /* phase 2 */
+#pragma omp parallel for schedule(dynamic)
+    for (int b = 0; b < nb; b++) {
+      if (k % L.f[b]) continue;
+      int n = m->blk[4 * b];
+      size_t np3 = (size_t)PADX(n) * PADX(n) * PADX(n);
+      double *qpad = malloc(np3 * nv * sizeof(double));
+      fill_pad(&L, b, k, 2, qpad);
+      double dtb = L.f[b] * dt0;
+      block_stage(&M, phi, b, qpad, L.Qend + M.off[b], 2, dtb, tk + dtb, L.Qnew + M.off[b], L.bf2 + M.ioff[b]);
+      excise_reset(&M, b, L.Qnew + M.off[b], tk + dtb);
+      free(qpad);
+    }
+    /* time-integrated boundary impulses (eq lat-flux-impulse) */
+#pragma omp parallel for schedule(dynamic)
+    for (int b = 0; b < nb; b++) {
+      if (k % L.f[b]) continue;
+      int n = m->blk[4 * b];
+      double dtb = L.f[b] * dt0;
+      for (int d = 0; d < 3; d++) {
+        double area = m->dx[(d + 1) % 3] * m->dx[(d + 2) % 3];
+        for (int side = 0; side < 2; side++)
+          for (int u1 = 0; u1 < n; u1++)
+            for (int u0 = 0; u0 < n; u0++) {
+              int cnb, u0n, u1n, ci;
+              int nbk = face_neighbor(&M, b, d, side, u0, u1, &cnb, &u0n, &u1n, &ci);
+              if (nbk < 0) continue;
+              int fw = L.f[b] > L.f[nbk] ? L.f[b] : L.f[nbk];
+              int overwrite = (k % fw) == 0;
+              for (int v = 0; v < nv; v++) {
+                size_t ix = M.ioff[b] + ((size_t)(2 * d + side) * nv + v) * n * n + fidx(n, u0, u1);
+                double Is = 0.5 * (L.bf1[ix] + L.bf2[ix]) * area * dtb;
+                L.imp[ix] = overwrite ? Is : L.imp[ix] + Is;
+              }
+            }
+      }
+    }
+    /* commit */
+    for (int b = 0; b < nb; b++) {
+      if (k % L.f[b]) continue;
+      int n = m->blk[4 * b];
+      size_t sz = (size_t)nv * n * n * n;
+      memcpy(L.Qstart + M.off[b], L.Qend + M.off[b], sz * sizeof(double));
+      memcpy(L.Qend + M.off[b], L.Qnew + M.off[b], sz * sizeof(double));
+      updates++;
+    }
+    /* reflux for blocks completing at k+1 against finer neighbours */
+    double tc = t0 + (k + 1) * dt0;
+#pragma omp parallel for schedule(dynamic)
+    for (int b = 0; b < nb; b++) {
+      if ((k + 1) % L.f[b]) continue;
+      int n = m->blk[4 * b];
+      size_t n3 = (size_t)n * n * n;
+      double vol = m->dx[0] * m->dx[1] * m->dx[2];
+      /* cells in increasing index order, faces in order x-, x+, y-, y+, z-, z+ */
+      for (int kk = 0; kk < n; kk++)
+        for (int jj = 0; jj < n; jj++)
+          for (int ii = 0; ii < n; ii++) {
+            int lc[3] = {ii, jj, kk};
+            for (int d = 0; d < 3; d++)
+              for (int side = 0; side < 2; side++) {
+                if (lc[d] != (side ? n - 1 : 0)) continue;
+                int u0 = d == 0 ? jj : ii;
+                int u1 = d == 2 ? jj : kk;
+                int cnb, u0n, u1n, ci;
+                int nbk = face_neighbor(&M, b, d, side, u0, u1, &cnb, &u0n, &u1n, &ci);
+                if (nbk < 0 || L.f[nbk] >= L.f[b]) continue;
+                int nn = m->blk[4 * nbk];
+                double sg = side ? 1.0 : -1.0;
+                double dI[6];
+                for (int v = 0; v < nv; v++) {
+                  size_t ib = M.ioff[b] + ((size_t)(2 * d + side) * nv + v) * n * n + fidx(n, u0, u1);
+                  size_t in = M.ioff[nbk] + ((size_t)(2 * d + (1 - side)) * nv + v) * nn * nn + fidx(nn, u0n, u1n);
+                  dI[v] = L.imp[ib] - L.imp[in];
+                }
+                size_t p = cidx(n, ii, jj, kk);
+                double *q = L.Qend + M.off[b];
+                if (cfg->grav_kind) {
+                  int ln[3] = {ii, jj, kk};
+                  ln[d] += side ? 1 : -1;
+                  double pn = phi_at(&M, phi, b, ln[0], ln[1], ln[2], tc);
+                  double pi = phi_at(&M, phi, b, ii, jj, kk, tc);
+                  q[IEN * n3 + p] += sg / (2.0 * vol) * dI[IDN] * (pn - pi);
+                }
+                for (int v = 0; v < nv; v++) q[v * n3 + p] += sg * dI[v] / vol;
+              }
+          }
+    }
+  }
+  free(L.Qstart); free(L.Q1); free(L.Qnew); free(L.imp); free(L.bf1); free(L.bf2); free(L.f);
+  mesh_free(&M);
+  return updates;
+}
+
+/*
+ * Synchronous RK2 steps: every block on one level.  dt_in (nullable) gives
+ * the step sizes; otherwise each step takes min_b of the CFL time step.
+ * The step sizes used are written to dt_out (nullable).
+ */
+int orc_run_sync(const orc_cfg *cfg, const orc_mesh *m, const orc_table *tab, double *U, const double *phi,
+                 int nsteps, const double *dt_in, double *dt_out, double t0) {
+  int nb = m->nblocks;
+  int *lev = calloc(nb, sizeof(int));
+  double *dtb = malloc(nb * sizeof(double));
+  double t = t0;
+  for (int s = 0; s < nsteps; s++) {
+    double dt;
+    if (dt_in) dt = dt_in[s];
+    else {
+      if (orc_cfl(cfg, m, tab, U, t, dtb)) { free(lev); free(dtb); return -1; }
+      dt = INFINITY;
+      for (int b = 0; b < nb; b++) if (dtb[b] < dt) dt = dtb[b];
+    }
+    if (orc_lat_window(cfg, m, tab, U, phi, lev, dt, t) < 0) { free(lev); free(dtb); return -1; }
+    if (dt_out) dt_out[s] = dt;
+    t += dt;
+  }
+  free(lev); free(dtb);
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* direct entry points to single pieces, for pins                      */
+/* ------------------------------------------------------------------ */
+void orc_eos_eval(const orc_cfg *cfg, const orc_table *tab, int64_t n, const double *rho, const double *U, double *P,
+                  double *cs) {
+  for (int64_t i = 0; i < n; i++) eos_pc(cfg, tab, rho[i], U[i], P + i, cs + i);
+}
+
+/* table-only inversion: log10 rho, log10 e -> (j, wT, log10 T) */
+void orc_table_invert(const orc_table *tab, int64_t n, const double *lr, const double *le, int *j, double *wT,
+                      double *lT) {
+  for (int64_t q = 0; q < n; q++) {
+    int i, jj; double w, wt;
+    table_rho_cell(tab, lr[q], &i, &w);
+    table_invert(tab, i, w, le[q], &jj, &wt);
+    j[q] = jj; wT[q] = wt;
+    lT[q] = tab->lT0 + (jj + wt) * tab->dlT;
+  }
+}
+
+/* HLLC flux of one face for given primitive states (x-normal), for pins */
+void orc_hllc_flux(const double *wl, double pl, double cl, const double *wr, double pr, double cr, double *f) {
+  hllc(wl, pl, cl, wr, pr, cr, f);
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
