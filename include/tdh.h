@@ -1,0 +1,180 @@
+/*
+ * tdh.h - C ABI of the MI355X (gfx950) MeshBlock hydro library.
+ *
+ * The library advances a mesh of cubic MeshBlocks with the finite-volume
+ * Godunov update of "An End-to-End Numerical Framework for Tidal Disruption
+ * Events with AthenaK": RK2 + PLM + a Riemann solver (Table 1; the solver here
+ * is HLLC), pressure and sound speed from an ideal gas or a tabulated EOS in
+ * (log rho, log T) (Sec. Tabulated EOS construction, eqs eos-table-range and
+ * eos-table-fields), dual-energy internal-energy evolution (Sec. Dual-energy
+ * evolution, eqs dual-econs to dual-sync), fixed-potential gravity with
+ * centred momentum and flux-form energy sources (eqs lat-grav-momentum,
+ * lat-grav-energy) or a softened point mass with an excised sink
+ * (eq bh-softened-gravity), all under localized adaptive time stepping:
+ * per-block power-of-two steps, windows, time-interpolated ghosts and
+ * delayed flux correction with gravitational work (Sec. LAT method and
+ * Coupling with gravity, eqs lat-base-dt, lat-factor, lat-flux-impulse,
+ * lat-mass-impulse-mismatch, lat-grav-reflux).
+ *
+ * Conventions for every entry point
+ *   - Every call returns tdh_status (0 = success) and never aborts or throws.
+ *     tdh_last_error() gives a message for the last failing call.
+ *   - After TDH_EHIP (a HIP runtime error) the context is poisoned: every
+ *     later call except tdh_last_error and tdh_destroy returns TDH_ESTATE.
+ *   - Pointers named host_* are host memory, read or written synchronously.
+ *     Pointers named dev_* are device memory on the context's GPU; the caller
+ *     owns them and keeps them alive while the context uses them.
+ *   - All device work is enqueued on the stream given to tdh_init; calls that
+ *     return host data synchronise that stream first.
+ *   - Only tdh_init, tdh_init_blocks, tdh_set_eos_table and tdh_mlp_init
+ *     allocate device memory (small metadata only: block tables, lattice
+ *     map, EOS table, network weights).  The state lives in the caller's
+ *     arena.  Stepping calls allocate nothing.
+ *
+ * State layout (host and device): blocks one after another in the order of
+ * the block list; block b holds nv arrays of n_b^3 doubles, x fastest, with
+ * nv = 5 (rho, m_x, m_y, m_z, E) or 6 (plus the auxiliary internal energy
+ * density U_aux when dual energy is on).
+ */
+#ifndef TDH_H
+#define TDH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tdh_ctx tdh_ctx;
+
+typedef enum {
+  TDH_OK = 0,
+  TDH_EINVAL = -1, /* argument outside its documented range */
+  TDH_ENOMEM = -2, /* arena too small, or a setup allocation failed */
+  TDH_EHIP = -3,   /* HIP runtime error; the context is poisoned */
+  TDH_ESTATE = -4, /* call out of order (e.g. stepping before init_blocks) */
+  TDH_ERANGE = -5  /* sizes beyond a documented maximum */
+} tdh_status;
+
+/* Run parameters. */
+typedef struct {
+  int eos_kind;   /* 0 ideal gas (gamma), 1 tabulated (tdh_set_eos_table) */
+  int dual;       /* 1: evolve U_aux and use the eta1 switch (eq dual-primitive-switch) */
+  int grav_kind;  /* 0 none; 1 stored cell-centred potential (tdh_init_blocks host_phi);
+                     2 softened point mass at bh_x0 - v_frame * t (eq bh-softened-gravity)
+                        with cells closer than r_exc excised */
+  int n_lat;      /* N_LAT of eq lat-factor: factors up to 2^n_lat (0 = synchronous) */
+  double gamma;   /* ideal-gas adiabatic index */
+  double eta1;    /* pressure-recovery switch threshold (eq dual-primitive-switch) */
+  double eta2;    /* resynchronisation threshold (eq dual-sync) */
+  double cfl;     /* Courant number */
+  double rho_floor, p_floor; /* density floor; pressure floor of the ideal gas */
+  double e_floor; /* specific internal energy floor of the tabulated EOS */
+  double merge_frac; /* top LAT bins holding fewer than merge_frac * nblocks blocks merge down */
+  double gm_bh, r_soft, r_exc; /* G M, softening length, excision radius (grav_kind 2) */
+  double bh_x0[3], v_frame[3]; /* point-mass position at t = 0 and frame velocity */
+  int inv_mode;   /* table inversion: 0 bisection for every query;
+                     1 cell-centre query seeded by the learned network, face and compression
+                       queries seeded by the centre's cell; 2 as 1 but the centre bisected */
+  int newton_max_iter; /* seeded secant steps before falling back to bisection (>= 0) */
+} tdh_config;
+
+/* Mesh: uniform spacing dx, cubic blocks of edge n (a multiple of the
+ * smallest edge, which defines the lattice the blocks are aligned to). */
+typedef struct {
+  int nx, ny, nz;   /* global cells per axis */
+  int bc[3];        /* per axis: 0 periodic, 1 outflow (zero gradient) */
+  double x0[3];     /* lower domain corner */
+  double dx[3];     /* cell widths */
+  int nblocks;
+  const int *blk;   /* host [nblocks][4] = n, ox, oy, oz (global cell origin) */
+} tdh_mesh;
+
+/* Counters since tdh_init_blocks. */
+typedef struct {
+  int64_t block_updates;  /* RK2 steps taken by blocks */
+  int64_t cell_updates;   /* sum over block updates of the block's cells */
+  int64_t windows;        /* completed LAT windows */
+  int64_t sub_cycles;     /* step_level calls */
+  int64_t kernel_launches;
+} tdh_stats;
+
+/* Device bytes the state arena must hold for this configuration and mesh
+ * (two state copies, the stage-1 state, the potential, face impulses).
+ * Returns 0 for an invalid mesh. */
+size_t tdh_arena_bytes(const tdh_config *cfg, const tdh_mesh *mesh);
+
+/* Create a context on the current HIP device; hip_stream is a hipStream_t
+ * (NULL = default stream).  The configuration is copied. */
+tdh_status tdh_init(const tdh_config *cfg, void *hip_stream, tdh_ctx **out);
+
+/* Install the mesh and the initial state.  dev_arena: caller-owned device
+ * buffer of at least tdh_arena_bytes() bytes, 256-byte aligned.
+ * host_state: initial conserved state (layout above).  host_phi: for
+ * grav_kind 1, per block (n+2)^3 cell-centred potential values including one
+ * ghost layer, x fastest (else NULL).  Levels start at 0 (synchronous). */
+tdh_status tdh_init_blocks(tdh_ctx *ctx, const tdh_mesh *mesh, void *dev_arena, size_t arena_bytes,
+                           const double *host_state, const double *host_phi);
+
+/* Tabulated EOS (Sec. Tabulated EOS construction): node (i, j) at
+ * log10 rho = lr0 + i*dlr, log10 T = lT0 + j*dlT; host arrays [nrho][nT],
+ * T contiguous, of log10 P, log10 e (specific internal energy, strictly
+ * increasing in T on every row) and log10 c_s^2.  2 <= nrho, nT <= 4096. */
+tdh_status tdh_set_eos_table(tdh_ctx *ctx, int nrho, int nT, double lr0, double dlr, double lT0, double dlT,
+                             const double *host_logP, const double *host_loge, const double *host_logcs2);
+
+/* Per-block CFL step dt_b = cfl * min over cells, axes of dx/(|v|+c_s)
+ * (excised cells skipped), its minimum dt0 (eq lat-base-dt) and the LAT
+ * levels of eq lat-factor after bin merging and the one-level neighbour
+ * limit; level = Lmax - log2(f_b), level 0 coarsest.  The levels are
+ * installed and start a new window.  host_dt_block [nblocks] and
+ * host_levels [nblocks] may be NULL.  Synchronises the stream. */
+tdh_status tdh_reduce_dt(tdh_ctx *ctx, double *host_dt_block, double *host_dt0, int8_t *host_levels,
+                         int *host_lmax);
+
+/* Install host-chosen levels (each 0..30, neighbours at most one apart)
+ * and start a new window. */
+tdh_status tdh_set_levels(tdh_ctx *ctx, const int8_t *host_levels);
+
+/* One LAT sub-cycle: every block whose level is >= level takes one RK2
+ * step, a block on level L with dt * 2^(level - L).  Within a window of
+ * 2^Lmax sub-cycles the calls must follow the schedule: sub-cycle k
+ * (k = 0 .. 2^Lmax - 1) has level 0 for k = 0 and Lmax - ctz(k) otherwise,
+ * and dt * 2^level must equal the window's coarse step; the window ends
+ * after its last sub-cycle, when every block is synchronised.
+ * Returns TDH_ESTATE for a call out of schedule. */
+tdh_status tdh_step_level(tdh_ctx *ctx, int level, double dt);
+
+/* A whole window: all 2^Lmax sub-cycles with coarse step dt_coarse.
+ * batched = 1 advances every active level in one launch per phase;
+ * batched = 0 launches each level separately (same results bit for bit).
+ * use_graph = 1 captures the window into a hipGraph and replays it. */
+tdh_status tdh_run_window(tdh_ctx *ctx, double dt_coarse, int batched, int use_graph);
+
+/* Simulation time of the synchronised state. */
+tdh_status tdh_get_time(tdh_ctx *ctx, double *host_t);
+tdh_status tdh_set_time(tdh_ctx *ctx, double t);
+
+/* Copy the current (synchronised) state to / from host memory. */
+tdh_status tdh_get_state(tdh_ctx *ctx, double *host_state);
+tdh_status tdh_set_state(tdh_ctx *ctx, const double *host_state);
+
+/* Batched EOS queries on device arrays of n values (n <= 2^31):
+ *   invert: log10 rho, log10 e -> log10 T, table cell j, secant steps taken
+ *           (-1 when the bisection fallback ran); mode as tdh_config.inv_mode
+ *           with the seed taken from the network (mode 1) or bisection.
+ *   eval:   rho, U (internal energy density) -> P, c_s. */
+tdh_status tdh_eos_invert_batch(tdh_ctx *ctx, const double *dev_lrho, const double *dev_le, double *dev_lT,
+                                int32_t *dev_j, int32_t *dev_iters, int64_t n, int mode);
+tdh_status tdh_eos_eval_batch(tdh_ctx *ctx, const double *dev_rho, const double *dev_U, double *dev_P,
+                              double *dev_cs, int64_t n);
+
+tdh_status tdh_get_stats(tdh_ctx *ctx, tdh_stats *out);
+const char *tdh_last_error(const tdh_ctx *ctx);
+void tdh_destroy(tdh_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TDH_H */

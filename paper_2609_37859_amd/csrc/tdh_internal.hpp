@@ -1,0 +1,89 @@
+// Internal declarations shared by the gfx950 kernels and the host runtime of
+// libtdh.  Not part of the C ABI (include/tdh.h is).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tdh {
+
+enum { IDN = 0, IM1 = 1, IM2 = 2, IM3 = 3, IEN = 4, IAX = 5 };
+
+constexpr int kChunk = 256;       // cells per stage work item (one workgroup)
+constexpr int kMaxLevel = 30;
+constexpr int kCntSlots = 33;     // cnt_ge[0..32]
+
+// One MeshBlock as the kernels see it.
+struct BlockInfo {
+  int n, ox, oy, oz;
+  long long off;   // offset (doubles) of the block in every state buffer
+  long long poff;  // offset of its (n+2)^3 potential
+  long long ioff;  // offset of its [6][nv][n^2] face arrays
+};
+
+struct MeshDev {
+  int nx, ny, nz;
+  int bc[3];
+  double x0[3], dx[3], inv_dx[3];
+  int lat, lx, ly, lz;
+  int nv;
+  const int *lmap;          // lattice cell -> block
+  const BlockInfo *blocks;
+};
+
+struct Phys {
+  int eos_kind, dual, grav_kind, inv_mode, newton_max_iter;
+  double gamma, eta1, eta2, rho_floor, p_floor, e_floor;
+  double gm_bh, r_soft, r_exc;
+  double bh_x0[3], v_frame[3];
+};
+
+struct Table {
+  int nrho, nT;
+  double lr0, dlr, inv_dlr, lT0, dlT;
+  const double *lP, *le, *lc2;
+};
+
+// Learned seed network (2 -> 64 -> 64 -> 1), bf16 weights packed for the kernels.
+struct Seed {
+  int enabled;
+  const uint16_t *w1;   // [64][2]
+  const float *b1;      // [64]
+  const uint16_t *w2;   // [64 out][64 in]
+  const float *b2;      // [64]
+  const uint16_t *w3;   // [64]
+  const float *b3;      // [1]
+  double le_lo, le_hi, lr_lo, lr_hi, lt_lo, lt_hi;   // input / output normalisation ranges
+};
+
+struct StageArgs {
+  MeshDev m;
+  Phys p;
+  Table t;
+  Seed s;
+  double *Qa, *Qb, *Qs;     // state ping-pong pair and stage-1 state
+  double *imp, *bf1;        // face impulses, stage-1 boundary fluxes
+  const double *phi;        // stored potential (grav_kind 1)
+  const int *fac;           // factor (in dt0 units) per block
+  const int *par;           // 0: latest state in Qa, 1: in Qb
+  const int *order;         // block ids sorted by level, finest first
+  const int *item_start;    // prefix sum of work items over `order`
+  const int *cnt_ge;        // cnt_ge[L] = blocks with level >= L
+  int Llo, Lhi;             // levels advanced by this launch
+  int k;                    // sub-cycle index in the window (dt0 units)
+  int phase;                // 1 or 2
+  const double *win;        // device {window start time, finest step dt0}
+};
+
+// host-side launchers (tdh_kernels.hip)
+hipError_t launch_stage(const StageArgs &a, int grid, hipStream_t s);
+hipError_t launch_set_window(double *win, double t, double dt0, hipStream_t s);
+hipError_t launch_commit(const int *order, const int *cnt_ge, int lmin, int *par, hipStream_t s);
+hipError_t launch_reflux(const StageArgs &a, int lc, int dir, int nmax, int grid, hipStream_t s);  // a.k = completing index
+hipError_t launch_cfl(const StageArgs &a, double cfl, double t, const int *item_block, int nitems,
+                      double *part, int nblocks, const int *block_item_start, double *dtb, hipStream_t s);
+hipError_t launch_eos_invert(const Table &t, const Seed &s, int newton_max_iter, const double *lr, const double *le,
+                             double *lT, int32_t *j, int32_t *iters, int64_t n, int mode, hipStream_t st);
+hipError_t launch_eos_eval(const Phys &p, const Table &t, const double *rho, const double *U, double *P,
+                           double *cs, int64_t n, hipStream_t st);
+
+}  // namespace tdh

@@ -1,0 +1,726 @@
+// Host runtime of libtdh: context, state arena, block registry, LAT level
+// assignment and sub-cycle scheduling, hipGraph capture, and the C ABI of
+// include/tdh.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/tdh.h"
+#include "tdh_internal.hpp"
+
+using namespace tdh;
+
+struct tdh_ctx {
+  tdh_config cfg{};
+  hipStream_t stream = nullptr;
+  bool poisoned = false;
+  std::string err;
+
+  // mesh (host copy)
+  bool have_mesh = false;
+  int nx = 0, ny = 0, nz = 0, bc[3] = {0, 0, 0};
+  double x0[3] = {0, 0, 0}, dx[3] = {1, 1, 1};
+  int nb = 0, nv = 5, lat = 0, lx = 0, ly = 0, lz = 0, nmax = 0;
+  std::vector<int> blk;                 // [nb][4]
+  std::vector<int> lmap;
+  std::vector<BlockInfo> binfo;
+  std::vector<std::vector<int>> adj;    // face/edge/corner neighbours
+  long long total = 0, ptotal = 0, itotal = 0;
+  long long ncells = 0;
+
+  // device memory: state in the caller's arena, metadata owned here
+  double *Qa = nullptr, *Qb = nullptr, *Qs = nullptr, *imp = nullptr, *bf1 = nullptr, *phi = nullptr;
+  BlockInfo *d_blocks = nullptr;
+  int *d_lmap = nullptr, *d_fac = nullptr, *d_par = nullptr, *d_order = nullptr, *d_item_start = nullptr;
+  int *d_cnt_ge = nullptr, *d_cfl_item_block = nullptr, *d_cfl_block_start = nullptr;
+  double *d_cfl_part = nullptr, *d_dtb = nullptr, *d_win = nullptr;
+  int cfl_nitems = 0;
+  std::vector<void *> owned;
+
+  // EOS table
+  bool have_table = false;
+  Table tab{};
+  double *d_table = nullptr;
+  // learned seed (set by the network code)
+  Seed seed{};
+
+  // LAT window state
+  std::vector<int> levels, fac, par, order, item_start, cnt_ge;
+  int Lmax = 0;
+  int k = 0;                 // next sub-cycle
+  double dt_coarse = 0.0, dt0 = 0.0;
+  double t = 0.0;            // time of the last synchronised state
+  int grid = 2048;           // persistent grid of the stage kernel
+  tdh_stats stats{};
+
+  // captured windows: key = (Lmax, batched)
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+};
+
+static thread_local std::string g_err;
+
+static tdh_status fail(tdh_ctx *c, tdh_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  g_err = buf;
+  return s;
+}
+
+static tdh_status hip_fail(tdh_ctx *c, hipError_t e, const char *what) {
+  if (c) c->poisoned = true;
+  return fail(c, TDH_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(c, expr)                                   \
+  do {                                                    \
+    hipError_t e_ = (expr);                               \
+    if (e_ != hipSuccess) return hip_fail((c), e_, #expr); \
+  } while (0)
+
+static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// ---------------------------------------------------------------------------
+// mesh validation and layout
+// ---------------------------------------------------------------------------
+struct Layout {
+  long long total = 0, ptotal = 0, itotal = 0, ncells = 0;
+  std::vector<long long> off, poff, ioff;
+  int lat = 0, nmax = 0;
+};
+
+static const char *mesh_layout(const tdh_config *cfg, const tdh_mesh *m, Layout &L) {
+  if (!m || m->nblocks <= 0 || !m->blk) return "empty mesh";
+  const int nv = cfg->dual ? 6 : 5;
+  int lat = 1 << 30, nmax = 0;
+  for (int b = 0; b < m->nblocks; ++b) {
+    const int n = m->blk[4 * b];
+    if (!is_pow2(n) || n < 2 || n > 256) return "block edge must be a power of two in [2, 256]";
+    lat = std::min(lat, n);
+    nmax = std::max(nmax, n);
+  }
+  if (m->nx <= 0 || m->ny <= 0 || m->nz <= 0 || m->nx % lat || m->ny % lat || m->nz % lat)
+    return "domain size must be a positive multiple of the smallest block edge";
+  for (int d = 0; d < 3; ++d) {
+    if (m->bc[d] != 0 && m->bc[d] != 1) return "boundary kind must be 0 or 1";
+    if (!(m->dx[d] > 0.0)) return "cell widths must be positive";
+  }
+  L.off.resize(m->nblocks);
+  L.poff.resize(m->nblocks);
+  L.ioff.resize(m->nblocks);
+  for (int b = 0; b < m->nblocks; ++b) {
+    const long long n = m->blk[4 * b];
+    L.off[b] = L.total;
+    L.total += nv * n * n * n;
+    L.poff[b] = L.ptotal;
+    L.ptotal += (n + 2) * (n + 2) * (n + 2);
+    L.ioff[b] = L.itotal;
+    L.itotal += 6LL * nv * n * n;
+    L.ncells += n * n * n;
+  }
+  L.lat = lat;
+  L.nmax = nmax;
+  return nullptr;
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static size_t arena_need(const tdh_config *cfg, const Layout &L) {
+  size_t s = 0;
+  s += 3 * align256(L.total * sizeof(double));   // Qa, Qb, Qs
+  s += 2 * align256(L.itotal * sizeof(double));  // impulses, stage-1 boundary fluxes
+  if (cfg->grav_kind == 1) s += align256(L.ptotal * sizeof(double));
+  return s;
+}
+
+extern "C" size_t tdh_arena_bytes(const tdh_config *cfg, const tdh_mesh *mesh) {
+  if (!cfg) return 0;
+  Layout L;
+  if (mesh_layout(cfg, mesh, L)) return 0;
+  return arena_need(cfg, L);
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+extern "C" tdh_status tdh_init(const tdh_config *cfg, void *hip_stream, tdh_ctx **out) {
+  if (!cfg || !out) return fail(nullptr, TDH_EINVAL, "tdh_init: null argument");
+  if (cfg->eos_kind < 0 || cfg->eos_kind > 1) return fail(nullptr, TDH_EINVAL, "eos_kind must be 0 or 1");
+  if (cfg->grav_kind < 0 || cfg->grav_kind > 2) return fail(nullptr, TDH_EINVAL, "grav_kind must be 0, 1 or 2");
+  if (cfg->n_lat < 0 || cfg->n_lat > kMaxLevel) return fail(nullptr, TDH_EINVAL, "n_lat must be in [0, 30]");
+  if (cfg->inv_mode < 0 || cfg->inv_mode > 2) return fail(nullptr, TDH_EINVAL, "inv_mode must be 0, 1 or 2");
+  if (cfg->newton_max_iter < 0 || cfg->newton_max_iter > 64)
+    return fail(nullptr, TDH_EINVAL, "newton_max_iter must be in [0, 64]");
+  if (cfg->eos_kind == 0 && !(cfg->gamma > 1.0)) return fail(nullptr, TDH_EINVAL, "gamma must exceed 1");
+  if (!(cfg->cfl > 0.0)) return fail(nullptr, TDH_EINVAL, "cfl must be positive");
+  tdh_ctx *c = new tdh_ctx();
+  c->cfg = *cfg;
+  c->stream = (hipStream_t)hip_stream;
+  c->nv = cfg->dual ? 6 : 5;
+  hipDeviceProp_t prop;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    delete c;
+    return fail(nullptr, TDH_EHIP, "tdh_init: no HIP device");
+  }
+  c->grid = prop.multiProcessorCount * 8;
+  *out = c;
+  return TDH_OK;
+}
+
+extern "C" void tdh_destroy(tdh_ctx *c) {
+  if (!c) return;
+  for (auto &g : c->graphs) hipGraphExecDestroy(g.second);
+  for (void *p : c->owned) hipFree(p);
+  delete c;
+}
+
+extern "C" const char *tdh_last_error(const tdh_ctx *c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+#define CHECK_CTX(c)                                                                   \
+  do {                                                                                 \
+    if (!(c)) return fail(nullptr, TDH_EINVAL, "null context");                        \
+    if ((c)->poisoned) return fail((c), TDH_ESTATE, "context poisoned by a HIP error"); \
+  } while (0)
+
+template <class T>
+static tdh_status dev_alloc(tdh_ctx *c, T **p, size_t count) {
+  void *q = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) return fail(c, TDH_ENOMEM, "hipMalloc of %zu bytes failed", count * sizeof(T));
+  c->owned.push_back(q);
+  *p = (T *)q;
+  return TDH_OK;
+}
+
+static Phys make_phys(const tdh_config &g) {
+  Phys p{};
+  p.eos_kind = g.eos_kind;
+  p.dual = g.dual;
+  p.grav_kind = g.grav_kind;
+  p.inv_mode = g.inv_mode;
+  p.newton_max_iter = g.newton_max_iter;
+  p.gamma = g.gamma;
+  p.eta1 = g.eta1;
+  p.eta2 = g.eta2;
+  p.rho_floor = g.rho_floor;
+  p.p_floor = g.p_floor;
+  p.e_floor = g.e_floor;
+  p.gm_bh = g.gm_bh;
+  p.r_soft = g.r_soft;
+  p.r_exc = g.r_exc;
+  for (int d = 0; d < 3; ++d) {
+    p.bh_x0[d] = g.bh_x0[d];
+    p.v_frame[d] = g.v_frame[d];
+  }
+  return p;
+}
+
+static StageArgs base_args(tdh_ctx *c) {
+  StageArgs a{};
+  a.m.nx = c->nx;
+  a.m.ny = c->ny;
+  a.m.nz = c->nz;
+  for (int d = 0; d < 3; ++d) {
+    a.m.bc[d] = c->bc[d];
+    a.m.x0[d] = c->x0[d];
+    a.m.dx[d] = c->dx[d];
+    a.m.inv_dx[d] = 1.0 / c->dx[d];
+  }
+  a.m.lat = c->lat;
+  a.m.lx = c->lx;
+  a.m.ly = c->ly;
+  a.m.lz = c->lz;
+  a.m.nv = c->nv;
+  a.m.lmap = c->d_lmap;
+  a.m.blocks = c->d_blocks;
+  a.p = make_phys(c->cfg);
+  a.t = c->tab;
+  a.s = c->seed;
+  a.Qa = c->Qa;
+  a.Qb = c->Qb;
+  a.Qs = c->Qs;
+  a.imp = c->imp;
+  a.bf1 = c->bf1;
+  a.phi = c->phi;
+  a.fac = c->d_fac;
+  a.par = c->d_par;
+  a.order = c->d_order;
+  a.item_start = c->d_item_start;
+  a.cnt_ge = c->d_cnt_ge;
+  a.win = c->d_win;
+  return a;
+}
+
+// face/edge/corner adjacency through the lattice (periodic wrap, nothing beyond outflow edges)
+static void build_adjacency(tdh_ctx *c) {
+  c->adj.assign(c->nb, {});
+  const int L = c->lat;
+  const int N[3] = {c->nx, c->ny, c->nz};
+  for (int b = 0; b < c->nb; ++b) {
+    const int n = c->blk[4 * b];
+    const int o[3] = {c->blk[4 * b + 1], c->blk[4 * b + 2], c->blk[4 * b + 3]};
+    std::vector<int> &A = c->adj[b];
+    for (int cz = o[2] - L; cz < o[2] + n + L; cz += L)
+      for (int cy = o[1] - L; cy < o[1] + n + L; cy += L)
+        for (int cx = o[0] - L; cx < o[0] + n + L; cx += L) {
+          int g[3] = {cx, cy, cz};
+          bool ok = true;
+          for (int d = 0; d < 3; ++d) {
+            if (c->bc[d] == 0) g[d] = ((g[d] % N[d]) + N[d]) % N[d];
+            else if (g[d] < 0 || g[d] >= N[d]) ok = false;
+          }
+          if (!ok) continue;
+          const int nb2 = c->lmap[((g[2] / L) * c->ly + g[1] / L) * c->lx + g[0] / L];
+          if (nb2 != b && std::find(A.begin(), A.end(), nb2) == A.end()) A.push_back(nb2);
+        }
+  }
+}
+
+// device copies of the level-dependent tables; starts a new window
+static tdh_status install_levels(tdh_ctx *c, const std::vector<int> &lev) {
+  c->levels = lev;
+  c->Lmax = 0;
+  for (int l : lev) c->Lmax = std::max(c->Lmax, l);
+  c->fac.resize(c->nb);
+  for (int b = 0; b < c->nb; ++b) c->fac[b] = 1 << (c->Lmax - lev[b]);
+  c->order.resize(c->nb);
+  for (int b = 0; b < c->nb; ++b) c->order[b] = b;
+  std::stable_sort(c->order.begin(), c->order.end(), [&](int x, int y) { return lev[x] > lev[y]; });
+  c->item_start.assign(c->nb + 1, 0);
+  for (int i = 0; i < c->nb; ++i) {
+    const long long n = c->blk[4 * c->order[i]];
+    c->item_start[i + 1] = c->item_start[i] + (int)((n * n * n + kChunk - 1) / kChunk);
+  }
+  c->cnt_ge.assign(kCntSlots, 0);
+  for (int L = 0; L < kCntSlots; ++L)
+    for (int b = 0; b < c->nb; ++b)
+      if (lev[b] >= L) c->cnt_ge[L]++;
+  HIPCHK(c, hipMemcpyAsync(c->d_fac, c->fac.data(), c->nb * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_order, c->order.data(), c->nb * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_item_start, c->item_start.data(), (c->nb + 1) * sizeof(int), hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_cnt_ge, c->cnt_ge.data(), kCntSlots * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->k = 0;
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_init_blocks(tdh_ctx *c, const tdh_mesh *m, void *dev_arena, size_t arena_bytes,
+                                      const double *host_state, const double *host_phi) {
+  CHECK_CTX(c);
+  if (c->have_mesh) return fail(c, TDH_ESTATE, "tdh_init_blocks: mesh already installed");
+  Layout L;
+  if (const char *why = mesh_layout(&c->cfg, m, L)) return fail(c, TDH_EINVAL, "tdh_init_blocks: %s", why);
+  if (!dev_arena || ((uintptr_t)dev_arena & 255)) return fail(c, TDH_EINVAL, "arena must be non-null, 256-byte aligned");
+  if (arena_bytes < arena_need(&c->cfg, L)) return fail(c, TDH_ENOMEM, "arena holds %zu bytes, %zu needed", arena_bytes,
+                                                        arena_need(&c->cfg, L));
+  if (!host_state) return fail(c, TDH_EINVAL, "host_state is null");
+  if (c->cfg.grav_kind == 1 && !host_phi) return fail(c, TDH_EINVAL, "grav_kind 1 needs host_phi");
+  c->nx = m->nx; c->ny = m->ny; c->nz = m->nz;
+  for (int d = 0; d < 3; ++d) { c->bc[d] = m->bc[d]; c->x0[d] = m->x0[d]; c->dx[d] = m->dx[d]; }
+  c->nb = m->nblocks;
+  c->blk.assign(m->blk, m->blk + 4 * m->nblocks);
+  c->lat = L.lat;
+  c->nmax = L.nmax;
+  c->lx = c->nx / c->lat; c->ly = c->ny / c->lat; c->lz = c->nz / c->lat;
+  c->lmap.assign((size_t)c->lx * c->ly * c->lz, -1);
+  for (int b = 0; b < c->nb; ++b) {
+    const int n = c->blk[4 * b], ox = c->blk[4 * b + 1], oy = c->blk[4 * b + 2], oz = c->blk[4 * b + 3];
+    if (ox % c->lat || oy % c->lat || oz % c->lat || ox < 0 || oy < 0 || oz < 0 || ox + n > c->nx ||
+        oy + n > c->ny || oz + n > c->nz)
+      return fail(c, TDH_EINVAL, "block %d is not aligned to the lattice or leaves the domain", b);
+    for (int z = oz / c->lat; z < (oz + n) / c->lat; ++z)
+      for (int y = oy / c->lat; y < (oy + n) / c->lat; ++y)
+        for (int x = ox / c->lat; x < (ox + n) / c->lat; ++x) {
+          int &slot = c->lmap[((size_t)z * c->ly + y) * c->lx + x];
+          if (slot != -1) return fail(c, TDH_EINVAL, "blocks %d and %d overlap", slot, b);
+          slot = b;
+        }
+  }
+  for (int v : c->lmap)
+    if (v < 0) return fail(c, TDH_EINVAL, "the blocks do not cover the domain");
+  c->binfo.resize(c->nb);
+  for (int b = 0; b < c->nb; ++b) {
+    BlockInfo &B = c->binfo[b];
+    B.n = c->blk[4 * b]; B.ox = c->blk[4 * b + 1]; B.oy = c->blk[4 * b + 2]; B.oz = c->blk[4 * b + 3];
+    B.off = L.off[b]; B.poff = L.poff[b]; B.ioff = L.ioff[b];
+  }
+  c->total = L.total; c->ptotal = L.ptotal; c->itotal = L.itotal; c->ncells = L.ncells;
+  // carve the arena
+  char *p = (char *)dev_arena;
+  auto take = [&](size_t bytes) { char *r = p; p += align256(bytes); return r; };
+  c->Qa = (double *)take(L.total * sizeof(double));
+  c->Qb = (double *)take(L.total * sizeof(double));
+  c->Qs = (double *)take(L.total * sizeof(double));
+  c->imp = (double *)take(L.itotal * sizeof(double));
+  c->bf1 = (double *)take(L.itotal * sizeof(double));
+  if (c->cfg.grav_kind == 1) c->phi = (double *)take(L.ptotal * sizeof(double));
+  // metadata
+  tdh_status s;
+  if ((s = dev_alloc(c, &c->d_blocks, c->nb)) || (s = dev_alloc(c, &c->d_lmap, c->lmap.size())) ||
+      (s = dev_alloc(c, &c->d_fac, c->nb)) || (s = dev_alloc(c, &c->d_par, c->nb)) ||
+      (s = dev_alloc(c, &c->d_order, c->nb)) || (s = dev_alloc(c, &c->d_item_start, c->nb + 1)) ||
+      (s = dev_alloc(c, &c->d_cnt_ge, kCntSlots)) || (s = dev_alloc(c, &c->d_dtb, c->nb)) ||
+      (s = dev_alloc(c, &c->d_win, 2)) ||
+      (s = dev_alloc(c, &c->d_cfl_block_start, c->nb + 1)))
+    return s;
+  std::vector<int> cstart(c->nb + 1, 0), citem;
+  for (int b = 0; b < c->nb; ++b) {
+    const long long n = c->blk[4 * b];
+    const int ni = (int)((n * n * n + kChunk - 1) / kChunk);
+    cstart[b + 1] = cstart[b] + ni;
+    for (int i = 0; i < ni; ++i) citem.push_back(b);
+  }
+  c->cfl_nitems = cstart[c->nb];
+  if ((s = dev_alloc(c, &c->d_cfl_item_block, citem.size())) || (s = dev_alloc(c, &c->d_cfl_part, citem.size())))
+    return s;
+  HIPCHK(c, hipMemcpyAsync(c->d_blocks, c->binfo.data(), c->nb * sizeof(BlockInfo), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_lmap, c->lmap.data(), c->lmap.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_cfl_block_start, cstart.data(), cstart.size() * sizeof(int), hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_cfl_item_block, citem.data(), citem.size() * sizeof(int), hipMemcpyHostToDevice,
+                           c->stream));
+  c->par.assign(c->nb, 0);
+  HIPCHK(c, hipMemcpyAsync(c->d_par, c->par.data(), c->nb * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->Qa, host_state, L.total * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  if (c->phi) HIPCHK(c, hipMemcpyAsync(c->phi, host_phi, L.ptotal * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  build_adjacency(c);
+  c->have_mesh = true;
+  return install_levels(c, std::vector<int>(c->nb, 0));
+}
+
+extern "C" tdh_status tdh_set_eos_table(tdh_ctx *c, int nrho, int nT, double lr0, double dlr, double lT0, double dlT,
+                                        const double *lP, const double *le, const double *lc2) {
+  CHECK_CTX(c);
+  if (nrho < 2 || nT < 2 || nrho > 4096 || nT > 4096) return fail(c, TDH_ERANGE, "table dimensions out of range");
+  if (!lP || !le || !lc2) return fail(c, TDH_EINVAL, "null table array");
+  if (!(dlr > 0.0) || !(dlT > 0.0)) return fail(c, TDH_EINVAL, "table spacings must be positive");
+  for (int i = 0; i < nrho; ++i)
+    for (int j = 0; j + 1 < nT; ++j)
+      if (!(le[(size_t)i * nT + j + 1] > le[(size_t)i * nT + j]))
+        return fail(c, TDH_EINVAL, "log e is not increasing in T on row %d", i);
+  const size_t sz = (size_t)nrho * nT;
+  if (!c->d_table || c->tab.nrho * c->tab.nT != (int)sz) {
+    tdh_status s = dev_alloc(c, &c->d_table, 3 * sz);
+    if (s) return s;
+  }
+  HIPCHK(c, hipMemcpyAsync(c->d_table, lP, sz * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_table + sz, le, sz * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_table + 2 * sz, lc2, sz * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->tab.nrho = nrho;
+  c->tab.nT = nT;
+  c->tab.lr0 = lr0;
+  c->tab.dlr = dlr;
+  c->tab.inv_dlr = 1.0 / dlr;
+  c->tab.lT0 = lT0;
+  c->tab.dlT = dlT;
+  c->tab.lP = c->d_table;
+  c->tab.le = c->d_table + sz;
+  c->tab.lc2 = c->d_table + 2 * sz;
+  c->have_table = true;
+  for (auto &g : c->graphs) hipGraphExecDestroy(g.second);
+  c->graphs.clear();
+  return TDH_OK;
+}
+
+static tdh_status ready(tdh_ctx *c) {
+  if (!c->have_mesh) return fail(c, TDH_ESTATE, "no mesh: call tdh_init_blocks first");
+  if (c->cfg.eos_kind == 1 && !c->have_table) return fail(c, TDH_ESTATE, "tabulated EOS selected but no table set");
+  return TDH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// LAT level assignment (eq lat-factor, bin merging, neighbour limit)
+// ---------------------------------------------------------------------------
+static std::vector<int> assign_levels(const tdh_ctx *c, const std::vector<double> &dtb, double &dt0) {
+  const int nb = c->nb;
+  dt0 = INFINITY;
+  for (double v : dtb) dt0 = std::min(dt0, v);
+  std::vector<int> e(nb);
+  for (int b = 0; b < nb; ++b) {
+    // floor(log2(dt_b / dt0)) exactly, from the binary exponent of the ratio
+    int ex = std::ilogb(dtb[b] / dt0);
+    e[b] = std::max(0, std::min(c->cfg.n_lat, ex));
+  }
+  for (;;) {  // merge sparsely filled top bins into the next lower one
+    int top = *std::max_element(e.begin(), e.end());
+    if (top == 0) break;
+    int cnt = (int)std::count(e.begin(), e.end(), top);
+    if ((double)cnt >= c->cfg.merge_frac * nb) break;
+    for (int &v : e)
+      if (v == top) v = top - 1;
+  }
+  // neighbours differ by at most one exponent: relax to the fixed point
+  for (bool changed = true; changed;) {
+    changed = false;
+    for (int b = 0; b < nb; ++b)
+      for (int n : c->adj[b])
+        if (e[b] > e[n] + 1) { e[b] = e[n] + 1; changed = true; }
+  }
+  const int L = *std::max_element(e.begin(), e.end());
+  std::vector<int> lev(nb);
+  for (int b = 0; b < nb; ++b) lev[b] = L - e[b];
+  return lev;
+}
+
+static tdh_status require_window_boundary(tdh_ctx *c) {
+  if (c->k != 0) return fail(c, TDH_ESTATE, "a LAT window is in progress (sub-cycle %d)", c->k);
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_reduce_dt(tdh_ctx *c, double *host_dtb, double *host_dt0, int8_t *host_levels,
+                                    int *host_lmax) {
+  CHECK_CTX(c);
+  tdh_status s;
+  if ((s = ready(c)) || (s = require_window_boundary(c))) return s;
+  StageArgs a = base_args(c);
+  HIPCHK(c, launch_cfl(a, c->cfg.cfl, c->t, c->d_cfl_item_block, c->cfl_nitems, c->d_cfl_part, c->nb,
+                       c->d_cfl_block_start, c->d_dtb, c->stream));
+  c->stats.kernel_launches += 2;
+  std::vector<double> dtb(c->nb);
+  HIPCHK(c, hipMemcpyAsync(dtb.data(), c->d_dtb, c->nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double dt0;
+  std::vector<int> lev = c->cfg.n_lat > 0 ? assign_levels(c, dtb, dt0) : std::vector<int>(c->nb, 0);
+  if (c->cfg.n_lat == 0) {
+    dt0 = INFINITY;
+    for (double v : dtb) dt0 = std::min(dt0, v);
+  }
+  if (!(dt0 > 0.0) || !std::isfinite(dt0)) return fail(c, TDH_ERANGE, "CFL step is not a positive finite number");
+  if ((s = install_levels(c, lev))) return s;
+  if (host_dtb) std::copy(dtb.begin(), dtb.end(), host_dtb);
+  if (host_dt0) *host_dt0 = dt0;
+  if (host_levels)
+    for (int b = 0; b < c->nb; ++b) host_levels[b] = (int8_t)lev[b];
+  if (host_lmax) *host_lmax = c->Lmax;
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_set_levels(tdh_ctx *c, const int8_t *host_levels) {
+  CHECK_CTX(c);
+  tdh_status s;
+  if ((s = ready(c)) || (s = require_window_boundary(c))) return s;
+  if (!host_levels) return fail(c, TDH_EINVAL, "null levels");
+  std::vector<int> lev(c->nb);
+  for (int b = 0; b < c->nb; ++b) {
+    lev[b] = host_levels[b];
+    if (lev[b] < 0 || lev[b] > kMaxLevel) return fail(c, TDH_EINVAL, "level of block %d outside [0, 30]", b);
+  }
+  for (int b = 0; b < c->nb; ++b)
+    for (int n : c->adj[b])
+      if (std::abs(lev[b] - lev[n]) > 1) return fail(c, TDH_EINVAL, "neighbours %d and %d differ by more than one level", b, n);
+  return install_levels(c, lev);
+}
+
+// ---------------------------------------------------------------------------
+// stepping
+// ---------------------------------------------------------------------------
+static int ctz(int v) { return __builtin_ctz((unsigned)v); }
+
+static int lmin_of(int k, int Lmax) { return k == 0 ? 0 : Lmax - ctz(k); }
+
+// enqueue sub-cycle k of the current window
+static tdh_status enqueue_subcycle(tdh_ctx *c, int k, bool batched) {
+  const int lmin = lmin_of(k, c->Lmax);
+  StageArgs a = base_args(c);
+  a.k = k;
+  for (int phase = 1; phase <= 2; ++phase) {
+    a.phase = phase;
+    if (batched) {
+      a.Llo = lmin;
+      a.Lhi = kCntSlots - 2;
+      HIPCHK(c, launch_stage(a, c->grid, c->stream));
+      c->stats.kernel_launches++;
+    } else {
+      for (int L = lmin; L <= c->Lmax; ++L) {
+        a.Llo = L;
+        a.Lhi = L;
+        HIPCHK(c, launch_stage(a, c->grid, c->stream));
+        c->stats.kernel_launches++;
+      }
+    }
+  }
+  HIPCHK(c, launch_commit(c->d_order, c->d_cnt_ge, lmin, c->d_par, c->stream));
+  c->stats.kernel_launches++;
+  if (c->Lmax > 0) {
+    const int fmax = 1 << c->Lmax;
+    const int lc = (k + 1 == fmax) ? 0 : c->Lmax - ctz(k + 1);
+    a.k = k + 1;
+    for (int d = 0; d < 3; ++d) {
+      HIPCHK(c, launch_reflux(a, lc, d, c->nmax, 1024, c->stream));
+      c->stats.kernel_launches++;
+    }
+  }
+  return TDH_OK;
+}
+
+static void account_subcycle(tdh_ctx *c, int k) {
+  const int lmin = lmin_of(k, c->Lmax);
+  for (int b = 0; b < c->nb; ++b)
+    if (c->levels[b] >= lmin) {
+      c->par[b] ^= 1;
+      const long long n = c->blk[4 * b];
+      c->stats.block_updates++;
+      c->stats.cell_updates += n * n * n;
+    }
+  c->stats.sub_cycles++;
+}
+
+static void finish_window(tdh_ctx *c) {
+  c->t = c->t + c->dt_coarse;
+  c->k = 0;
+  c->stats.windows++;
+}
+
+extern "C" tdh_status tdh_step_level(tdh_ctx *c, int level, double dt) {
+  CHECK_CTX(c);
+  tdh_status s;
+  if ((s = ready(c))) return s;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, TDH_EINVAL, "dt must be positive and finite");
+  const int want = lmin_of(c->k, c->Lmax);
+  if (level != want) return fail(c, TDH_ESTATE, "sub-cycle %d of the window advances level %d, not %d", c->k, want, level);
+  if (c->k == 0) {
+    c->dt_coarse = dt;
+    c->dt0 = std::ldexp(dt, -c->Lmax);
+    HIPCHK(c, launch_set_window(c->d_win, c->t, c->dt0, c->stream));
+  } else if (std::ldexp(dt, level) != c->dt_coarse) {
+    return fail(c, TDH_EINVAL, "dt * 2^level must equal the window's coarse step");
+  }
+  if ((s = enqueue_subcycle(c, c->k, true))) return s;
+  account_subcycle(c, c->k);
+  c->k++;
+  if (c->k == (1 << c->Lmax)) finish_window(c);
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_run_window(tdh_ctx *c, double dt_coarse, int batched, int use_graph) {
+  CHECK_CTX(c);
+  tdh_status s;
+  if ((s = ready(c)) || (s = require_window_boundary(c))) return s;
+  if (!(dt_coarse > 0.0) || !std::isfinite(dt_coarse)) return fail(c, TDH_EINVAL, "dt must be positive and finite");
+  c->dt_coarse = dt_coarse;
+  c->dt0 = std::ldexp(dt_coarse, -c->Lmax);
+  const int nsub = 1 << c->Lmax;
+  HIPCHK(c, launch_set_window(c->d_win, c->t, c->dt0, c->stream));
+  if (use_graph) {
+    // The graph holds the window's launches for this Lmax; the window time,
+    // step and the level-dependent work lists live in device memory, so one
+    // capture serves every later window with the same Lmax.
+    const auto key = std::make_pair(c->Lmax, batched ? 1 : 0);
+    auto it = c->graphs.find(key);
+    if (it != c->graphs.end()) {
+      HIPCHK(c, hipGraphLaunch(it->second, c->stream));
+      for (int k = 0; k < nsub; ++k) account_subcycle(c, k);
+      c->stats.kernel_launches += 1;
+      finish_window(c);
+      return TDH_OK;
+    }
+    hipGraph_t g;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < nsub; ++k) {
+      if ((s = enqueue_subcycle(c, k, batched != 0))) {
+        hipGraph_t dummy;
+        hipStreamEndCapture(c->stream, &dummy);
+        return s;
+      }
+    }
+    HIPCHK(c, hipStreamEndCapture(c->stream, &g));
+    hipGraphExec_t ge;
+    HIPCHK(c, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+    hipGraphDestroy(g);
+    c->graphs[key] = ge;
+    HIPCHK(c, hipGraphLaunch(ge, c->stream));
+  } else {
+    for (int k = 0; k < nsub; ++k)
+      if ((s = enqueue_subcycle(c, k, batched != 0))) return s;
+  }
+  for (int k = 0; k < nsub; ++k) account_subcycle(c, k);
+  finish_window(c);
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_get_time(tdh_ctx *c, double *t) {
+  CHECK_CTX(c);
+  if (!t) return fail(c, TDH_EINVAL, "null output");
+  *t = c->t;
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_set_time(tdh_ctx *c, double t) {
+  CHECK_CTX(c);
+  tdh_status s;
+  if ((s = require_window_boundary(c))) return s;
+  c->t = t;
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_get_state(tdh_ctx *c, double *host) {
+  CHECK_CTX(c);
+  tdh_status s;
+  if ((s = ready(c))) return s;
+  if (!host) return fail(c, TDH_EINVAL, "null output");
+  if (c->k != 0) return fail(c, TDH_ESTATE, "state is only defined between windows");
+  for (int b = 0; b < c->nb; ++b) {
+    const long long n = c->blk[4 * b];
+    const double *src = (c->par[b] ? c->Qb : c->Qa) + c->binfo[b].off;
+    HIPCHK(c, hipMemcpyAsync(host + c->binfo[b].off, src, c->nv * n * n * n * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_set_state(tdh_ctx *c, const double *host) {
+  CHECK_CTX(c);
+  tdh_status s;
+  if ((s = ready(c)) || (s = require_window_boundary(c))) return s;
+  if (!host) return fail(c, TDH_EINVAL, "null input");
+  HIPCHK(c, hipMemcpyAsync(c->Qa, host, c->total * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  c->par.assign(c->nb, 0);
+  HIPCHK(c, hipMemcpyAsync(c->d_par, c->par.data(), c->nb * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_eos_invert_batch(tdh_ctx *c, const double *lr, const double *le, double *lT, int32_t *j,
+                                           int32_t *iters, int64_t n, int mode) {
+  CHECK_CTX(c);
+  if (!c->have_table) return fail(c, TDH_ESTATE, "no EOS table");
+  if (n < 0 || n > (1LL << 31)) return fail(c, TDH_ERANGE, "n out of range");
+  if (mode < 0 || mode > 2) return fail(c, TDH_EINVAL, "mode must be 0, 1 or 2");
+  if (mode == 1 && !c->seed.enabled) return fail(c, TDH_ESTATE, "mode 1 needs a trained seed network");
+  if (!lr || !le) return fail(c, TDH_EINVAL, "null input");
+  HIPCHK(c, launch_eos_invert(c->tab, c->seed, c->cfg.newton_max_iter, lr, le, lT, j, iters, n, mode, c->stream));
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_eos_eval_batch(tdh_ctx *c, const double *rho, const double *U, double *P, double *cs,
+                                         int64_t n) {
+  CHECK_CTX(c);
+  if (c->cfg.eos_kind == 1 && !c->have_table) return fail(c, TDH_ESTATE, "no EOS table");
+  if (n < 0 || n > (1LL << 31)) return fail(c, TDH_ERANGE, "n out of range");
+  if (!rho || !U || !P || !cs) return fail(c, TDH_EINVAL, "null argument");
+  HIPCHK(c, launch_eos_eval(make_phys(c->cfg), c->tab, rho, U, P, cs, n, c->stream));
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_get_stats(tdh_ctx *c, tdh_stats *out) {
+  CHECK_CTX(c);
+  if (!out) return fail(c, TDH_EINVAL, "null output");
+  *out = c->stats;
+  return TDH_OK;
+}

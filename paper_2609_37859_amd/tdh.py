@@ -1,0 +1,264 @@
+"""Python binding of libtdh (include/tdh.h): argument marshalling only.
+
+Every step of the update runs in the HIP library; PyTorch provides the device
+arena and the stream.  There is no fallback: if libtdh.so is missing or a
+call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtdh.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "tdh.h")
+
+
+class TdhError(RuntimeError):
+    pass
+
+
+class tdh_config(C.Structure):
+    _fields_ = [("eos_kind", C.c_int), ("dual", C.c_int), ("grav_kind", C.c_int), ("n_lat", C.c_int),
+                ("gamma", C.c_double), ("eta1", C.c_double), ("eta2", C.c_double), ("cfl", C.c_double),
+                ("rho_floor", C.c_double), ("p_floor", C.c_double), ("e_floor", C.c_double),
+                ("merge_frac", C.c_double), ("gm_bh", C.c_double), ("r_soft", C.c_double), ("r_exc", C.c_double),
+                ("bh_x0", C.c_double * 3), ("v_frame", C.c_double * 3),
+                ("inv_mode", C.c_int), ("newton_max_iter", C.c_int)]
+
+
+class tdh_mesh(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("bc", C.c_int * 3),
+                ("x0", C.c_double * 3), ("dx", C.c_double * 3), ("nblocks", C.c_int),
+                ("blk", C.POINTER(C.c_int))]
+
+
+class tdh_stats(C.Structure):
+    _fields_ = [("block_updates", C.c_int64), ("cell_updates", C.c_int64), ("windows", C.c_int64),
+                ("sub_cycles", C.c_int64), ("kernel_launches", C.c_int64)]
+
+
+_lib = None
+
+
+def header_functions():
+    """Names of the functions include/tdh.h declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(tdh_[a-z0-9_]+)\s*\(", txt)))
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise TdhError(f"{LIB_PATH} is not built: run __graft_entry__.build() (hipcc for gfx950)")
+    L = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    vp, d, i, st = C.c_void_p, C.c_double, C.c_int, C.c_int
+    ctx = vp
+    sig = {
+        "tdh_arena_bytes": ([P(tdh_config), P(tdh_mesh)], C.c_size_t),
+        "tdh_init": ([P(tdh_config), vp, P(ctx)], st),
+        "tdh_init_blocks": ([ctx, P(tdh_mesh), vp, C.c_size_t, P(d), P(d)], st),
+        "tdh_set_eos_table": ([ctx, i, i, d, d, d, d, P(d), P(d), P(d)], st),
+        "tdh_reduce_dt": ([ctx, P(d), P(d), P(C.c_int8), P(i)], st),
+        "tdh_set_levels": ([ctx, P(C.c_int8)], st),
+        "tdh_step_level": ([ctx, i, d], st),
+        "tdh_run_window": ([ctx, d, i, i], st),
+        "tdh_get_time": ([ctx, P(d)], st),
+        "tdh_set_time": ([ctx, d], st),
+        "tdh_get_state": ([ctx, P(d)], st),
+        "tdh_set_state": ([ctx, P(d)], st),
+        "tdh_eos_invert_batch": ([ctx, vp, vp, vp, vp, vp, C.c_int64, i], st),
+        "tdh_eos_eval_batch": ([ctx, vp, vp, vp, vp, C.c_int64], st),
+        "tdh_get_stats": ([ctx, P(tdh_stats)], st),
+        "tdh_last_error": ([ctx], C.c_char_p),
+        "tdh_destroy": ([ctx], None),
+        "tdh_mlp_init": ([ctx, P(C.c_float), d, d, d, d, d, d], st),
+        "tdh_mlp_train": ([ctx, vp, vp, C.c_int64, i, i, C.c_float, C.c_uint64, P(C.c_float)], st),
+        "tdh_mlp_get_params": ([ctx, P(C.c_float)], st),
+        "tdh_mlp_forward": ([ctx, vp, vp, C.c_int64], st),
+        "tdh_mlp_loss_grad": ([ctx, vp, vp, C.c_int64, P(C.c_float), P(C.c_float)], st),
+        "tdh_mlp_enable_seed": ([ctx, i], st),
+    }
+    for name, (args, res) in sig.items():
+        if hasattr(L, name):
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+    _lib = L
+    return L
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_config(cfg, inv_mode=0, newton_max_iter=4) -> tdh_config:
+    c = tdh_config()
+    for f, _ in tdh_config._fields_:
+        if f == "inv_mode":
+            c.inv_mode = inv_mode
+        elif f == "newton_max_iter":
+            c.newton_max_iter = newton_max_iter
+        elif f in ("bh_x0", "v_frame"):
+            getattr(c, f)[:] = [float(x) for x in getattr(cfg, f)]
+        else:
+            setattr(c, f, getattr(cfg, f))
+    return c
+
+
+def make_mesh(mesh):
+    blk = np.ascontiguousarray(mesh.blk, dtype=np.int32)
+    m = tdh_mesh()
+    m.nx, m.ny, m.nz = mesh.nx, mesh.ny, mesh.nz
+    m.bc[:] = list(mesh.bc)
+    m.x0[:] = list(mesh.x0)
+    m.dx[:] = list(mesh.dx)
+    m.nblocks = mesh.nblocks
+    m.blk = blk.ctypes.data_as(C.POINTER(C.c_int))
+    return m, blk
+
+
+class Context:
+    """One library context on one GPU, owning a torch arena for the state."""
+
+    def __init__(self, cfg, mesh, state, phi=None, table=None, inv_mode=0, newton_max_iter=4, device="cuda:0",
+                 stream=None):
+        import torch
+        self.torch = torch
+        self.L = lib()
+        self.cfg, self.mesh = cfg, mesh
+        self.nv = cfg.nv
+        self.device = torch.device(device)
+        torch.cuda.set_device(self.device)
+        # a stream of our own (default priority): graph capture needs a non-legacy stream
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self._cfg = make_config(cfg, inv_mode, newton_max_iter)
+        self._mesh, self._blk = make_mesh(mesh)
+        nbytes = self.L.tdh_arena_bytes(C.byref(self._cfg), C.byref(self._mesh))
+        if nbytes == 0:
+            raise TdhError("tdh_arena_bytes rejected the mesh")
+        self.arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        self.arena.record_stream(self.stream)
+        base = self.arena.data_ptr()
+        self._arena_ptr = (base + 255) & ~255
+        self.ctx = C.c_void_p()
+        self._check(self.L.tdh_init(C.byref(self._cfg), C.c_void_p(self.stream.cuda_stream), C.byref(self.ctx)),
+                    "tdh_init", ctx=False)
+        if table is not None:
+            self.set_eos_table(table)
+        st = np.ascontiguousarray(state, dtype=np.float64)
+        if st.size != mesh.offsets(self.nv)[-1]:
+            raise TdhError("state has the wrong size for this mesh")
+        ph = None if phi is None else np.ascontiguousarray(phi, dtype=np.float64)
+        self._check(self.L.tdh_init_blocks(self.ctx, C.byref(self._mesh), C.c_void_p(self._arena_ptr), nbytes,
+                                           _dp(st), None if ph is None else _dp(ph)), "tdh_init_blocks")
+
+    def _check(self, rc, what, ctx=True):
+        if rc != 0:
+            msg = self.L.tdh_last_error(self.ctx if ctx else None)
+            raise TdhError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")
+
+    def set_eos_table(self, t):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (t.lP, t.le, t.lc2)]
+        self._check(self.L.tdh_set_eos_table(self.ctx, t.nrho, t.nT, t.lr0, t.dlr, t.lT0, t.dlT, *map(_dp, arrs)),
+                    "tdh_set_eos_table")
+
+    def reduce_dt(self):
+        nb = self.mesh.nblocks
+        dtb = np.zeros(nb)
+        lev = np.zeros(nb, dtype=np.int8)
+        dt0 = C.c_double()
+        lmax = C.c_int()
+        self._check(self.L.tdh_reduce_dt(self.ctx, _dp(dtb), C.byref(dt0),
+                                         lev.ctypes.data_as(C.POINTER(C.c_int8)), C.byref(lmax)), "tdh_reduce_dt")
+        return dtb, dt0.value, lev.astype(np.int32), lmax.value
+
+    def set_levels(self, levels):
+        lev = np.ascontiguousarray(levels, dtype=np.int8)
+        self._check(self.L.tdh_set_levels(self.ctx, lev.ctypes.data_as(C.POINTER(C.c_int8))), "tdh_set_levels")
+
+    def step_level(self, level, dt):
+        self._check(self.L.tdh_step_level(self.ctx, int(level), float(dt)), "tdh_step_level")
+
+    def run_window(self, dt_coarse, batched=True, graph=False):
+        self._check(self.L.tdh_run_window(self.ctx, float(dt_coarse), int(batched), int(graph)), "tdh_run_window")
+
+    @property
+    def time(self):
+        t = C.c_double()
+        self._check(self.L.tdh_get_time(self.ctx, C.byref(t)), "tdh_get_time")
+        return t.value
+
+    @time.setter
+    def time(self, t):
+        self._check(self.L.tdh_set_time(self.ctx, float(t)), "tdh_set_time")
+
+    def get_state(self):
+        out = np.empty(self.mesh.offsets(self.nv)[-1])
+        self._check(self.L.tdh_get_state(self.ctx, _dp(out)), "tdh_get_state")
+        return out
+
+    def set_state(self, U):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        self._check(self.L.tdh_set_state(self.ctx, _dp(U)), "tdh_set_state")
+
+    def eos_invert(self, lr, le, mode=0):
+        torch = self.torch
+        lr = lr.to(self.device, torch.float64).contiguous()
+        le = le.to(self.device, torch.float64).contiguous()
+        n = lr.numel()
+        lT = torch.empty(n, dtype=torch.float64, device=self.device)
+        j = torch.empty(n, dtype=torch.int32, device=self.device)
+        it = torch.empty(n, dtype=torch.int32, device=self.device)
+        self._check(self.L.tdh_eos_invert_batch(self.ctx, lr.data_ptr(), le.data_ptr(), lT.data_ptr(), j.data_ptr(),
+                                                it.data_ptr(), n, int(mode)), "tdh_eos_invert_batch")
+        return lT, j, it
+
+    def eos_eval(self, rho, U):
+        torch = self.torch
+        rho = rho.to(self.device, torch.float64).contiguous()
+        U = U.to(self.device, torch.float64).contiguous()
+        P = torch.empty_like(rho)
+        cs = torch.empty_like(rho)
+        self._check(self.L.tdh_eos_eval_batch(self.ctx, rho.data_ptr(), U.data_ptr(), P.data_ptr(), cs.data_ptr(),
+                                              rho.numel()), "tdh_eos_eval_batch")
+        return P, cs
+
+    def stats(self):
+        s = tdh_stats()
+        self._check(self.L.tdh_get_stats(self.ctx, C.byref(s)), "tdh_get_stats")
+        return {f: getattr(s, f) for f, _ in tdh_stats._fields_}
+
+    def sync(self):
+        self.stream.synchronize()
+
+    def close(self):
+        if self.ctx:
+            self.L.tdh_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run_sync_steps(ctx: Context, nsteps, dts=None):
+    """nsteps synchronous steps; dt from the library's CFL reduction unless given."""
+    used = []
+    for s in range(nsteps):
+        if dts is None:
+            _, dt, _, _ = ctx.reduce_dt()
+        else:
+            dt = float(dts[s])
+        ctx.step_level(0, dt)
+        used.append(dt)
+    return np.array(used)

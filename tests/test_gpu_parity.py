@@ -1,0 +1,208 @@
+"""GPU path (libtdh through its C ABI) against the CPU oracle.
+
+Both sides get the same seeded synthetic inputs from the input module; the
+oracle never sees GPU output.  Bar: max relative error <= 1e-11 per variable
+and cell (tests/parity.py), bit-exact for integer results (levels, schedule,
+table cells) and between launch forms of the GPU path itself.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2609_37859_amd import workloads as W
+from tests.parity import TOL, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tdh():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_37859_amd import tdh as T
+    T.lib()
+    return T
+
+
+def _run_gpu_sync(T, cfg, mesh, U, nsteps, table=None, phi=None, dts=None, **kw):
+    ctx = T.Context(cfg, mesh, U, phi=phi, table=table, **kw)
+    used = T.run_sync_steps(ctx, nsteps, dts)
+    out = ctx.get_state()
+    ctx.close()
+    return out, used
+
+
+def test_c1_entropy_wave_20_steps(tdh, orc):
+    """One periodic 32^3 block, ideal gas, each side choosing its own CFL steps."""
+    cfg, mesh, U = W.entropy_wave_c1()
+    g, dg = _run_gpu_sync(tdh, cfg, mesh, U, 20)
+    o, do = orc.run_sync(cfg, mesh, U, 20)
+    assert np.max(np.abs(dg / do - 1)) < 1e-13
+    err = rel_err(5, mesh, g, o)
+    print("C1 rel err per variable", err)
+    assert np.all(err <= TOL)
+
+
+def test_uniform_state_bit_exact(tdh, orc):
+    for dual in (0, 1):
+        cfg = W.Config(dual=dual)
+        mesh = W.uniform_mesh(2, 2, 1, 16, (0.1, 0.2, 0.15))
+        U = W.uniform_state(mesh, cfg)
+        g, _ = _run_gpu_sync(tdh, cfg, mesh, U, 5, dts=[1e-3] * 5)
+        assert np.array_equal(g, U)
+
+
+def test_periodic_conservation_gpu(tdh, orc):
+    cfg = W.Config(dual=1)
+    mesh = W.uniform_mesh(2, 2, 2, 16, 1.0 / 32)
+    U = W.random_smooth_state(mesh, cfg, seed=3, amp=0.3)
+    g, dts = _run_gpu_sync(tdh, cfg, mesh, U, 10)
+    o, _ = orc.run_sync(cfg, mesh, U, 10, dts=dts)
+    G0, G1 = W.to_global(mesh, 6, U), W.to_global(mesh, 6, g)
+    for v in (0, 4):
+        assert abs(math.fsum(G1[v].ravel()) - math.fsum(G0[v].ravel())) <= 1e-14 * math.fsum(G0[v].ravel())
+    err = rel_err(6, mesh, g, o)
+    assert np.all(err <= TOL), err
+
+
+@pytest.mark.parametrize("inv_mode", [0, 2])
+def test_c2_table_dual_energy_20_steps(tdh, orc, saha, inv_mode):
+    """C2: 128^3 as 64 blocks of 32^3, Saha table, dual energy, Mach 1e7 stream."""
+    cfg, mesh, U = W.stream_c2(saha)
+    g, dg = _run_gpu_sync(tdh, cfg, mesh, U, 20, table=saha, inv_mode=inv_mode)
+    o, do = orc.run_sync(cfg, mesh, U, 20, table=saha)
+    assert np.max(np.abs(dg / do - 1)) < 1e-13
+    err = rel_err(6, mesh, g, o)
+    print("C2 rel err per variable", err)
+    assert np.all(err <= TOL)
+
+
+def test_inversion_modes_agree_bitwise_and_with_oracle(tdh, orc, saha):
+    import torch
+    cfg = W.Config(eos_kind=1, e_floor=saha.e_floor)
+    ctx = tdh.Context(cfg, W.uniform_mesh(1, 1, 1, 8, 1.0), W.uniform_state(W.uniform_mesh(1, 1, 1, 8, 1.0), W.Config()),
+                      table=saha)
+    rng = np.random.default_rng(5)
+    n = 1 << 16
+    lr = rng.uniform(-12.2, 2.2, n)
+    le = rng.uniform(saha.le.min() - 0.2, saha.le.max() + 0.2, n)
+    lT0, j0, it0 = ctx.eos_invert(torch.from_numpy(lr), torch.from_numpy(le), mode=0)
+    lT2, j2, it2 = ctx.eos_invert(torch.from_numpy(lr), torch.from_numpy(le), mode=2)
+    torch.cuda.synchronize()
+    assert torch.equal(j0, j2) and torch.equal(lT0, lT2)
+    jo, wo, lTo = orc.table_invert(saha, lr, le)
+    jg = j0.cpu().numpy()
+    lTg = lT0.cpu().numpy()
+    same = jg == jo
+    assert same.mean() > 0.999
+    assert np.max(np.abs(lTg - lTo)) < 1e-12
+    ctx.close()
+
+
+def test_levels_bit_exact_and_dt_parity(tdh, orc):
+    """C3-shaped polytrope (reduced to 4^3 blocks of 16^3): per-block CFL steps
+    agree to 1e-13, and the level assignment computed by the library from its
+    own dt_b equals the oracle's assignment on the same dt_b bit for bit."""
+    cfg, mesh, U, phi, info = W.polytrope_c3(nb=4, n=16)
+    ctx = tdh.Context(cfg, mesh, U, phi=phi)
+    dtb, dt0, lev, L = ctx.reduce_dt()
+    ctx.close()
+    dto = orc.cfl(cfg, mesh, U)
+    assert np.max(np.abs(dtb / dto - 1)) < 1e-13
+    lev_o, L_o, dt0_o = orc.lat_assign(cfg, mesh, dtb)
+    assert L == L_o and dt0 == dt0_o
+    assert np.array_equal(lev, lev_o)
+    assert L >= 1
+
+
+def _lat_run_gpu(T, cfg, mesh, U, phi, levels, dt0, windows, batched=True, graph=False, step_api=False):
+    ctx = T.Context(cfg, mesh, U, phi=phi)
+    Lmax = int(np.max(levels))
+    for w in range(windows):
+        ctx.set_levels(levels)
+        dtc = dt0 * 2 ** Lmax
+        if step_api:
+            for k in range(2 ** Lmax):
+                lmin = 0 if k == 0 else Lmax - ((k & -k).bit_length() - 1)
+                ctx.step_level(lmin, dtc / 2 ** lmin)
+        else:
+            ctx.run_window(dtc, batched=batched, graph=graph)
+    out = ctx.get_state()
+    st = ctx.stats()
+    ctx.close()
+    return out, st
+
+
+def test_lat_window_parity_polytrope(tdh, orc):
+    """LAT windows on the reduced polytrope: GPU equals the oracle to 1e-11
+    with the oracle's level assignment; all launch forms agree bit for bit."""
+    cfg, mesh, U, phi, info = W.polytrope_c3(nb=4, n=16)
+    dto = orc.cfl(cfg, mesh, U)
+    lev, L, dt0 = orc.lat_assign(cfg, mesh, dto)
+    assert L >= 1
+    o = U
+    t = 0.0
+    for w in range(2):
+        o, nupd = orc.lat_window(cfg, mesh, o, lev, dt0, phi=phi, t0=t)
+        t += dt0 * 2 ** L
+    g, st = _lat_run_gpu(tdh, cfg, mesh, U, phi, lev, dt0, 2)
+    err = rel_err(5, mesh, g, o)
+    print("LAT rel err", err, st)
+    assert np.all(err <= TOL)
+    assert st["block_updates"] == 2 * nupd
+    g2, _ = _lat_run_gpu(tdh, cfg, mesh, U, phi, lev, dt0, 2, batched=False)
+    g3, _ = _lat_run_gpu(tdh, cfg, mesh, U, phi, lev, dt0, 2, graph=True)
+    g4, _ = _lat_run_gpu(tdh, cfg, mesh, U, phi, lev, dt0, 2, step_api=True)
+    assert np.array_equal(g, g2) and np.array_equal(g, g3) and np.array_equal(g, g4)
+
+
+def test_lat_reflux_conservation_gpu(tdh, orc):
+    cfg = W.Config(dual=1)
+    mesh = W.uniform_mesh(4, 2, 2, 8, 1.0 / 32)
+    U = W.random_smooth_state(mesh, cfg, seed=8, amp=0.3)
+    bx = mesh.blk[:, 1] // 8
+    lev = np.array([{0: 2, 1: 1, 2: 0, 3: 1}[int(x)] for x in bx], dtype=np.int32)
+    g, st = _lat_run_gpu(tdh, cfg, mesh, U, None, lev, 1e-3, 1)
+    o, n = orc.lat_window(cfg, mesh, U, lev, 1e-3)
+    assert np.all(rel_err(6, mesh, g, o) <= TOL)
+    G0, G1 = W.to_global(mesh, 6, U), W.to_global(mesh, 6, g)
+    for v in range(5):
+        assert abs(math.fsum(G1[v].ravel()) - math.fsum(G0[v].ravel())) <= 1e-14 * math.fsum(G0[0].ravel())
+
+
+def test_high_mach_wave_gpu(tdh, orc):
+    """Dual-energy entropy wave at Mach ~7.7e7 (blocks of 16^3): GPU = oracle."""
+    cfg, mesh, U = W.high_mach_wave(ncell=64, nt=16, dual=1)
+    g, dts = _run_gpu_sync(tdh, cfg, mesh, U, 30)
+    o, _ = orc.run_sync(cfg, mesh, U, 30, dts=dts)
+    assert np.all(rel_err(6, mesh, g, o) <= TOL)
+
+
+def test_mixed_block_sizes_point_mass_excision(tdh, orc, saha):
+    """Mixed 16^3 / 32^3 blocks (some 32^3 regions split into eight 16^3), Saha
+    table, dual energy, moving softened point mass with excision, outflow."""
+    split = np.zeros((2, 2, 3), dtype=bool)
+    split[0, 1, 1] = split[1, 0, 2] = True
+    dx = 2e10
+    mesh = W.mixed_mesh((3, 2, 2), 32, split, dx, x0=(0.0, 0.0, 0.0), bc=(1, 1, 1))
+    cfg = W.Config(eos_kind=1, dual=1, grav_kind=2, rho_floor=1e-12, p_floor=0.0, e_floor=saha.e_floor,
+                   gm_bh=1.327e29, r_exc=4 * dx, r_soft=0.1 * dx, bh_x0=(50 * dx, 30 * dx, 33 * dx),
+                   v_frame=(1e7, 0.0, 0.0))
+    L = np.array([mesh.nx, mesh.ny, mesh.nz]) * dx
+
+    def fn(x, y, z):
+        r2 = (y - 0.5 * L[1]) ** 2 + (z - 0.5 * L[2]) ** 2
+        rho = 1e-11 + 1e-4 * np.exp(-r2 / (2 * (6 * dx) ** 2))
+        _, e = W.saha_pe(rho, 8e3)
+        Uint = rho * e
+        vx = 3e6 * np.sin(2 * np.pi * x / L[0])
+        return [rho, rho * vx, 0 * x, 0 * x, Uint + 0.5 * rho * vx * vx, Uint]
+    U = W.pack_state(mesh, 6, fn)
+    dts = [orc.cfl(cfg, mesh, U).min()] * 6
+    g, _ = _run_gpu_sync(tdh, cfg, mesh, U, 6, table=saha, dts=dts)
+    o, _ = orc.run_sync(cfg, mesh, U, 6, table=saha, dts=dts)
+    err = rel_err(6, mesh, g, o)
+    print("mixed rel err", err)
+    assert np.all(err <= TOL)
