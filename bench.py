@@ -1,0 +1,164 @@
+#!/usr/bin/env python3
+"""Benchmark of the MeshBlock hydro update on one MI355X.
+
+Workload: a 128^3 periodic domain as 64 MeshBlocks of 32^3 cells with the
+Saha H/He table EOS and dual energy (cold Mach-1e7 Gaussian stream), FP64.
+One step = one pass of the whole hot path: the CFL reduction (per-block
+minimum, global minimum, level assignment) and one RK2 step of every block
+(two stage launches with PLM, table EOS inversion, HLLC, divergence, dual
+energy update), inputs resident in HBM.
+
+Prints one JSON line.  `value` is the cell-updates/s of the seeded form
+(table inversion of each face's second query seeded by the first, one launch
+per phase for all levels); the plain form (bisection for every query, one
+launch per level) is reported beside it.  The roofline entry is for the
+stage kernel (HIP events on the library's stream); the CPU baseline is the
+FP64 oracle on the host, on a bounded number of steps of the same workload,
+and its final state doubles as the accuracy check of the GPU run.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("tdh_kernels.hip", "tdh_internal.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2609_37859_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(workload):
+    """HBM bytes per stage launch from the committed counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(PROFILES, f"stage_traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def run_form(T, cfg, mesh, U, table, steps, warmup, inv_mode, batched):
+    import torch
+    ctx = T.Context(cfg, mesh, U, table=table, inv_mode=inv_mode)
+    ctx.autotune(reps=2)
+    for _ in range(warmup):
+        _, dt0, lev, L = ctx.reduce_dt()
+        ctx.run_window(dt0 * 2 ** L, batched=batched)
+    ctx.sync()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, dt0, lev, L = ctx.reduce_dt()
+        ctx.run_window(dt0 * 2 ** L, batched=batched)
+    ctx.sync()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    stage_ms, launches = ctx.stage_time()
+    st = ctx.stats()
+    tile = ctx.get_tile()
+    ctx.close()
+    return el, stage_ms, launches, st, tile
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps for the CPU baseline / accuracy check")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2609_37859_amd import tdh as T
+    from paper_2609_37859_amd import workloads as W
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    T.lib()
+
+    table = W.saha_table()
+    cfg, mesh, U = W.stream_c2(table)
+    ncell = mesh.ncells
+    nv = cfg.nv
+
+    # accuracy check and CPU baseline on the same bounded sample
+    acc = None
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        from tests.parity import rel_err
+        ctx = T.Context(cfg, mesh, U, table=table, inv_mode=2)
+        dts = T.run_sync_steps(ctx, args.cpu_steps)
+        g = ctx.get_state()
+        ctx.close()
+        t0 = time.perf_counter()
+        o, _ = oracle.run_sync(cfg, mesh, U, args.cpu_steps, table=table, dts=dts)
+        cpu_s = time.perf_counter() - t0
+        acc = float(np.max(rel_err(nv, mesh, g, o)))
+        cpu = {"value": ncell * args.cpu_steps / cpu_s, "unit": "cell-updates/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"{args.cpu_steps} RK2 steps of the full 128^3 workload (GPU step sizes), {cpu_s:.1f} s"}
+
+    el, stage_ms, launches, st, tile = run_form(T, cfg, mesh, U, table, args.steps, args.warmup, inv_mode=2,
+                                                batched=True)
+    el_p, stage_ms_p, launches_p, st_p, tile_p = run_form(T, cfg, mesh, U, table, args.steps, args.warmup,
+                                                          inv_mode=0, batched=False)
+    value = ncell * args.steps / el
+    plain = ncell * args.steps / el_p
+    # algorithmic HBM bytes of the stage kernel: stage 1 reads Q^n and writes Q^(1),
+    # stage 2 reads Q^n and Q^(1) and writes Q^(n+1): 5 nv doubles per cell and step
+    bytes_per_step = 5 * nv * 8 * ncell
+    achieved = bytes_per_step * args.steps / (stage_ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles("c2")
+    out = {
+        "metric": "FP64 cell-updates/s (LAT-batched+MLP-EOS vs plain) at <=1e-11 rel err; % HBM roof",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "c2: 128^3 periodic as 64 MeshBlocks of 32^3, Saha H/He table EOS 256x256, dual "
+                               "energy, cold Mach-1e7 Gaussian stream, CFL 0.3", "cells": ncell, "nv": nv,
+                   "form": "batched, table inversion seeded (second query of each face from the first)",
+                   "tile": T.tile_shapes()[tile]},
+        "plain": {"value": plain, "ms_per_step": 1e3 * el_p / args.steps,
+                  "form": "one launch per level, bisection for every table query",
+                  "tile": T.tile_shapes()[tile_p]},
+        "speedup_vs_plain": value / plain,
+        "max_rel_err_vs_oracle": acc,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": "stage_tiled", "avg_launch_ms": stage_ms / max(launches, 1),
+                     "algorithmic_bytes_per_cell_update": 5 * nv * 8},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

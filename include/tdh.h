@@ -74,14 +74,17 @@ typedef struct {
   double merge_frac; /* top LAT bins holding fewer than merge_frac * nblocks blocks merge down */
   double gm_bh, r_soft, r_exc; /* G M, softening length, excision radius (grav_kind 2) */
   double bh_x0[3], v_frame[3]; /* point-mass position at t = 0 and frame velocity */
-  int inv_mode;   /* table inversion: 0 bisection for every query;
-                     1 cell-centre query seeded by the learned network, face and compression
-                       queries seeded by the centre's cell; 2 as 1 but the centre bisected */
+  int inv_mode;   /* table inversion (every mode gives the same cell, hence the same result):
+                     0 bisection for every query;
+                     1 a face's left state seeded by the learned network (tdh_mlp_*), its
+                       right state and the cell's compression query seeded by that cell;
+                     2 as 1 with the left state bisected */
   int newton_max_iter; /* seeded secant steps before falling back to bisection (>= 0) */
 } tdh_config;
 
-/* Mesh: uniform spacing dx, cubic blocks of edge n (a multiple of the
- * smallest edge, which defines the lattice the blocks are aligned to). */
+/* Mesh: uniform spacing dx; cubic blocks whose edge n is a power of two in
+ * [8, 256], with origins on the lattice of the smallest edge, covering the
+ * domain exactly once. */
 typedef struct {
   int nx, ny, nz;   /* global cells per axis */
   int bc[3];        /* per axis: 0 periodic, 1 outflow (zero gradient) */
@@ -169,6 +172,25 @@ tdh_status tdh_eos_invert_batch(tdh_ctx *ctx, const double *dev_lrho, const doub
                                 int32_t *dev_j, int32_t *dev_iters, int64_t n, int mode);
 tdh_status tdh_eos_eval_batch(tdh_ctx *ctx, const double *dev_rho, const double *dev_U, double *dev_P,
                               double *dev_cs, int64_t n);
+
+/* Stage tile shapes: tdh_num_tiles() shapes, id -> (x, y, z) edges.  Every
+ * shape gives bit-identical results; a shape must divide the smallest block.
+ * tdh_autotune times one stage over all blocks reps times per fitting shape
+ * (state unchanged), keeps the fastest, returns its id and per-shape
+ * milliseconds (host_ms [tdh_num_tiles()], -1 where a shape does not fit;
+ * may be NULL).  Call between windows. */
+int tdh_num_tiles(void);
+tdh_status tdh_tile_shape(int id, int *host_dims3);
+tdh_status tdh_set_tile(tdh_ctx *ctx, int id);
+tdh_status tdh_get_tile(tdh_ctx *ctx, int *host_id);
+tdh_status tdh_autotune(tdh_ctx *ctx, int reps, int *host_best, float *host_ms);
+
+/* Stage-kernel timing: with on = 1 every stage launch outside graph replay
+ * is bracketed by HIP events recorded on the context's stream;
+ * tdh_get_stage_time returns the summed kernel milliseconds and the number
+ * of timed launches since tdh_set_timing (synchronising on the last event). */
+tdh_status tdh_set_timing(tdh_ctx *ctx, int on);
+tdh_status tdh_get_stage_time(tdh_ctx *ctx, double *host_ms, int64_t *host_launches);
 
 tdh_status tdh_get_stats(tdh_ctx *ctx, tdh_stats *out);
 const char *tdh_last_error(const tdh_ctx *ctx);

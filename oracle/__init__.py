@@ -103,6 +103,8 @@ class _Keep:
     """Holds the ctypes structs and the numpy buffers they point into."""
 
     def __init__(self, cfg, mesh, table):
+        if getattr(cfg, "eos_kind", 0) == 1 and table is None and not isinstance(cfg, _DummyCfg):
+            raise ValueError("the tabulated EOS needs a table")
         c = _Cfg()
         for f, _ in _Cfg._fields_:
             v = getattr(cfg, f)

@@ -75,7 +75,9 @@ struct StageArgs {
 };
 
 // host-side launchers (tdh_kernels.hip)
-hipError_t launch_stage(const StageArgs &a, int grid, hipStream_t s);
+int num_tiles();
+void tile_shape(int id, int *dims);  // x, y, z edge of tile shape id
+hipError_t launch_stage(const StageArgs &a, int tile, int grid, hipStream_t s);
 hipError_t launch_set_window(double *win, double t, double dt0, hipStream_t s);
 hipError_t launch_commit(const int *order, const int *cnt_ge, int lmin, int *par, hipStream_t s);
 hipError_t launch_reflux(const StageArgs &a, int lc, int dir, int nmax, int grid, hipStream_t s);  // a.k = completing index

@@ -325,170 +325,238 @@ __device__ __forceinline__ void load_q(const StageArgs &a, int b, const BlockInf
   if (nb_out) { *nb_out = nb; *idx_out = idx; }
 }
 
-// flux through the face between stencil cells 1 and 2 of w[0..3] (rotated primitives)
-__device__ __forceinline__ void face_flux(const Phys &p, const Table &t, int nv, const double (*w)[6], int jseed,
-                                          double *f, double &vf) {
-  double wl[6], wr[6];
-#pragma unroll
-  for (int v = 0; v < 6; ++v) {
-    if (v >= nv) break;
-    const double q0 = w[0][v], q1 = w[1][v], q2 = w[2][v], q3 = w[3][v];
-    wl[v] = q1 + 0.5 * vanleer(q1 - q0, q2 - q1);
-    wr[v] = q2 - 0.5 * vanleer(q2 - q1, q3 - q2);
-  }
-  double pl, cl, pr, cr;
-  eos_pc(p, t, wl[0], wl[4], jseed, pl, cl);
-  eos_pc(p, t, wr[0], wr[4], jseed, pr, cr);
-  hllc(wl, pl, cl, wr, pr, cr, f);
-  const double *wu = f[0] >= 0.0 ? wl : wr;
-  f[5] = p.dual ? f[0] * (wu[5] / wu[0]) : 0.0;
-  vf = f[0] / wu[0];
-}
+// ---------------------------------------------------------------------------
+// tiled stage kernel
+//
+// A workgroup advances one tile of TX x TY x TZ cells (256 cells, one per
+// thread).  For each axis it stages the tile extended by two cells along
+// that axis in LDS as primitives (C2P done once per staged cell), computes
+// every face flux of the tile once (PLM -> EOS -> HLLC), and each thread
+// accumulates the divergence, gravity sources and neighbour energies of its
+// own cell.  Tile shapes are template parameters so the runtime can pick
+// the fastest; every shape gives the same result bit for bit.
+// ---------------------------------------------------------------------------
+template <int TX, int TY, int TZ>
+struct TileGeom {
+  static constexpr int TV = TX * TY * TZ;
+  static constexpr int S0 = (TX + 4) * TY * TZ, S1 = TX * (TY + 4) * TZ, S2 = TX * TY * (TZ + 4);
+  static constexpr int SLAB = S0 > S1 ? (S0 > S2 ? S0 : S2) : (S1 > S2 ? S1 : S2);
+  static constexpr int F0 = (TX + 1) * TY * TZ, F1 = TX * (TY + 1) * TZ, F2 = TX * TY * (TZ + 1);
+  static constexpr int NF = F0 > F1 ? (F0 > F2 ? F0 : F2) : (F1 > F2 ? F1 : F2);
+};
 
-__global__ __launch_bounds__(kChunk) void stage_kernel(StageArgs a) {
-  const int a0 = a.cnt_ge[a.Lhi + 1], a1 = a.cnt_ge[a.Llo];
-  if (a1 <= a0) return;
-  const int i0 = a.item_start[a0], i1 = a.item_start[a1];
+struct TileCtx {
+  int b;
+  BlockInfo B;
+  int to[3];      // tile origin in the block
+  int fb;         // block factor
+  double dtb, t;  // block step, stage time
+  Src own;
+};
+
+template <int TX, int TY, int TZ, int NV, int D>
+__device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, double *sW, double *sF, int *sB,
+                                          int *sJ, const double *qc, const int *cc, const int *lc, double *rhs,
+                                          double &divv, double &emax, int &jcell) {
+  using G = TileGeom<TX, TY, TZ>;
+  constexpr int L0 = TX + (D == 0 ? 4 : 0), L1 = TY + (D == 1 ? 4 : 0), L2 = TZ + (D == 2 ? 4 : 0);
+  constexpr int NS = L0 * L1 * L2;
+  constexpr int STR = D == 0 ? 1 : (D == 1 ? L0 : L0 * L1);
+  constexpr int F0 = TX + (D == 0), F1 = TY + (D == 1), F2 = TZ + (D == 2);
+  constexpr int NFD = F0 * F1 * F2;
+  constexpr int FSTR = D == 0 ? 1 : (D == 1 ? F0 : F0 * F1);
+  constexpr int PN = 1 + D, P1 = 1 + (D + 1) % 3, P2 = 1 + (D + 2) % 3;
   const Phys &p = a.p;
   const MeshDev &m = a.m;
-  const int nv = m.nv;
-  for (int item = i0 + (int)blockIdx.x; item < i1; item += (int)gridDim.x) {
-    int lo = a0, hi = a1;  // item_start[lo] <= item < item_start[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (a.item_start[mid] <= item) lo = mid; else hi = mid;
+  const int tid = threadIdx.x;
+  const int n = T.B.n;
+  const int Nd = D == 0 ? m.nx : (D == 1 ? m.ny : m.nz);
+  // stage the slab: tile extended by two cells along D
+  for (int s = tid; s < NS; s += kChunk) {
+    int sc[3] = {s % L0, (s / L0) % L1, s / (L0 * L1)};
+    sc[D] -= 2;
+    const int g[3] = {T.B.ox + T.to[0] + sc[0], T.B.oy + T.to[1] + sc[1], T.B.oz + T.to[2] + sc[2]};
+    double q[6], w[6];
+    int nb_;
+    long long id_;
+    load_q(a, T.b, T.B, T.own, T.fb, g[0], g[1], g[2], q, &nb_, &id_);
+    c2p(p, q, w);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sW[v * G::SLAB + s] = w[v];
+    sW[6 * G::SLAB + s] = q[IEN];
+    sB[s] = (m.bc[D] == 0 || (g[D] >= 0 && g[D] < Nd)) ? nb_ : -1;
+  }
+  __syncthreads();
+  // every face of the tile along D, once
+  for (int f = tid; f < NFD; f += kChunk) {
+    const int fc[3] = {f % F0, (f / F0) % F1, f / (F0 * F1)};
+    const int s0 = fc[0] + L0 * (fc[1] + L1 * fc[2]);  // stencil start (tile cell fd - 2)
+    double wl[6], wr[6];
+    constexpr int perm[6] = {0, PN, P1, P2, 4, 5};
+#pragma unroll
+    for (int vv = 0; vv < NV; ++vv) {
+      const double *col = sW + perm[vv] * G::SLAB + s0;
+      const double q0 = col[0], q1 = col[STR], q2 = col[2 * STR], q3 = col[3 * STR];
+      wl[vv] = q1 + 0.5 * vanleer(q1 - q0, q2 - q1);
+      wr[vv] = q2 - 0.5 * vanleer(q2 - q1, q3 - q2);
     }
-    const int b = a.order[lo];
-    const BlockInfo B = m.blocks[b];
-    const int n = B.n;
-    const long long n3 = (long long)n * n * n;
-    const long long cell = (long long)(item - a.item_start[lo]) * kChunk + threadIdx.x;
-    if (cell >= n3) continue;
-    const int ci = (int)(cell % n), cj = (int)((cell / n) % n), ck = (int)(cell / ((long long)n * n));
-    const int g[3] = {B.ox + ci, B.oy + cj, B.oz + ck};
-    const int lc[3] = {ci, cj, ck};
-    const int fb = a.fac[b];
-    const double dt0 = a.win[1];
-    const double tk = a.win[0] + a.k * dt0;
-    const double dtb = fb * dt0;
-    const double t = a.phase == 1 ? tk : tk + dtb;
-    const Src own = source_of(a, fb, b);
-    double qc[6], wc[6];
-    for (int v = 0; v < nv; ++v) qc[v] = src_val(own, B.off + v * n3 + cell);
-    c2p(p, qc, wc);
-    const int jseed = (p.eos_kind == 1 && p.inv_mode != 0) ? centre_cell(p, a.t, a.s, wc[0], wc[4]) : -1;
-    const bool exc_on = p.grav_kind == 2 && p.r_exc > 0.0;
-    const bool exc_c = exc_on && excised(p, m, g[0], g[1], g[2], t);
-    double rhs[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    double divv = 0.0;
-    double emax = qc[IEN];
-    const int N[3] = {m.nx, m.ny, m.nz};
-    for (int d = 0; d < 3; ++d) {
-      const int pn = 1 + d, p1 = 1 + (d + 1) % 3, p2 = 1 + (d + 2) % 3;
-      double W[5][6];
-      int nbk[2] = {b, b};
-      long long nidx[2] = {0, 0};
-      bool inside[2] = {true, true};
-      for (int s = 0; s < 5; ++s) {
-        double q[6], w[6];
-        if (s == 2) {
-          for (int v = 0; v < nv; ++v) w[v] = wc[v];
-        } else {
-          int gg[3] = {g[0], g[1], g[2]};
-          gg[d] += s - 2;
-          int nb_;
-          long long id_;
-          load_q(a, b, B, own, fb, gg[0], gg[1], gg[2], q, &nb_, &id_);
-          c2p(p, q, w);
-          if (s == 1 || s == 3) {
-            const int side = s == 3;
-            if (q[IEN] > emax) emax = q[IEN];
-            nbk[side] = nb_;
-            nidx[side] = id_;
-            inside[side] = m.bc[d] == 0 || (gg[d] >= 0 && gg[d] < N[d]);
-          }
-        }
-        W[s][0] = w[0]; W[s][1] = w[pn]; W[s][2] = w[p1]; W[s][3] = w[p2]; W[s][4] = w[4];
-        if (nv > 5) W[s][5] = w[5];
-      }
-      double F[2][6], vf[2];
-      face_flux(p, a.t, nv, W, jseed, F[0], vf[0]);
-      face_flux(p, a.t, nv, W + 1, jseed, F[1], vf[1]);
-      // excision: a face between an active and an excised cell keeps its flux
-      // unless the mass flux leaves the sink
-      if (exc_on) {
-        for (int side = 0; side < 2; ++side) {
-          int gg[3] = {g[0], g[1], g[2]};
-          gg[d] += side ? 1 : -1;
-          const bool eo = excised(p, m, gg[0], gg[1], gg[2], t);
-          if (eo != exc_c) {
-            const bool right_exc = side ? eo : exc_c;  // is the cell on the + side excised
-            const bool into = right_exc ? (F[side][0] >= 0.0) : (F[side][0] <= 0.0);
-            if (!into) {
-              for (int v = 0; v < 6; ++v) F[side][v] = 0.0;
-              vf[side] = 0.0;
-            }
-          }
+    double pl, cl, pr, cr;
+    int jl = -1;
+    eos_pc(p, a.t, wl[0], wl[4], -1, pl, cl, &jl);
+    eos_pc(p, a.t, wr[0], wr[4], p.inv_mode == 0 ? -1 : jl, pr, cr);
+    double F[5];
+    hllc(wl, pl, cl, wr, pr, cr, F);
+    double FA = 0.0, vf;
+    {
+      const bool up_left = F[0] >= 0.0;
+      const double ru = up_left ? wl[0] : wr[0];
+      if (NV > 5) FA = F[0] * ((up_left ? wl[5] : wr[5]) / ru);
+      vf = F[0] / ru;
+    }
+    const int fr[3] = {T.to[0] + fc[0], T.to[1] + fc[1], T.to[2] + fc[2]};  // cell right of the face
+    if (p.grav_kind == 2 && p.r_exc > 0.0) {
+      int gl[3] = {T.B.ox + fr[0], T.B.oy + fr[1], T.B.oz + fr[2]};
+      const bool eR = excised(p, m, gl[0], gl[1], gl[2], T.t);
+      gl[D] -= 1;
+      const bool eL = excised(p, m, gl[0], gl[1], gl[2], T.t);
+      if (eL != eR) {
+        const bool into = eR ? (F[0] >= 0.0) : (F[0] <= 0.0);
+        if (!into) {
+#pragma unroll
+          for (int v = 0; v < 5; ++v) F[v] = 0.0;
+          FA = 0.0;
+          vf = 0.0;
         }
       }
-      // back to (rho, mx, my, mz, E, A)
-      double G[2][6];
-      for (int side = 0; side < 2; ++side) {
-        G[side][IDN] = F[side][0];
-        G[side][pn] = F[side][1];
-        G[side][p1] = F[side][2];
-        G[side][p2] = F[side][3];
-        G[side][IEN] = F[side][4];
-        G[side][IAX] = F[side][5];
-      }
-      const double idx = m.inv_dx[d];
-      for (int v = 0; v < nv; ++v) rhs[v] -= (G[1][v] - G[0][v]) * idx;
-      divv += (vf[1] - vf[0]) * idx;
-      if (p.grav_kind) {
-        int im[3] = {ci, cj, ck}, ip[3] = {ci, cj, ck};
-        im[d] -= 1;
-        ip[d] += 1;
-        const double pm = phi_at(a, B, im[0], im[1], im[2], t);
-        const double p0 = phi_at(a, B, ci, cj, ck, t);
-        const double pp = phi_at(a, B, ip[0], ip[1], ip[2], t);
-        rhs[pn] -= qc[IDN] * (pp - pm) / (2.0 * m.dx[d]);
-        rhs[IEN] -= (G[1][IDN] * (pp - p0) + G[0][IDN] * (p0 - pm)) / (2.0 * m.dx[d]);
-      }
-      // boundary faces: stage-1 flux, then the time-integrated impulse
-      for (int side = 0; side < 2; ++side) {
-        if (lc[d] != (side ? n - 1 : 0)) continue;
-        const int u0 = d == 0 ? cj : ci;
-        const int u1 = d == 2 ? cj : ck;
-        const long long base = B.ioff + (long long)(2 * d + side) * nv * n * n + (long long)u1 * n + u0;
-        if (a.phase == 1) {
-          for (int v = 0; v < nv; ++v) a.bf1[base + (long long)v * n * n] = G[side][v];
-        } else if (inside[side]) {
-          const double area = m.dx[(d + 1) % 3] * m.dx[(d + 2) % 3];
-          const int fn = a.fac[nbk[side]];
-          const int fw = fb > fn ? fb : fn;
+    }
+    double Gf[6];
+    Gf[IDN] = F[0];
+    Gf[PN] = F[1];
+    Gf[P1] = F[2];
+    Gf[P2] = F[3];
+    Gf[IEN] = F[4];
+    Gf[5] = FA;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sF[v * G::NF + f] = Gf[v];
+    sF[6 * G::NF + f] = vf;
+    sJ[f] = jl;
+    // block-boundary faces: stage-1 flux, then the time-integrated impulse
+    const int bd = fr[D];
+    if (bd == 0 || bd == n) {
+      const int side = bd == n;
+      const int u0 = D == 0 ? fr[1] : fr[0];
+      const int u1 = D == 2 ? fr[1] : fr[2];
+      const long long nn2 = (long long)n * n;
+      const long long base = T.B.ioff + (long long)(2 * D + side) * NV * nn2 + (long long)u1 * n + u0;
+      if (a.phase == 1) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) a.bf1[base + v * nn2] = Gf[v];
+      } else {
+        const int nbo = sB[s0 + (side ? 2 : 1) * STR];  // cell across the block face
+        if (nbo >= 0) {
+          const double area = m.dx[(D + 1) % 3] * m.dx[(D + 2) % 3];
+          const int fn = a.fac[nbo];
+          const int fw = T.fb > fn ? T.fb : fn;
           const bool overwrite = (a.k % fw) == 0;
-          for (int v = 0; v < nv; ++v) {
-            const long long ix = base + (long long)v * n * n;
-            const double Is = 0.5 * (a.bf1[ix] + G[side][v]) * area * dtb;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const long long ix = base + v * nn2;
+            const double Is = 0.5 * (a.bf1[ix] + Gf[v]) * area * T.dtb;
             a.imp[ix] = overwrite ? Is : a.imp[ix] + Is;
           }
         }
       }
     }
-    // combine
-    const double *Qbase = a.par[b] ? a.Qb : a.Qa;
-    double qn[6];
-    for (int v = 0; v < nv; ++v) {
-      const double qs = qc[v] + dtb * rhs[v];
-      qn[v] = a.phase == 1 ? qs : 0.5 * Qbase[B.off + v * n3 + cell] + 0.5 * qs;
+  }
+  __syncthreads();
+  // own cell: divergence, gravity, neighbour energies
+  {
+    const int flo = cc[0] + F0 * (cc[1] + F1 * cc[2]);
+    const int fhi = flo + FSTR;
+    const double idx = m.inv_dx[D];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) rhs[v] -= (sF[v * G::NF + fhi] - sF[v * G::NF + flo]) * idx;
+    divv += (sF[6 * G::NF + fhi] - sF[6 * G::NF + flo]) * idx;
+    if (D == 0) jcell = sJ[flo];
+    const int sbase = cc[0] + L0 * (cc[1] + L1 * cc[2]);
+    emax = fmax(emax, fmax(sW[6 * G::SLAB + sbase + STR], sW[6 * G::SLAB + sbase + 3 * STR]));
+    if (p.grav_kind) {
+      int im[3] = {lc[0], lc[1], lc[2]}, ip[3] = {lc[0], lc[1], lc[2]};
+      im[D] -= 1;
+      ip[D] += 1;
+      const double pm = phi_at(a, T.B, im[0], im[1], im[2], T.t);
+      const double p0 = phi_at(a, T.B, lc[0], lc[1], lc[2], T.t);
+      const double pp = phi_at(a, T.B, ip[0], ip[1], ip[2], T.t);
+      rhs[PN] -= qc[IDN] * (pp - pm) / (2.0 * m.dx[D]);
+      rhs[IEN] -= (sF[IDN * G::NF + fhi] * (pp - p0) + sF[IDN * G::NF + flo] * (p0 - pm)) / (2.0 * m.dx[D]);
     }
-    if (p.dual) {
-      const double tau = a.phase == 1 ? dtb : 0.5 * dtb;
+  }
+  __syncthreads();
+}
+
+template <int TX, int TY, int TZ, int NV>
+__global__ __launch_bounds__(kChunk) void stage_tiled(StageArgs a) {
+  using G = TileGeom<TX, TY, TZ>;
+  static_assert(G::TV == kChunk, "one cell per thread");
+  __shared__ double sW[7 * G::SLAB];   // primitives (rho, vx, vy, vz, U_EOS, A) + stage-input E
+  __shared__ double sF[7 * G::NF];     // fluxes (rho, mx, my, mz, E, A) + face velocity
+  __shared__ int sB[G::SLAB];          // owning block of a staged cell, -1 beyond an outflow edge
+  __shared__ int sJ[G::NF];            // table cell of each face's first EOS query
+  const int tid = threadIdx.x;
+  const Phys &p = a.p;
+  const MeshDev &m = a.m;
+  const int a0 = a.cnt_ge[a.Lhi + 1], a1 = a.cnt_ge[a.Llo];
+  if (a1 <= a0) return;
+  const int i0 = a.item_start[a0], i1 = a.item_start[a1];
+  const double dt0 = a.win[1];
+  const double tk = a.win[0] + a.k * dt0;
+  for (int item = i0 + (int)blockIdx.x; item < i1; item += (int)gridDim.x) {
+    int lo = a0, hi = a1;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (a.item_start[mid] <= item) lo = mid; else hi = mid;
+    }
+    TileCtx T;
+    T.b = a.order[lo];
+    T.B = m.blocks[T.b];
+    const int n = T.B.n;
+    const long long n3 = (long long)n * n * n;
+    const int tile = item - a.item_start[lo];
+    const int ntx = n / TX, nty = n / TY;
+    T.to[0] = (tile % ntx) * TX;
+    T.to[1] = ((tile / ntx) % nty) * TY;
+    T.to[2] = (tile / (ntx * nty)) * TZ;
+    T.fb = a.fac[T.b];
+    T.dtb = T.fb * dt0;
+    T.t = a.phase == 1 ? tk : tk + T.dtb;
+    T.own = source_of(a, T.fb, T.b);
+    const int cc[3] = {tid % TX, (tid / TX) % TY, tid / (TX * TY)};
+    const int lc[3] = {T.to[0] + cc[0], T.to[1] + cc[1], T.to[2] + cc[2]};
+    const long long cell = ((long long)lc[2] * n + lc[1]) * n + lc[0];
+    double qc[6];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) qc[v] = src_val(T.own, T.B.off + v * n3 + cell);
+    double rhs[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double divv = 0.0, emax = qc[IEN];
+    int jcell = -1;
+    tile_axis<TX, TY, TZ, NV, 0>(a, T, sW, sF, sB, sJ, qc, cc, lc, rhs, divv, emax, jcell);
+    tile_axis<TX, TY, TZ, NV, 1>(a, T, sW, sF, sB, sJ, qc, cc, lc, rhs, divv, emax, jcell);
+    tile_axis<TX, TY, TZ, NV, 2>(a, T, sW, sF, sB, sJ, qc, cc, lc, rhs, divv, emax, jcell);
+    // combine
+    const double *Qbase = a.par[T.b] ? a.Qb : a.Qa;
+    double qn[6];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double qs = qc[v] + T.dtb * rhs[v];
+      qn[v] = a.phase == 1 ? qs : 0.5 * Qbase[T.B.off + v * n3 + cell] + 0.5 * qs;
+    }
+    if (NV > 5) {
+      const double tau = a.phase == 1 ? T.dtb : 0.5 * T.dtb;
       if (p.eos_kind == 0) {
         qn[IAX] = qn[IAX] * exp(-(p.gamma - 1.0) * divv * tau);
       } else {
         double Pa, ca;
-        eos_pc(p, a.t, qc[IDN], qn[IAX], jseed, Pa, ca);
+        eos_pc(p, a.t, qc[IDN], qn[IAX], p.inv_mode == 0 ? -1 : jcell, Pa, ca);
         qn[IAX] = qn[IAX] - Pa * divv * tau;
       }
       const double uf = u_floor(p, qn[IDN] > p.rho_floor ? qn[IDN] : p.rho_floor);
@@ -501,25 +569,31 @@ __global__ __launch_bounds__(kChunk) void stage_kernel(StageArgs a) {
       const double uf = u_floor(p, qn[IDN]);
       if (w[4] < uf) {
         qn[IEN] += uf - w[4];
-        if (p.dual && qn[IAX] < uf) qn[IAX] = uf;
+        if (NV > 5 && qn[IAX] < uf) qn[IAX] = uf;
       }
     }
-    if (p.dual) {
+    if (NV > 5) {
       const double K = 0.5 * (qn[IM1] * qn[IM1] + qn[IM2] * qn[IM2] + qn[IM3] * qn[IM3]) / qn[IDN];
       const double Uc = qn[IEN] - K;
       if (Uc > 0.0 && Uc > p.eta2 * emax) qn[IAX] = Uc;
     }
-    if (a.phase == 2 && exc_on && excised(p, m, g[0], g[1], g[2], tk + dtb)) {
-      const double uf = u_floor(p, p.rho_floor);
-      qn[IDN] = p.rho_floor;
-      qn[IM1] = qn[IM2] = qn[IM3] = 0.0;
-      qn[IEN] = uf;
-      if (p.dual) qn[IAX] = uf;
+    if (a.phase == 2 && p.grav_kind == 2 && p.r_exc > 0.0) {
+      if (excised(p, m, T.B.ox + lc[0], T.B.oy + lc[1], T.B.oz + lc[2], tk + T.dtb)) {
+        const double uf = u_floor(p, p.rho_floor);
+        qn[IDN] = p.rho_floor;
+        qn[IM1] = qn[IM2] = qn[IM3] = 0.0;
+        qn[IEN] = uf;
+        if (NV > 5) qn[IAX] = uf;
+      }
     }
-    double *out = a.phase == 1 ? a.Qs : (a.par[b] ? a.Qa : a.Qb);
-    for (int v = 0; v < nv; ++v) out[B.off + v * n3 + cell] = qn[v];
+    double *out = a.phase == 1 ? a.Qs : (a.par[T.b] ? a.Qa : a.Qb);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[T.B.off + v * n3 + cell] = qn[v];
   }
 }
+
+// tile shapes offered to the runtime (x fastest); all divide blocks of edge >= 8
+#define TDH_TILES(X) X(8, 8, 4) X(16, 4, 4) X(4, 8, 8) X(8, 4, 8)
 
 __global__ void set_window_kernel(double *win, double t, double dt0) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -694,9 +768,39 @@ __global__ void eos_eval_kernel(Phys p, Table t, const double *rho, const double
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_stage(const StageArgs &a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(stage_kernel, dim3(grid), dim3(kChunk), 0, s, a);
-  return hipGetLastError();
+int num_tiles() {
+  int n = 0;
+#define TDH_COUNT(x, y, z) ++n;
+  TDH_TILES(TDH_COUNT)
+#undef TDH_COUNT
+  return n;
+}
+
+void tile_shape(int id, int *dims) {
+  int i = 0;
+#define TDH_SHAPE(x, y, z)                 \
+  if (i++ == id) {                         \
+    dims[0] = x; dims[1] = y; dims[2] = z; \
+    return;                                \
+  }
+  TDH_TILES(TDH_SHAPE)
+#undef TDH_SHAPE
+  dims[0] = dims[1] = dims[2] = 0;
+}
+
+hipError_t launch_stage(const StageArgs &a, int tile, int grid, hipStream_t s) {
+  int i = 0;
+#define TDH_LAUNCH(x, y, z)                                                             \
+  if (i++ == tile) {                                                                    \
+    if (a.m.nv == 6)                                                                    \
+      hipLaunchKernelGGL((stage_tiled<x, y, z, 6>), dim3(grid), dim3(kChunk), 0, s, a); \
+    else                                                                                \
+      hipLaunchKernelGGL((stage_tiled<x, y, z, 5>), dim3(grid), dim3(kChunk), 0, s, a); \
+    return hipGetLastError();                                                           \
+  }
+  TDH_TILES(TDH_LAUNCH)
+#undef TDH_LAUNCH
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_set_window(double *win, double t, double dt0, hipStream_t s) {

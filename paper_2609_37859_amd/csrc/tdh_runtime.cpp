@@ -58,7 +58,16 @@ struct tdh_ctx {
   double dt_coarse = 0.0, dt0 = 0.0;
   double t = 0.0;            // time of the last synchronised state
   int grid = 2048;           // persistent grid of the stage kernel
+  int tile = 0;              // stage tile shape (launch_stage id)
   tdh_stats stats{};
+
+  // stage-kernel timing (HIP events around each stage launch, non-graph path)
+  bool timing = false;
+  bool capturing = false;
+  std::vector<hipEvent_t> ev;       // pairs
+  size_t ev_used = 0;
+  double stage_ms = 0.0;
+  long long stage_launches = 0;
 
   // captured windows: key = (Lmax, batched)
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
@@ -180,6 +189,7 @@ extern "C" tdh_status tdh_init(const tdh_config *cfg, void *hip_stream, tdh_ctx 
 
 extern "C" void tdh_destroy(tdh_ctx *c) {
   if (!c) return;
+  for (hipEvent_t e : c->ev) hipEventDestroy(e);
   for (auto &g : c->graphs) hipGraphExecDestroy(g.second);
   for (void *p : c->owned) hipFree(p);
   delete c;
@@ -287,6 +297,8 @@ static void build_adjacency(tdh_ctx *c) {
         }
   }
 }
+
+static bool tile_fits(const tdh_ctx *c, int id);
 
 // device copies of the level-dependent tables; starts a new window
 static tdh_status install_levels(tdh_ctx *c, const std::vector<int> &lev) {
@@ -398,6 +410,9 @@ extern "C" tdh_status tdh_init_blocks(tdh_ctx *c, const tdh_mesh *m, void *dev_a
   if (c->phi) HIPCHK(c, hipMemcpyAsync(c->phi, host_phi, L.ptotal * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   build_adjacency(c);
+  if (c->lat < 8) return fail(c, TDH_EINVAL, "blocks must have an edge of at least 8 cells");
+  c->tile = 0;
+  while (c->tile < num_tiles() && !tile_fits(c, c->tile)) c->tile++;
   c->have_mesh = true;
   return install_levels(c, std::vector<int>(c->nb, 0));
 }
@@ -533,8 +548,37 @@ static int ctz(int v) { return __builtin_ctz((unsigned)v); }
 
 static int lmin_of(int k, int Lmax) { return k == 0 ? 0 : Lmax - ctz(k); }
 
+static tdh_status collect_timing(tdh_ctx *c) {
+  if (c->ev_used == 0) return TDH_OK;
+  HIPCHK(c, hipEventSynchronize(c->ev[2 * c->ev_used - 1]));
+  for (size_t i = 0; i < c->ev_used; ++i) {
+    float ms = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
+    c->stage_ms += ms;
+    c->stage_launches++;
+  }
+  c->ev_used = 0;
+  return TDH_OK;
+}
+
+static tdh_status timed_stage(tdh_ctx *c, const StageArgs &a) {
+  const bool t = c->timing && !c->capturing;
+  tdh_status s;
+  if (t && 2 * (c->ev_used + 1) > c->ev.size())
+    if ((s = collect_timing(c))) return s;
+  if (t) HIPCHK(c, hipEventRecord(c->ev[2 * c->ev_used], c->stream));
+  HIPCHK(c, launch_stage(a, c->tile, c->grid, c->stream));
+  if (t) {
+    HIPCHK(c, hipEventRecord(c->ev[2 * c->ev_used + 1], c->stream));
+    c->ev_used++;
+  }
+  c->stats.kernel_launches++;
+  return TDH_OK;
+}
+
 // enqueue sub-cycle k of the current window
 static tdh_status enqueue_subcycle(tdh_ctx *c, int k, bool batched) {
+  tdh_status s;
   const int lmin = lmin_of(k, c->Lmax);
   StageArgs a = base_args(c);
   a.k = k;
@@ -543,14 +587,12 @@ static tdh_status enqueue_subcycle(tdh_ctx *c, int k, bool batched) {
     if (batched) {
       a.Llo = lmin;
       a.Lhi = kCntSlots - 2;
-      HIPCHK(c, launch_stage(a, c->grid, c->stream));
-      c->stats.kernel_launches++;
+      if ((s = timed_stage(c, a))) return s;
     } else {
       for (int L = lmin; L <= c->Lmax; ++L) {
         a.Llo = L;
         a.Lhi = L;
-        HIPCHK(c, launch_stage(a, c->grid, c->stream));
-        c->stats.kernel_launches++;
+        if ((s = timed_stage(c, a))) return s;
       }
     }
   }
@@ -631,13 +673,16 @@ extern "C" tdh_status tdh_run_window(tdh_ctx *c, double dt_coarse, int batched, 
     }
     hipGraph_t g;
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    c->capturing = true;
     for (int k = 0; k < nsub; ++k) {
       if ((s = enqueue_subcycle(c, k, batched != 0))) {
         hipGraph_t dummy;
         hipStreamEndCapture(c->stream, &dummy);
+        c->capturing = false;
         return s;
       }
     }
+    c->capturing = false;
     HIPCHK(c, hipStreamEndCapture(c->stream, &g));
     hipGraphExec_t ge;
     HIPCHK(c, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
@@ -722,5 +767,110 @@ extern "C" tdh_status tdh_get_stats(tdh_ctx *c, tdh_stats *out) {
   CHECK_CTX(c);
   if (!out) return fail(c, TDH_EINVAL, "null output");
   *out = c->stats;
+  return TDH_OK;
+}
+
+static bool tile_fits(const tdh_ctx *c, int id) {
+  int d[3];
+  tile_shape(id, d);
+  return d[0] > 0 && c->lat % d[0] == 0 && c->lat % d[1] == 0 && c->lat % d[2] == 0;
+}
+
+extern "C" int tdh_num_tiles(void) { return num_tiles(); }
+
+extern "C" tdh_status tdh_tile_shape(int id, int *dims) {
+  if (!dims || id < 0 || id >= num_tiles()) return fail(nullptr, TDH_EINVAL, "tile id out of range");
+  tile_shape(id, dims);
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_set_tile(tdh_ctx *c, int id) {
+  CHECK_CTX(c);
+  tdh_status s;
+  if ((s = ready(c)) || (s = require_window_boundary(c))) return s;
+  if (id < 0 || id >= num_tiles()) return fail(c, TDH_EINVAL, "tile id out of range");
+  if (!tile_fits(c, id)) return fail(c, TDH_EINVAL, "tile %d does not divide the smallest block", id);
+  if (id != c->tile) {
+    for (auto &g : c->graphs) hipGraphExecDestroy(g.second);
+    c->graphs.clear();
+  }
+  c->tile = id;
+  return TDH_OK;
+}
+
+// Time one stage-1 launch over every block for each tile shape that fits and
+// keep the fastest.  Stage 1 only writes the stage buffers, which the next
+// sub-cycle overwrites, so the state is unchanged.
+extern "C" tdh_status tdh_autotune(tdh_ctx *c, int reps, int *host_best, float *host_ms) {
+  CHECK_CTX(c);
+  tdh_status s;
+  if ((s = ready(c)) || (s = require_window_boundary(c))) return s;
+  if (reps < 1 || reps > 100) return fail(c, TDH_EINVAL, "reps must be in [1, 100]");
+  const std::vector<int> saved = c->levels;
+  if ((s = install_levels(c, std::vector<int>(c->nb, 0)))) return s;
+  HIPCHK(c, launch_set_window(c->d_win, c->t, c->dt_coarse > 0.0 ? c->dt_coarse : 1e-30, c->stream));
+  StageArgs a = base_args(c);
+  a.k = 0;
+  a.phase = 1;
+  a.Llo = 0;
+  a.Lhi = kCntSlots - 2;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  int best = -1;
+  float best_ms = 0.0f;
+  for (int id = 0; id < num_tiles(); ++id) {
+    float ms = -1.0f;
+    if (tile_fits(c, id)) {
+      HIPCHK(c, launch_stage(a, id, c->grid, c->stream));  // warm-up
+      HIPCHK(c, hipEventRecord(e0, c->stream));
+      for (int r = 0; r < reps; ++r) HIPCHK(c, launch_stage(a, id, c->grid, c->stream));
+      HIPCHK(c, hipEventRecord(e1, c->stream));
+      HIPCHK(c, hipEventSynchronize(e1));
+      HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+      ms /= reps;
+      if (best < 0 || ms < best_ms) { best = id; best_ms = ms; }
+    }
+    if (host_ms) host_ms[id] = ms;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if ((s = install_levels(c, saved))) return s;
+  if (best >= 0 && best != c->tile) {
+    for (auto &g : c->graphs) hipGraphExecDestroy(g.second);
+    c->graphs.clear();
+    c->tile = best;
+  }
+  if (host_best) *host_best = c->tile;
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_get_tile(tdh_ctx *c, int *id) {
+  CHECK_CTX(c);
+  if (!id) return fail(c, TDH_EINVAL, "null output");
+  *id = c->tile;
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_set_timing(tdh_ctx *c, int on) {
+  CHECK_CTX(c);
+  tdh_status s;
+  if ((s = collect_timing(c))) return s;
+  if (on && c->ev.empty()) {
+    c->ev.resize(512);
+    for (hipEvent_t &e : c->ev) HIPCHK(c, hipEventCreate(&e));
+  }
+  c->timing = on != 0;
+  c->stage_ms = 0.0;
+  c->stage_launches = 0;
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_get_stage_time(tdh_ctx *c, double *host_ms, int64_t *host_launches) {
+  CHECK_CTX(c);
+  tdh_status s;
+  if ((s = collect_timing(c))) return s;
+  if (host_ms) *host_ms = c->stage_ms;
+  if (host_launches) *host_launches = c->stage_launches;
   return TDH_OK;
 }

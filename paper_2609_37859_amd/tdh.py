@@ -79,6 +79,13 @@ def lib():
         "tdh_get_stats": ([ctx, P(tdh_stats)], st),
         "tdh_last_error": ([ctx], C.c_char_p),
         "tdh_destroy": ([ctx], None),
+        "tdh_num_tiles": ([], i),
+        "tdh_tile_shape": ([i, P(i)], st),
+        "tdh_set_tile": ([ctx, i], st),
+        "tdh_get_tile": ([ctx, P(i)], st),
+        "tdh_autotune": ([ctx, i, P(i), P(C.c_float)], st),
+        "tdh_set_timing": ([ctx, i], st),
+        "tdh_get_stage_time": ([ctx, P(d), P(C.c_int64)], st),
         "tdh_mlp_init": ([ctx, P(C.c_float), d, d, d, d, d, d], st),
         "tdh_mlp_train": ([ctx, vp, vp, C.c_int64, i, i, C.c_float, C.c_uint64, P(C.c_float)], st),
         "tdh_mlp_get_params": ([ctx, P(C.c_float)], st),
@@ -231,6 +238,30 @@ class Context:
                                               rho.numel()), "tdh_eos_eval_batch")
         return P, cs
 
+    def set_tile(self, tile_id):
+        self._check(self.L.tdh_set_tile(self.ctx, int(tile_id)), "tdh_set_tile")
+
+    def get_tile(self):
+        t = C.c_int()
+        self._check(self.L.tdh_get_tile(self.ctx, C.byref(t)), "tdh_get_tile")
+        return t.value
+
+    def autotune(self, reps=3):
+        nt = self.L.tdh_num_tiles()
+        ms = (C.c_float * nt)()
+        best = C.c_int()
+        self._check(self.L.tdh_autotune(self.ctx, int(reps), C.byref(best), ms), "tdh_autotune")
+        return best.value, [float(x) for x in ms]
+
+    def set_timing(self, on=True):
+        self._check(self.L.tdh_set_timing(self.ctx, int(on)), "tdh_set_timing")
+
+    def stage_time(self):
+        ms = C.c_double()
+        n = C.c_int64()
+        self._check(self.L.tdh_get_stage_time(self.ctx, C.byref(ms), C.byref(n)), "tdh_get_stage_time")
+        return ms.value, n.value
+
     def stats(self):
         s = tdh_stats()
         self._check(self.L.tdh_get_stats(self.ctx, C.byref(s)), "tdh_get_stats")
@@ -262,3 +293,13 @@ def run_sync_steps(ctx: Context, nsteps, dts=None):
         ctx.step_level(0, dt)
         used.append(dt)
     return np.array(used)
+
+
+def tile_shapes():
+    L = lib()
+    out = []
+    for t in range(L.tdh_num_tiles()):
+        d = (C.c_int * 3)()
+        L.tdh_tile_shape(t, d)
+        out.append(tuple(d))
+    return out

@@ -200,9 +200,42 @@ def test_mixed_block_sizes_point_mass_excision(tdh, orc, saha):
         vx = 3e6 * np.sin(2 * np.pi * x / L[0])
         return [rho, rho * vx, 0 * x, 0 * x, Uint + 0.5 * rho * vx * vx, Uint]
     U = W.pack_state(mesh, 6, fn)
-    dts = [orc.cfl(cfg, mesh, U).min()] * 6
+    dts = [orc.cfl(cfg, mesh, U, table=saha).min()] * 6
     g, _ = _run_gpu_sync(tdh, cfg, mesh, U, 6, table=saha, dts=dts)
     o, _ = orc.run_sync(cfg, mesh, U, 6, table=saha, dts=dts)
     err = rel_err(6, mesh, g, o)
     print("mixed rel err", err)
     assert np.all(err <= TOL)
+
+
+def test_all_tiles_bitwise_equal(tdh, orc, saha):
+    """Every stage tile shape gives the same state bit for bit (C2 stream on
+    a 2^3-block mesh, 4 steps), and the autotuner picks one of them."""
+    cfg, mesh, U = W.stream_c2(saha, nb=2)
+    shapes = tdh.tile_shapes()
+    outs = []
+    for t in range(len(shapes)):
+        ctx = tdh.Context(cfg, mesh, U, table=saha, inv_mode=2)
+        ctx.set_tile(t)
+        tdh.run_sync_steps(ctx, 4, dts=[3e-4] * 4)
+        outs.append(ctx.get_state())
+        ctx.close()
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
+    ctx = tdh.Context(cfg, mesh, U, table=saha)
+    best, ms = ctx.autotune(reps=1)
+    assert 0 <= best < len(shapes) and ms[best] > 0
+    ctx.close()
+
+
+def test_bench_workload_parity_sampled(tdh, orc, saha):
+    """The benchmark's workload (C2, 128^3, seeded form, tile from the
+    autotuner) after 3 GPU steps equals 3 oracle steps."""
+    cfg, mesh, U = W.stream_c2(saha)
+    ctx = tdh.Context(cfg, mesh, U, table=saha, inv_mode=2)
+    ctx.autotune(reps=1)
+    dts = tdh.run_sync_steps(ctx, 3)
+    g = ctx.get_state()
+    ctx.close()
+    o, _ = orc.run_sync(cfg, mesh, U, 3, table=saha, dts=dts)
+    assert np.all(rel_err(6, mesh, g, o) <= TOL)
