@@ -127,8 +127,9 @@ tdh_status tdh_init_blocks(tdh_ctx *ctx, const tdh_mesh *mesh, void *dev_arena, 
 tdh_status tdh_set_eos_table(tdh_ctx *ctx, int nrho, int nT, double lr0, double dlr, double lT0, double dlT,
                              const double *host_logP, const double *host_loge, const double *host_logcs2);
 
-/* Per-block CFL step dt_b = cfl * min over cells, axes of dx/(|v|+c_s)
- * (excised cells skipped), its minimum dt0 (eq lat-base-dt) and the LAT
+/* Per-block CFL step dt_b = cfl * min over cells of min over axes of
+ * dx/(|v|+c_s) and, with gravity, sqrt(dx_min/|g|) (g the centred potential
+ * gradient; excised cells skipped), its minimum dt0 (eq lat-base-dt) and the LAT
  * levels of eq lat-factor after bin merging and the one-level neighbour
  * limit; level = Lmax - log2(f_b), level 0 coarsest.  The levels are
  * installed and start a new window.  host_dt_block [nblocks] and
@@ -191,6 +192,32 @@ tdh_status tdh_autotune(tdh_ctx *ctx, int reps, int *host_best, float *host_ms);
  * of timed launches since tdh_set_timing (synchronising on the last event). */
 tdh_status tdh_set_timing(tdh_ctx *ctx, int on);
 tdh_status tdh_get_stage_time(tdh_ctx *ctx, double *host_ms, int64_t *host_launches);
+
+/* Learned seed of the table inversion (not part of the paper's method; the
+ * plain bisection stays the fallback and decides the result): a
+ * 2 -> 64 -> 64 -> 1 ReLU network mapping normalised (log10 rho, log10 e)
+ * to normalised log10 T, bf16 operands and fp32 accumulation, hidden layer
+ * on the matrix cores.  Inputs are normalised as 2 (v - lo)/(hi - lo) - 1.
+ *   init:      fp32 parameters [4417] = W1[64][2], b1[64], W2[64 out][64 in],
+ *              b2[64], W3[64], b3; resets the Adam moments; the seed is off.
+ *   train:     steps of Adam (beta 0.9/0.999, eps 1e-8, cosine-decayed lr) on
+ *              the mean squared error, each on `batch` samples (multiple of
+ *              64, <= 65536) drawn with replacement from dev_in [n][2]
+ *              (log10 rho, log10 e) / dev_lT [n] by a counter hash of seed
+ *              and step; host_loss [steps] (nullable) receives each step's loss.
+ *   loss_grad: loss and gradient [4417] over the first n samples (n a
+ *              multiple of 64, <= 65536), no update.
+ *   forward:   log10 T predictions for n queries.
+ *   enable_seed: use the network for inv_mode 1 (tdh_config) and eos mode 1. */
+tdh_status tdh_mlp_init(tdh_ctx *ctx, const float *host_params, double lr_lo, double lr_hi, double le_lo,
+                        double le_hi, double lt_lo, double lt_hi);
+tdh_status tdh_mlp_train(tdh_ctx *ctx, const double *dev_in, const double *dev_lT, int64_t n, int steps, int batch,
+                         float lr, uint64_t seed, float *host_loss);
+tdh_status tdh_mlp_loss_grad(tdh_ctx *ctx, const double *dev_in, const double *dev_lT, int64_t n, float *host_loss,
+                             float *host_grad);
+tdh_status tdh_mlp_forward(tdh_ctx *ctx, const double *dev_in, double *dev_lT, int64_t n);
+tdh_status tdh_mlp_get_params(tdh_ctx *ctx, float *host_params);
+tdh_status tdh_mlp_enable_seed(tdh_ctx *ctx, int on);
 
 tdh_status tdh_get_stats(tdh_ctx *ctx, tdh_stats *out);
 const char *tdh_last_error(const tdh_ctx *ctx);

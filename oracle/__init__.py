@@ -67,7 +67,7 @@ def lib():
         d, i = C.c_double, C.c_int
         _lib.orc_run_sync.argtypes = [P(_Cfg), P(_Mesh), P(_Table), P(d), P(d), i, P(d), P(d), d]
         _lib.orc_run_sync.restype = i
-        _lib.orc_cfl.argtypes = [P(_Cfg), P(_Mesh), P(_Table), P(d), d, P(d)]
+        _lib.orc_cfl.argtypes = [P(_Cfg), P(_Mesh), P(_Table), P(d), P(d), d, P(d)]
         _lib.orc_cfl.restype = i
         _lib.orc_lat_assign.argtypes = [P(_Cfg), P(_Mesh), P(d), P(i), P(d)]
         _lib.orc_lat_assign.restype = i
@@ -153,11 +153,15 @@ def run_sync(cfg, mesh, U, nsteps, table=None, phi=None, dts=None, t0=0.0):
     return U, dt_out
 
 
-def cfl(cfg, mesh, U, table=None, t=0.0):
+def cfl(cfg, mesh, U, table=None, t=0.0, phi=None):
     k = _Keep(cfg, mesh, table)
     U = np.ascontiguousarray(U, dtype=np.float64)
+    if cfg.grav_kind == 1 and phi is None:
+        raise ValueError("a stored potential is needed for grav_kind 1")
+    phi_a = None if phi is None else np.ascontiguousarray(phi, dtype=np.float64)
     out = np.zeros(mesh.nblocks)
-    if lib().orc_cfl(C.byref(k.cfg), C.byref(k.mesh), k.tptr(), _dp(U), float(t), _dp(out)) != 0:
+    if lib().orc_cfl(C.byref(k.cfg), C.byref(k.mesh), k.tptr(), _dp(U), None if phi_a is None else _dp(phi_a),
+                     float(t), _dp(out)) != 0:
         raise ValueError("oracle cfl rejected its input")
     return out
 

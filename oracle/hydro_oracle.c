@@ -541,7 +541,8 @@ static void excise_reset(const mesh_t *M, int b, double *q, double t) {
 /* ------------------------------------------------------------------ */
 /* CFL time step per block (eq lat-base-dt uses its minimum)           */
 /* ------------------------------------------------------------------ */
-int orc_cfl(const orc_cfg *cfg, const orc_mesh *m, const orc_table *tab, const double *U, double t, double *dt_block) {
+int orc_cfl(const orc_cfg *cfg, const orc_mesh *m, const orc_table *tab, const double *U, const double *phi, double t,
+            double *dt_block) {
   mesh_t M;
   if (mesh_build(&M, cfg, m, tab)) return -1;
   int nb = m->nblocks;
@@ -564,6 +565,23 @@ int orc_cfl(const orc_cfg *cfg, const orc_mesh *m, const orc_table *tab, const d
           for (int d = 0; d < 3; d++) {
             double s = m->dx[d] / (fabs(w[1 + d]) + cs);
             if (s < best) best = s;
+          }
+          /* source-term limit: the gravitational acceleration may move the gas
+           * at most one cell width within the step, sqrt(dx_min / |g|) */
+          if (cfg->grav_kind) {
+            double g2 = 0.0;
+            for (int d = 0; d < 3; d++) {
+              int ip[3] = {i, j, k}, im[3] = {i, j, k};
+              ip[d] += 1; im[d] -= 1;
+              double gd = (phi_at(&M, phi, b, ip[0], ip[1], ip[2], t) - phi_at(&M, phi, b, im[0], im[1], im[2], t)) /
+                          (2.0 * m->dx[d]);
+              g2 += gd * gd;
+            }
+            double dmin = fmin(m->dx[0], fmin(m->dx[1], m->dx[2]));
+            if (g2 > 0.0) {
+              double s = sqrt(dmin / sqrt(g2));
+              if (s < best) best = s;
+            }
           }
         }
     dt_block[b] = cfg->cfl * best;
@@ -889,7 +907,7 @@ int orc_run_sync(const orc_cfg *cfg, const orc_mesh *m, const orc_table *tab, do
     double dt;
     if (dt_in) dt = dt_in[s];
     else {
-      if (orc_cfl(cfg, m, tab, U, t, dtb)) { free(lev); free(dtb); return -1; }
+      if (orc_cfl(cfg, m, tab, U, phi, t, dtb)) { free(lev); free(dtb); return -1; }
       dt = INFINITY;
       for (int b = 0; b < nb; b++) if (dtb[b] < dt) dt = dtb[b];
     }

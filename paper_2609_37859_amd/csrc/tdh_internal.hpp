@@ -43,16 +43,22 @@ struct Table {
   const double *lP, *le, *lc2;
 };
 
-// Learned seed network (2 -> 64 -> 64 -> 1), bf16 weights packed for the kernels.
+constexpr int kMlpParams = 4417;  // W1[64][2], b1[64], W2[64][64], b2[64], W3[64], b3
+
+// Learned seed network weights as the kernels read them (bf16 operands).
+struct MlpDev {
+  const float *b1, *b2, *b3;
+  const short *w1b;   // [64][2]
+  const short *w2b;   // [64 out][64 in]
+  const short *w2tb;  // [64 in][64 out]
+  const short *w3b;   // [64]
+};
+
+// Seed network and the normalisation ranges of its inputs and output.
 struct Seed {
   int enabled;
-  const uint16_t *w1;   // [64][2]
-  const float *b1;      // [64]
-  const uint16_t *w2;   // [64 out][64 in]
-  const float *b2;      // [64]
-  const uint16_t *w3;   // [64]
-  const float *b3;      // [1]
-  double le_lo, le_hi, lr_lo, lr_hi, lt_lo, lt_hi;   // input / output normalisation ranges
+  MlpDev w;
+  double lr_lo, lr_hi, le_lo, le_hi, lt_lo, lt_hi;
 };
 
 struct StageArgs {
@@ -87,5 +93,15 @@ hipError_t launch_eos_invert(const Table &t, const Seed &s, int newton_max_iter,
                              double *lT, int32_t *j, int32_t *iters, int64_t n, int mode, hipStream_t st);
 hipError_t launch_eos_eval(const Phys &p, const Table &t, const double *rho, const double *U, double *P,
                            double *cs, int64_t n, hipStream_t st);
+
+hipError_t mlp_launch_forward(const MlpDev &w, const Seed &s, const double *in, double *out, int64_t n,
+                              hipStream_t st);
+hipError_t mlp_launch_fwd_bwd(const MlpDev &w, const Seed &s, const double *in, const double *tgt, int64_t n,
+                              int batch, uint64_t seed, int step, int random_batch, float *part, float *loss_part,
+                              float *grad, float *loss, hipStream_t st);
+hipError_t mlp_launch_adam(float *wm, float *m, float *v, const float *g, float lr, float b1, float b2, float eps,
+                           float c1, float c2, hipStream_t st);
+hipError_t mlp_launch_pack(const float *wm, short *w1b, short *w2b, short *w2tb, short *w3b, float *b1, float *b2,
+                           float *b3, hipStream_t st);
 
 }  // namespace tdh

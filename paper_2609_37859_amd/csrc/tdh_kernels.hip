@@ -23,7 +23,7 @@
 // HLLC follows Toro (Riemann Solvers and Numerical Methods for Fluid
 // Dynamics, 3rd ed., Sec. 10.4) with Davis wave speeds; the limiter is van
 // Leer's harmonic mean; RK2 is Heun's method.
-#include "tdh_internal.hpp"
+#include "tdh_mlp_dev.hpp"
 
 namespace tdh {
 
@@ -139,34 +139,10 @@ __device__ __forceinline__ double tbil(const double *F, int nT, int i, double w,
   return (1.0 - wT) * tcol(F, nT, i, w, j) + wT * tcol(F, nT, i, w, j + 1);
 }
 
-__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even (finite inputs)
-  return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
-
-// Learned seed: log T from (log rho, log e) by the 2-64-64-1 network, bf16
-// operands, fp32 accumulation; returns a table cell index.
-__device__ __forceinline__ int seed_cell(const Seed &s, const Table &t, double lr, double le) {
-  const float x0 = (float)(2.0 * (lr - s.lr_lo) / (s.lr_hi - s.lr_lo) - 1.0);
-  const float x1 = (float)(2.0 * (le - s.le_lo) / (s.le_hi - s.le_lo) - 1.0);
-  const float xb0 = bf16_to_f32(f32_to_bf16(x0)), xb1 = bf16_to_f32(f32_to_bf16(x1));
-  float h1[64];
-#pragma unroll
-  for (int o = 0; o < 64; ++o) {
-    float z = s.b1[o];
-    z += bf16_to_f32(s.w1[2 * o]) * xb0;
-    z += bf16_to_f32(s.w1[2 * o + 1]) * xb1;
-    h1[o] = bf16_to_f32(f32_to_bf16(fmaxf(z, 0.0f)));
-  }
-  float y = s.b3[0];
-  for (int o = 0; o < 64; ++o) {
-    float z = s.b2[o];
-#pragma unroll
-    for (int q = 0; q < 64; ++q) z += bf16_to_f32(s.w2[o * 64 + q]) * h1[q];
-    y += bf16_to_f32(s.w3[o]) * bf16_to_f32(f32_to_bf16(fmaxf(z, 0.0f)));
-  }
+// Table cell seed from the learned network for this lane's (log rho, log e);
+// every lane of the wave must call it (the hidden layer runs on the matrix cores).
+__device__ __forceinline__ int seed_cell_wave(const Seed &s, const Table &t, double lr, double le) {
+  const float y = mlp_wave_forward(s.w, norm01(lr, s.lr_lo, s.lr_hi), norm01(le, s.le_lo, s.le_hi));
   const double lT = s.lt_lo + 0.5 * ((double)y + 1.0) * (s.lt_hi - s.lt_lo);
   const double x = (lT - t.lT0) / t.dlT;
   if (!(x > 0.0)) return 0;
@@ -191,18 +167,6 @@ __device__ __forceinline__ void eos_pc(const Phys &p, const Table &t, double rho
   P = exp10(tbil(t.lP, t.nT, i, w, j, wT));
   cs = exp10(0.5 * tbil(t.lc2, t.nT, i, w, j, wT));
   if (jout) *jout = j;
-}
-
-// table cell of the cell-centre state, used to seed the face and compression queries
-__device__ __forceinline__ int centre_cell(const Phys &p, const Table &t, const Seed &s, double rho, double U) {
-  const double Ue = fmax(U, rho * p.e_floor);
-  const double lr = log10(rho), le = log10(Ue / rho);
-  int i, j, it;
-  double w, wT;
-  table_rho(t, lr, i, w);
-  const int seed = (p.inv_mode == 1 && s.enabled) ? seed_cell(s, t, lr, le) : -1;
-  table_invert(t, i, w, le, seed, p.newton_max_iter, j, wT, it);
-  return j;
 }
 
 // ---------------------------------------------------------------------------
@@ -388,7 +352,12 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
   }
   __syncthreads();
   // every face of the tile along D, once
-  for (int f = tid; f < NFD; f += kChunk) {
+  for (int f0 = 0; f0 < NFD; f0 += kChunk) {
+    if (f0 + (tid & ~63) >= NFD) continue;  // the whole wave is idle this round
+    // lanes past the end repeat the last face so the wave stays converged for
+    // the network seed; they store nothing
+    const bool valid = f0 + tid < NFD;
+    const int f = valid ? f0 + tid : NFD - 1;
     const int fc[3] = {f % F0, (f / F0) % F1, f / (F0 * F1)};
     const int s0 = fc[0] + L0 * (fc[1] + L1 * fc[2]);  // stencil start (tile cell fd - 2)
     double wl[6], wr[6];
@@ -401,9 +370,14 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
       wr[vv] = q2 - 0.5 * vanleer(q2 - q1, q3 - q2);
     }
     double pl, cl, pr, cr;
-    int jl = -1;
-    eos_pc(p, a.t, wl[0], wl[4], -1, pl, cl, &jl);
+    int jl = -1, seedl = -1;
+    if (p.eos_kind == 1 && p.inv_mode == 1 && a.s.enabled) {
+      const double Ue = fmax(wl[4], wl[0] * p.e_floor);
+      seedl = seed_cell_wave(a.s, a.t, log10(wl[0]), log10(Ue / wl[0]));
+    }
+    eos_pc(p, a.t, wl[0], wl[4], seedl, pl, cl, &jl);
     eos_pc(p, a.t, wr[0], wr[4], p.inv_mode == 0 ? -1 : jl, pr, cr);
+    if (!valid) continue;
     double F[5];
     hllc(wl, pl, cl, wr, pr, cr, F);
     double FA = 0.0, vf;
@@ -699,13 +673,23 @@ __global__ __launch_bounds__(kChunk) void cfl_items_kernel(StageArgs a, double t
         for (int v = 0; v < nv; ++v) q[v] = Q[B.off + v * n3 + cell];
         c2p(p, q, w);
         double P, cs;
-        int seed = -1;
-        if (p.eos_kind == 1 && p.inv_mode == 1 && a.s.enabled) {
-          const double Ue = fmax(w[4], w[0] * p.e_floor);
-          seed = seed_cell(a.s, a.t, log10(w[0]), log10(Ue / w[0]));
-        }
-        eos_pc(p, a.t, w[0], w[4], seed, P, cs);
+        eos_pc(p, a.t, w[0], w[4], -1, P, cs);
         for (int d = 0; d < 3; ++d) best = fmin(best, m.dx[d] / (fabs(w[1 + d]) + cs));
+        // source-term limit: sqrt(dx_min / |g|) with g the centred potential gradient
+        if (p.grav_kind) {
+          double g2 = 0.0;
+          const int lc[3] = {ci, cj, ck};
+          for (int d = 0; d < 3; ++d) {
+            int ip[3] = {lc[0], lc[1], lc[2]}, im[3] = {lc[0], lc[1], lc[2]};
+            ip[d] += 1;
+            im[d] -= 1;
+            const double gd = (phi_at(a, B, ip[0], ip[1], ip[2], t) - phi_at(a, B, im[0], im[1], im[2], t)) /
+                              (2.0 * m.dx[d]);
+            g2 += gd * gd;
+          }
+          const double dmin = fmin(m.dx[0], fmin(m.dx[1], m.dx[2]));
+          if (g2 > 0.0) best = fmin(best, sqrt(dmin / sqrt(g2)));
+        }
       }
     }
     best = wave_min(best);
@@ -732,26 +716,34 @@ __global__ void cfl_blocks_kernel(const double *part, const int *block_item_star
 // ---------------------------------------------------------------------------
 // batched EOS queries
 // ---------------------------------------------------------------------------
-__global__ void eos_invert_kernel(Table t, Seed s, int maxit, const double *lr, const double *le, double *lT,
-                                  int32_t *jo, int32_t *iters, long long n, int mode) {
-  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+__global__ __launch_bounds__(256) void eos_invert_kernel(Table t, Seed s, int maxit, const double *lr,
+                                                         const double *le, double *lT, int32_t *jo, int32_t *iters,
+                                                         long long n, int mode) {
+  const long long nw = (n + 63) / 64;
+  const long long wstride = ((long long)gridDim.x * blockDim.x) / 64;
+  const int l = threadIdx.x & 63;
+  for (long long wv = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / 64; wv < nw; wv += wstride) {
+    const long long q = wv * 64 + l;  // the loop is uniform across the wave
+    const bool ok = q < n;
+    const double qlr = ok ? lr[q] : t.lr0, qle = ok ? le[q] : t.le[0];
     int i, j, it;
     double w, wT;
-    table_rho(t, lr[q], i, w);
+    table_rho(t, qlr, i, w);
     int seed = -1;
-    if (mode == 1 && s.enabled) seed = seed_cell(s, t, lr[q], le[q]);
+    if (mode == 1) seed = seed_cell_wave(s, t, qlr, qle);
     if (mode == 2) {
-      // bisection result as the seed: the secant loop accepts it at once
-      int jj;
+      // the bisection result as the seed: the secant loop accepts it at once
+      int jj, it2;
       double ww;
-      int it2;
-      table_invert(t, i, w, le[q], -1, 0, jj, ww, it2);
+      table_invert(t, i, w, qle, -1, 0, jj, ww, it2);
       seed = jj;
     }
-    table_invert(t, i, w, le[q], seed, maxit, j, wT, it);
-    if (lT) lT[q] = t.lT0 + (j + wT) * t.dlT;
-    if (jo) jo[q] = j;
-    if (iters) iters[q] = it;
+    table_invert(t, i, w, qle, seed, maxit, j, wT, it);
+    if (ok) {
+      if (lT) lT[q] = t.lT0 + (j + wT) * t.dlT;
+      if (jo) jo[q] = j;
+      if (iters) iters[q] = it;
+    }
   }
 }
 

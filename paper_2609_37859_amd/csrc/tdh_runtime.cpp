@@ -48,8 +48,13 @@ struct tdh_ctx {
   bool have_table = false;
   Table tab{};
   double *d_table = nullptr;
-  // learned seed (set by the network code)
+  // learned seed network
   Seed seed{};
+  bool have_mlp = false;
+  float *d_mw = nullptr, *d_mm = nullptr, *d_mv = nullptr, *d_mgrad = nullptr, *d_mpart = nullptr;
+  float *d_mloss_part = nullptr, *d_mloss = nullptr, *d_mb = nullptr;
+  short *d_mwb = nullptr;
+  int mlp_steps_done = 0;
 
   // LAT window state
   std::vector<int> levels, fac, par, order, item_start, cnt_ge;
@@ -747,7 +752,7 @@ extern "C" tdh_status tdh_eos_invert_batch(tdh_ctx *c, const double *lr, const d
   if (!c->have_table) return fail(c, TDH_ESTATE, "no EOS table");
   if (n < 0 || n > (1LL << 31)) return fail(c, TDH_ERANGE, "n out of range");
   if (mode < 0 || mode > 2) return fail(c, TDH_EINVAL, "mode must be 0, 1 or 2");
-  if (mode == 1 && !c->seed.enabled) return fail(c, TDH_ESTATE, "mode 1 needs a trained seed network");
+  if (mode == 1 && !c->have_mlp) return fail(c, TDH_ESTATE, "mode 1 needs the seed network (tdh_mlp_init)");
   if (!lr || !le) return fail(c, TDH_EINVAL, "null input");
   HIPCHK(c, launch_eos_invert(c->tab, c->seed, c->cfg.newton_max_iter, lr, le, lT, j, iters, n, mode, c->stream));
   return TDH_OK;
@@ -872,5 +877,122 @@ extern "C" tdh_status tdh_get_stage_time(tdh_ctx *c, double *host_ms, int64_t *h
   if ((s = collect_timing(c))) return s;
   if (host_ms) *host_ms = c->stage_ms;
   if (host_launches) *host_launches = c->stage_launches;
+  return TDH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// learned EOS seed network
+// ---------------------------------------------------------------------------
+static constexpr int kMlpMaxBatch = 65536;
+static constexpr int kMlpMaxSteps = 1 << 20;
+
+static void invalidate_graphs(tdh_ctx *c) {
+  for (auto &g : c->graphs) hipGraphExecDestroy(g.second);
+  c->graphs.clear();
+}
+
+extern "C" tdh_status tdh_mlp_init(tdh_ctx *c, const float *host_params, double lr_lo, double lr_hi, double le_lo,
+                                   double le_hi, double lt_lo, double lt_hi) {
+  CHECK_CTX(c);
+  if (!host_params) return fail(c, TDH_EINVAL, "null parameters");
+  if (!(lr_hi > lr_lo) || !(le_hi > le_lo) || !(lt_hi > lt_lo)) return fail(c, TDH_EINVAL, "empty normalisation range");
+  tdh_status s;
+  if (!c->have_mlp) {
+    if ((s = dev_alloc(c, &c->d_mw, kMlpParams)) || (s = dev_alloc(c, &c->d_mm, kMlpParams)) ||
+        (s = dev_alloc(c, &c->d_mv, kMlpParams)) || (s = dev_alloc(c, &c->d_mgrad, kMlpParams)) ||
+        (s = dev_alloc(c, &c->d_mpart, (size_t)(kMlpMaxBatch / 64) * kMlpParams)) ||
+        (s = dev_alloc(c, &c->d_mloss_part, kMlpMaxBatch / 64)) || (s = dev_alloc(c, &c->d_mloss, kMlpMaxSteps)) ||
+        (s = dev_alloc(c, &c->d_mb, 64 + 64 + 1)) || (s = dev_alloc(c, &c->d_mwb, 128 + 4096 + 4096 + 64)))
+      return s;
+  }
+  std::vector<float> zero(kMlpParams, 0.0f);
+  HIPCHK(c, hipMemcpyAsync(c->d_mw, host_params, kMlpParams * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_mm, zero.data(), kMlpParams * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_mv, zero.data(), kMlpParams * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  MlpDev &w = c->seed.w;
+  w.b1 = c->d_mb;
+  w.b2 = c->d_mb + 64;
+  w.b3 = c->d_mb + 128;
+  w.w1b = c->d_mwb;
+  w.w2b = c->d_mwb + 128;
+  w.w2tb = c->d_mwb + 128 + 4096;
+  w.w3b = c->d_mwb + 128 + 8192;
+  HIPCHK(c, mlp_launch_pack(c->d_mw, (short *)w.w1b, (short *)w.w2b, (short *)w.w2tb, (short *)w.w3b, (float *)w.b1,
+                            (float *)w.b2, (float *)w.b3, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->seed.lr_lo = lr_lo; c->seed.lr_hi = lr_hi;
+  c->seed.le_lo = le_lo; c->seed.le_hi = le_hi;
+  c->seed.lt_lo = lt_lo; c->seed.lt_hi = lt_hi;
+  c->seed.enabled = 0;
+  c->have_mlp = true;
+  c->mlp_steps_done = 0;
+  invalidate_graphs(c);
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_mlp_train(tdh_ctx *c, const double *dev_in, const double *dev_lT, int64_t n, int steps,
+                                    int batch, float lr, uint64_t seed, float *host_loss) {
+  CHECK_CTX(c);
+  if (!c->have_mlp) return fail(c, TDH_ESTATE, "call tdh_mlp_init first");
+  if (!dev_in || !dev_lT || n < 64) return fail(c, TDH_EINVAL, "need at least 64 samples");
+  if (batch < 64 || batch % 64 || batch > kMlpMaxBatch) return fail(c, TDH_EINVAL, "batch must be a multiple of 64 up to 65536");
+  if (steps < 1 || steps > kMlpMaxSteps) return fail(c, TDH_ERANGE, "steps must be in [1, 2^20]");
+  if (!(lr > 0.0f)) return fail(c, TDH_EINVAL, "lr must be positive");
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  MlpDev &w = c->seed.w;
+  for (int st = 0; st < steps; ++st) {
+    const int t = ++c->mlp_steps_done;
+    const float lr_t = (float)(0.5 * lr * (1.0 + std::cos(M_PI * st / (double)steps)));  // cosine decay
+    HIPCHK(c, mlp_launch_fwd_bwd(w, c->seed, dev_in, dev_lT, n, batch, seed, t, 1, c->d_mpart, c->d_mloss_part,
+                                 c->d_mgrad, c->d_mloss + st, c->stream));
+    const float c1 = (float)(1.0 - std::pow((double)b1, t)), c2 = (float)(1.0 - std::pow((double)b2, t));
+    HIPCHK(c, mlp_launch_adam(c->d_mw, c->d_mm, c->d_mv, c->d_mgrad, lr_t, b1, b2, eps, c1, c2, c->stream));
+    HIPCHK(c, mlp_launch_pack(c->d_mw, (short *)w.w1b, (short *)w.w2b, (short *)w.w2tb, (short *)w.w3b, (float *)w.b1,
+                              (float *)w.b2, (float *)w.b3, c->stream));
+  }
+  if (host_loss)
+    HIPCHK(c, hipMemcpyAsync(host_loss, c->d_mloss, steps * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  invalidate_graphs(c);
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_mlp_loss_grad(tdh_ctx *c, const double *dev_in, const double *dev_lT, int64_t n,
+                                        float *host_loss, float *host_grad) {
+  CHECK_CTX(c);
+  if (!c->have_mlp) return fail(c, TDH_ESTATE, "call tdh_mlp_init first");
+  if (!dev_in || !dev_lT || n < 64 || n % 64 || n > kMlpMaxBatch)
+    return fail(c, TDH_EINVAL, "n must be a multiple of 64 up to 65536");
+  HIPCHK(c, mlp_launch_fwd_bwd(c->seed.w, c->seed, dev_in, dev_lT, n, (int)n, 0, 0, 0, c->d_mpart, c->d_mloss_part,
+                               c->d_mgrad, c->d_mloss, c->stream));
+  if (host_grad)
+    HIPCHK(c, hipMemcpyAsync(host_grad, c->d_mgrad, kMlpParams * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  if (host_loss) HIPCHK(c, hipMemcpyAsync(host_loss, c->d_mloss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_mlp_forward(tdh_ctx *c, const double *dev_in, double *dev_lT, int64_t n) {
+  CHECK_CTX(c);
+  if (!c->have_mlp) return fail(c, TDH_ESTATE, "call tdh_mlp_init first");
+  if (!dev_in || !dev_lT || n < 0 || n > (1LL << 31)) return fail(c, TDH_EINVAL, "bad arguments");
+  HIPCHK(c, mlp_launch_forward(c->seed.w, c->seed, dev_in, dev_lT, n, c->stream));
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_mlp_get_params(tdh_ctx *c, float *host_params) {
+  CHECK_CTX(c);
+  if (!c->have_mlp) return fail(c, TDH_ESTATE, "call tdh_mlp_init first");
+  if (!host_params) return fail(c, TDH_EINVAL, "null output");
+  HIPCHK(c, hipMemcpyAsync(host_params, c->d_mw, kMlpParams * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_mlp_enable_seed(tdh_ctx *c, int on) {
+  CHECK_CTX(c);
+  if (on && !c->have_mlp) return fail(c, TDH_ESTATE, "call tdh_mlp_init first");
+  c->seed.enabled = on ? 1 : 0;
+  invalidate_graphs(c);
   return TDH_OK;
 }

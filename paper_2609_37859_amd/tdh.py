@@ -262,6 +262,42 @@ class Context:
         self._check(self.L.tdh_get_stage_time(self.ctx, C.byref(ms), C.byref(n)), "tdh_get_stage_time")
         return ms.value, n.value
 
+    # --- learned seed network ---
+    def mlp_init(self, params, ranges):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == 4417
+        self._check(self.L.tdh_mlp_init(self.ctx, p.ctypes.data_as(C.POINTER(C.c_float)), *map(float, ranges)),
+                    "tdh_mlp_init")
+
+    def mlp_train(self, x, lT, steps, batch=4096, lr=1e-3, seed=1):
+        """x: device float64 [n, 2] (log10 rho, log10 e); lT: device float64 [n]."""
+        loss = np.zeros(steps, dtype=np.float32)
+        self._check(self.L.tdh_mlp_train(self.ctx, x.data_ptr(), lT.data_ptr(), x.shape[0], int(steps), int(batch),
+                                         float(lr), int(seed), loss.ctypes.data_as(C.POINTER(C.c_float))),
+                    "tdh_mlp_train")
+        return loss
+
+    def mlp_loss_grad(self, x, lT):
+        g = np.zeros(4417, dtype=np.float32)
+        loss = C.c_float()
+        self._check(self.L.tdh_mlp_loss_grad(self.ctx, x.data_ptr(), lT.data_ptr(), x.shape[0], C.byref(loss),
+                                             g.ctypes.data_as(C.POINTER(C.c_float))), "tdh_mlp_loss_grad")
+        return loss.value, g
+
+    def mlp_forward(self, x):
+        torch = self.torch
+        out = torch.empty(x.shape[0], dtype=torch.float64, device=self.device)
+        self._check(self.L.tdh_mlp_forward(self.ctx, x.data_ptr(), out.data_ptr(), x.shape[0]), "tdh_mlp_forward")
+        return out
+
+    def mlp_params(self):
+        p = np.zeros(4417, dtype=np.float32)
+        self._check(self.L.tdh_mlp_get_params(self.ctx, p.ctypes.data_as(C.POINTER(C.c_float))), "tdh_mlp_get_params")
+        return p
+
+    def mlp_enable_seed(self, on=True):
+        self._check(self.L.tdh_mlp_enable_seed(self.ctx, int(on)), "tdh_mlp_enable_seed")
+
     def stats(self):
         s = tdh_stats()
         self._check(self.L.tdh_get_stats(self.ctx, C.byref(s)), "tdh_get_stats")

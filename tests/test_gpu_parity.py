@@ -109,7 +109,7 @@ def test_levels_bit_exact_and_dt_parity(tdh, orc):
     ctx = tdh.Context(cfg, mesh, U, phi=phi)
     dtb, dt0, lev, L = ctx.reduce_dt()
     ctx.close()
-    dto = orc.cfl(cfg, mesh, U)
+    dto = orc.cfl(cfg, mesh, U, phi=phi)
     assert np.max(np.abs(dtb / dto - 1)) < 1e-13
     lev_o, L_o, dt0_o = orc.lat_assign(cfg, mesh, dtb)
     assert L == L_o and dt0 == dt0_o
@@ -139,7 +139,7 @@ def test_lat_window_parity_polytrope(tdh, orc):
     """LAT windows on the reduced polytrope: GPU equals the oracle to 1e-11
     with the oracle's level assignment; all launch forms agree bit for bit."""
     cfg, mesh, U, phi, info = W.polytrope_c3(nb=4, n=16)
-    dto = orc.cfl(cfg, mesh, U)
+    dto = orc.cfl(cfg, mesh, U, phi=phi)
     lev, L, dt0 = orc.lat_assign(cfg, mesh, dto)
     assert L >= 1
     o = U

@@ -294,3 +294,20 @@ def test_point_mass_potential_equals_stored_potential(orc):
     a, _ = orc.run_sync(cfg1, mesh, U, 3, phi=phi, dts=[1e-3] * 3)
     b, _ = orc.run_sync(cfg2, mesh, U, 3, dts=[1e-3] * 3)
     assert np.allclose(a, b, rtol=1e-13, atol=1e-15)
+
+
+def test_cfl_closed_form_with_gravity_limit(orc):
+    """Per-block step (Sec. LAT method: CFL limit from the hydrodynamic and the
+    source terms): gas at rest, c_s = sqrt(gamma P / rho), in a uniform field g
+    gives dt = cfl * min(dx / c_s, sqrt(dx / g))."""
+    for g in (0.0, 0.05, 50.0):
+        cfg = W.Config(grav_kind=1 if g else 0, cfl=0.3)
+        mesh = W.uniform_mesh(2, 1, 1, 8, 0.05, bc=(1, 0, 0))
+        rho, P = 1.3, 0.8
+        U = W.pack_state(mesh, 5, lambda x, y, z: W.ideal_conserved(rho + 0 * x, 0 * x, 0 * x, 0 * x, P + 0 * x,
+                                                                     cfg.gamma, False))
+        phi = W.pack_potential(mesh, lambda x, y, z: g * x) if g else None
+        dt = orc.cfl(cfg, mesh, U, phi=phi)
+        cs = math.sqrt(cfg.gamma * P / rho)
+        expect = 0.3 * min(0.05 / cs, math.sqrt(0.05 / g) if g else math.inf)
+        assert np.allclose(dt, expect, rtol=1e-13, atol=0)
