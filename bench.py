@@ -82,7 +82,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps for the CPU baseline / accuracy check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="seeded,plain", help="comma list of forms to time: seeded, plain")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8, "launches": 3}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
@@ -117,10 +129,14 @@ def main():
                "kind": "oracle",
                "sample": f"{args.cpu_steps} RK2 steps of the full 128^3 workload (GPU step sizes), {cpu_s:.1f} s"}
 
+    forms = args.forms.split(",")
     el, stage_ms, launches, st, tile = run_form(T, cfg, mesh, U, table, args.steps, args.warmup, inv_mode=2,
                                                 batched=True)
-    el_p, stage_ms_p, launches_p, st_p, tile_p = run_form(T, cfg, mesh, U, table, args.steps, args.warmup,
-                                                          inv_mode=0, batched=False)
+    if "plain" in forms:
+        el_p, stage_ms_p, launches_p, st_p, tile_p = run_form(T, cfg, mesh, U, table, args.steps, args.warmup,
+                                                              inv_mode=0, batched=False)
+    else:
+        el_p, tile_p = float("nan"), tile
     value = ncell * args.steps / el
     plain = ncell * args.steps / el_p
     # algorithmic HBM bytes of the stage kernel: stage 1 reads Q^n and writes Q^(1),

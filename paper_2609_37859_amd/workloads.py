@@ -224,7 +224,7 @@ def _saha_core(rho, T, X=0.7, Y=0.3):
 
     lo = np.full(rho.shape, math.log(1e-60))
     hi = np.log(nH + 2.0 * nHe) + 1e-12
-    for _ in range(200):
+    for _ in range(64):  # the bracket spans < 200 in ln n_e: 64 halvings reach ~1e-17
         mid = 0.5 * (lo + hi)
         xH, y1, y2 = fractions(mid)
         f = nH * xH + nHe * (y1 + 2.0 * y2) - np.exp(mid)
@@ -473,3 +473,37 @@ def random_smooth_state(mesh: Mesh, cfg: Config, seed: int, amp=0.2, modes=3):
         return ideal_conserved(rho, vx, vy, vz, P, cfg.gamma, bool(cfg.dual))
 
     return pack_state(mesh, cfg.nv, fn)
+
+
+# ---------------------------------------------------------------------------
+# learned EOS seed: training samples, initial parameters, normalisation
+# ---------------------------------------------------------------------------
+def seed_ranges(table: EosTable):
+    """(log rho lo, hi, log e lo, hi, log T lo, hi) used to normalise to [-1, 1]."""
+    return (table.lr0, table.lr0 + (table.nrho - 1) * table.dlr, float(table.le.min()), float(table.le.max()),
+            table.lT0, table.lT0 + (table.nT - 1) * table.dlT)
+
+
+def seed_training_samples(table: EosTable, n: int, seed: int) -> np.ndarray:
+    """[n, 2] (log10 rho, log10 e): log rho uniform over the table, log e uniform
+    between the table's values at its lowest and highest temperature for that
+    density (the tighter of the two bracketing rows)."""
+    rng = np.random.default_rng(seed)
+    lr = rng.uniform(table.lr0, table.lr0 + (table.nrho - 1) * table.dlr, n)
+    i = np.clip(np.floor((lr - table.lr0) / table.dlr).astype(np.int64), 0, table.nrho - 2)
+    # bounds from the stored nodes of the two bracketing rows (inside both rows' range)
+    le_lo = np.maximum(table.le[i, 0], table.le[i + 1, 0])
+    le_hi = np.minimum(table.le[i, -1], table.le[i + 1, -1])
+    u = rng.uniform(0.0, 1.0, n)
+    le = le_lo + u * (le_hi - le_lo)
+    return np.ascontiguousarray(np.stack([lr, le], 1))
+
+
+def mlp_init_params(seed: int) -> np.ndarray:
+    """He-normal weights, zero biases, fp32 [4417] in the library's order."""
+    rng = np.random.default_rng(seed)
+    p = np.zeros(4417, dtype=np.float64)
+    p[0:128] = rng.normal(0.0, math.sqrt(2.0 / 2.0), 128)
+    p[192:4288] = rng.normal(0.0, math.sqrt(2.0 / 64.0), 4096)
+    p[4352:4416] = rng.normal(0.0, math.sqrt(1.0 / 64.0), 64)
+    return p.astype(np.float32)

@@ -1,0 +1,155 @@
+"""Learned EOS seed network on the GPU (MFMA bf16 kernels) against the oracle.
+
+Exactness: with dyadic inputs and weights (few significant bits) every fp32
+sum is exact, so the bf16 rounding decisions coincide and the GPU forward
+and gradient equal the oracle's exactly.  On random data the GPU accumulates
+in fp32 in another order; the comparison then allows the rare bf16 rounding
+flip that causes (each moves a value by one bf16 step, 2^-8 relative).
+"""
+import numpy as np
+import pytest
+
+from paper_2609_37859_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RANGES = (-12.0, 2.0, 10.0, 16.0, 3.0, 8.0)  # log rho, log e, log T ranges
+
+
+@pytest.fixture(scope="module")
+def gctx(saha):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_37859_amd import tdh as T
+    cfg = W.Config(eos_kind=1, e_floor=saha.e_floor)
+    mesh = W.uniform_mesh(1, 1, 1, 8, 1.0)
+    ctx = T.Context(cfg, mesh, W.uniform_state(mesh, W.Config()), table=saha)
+    yield ctx
+    ctx.close()
+
+
+def raw_from_norm(xn, lo, hi):
+    return lo + (xn + 1.0) * 0.5 * (hi - lo)
+
+
+def test_forward_and_gradient_exact_on_dyadic_data(gctx, orc):
+    import torch
+    rng = np.random.default_rng(11)
+    n = 128
+    p = np.zeros(orc.N_PARAMS)
+    p[0:128] = rng.integers(-8, 9, 128) / 8.0
+    p[128:192] = rng.integers(-8, 9, 64) / 16.0
+    p[192:4288] = rng.integers(-4, 5, 4096) / 64.0
+    p[4288:4352] = rng.integers(-4, 5, 64) / 16.0
+    p[4352:4416] = rng.integers(-4, 5, 64) / 32.0
+    p[4416] = 0.125
+    xn = rng.integers(-8, 9, (n, 2)) / 8.0
+    tn = rng.integers(-8, 9, n) / 8.0
+    lr_lo, lr_hi, le_lo, le_hi, lt_lo, lt_hi = RANGES
+    raw = np.stack([raw_from_norm(xn[:, 0], lr_lo, lr_hi), raw_from_norm(xn[:, 1], le_lo, le_hi)], 1)
+    # the library normalises raw inputs in FP64 then rounds to fp32; recover exactly what it sees
+    xs = np.stack([(2 * (raw[:, 0] - lr_lo) / (lr_hi - lr_lo) - 1).astype(np.float32),
+                   (2 * (raw[:, 1] - le_lo) / (le_hi - le_lo) - 1).astype(np.float32)], 1).astype(np.float64)
+    assert np.array_equal(xs, xn)
+    lT = raw_from_norm(tn, lt_lo, lt_hi)
+    gctx.mlp_init(p.astype(np.float32), RANGES)
+    yo = orc.mlp_forward(p, xn, round_bf16=True)
+    yg = gctx.mlp_forward(torch.from_numpy(raw).cuda()).cpu().numpy()
+    yg_n = 2 * (yg - lt_lo) / (lt_hi - lt_lo) - 1
+    assert np.max(np.abs(yg_n - yo)) < 1e-6
+    loss_g, grad_g = gctx.mlp_loss_grad(torch.from_numpy(raw).cuda(), torch.from_numpy(lT).cuda())
+    loss_o, grad_o = orc.mlp_loss_grad(p, xn, tn, round_bf16=True)
+    assert abs(loss_g - loss_o) <= 1e-6 * max(1.0, abs(loss_o))
+    assert np.max(np.abs(grad_g - grad_o)) <= 1e-5 * max(1.0, np.abs(grad_o).max())
+
+
+def test_gradient_matches_oracle_on_random_data(gctx, orc):
+    import torch
+    rng = np.random.default_rng(12)
+    n = 4096
+    p = (rng.normal(0, 0.3, orc.N_PARAMS)).astype(np.float32).astype(np.float64)
+    xn = rng.uniform(-1, 1, (n, 2))
+    lr_lo, lr_hi, le_lo, le_hi, lt_lo, lt_hi = RANGES
+    raw = np.stack([raw_from_norm(xn[:, 0], lr_lo, lr_hi), raw_from_norm(xn[:, 1], le_lo, le_hi)], 1)
+    xs = np.stack([(2 * (raw[:, 0] - lr_lo) / (lr_hi - lr_lo) - 1).astype(np.float32),
+                   (2 * (raw[:, 1] - le_lo) / (le_hi - le_lo) - 1).astype(np.float32)], 1).astype(np.float64)
+    tn = rng.uniform(-1, 1, n)
+    lT = raw_from_norm(tn, lt_lo, lt_hi)
+    tn_seen = (2 * (lT - lt_lo) / (lt_hi - lt_lo) - 1).astype(np.float32).astype(np.float64)
+    gctx.mlp_init(p.astype(np.float32), RANGES)
+    yo = orc.mlp_forward(p, xs, round_bf16=True)
+    yg = gctx.mlp_forward(torch.from_numpy(raw).cuda()).cpu().numpy()
+    yg_n = 2 * (yg - lt_lo) / (lt_hi - lt_lo) - 1
+    d = np.abs(yg_n - yo) / np.maximum(np.abs(yo), 1e-2)
+    assert np.mean(d < 1e-5) > 0.99 and d.max() < 2e-2
+    loss_g, grad_g = gctx.mlp_loss_grad(torch.from_numpy(raw).cuda(), torch.from_numpy(lT).cuda())
+    loss_o, grad_o = orc.mlp_loss_grad(p, xs, tn_seen, round_bf16=True)
+    assert abs(loss_g / loss_o - 1) < 1e-4
+    rel = np.linalg.norm(grad_g - grad_o) / np.linalg.norm(grad_o)
+    assert rel < 1e-3, rel
+
+
+def _train_seed(ctx, saha, steps=2000, n=1 << 20, seed=1):
+    """C4 recipe: 2^20 table samples, log rho ~ U[-12, 2], log e uniform between
+    the row's values at 1e3 K and 1e8 K; labels from the table inversion."""
+    import torch
+    x = W.seed_training_samples(saha, n, seed)
+    xt = torch.from_numpy(x).cuda()
+    lT, _, _ = ctx.eos_invert(xt[:, 0].contiguous(), xt[:, 1].contiguous(), mode=0)
+    p0 = W.mlp_init_params(seed=2)
+    ctx.mlp_init(p0, W.seed_ranges(saha))
+    loss = ctx.mlp_train(xt, lT, steps=steps, batch=4096, lr=1e-3, seed=seed)
+    return loss
+
+
+def test_training_on_gpu_reduces_loss_and_seeds_the_inversion(gctx, saha):
+    import torch
+    loss = _train_seed(gctx, saha, steps=600)
+    assert np.all(np.isfinite(loss))
+    assert loss[-20:].mean() < 0.05 * loss[:5].mean()
+    gctx.mlp_enable_seed(True)
+    xq = torch.from_numpy(W.seed_training_samples(saha, 1 << 16, 3)).cuda()
+    lT0, j0, it0 = gctx.eos_invert(xq[:, 0].contiguous(), xq[:, 1].contiguous(), mode=0)
+    lT1, j1, it1 = gctx.eos_invert(xq[:, 0].contiguous(), xq[:, 1].contiguous(), mode=1)
+    torch.cuda.synchronize()
+    assert torch.equal(j0, j1) and torch.equal(lT0, lT1)  # the seed never changes the answer
+    pred = gctx.mlp_forward(xq).cpu().numpy()
+    err = np.abs(pred - lT0.cpu().numpy())
+    assert np.percentile(err, 50) < 5 * saha.dlT  # within a few table cells
+    gctx.mlp_enable_seed(False)
+
+
+def test_corrupted_network_changes_nothing(gctx, saha):
+    """A broken seed (garbage weights) makes every query fall back; the
+    inversion results are unchanged bit for bit."""
+    import torch
+    p = np.full(4417, 37.0, dtype=np.float32)
+    gctx.mlp_init(p, W.seed_ranges(saha))
+    gctx.mlp_enable_seed(True)
+    xq = torch.from_numpy(W.seed_training_samples(saha, 1 << 14, 4)).cuda()
+    lT0, j0, _ = gctx.eos_invert(xq[:, 0].contiguous(), xq[:, 1].contiguous(), mode=0)
+    lT1, j1, it1 = gctx.eos_invert(xq[:, 0].contiguous(), xq[:, 1].contiguous(), mode=1)
+    torch.cuda.synchronize()
+    assert torch.equal(j0, j1) and torch.equal(lT0, lT1)
+    gctx.mlp_enable_seed(False)
+
+
+def test_hydro_with_learned_seed_equals_bisection_bitwise(gctx, saha):
+    """C2 stream on a 2^3-block mesh: inv_mode 1 (network seed) and 0
+    (bisection) give the same state bit for bit."""
+    from paper_2609_37859_amd import tdh as T
+    import torch
+    _train_seed(gctx, saha, steps=300)
+    params = gctx.mlp_params()
+    cfg, mesh, U = W.stream_c2(saha, nb=2)
+    outs = []
+    for mode in (0, 1, 2):
+        ctx = T.Context(cfg, mesh, U, table=saha, inv_mode=mode)
+        if mode == 1:
+            ctx.mlp_init(params, W.seed_ranges(saha))
+            ctx.mlp_enable_seed(True)
+        T.run_sync_steps(ctx, 3, dts=[3e-4] * 3)
+        outs.append(ctx.get_state())
+        ctx.close()
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
