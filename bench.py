@@ -8,10 +8,13 @@ minimum, global minimum, level assignment) and one RK2 step of every block
 (two stage launches with PLM, table EOS inversion, HLLC, divergence, dual
 energy update), inputs resident in HBM.
 
-Prints one JSON line.  `value` is the cell-updates/s of the seeded form
-(table inversion of each face's second query seeded by the first, one launch
-per phase for all levels); the plain form (bisection for every query, one
-launch per level) is reported beside it.  The roofline entry is for the
+Prints one JSON line.  `value` is the cell-updates/s of the learned form:
+one launch per RK phase for all levels, each face's first table query seeded
+by the learned network (trained first on the GPU by the library's own
+kernels; training time reported, not timed), the second query seeded by the
+first.  The chained form (first query bisected) and the plain form
+(bisection for every query, one launch per level) are reported beside it;
+all three give bit-identical states.  The roofline entry is for the
 stage kernel (HIP events on the library's stream); the CPU baseline is the
 FP64 oracle on the host, on a bounded number of steps of the same workload,
 and its final state doubles as the accuracy check of the GPU run.
@@ -51,9 +54,37 @@ def traffic_from_profiles(workload):
     return d.get("hbm_bytes_per_launch")
 
 
-def run_form(T, cfg, mesh, U, table, steps, warmup, inv_mode, batched):
+def train_seed(T, W, table, steps=2000, nsamples=1 << 20):
+    """Train the learned seed on the GPU with the library's kernels: 2^20
+    samples, labels from the library's table inversion.  Returns (params,
+    seconds, final loss, median |dlogT| of the prediction on fresh queries)."""
+    import torch
+    cfg = W.Config(eos_kind=1, e_floor=table.e_floor)
+    mesh = W.uniform_mesh(1, 1, 1, 8, 1.0)
+    ctx = T.Context(cfg, mesh, W.uniform_state(mesh, W.Config()), table=table)
+    x = torch.from_numpy(W.seed_training_samples(table, nsamples, 1)).cuda()
+    lT, _, _ = ctx.eos_invert(x[:, 0].contiguous(), x[:, 1].contiguous(), mode=0)
+    ctx.mlp_init(W.mlp_init_params(2), W.seed_ranges(table))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = ctx.mlp_train(x, lT, steps=steps, batch=4096, lr=1e-3, seed=1)
+    secs = time.perf_counter() - t0
+    xq = torch.from_numpy(W.seed_training_samples(table, 1 << 20, 3)).cuda()
+    lq, _, _ = ctx.eos_invert(xq[:, 0].contiguous(), xq[:, 1].contiguous(), mode=0)
+    err = (ctx.mlp_forward(xq) - lq).abs().cpu().numpy()
+    params = ctx.mlp_params()
+    ctx.close()
+    q = {f"p{p}": float(np.percentile(err, p)) for p in (50, 90, 99, 99.99)}
+    q["max"] = float(err.max())
+    return params, secs, float(loss[-1]), q
+
+
+def run_form(T, W, cfg, mesh, U, table, steps, warmup, inv_mode, batched, seed_params=None):
     import torch
     ctx = T.Context(cfg, mesh, U, table=table, inv_mode=inv_mode)
+    if seed_params is not None:
+        ctx.mlp_init(seed_params, W.seed_ranges(table))
+        ctx.mlp_enable_seed(True)
     ctx.autotune(reps=2)
     for _ in range(warmup):
         _, dt0, lev, L = ctx.reduce_dt()
@@ -82,7 +113,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps for the CPU baseline / accuracy check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="seeded,plain", help="comma list of forms to time: seeded, plain")
+    ap.add_argument("--forms", default="learned,chained,plain",
+                    help="comma list of forms to time: learned, chained, plain (the first present is the headline)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -130,15 +162,20 @@ def main():
                "sample": f"{args.cpu_steps} RK2 steps of the full 128^3 workload (GPU step sizes), {cpu_s:.1f} s"}
 
     forms = args.forms.split(",")
-    el, stage_ms, launches, st, tile = run_form(T, cfg, mesh, U, table, args.steps, args.warmup, inv_mode=2,
-                                                batched=True)
-    if "plain" in forms:
-        el_p, stage_ms_p, launches_p, st_p, tile_p = run_form(T, cfg, mesh, U, table, args.steps, args.warmup,
-                                                              inv_mode=0, batched=False)
-    else:
-        el_p, tile_p = float("nan"), tile
-    value = ncell * args.steps / el
-    plain = ncell * args.steps / el_p
+    params, train_s, train_loss, seed_err = train_seed(T, W, table)
+    res = {}
+    for name, mode, batched in (("learned", 1, True), ("chained", 2, True), ("plain", 0, False)):
+        if name in forms:
+            res[name] = run_form(T, W, cfg, mesh, U, table, args.steps, args.warmup, inv_mode=mode, batched=batched,
+                                 seed_params=params if mode == 1 else None)
+    head = "learned" if "learned" in res else next(iter(res))
+    el, stage_ms, launches, st, tile = res[head]
+
+    def rate(name):
+        return ncell * args.steps / res[name][0] if name in res else None
+
+    value = rate(head)
+    plain = rate("plain")
     # algorithmic HBM bytes of the stage kernel: stage 1 reads Q^n and writes Q^(1),
     # stage 2 reads Q^n and Q^(1) and writes Q^(n+1): 5 nv doubles per cell and step
     bytes_per_step = 5 * nv * 8 * ncell
@@ -159,12 +196,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": "c2: 128^3 periodic as 64 MeshBlocks of 32^3, Saha H/He table EOS 256x256, dual "
                                "energy, cold Mach-1e7 Gaussian stream, CFL 0.3", "cells": ncell, "nv": nv,
-                   "form": "batched, table inversion seeded (second query of each face from the first)",
+                   "form": {"learned": "batched launches; each face's first table query seeded by the learned "
+                                       "network, the second by the first",
+                            "chained": "batched launches; first query bisected, second seeded by the first",
+                            "plain": "one launch per level; bisection for every table query"}[head],
                    "tile": T.tile_shapes()[tile]},
-        "plain": {"value": plain, "ms_per_step": 1e3 * el_p / args.steps,
-                  "form": "one launch per level, bisection for every table query",
-                  "tile": T.tile_shapes()[tile_p]},
-        "speedup_vs_plain": value / plain,
+        "forms": {k: {"value": rate(k), "ms_per_step": 1e3 * v[0] / args.steps,
+                      "stage_kernel_ms": v[1] / max(v[2], 1), "tile": T.tile_shapes()[v[4]]} for k, v in res.items()},
+        "speedup_vs_plain": (value / plain) if plain else None,
+        "learned_seed": {"train_steps": 2000, "batch": 4096, "samples": 1 << 20, "train_seconds": train_s,
+                         "final_loss": train_loss, "abs_dlogT_percentiles": seed_err},
         "max_rel_err_vs_oracle": acc,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

@@ -174,14 +174,15 @@ tdh_status tdh_eos_invert_batch(tdh_ctx *ctx, const double *dev_lrho, const doub
 tdh_status tdh_eos_eval_batch(tdh_ctx *ctx, const double *dev_rho, const double *dev_U, double *dev_P,
                               double *dev_cs, int64_t n);
 
-/* Stage tile shapes: tdh_num_tiles() shapes, id -> (x, y, z) edges.  Every
- * shape gives bit-identical results; a shape must divide the smallest block.
+/* Stage-kernel variants: tdh_num_tiles() of them, id -> (x, y, z) tile edges
+ * and the waves per SIMD its register budget targets (host_dims4[4]).  Every
+ * variant gives bit-identical results; a tile must divide the smallest block.
  * tdh_autotune times one stage over all blocks reps times per fitting shape
  * (state unchanged), keeps the fastest, returns its id and per-shape
  * milliseconds (host_ms [tdh_num_tiles()], -1 where a shape does not fit;
  * may be NULL).  Call between windows. */
 int tdh_num_tiles(void);
-tdh_status tdh_tile_shape(int id, int *host_dims3);
+tdh_status tdh_tile_shape(int id, int *host_dims4);
 tdh_status tdh_set_tile(tdh_ctx *ctx, int id);
 tdh_status tdh_get_tile(tdh_ctx *ctx, int *host_id);
 tdh_status tdh_autotune(tdh_ctx *ctx, int reps, int *host_best, float *host_ms);

@@ -102,8 +102,8 @@ def _ip(a):
 class _Keep:
     """Holds the ctypes structs and the numpy buffers they point into."""
 
-    def __init__(self, cfg, mesh, table):
-        if getattr(cfg, "eos_kind", 0) == 1 and table is None and not isinstance(cfg, _DummyCfg):
+    def __init__(self, cfg, mesh, table, need_table=True):
+        if need_table and getattr(cfg, "eos_kind", 0) == 1 and table is None and not isinstance(cfg, _DummyCfg):
             raise ValueError("the tabulated EOS needs a table")
         c = _Cfg()
         for f, _ in _Cfg._fields_:
@@ -168,7 +168,7 @@ def cfl(cfg, mesh, U, table=None, t=0.0, phi=None):
 
 def lat_assign(cfg, mesh, dt_block):
     """Returns (levels int32[nblocks], Lmax, dt0)."""
-    k = _Keep(cfg, mesh, None)
+    k = _Keep(cfg, mesh, None, need_table=False)
     dtb = np.ascontiguousarray(dt_block, dtype=np.float64)
     lev = np.zeros(mesh.nblocks, dtype=np.int32)
     dt0 = C.c_double(0.0)

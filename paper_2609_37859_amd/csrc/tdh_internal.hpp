@@ -78,12 +78,14 @@ struct StageArgs {
   int k;                    // sub-cycle index in the window (dt0 units)
   int phase;                // 1 or 2
   const double *win;        // device {window start time, finest step dt0}
+  int *jc;                  // table cell of each cell's stage-input state (seeded inversion)
 };
 
 // host-side launchers (tdh_kernels.hip)
 int num_tiles();
-void tile_shape(int id, int *dims);  // x, y, z edge of tile shape id
+void tile_shape(int id, int *dims);  // x, y, z edges and waves per SIMD of variant id
 hipError_t launch_stage(const StageArgs &a, int tile, int grid, hipStream_t s);
+hipError_t launch_seed(const StageArgs &a, int grid, hipStream_t s);
 hipError_t launch_set_window(double *win, double t, double dt0, hipStream_t s);
 hipError_t launch_commit(const int *order, const int *cnt_ge, int lmin, int *par, hipStream_t s);
 hipError_t launch_reflux(const StageArgs &a, int lc, int dir, int nmax, int grid, hipStream_t s);  // a.k = completing index

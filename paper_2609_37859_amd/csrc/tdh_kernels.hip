@@ -320,8 +320,8 @@ struct TileCtx {
 
 template <int TX, int TY, int TZ, int NV, int D>
 __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, double *sW, double *sF, int *sB,
-                                          int *sJ, const double *qc, const int *cc, const int *lc, double *rhs,
-                                          double &divv, double &emax, int &jcell) {
+                                          const int *sJc, const double *qc, const int *cc, const int *lc,
+                                          double *rhs, double &divv, double &emax) {
   using G = TileGeom<TX, TY, TZ>;
   constexpr int L0 = TX + (D == 0 ? 4 : 0), L1 = TY + (D == 1 ? 4 : 0), L2 = TZ + (D == 2 ? 4 : 0);
   constexpr int NS = L0 * L1 * L2;
@@ -371,9 +371,12 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
     }
     double pl, cl, pr, cr;
     int jl = -1, seedl = -1;
-    if (p.eos_kind == 1 && p.inv_mode == 1 && a.s.enabled) {
-      const double Ue = fmax(wl[4], wl[0] * p.e_floor);
-      seedl = seed_cell_wave(a.s, a.t, log10(wl[0]), log10(Ue / wl[0]));
+    if (p.eos_kind == 1 && p.inv_mode != 0) {
+      // seed the left state from the table cell of the adjacent tile cell's centre
+      int tc[3] = {fc[0], fc[1], fc[2]};
+      if (tc[D] > 0) tc[D] -= 1;
+      if (tc[D] >= (D == 0 ? TX : (D == 1 ? TY : TZ))) tc[D] -= 1;
+      seedl = sJc[tc[0] + TX * (tc[1] + TY * tc[2])];
     }
     eos_pc(p, a.t, wl[0], wl[4], seedl, pl, cl, &jl);
     eos_pc(p, a.t, wr[0], wr[4], p.inv_mode == 0 ? -1 : jl, pr, cr);
@@ -413,7 +416,6 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
 #pragma unroll
     for (int v = 0; v < NV; ++v) sF[v * G::NF + f] = Gf[v];
     sF[6 * G::NF + f] = vf;
-    sJ[f] = jl;
     // block-boundary faces: stage-1 flux, then the time-integrated impulse
     const int bd = fr[D];
     if (bd == 0 || bd == n) {
@@ -422,14 +424,16 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
       const int u1 = D == 2 ? fr[1] : fr[2];
       const long long nn2 = (long long)n * n;
       const long long base = T.B.ioff + (long long)(2 * D + side) * NV * nn2 + (long long)u1 * n + u0;
-      if (a.phase == 1) {
+      // only faces towards a block on another schedule take part in the reflux
+      const int nbo = sB[s0 + (side ? 2 : 1) * STR];  // cell across the block face
+      const int fn = nbo >= 0 ? a.fac[nbo] : T.fb;
+      if (fn == T.fb) {
+      } else if (a.phase == 1) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) a.bf1[base + v * nn2] = Gf[v];
       } else {
-        const int nbo = sB[s0 + (side ? 2 : 1) * STR];  // cell across the block face
-        if (nbo >= 0) {
+        {
           const double area = m.dx[(D + 1) % 3] * m.dx[(D + 2) % 3];
-          const int fn = a.fac[nbo];
           const int fw = T.fb > fn ? T.fb : fn;
           const bool overwrite = (a.k % fw) == 0;
 #pragma unroll
@@ -451,7 +455,6 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
 #pragma unroll
     for (int v = 0; v < NV; ++v) rhs[v] -= (sF[v * G::NF + fhi] - sF[v * G::NF + flo]) * idx;
     divv += (sF[6 * G::NF + fhi] - sF[6 * G::NF + flo]) * idx;
-    if (D == 0) jcell = sJ[flo];
     const int sbase = cc[0] + L0 * (cc[1] + L1 * cc[2]);
     emax = fmax(emax, fmax(sW[6 * G::SLAB + sbase + STR], sW[6 * G::SLAB + sbase + 3 * STR]));
     if (p.grav_kind) {
@@ -468,14 +471,14 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
   __syncthreads();
 }
 
-template <int TX, int TY, int TZ, int NV>
-__global__ __launch_bounds__(kChunk) void stage_tiled(StageArgs a) {
+template <int TX, int TY, int TZ, int NV, int OCC>
+__global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void stage_tiled(StageArgs a) {
   using G = TileGeom<TX, TY, TZ>;
   static_assert(G::TV == kChunk, "one cell per thread");
   __shared__ double sW[7 * G::SLAB];   // primitives (rho, vx, vy, vz, U_EOS, A) + stage-input E
   __shared__ double sF[7 * G::NF];     // fluxes (rho, mx, my, mz, E, A) + face velocity
   __shared__ int sB[G::SLAB];          // owning block of a staged cell, -1 beyond an outflow edge
-  __shared__ int sJ[G::NF];            // table cell of each face's first EOS query
+  __shared__ int sJc[kChunk];          // table cell of each tile cell's centre state (seeds)
   const int tid = threadIdx.x;
   const Phys &p = a.p;
   const MeshDev &m = a.m;
@@ -512,10 +515,16 @@ __global__ __launch_bounds__(kChunk) void stage_tiled(StageArgs a) {
     for (int v = 0; v < NV; ++v) qc[v] = src_val(T.own, T.B.off + v * n3 + cell);
     double rhs[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double divv = 0.0, emax = qc[IEN];
+    // seeded inversion: the table cell of each tile cell's centre state (from
+    // seed_kernel) starts the face and compression queries
     int jcell = -1;
-    tile_axis<TX, TY, TZ, NV, 0>(a, T, sW, sF, sB, sJ, qc, cc, lc, rhs, divv, emax, jcell);
-    tile_axis<TX, TY, TZ, NV, 1>(a, T, sW, sF, sB, sJ, qc, cc, lc, rhs, divv, emax, jcell);
-    tile_axis<TX, TY, TZ, NV, 2>(a, T, sW, sF, sB, sJ, qc, cc, lc, rhs, divv, emax, jcell);
+    if (p.eos_kind == 1 && p.inv_mode != 0) {
+      jcell = a.jc[T.B.off / NV + cell];
+      sJc[tid] = jcell;
+    }
+    tile_axis<TX, TY, TZ, NV, 0>(a, T, sW, sF, sB, sJc, qc, cc, lc, rhs, divv, emax);
+    tile_axis<TX, TY, TZ, NV, 1>(a, T, sW, sF, sB, sJc, qc, cc, lc, rhs, divv, emax);
+    tile_axis<TX, TY, TZ, NV, 2>(a, T, sW, sF, sB, sJc, qc, cc, lc, rhs, divv, emax);
     // combine
     const double *Qbase = a.par[T.b] ? a.Qb : a.Qa;
     double qn[6];
@@ -566,8 +575,46 @@ __global__ __launch_bounds__(kChunk) void stage_tiled(StageArgs a) {
   }
 }
 
-// tile shapes offered to the runtime (x fastest); all divide blocks of edge >= 8
-#define TDH_TILES(X) X(8, 8, 4) X(16, 4, 4) X(4, 8, 8) X(8, 4, 8)
+// Table cell of every active cell's stage-input centre state.  Mode 1 starts
+// the search from the learned network's prediction (its hidden layer on the
+// matrix cores), mode 2 bisects; both end at the same, exact cell, which
+// seeds the stage kernel's face and compression queries.  Blocks hold a
+// multiple of 256 cells, so every wave is full when it calls the network.
+__global__ __launch_bounds__(kChunk) void seed_kernel(StageArgs a) {
+  const int a0 = a.cnt_ge[a.Lhi + 1], a1 = a.cnt_ge[a.Llo];
+  if (a1 <= a0) return;
+  const int i0 = a.item_start[a0], i1 = a.item_start[a1];
+  const Phys &p = a.p;
+  const int nv = a.m.nv;
+  for (int item = i0 + (int)blockIdx.x; item < i1; item += (int)gridDim.x) {
+    int lo = a0, hi = a1;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (a.item_start[mid] <= item) lo = mid; else hi = mid;
+    }
+    const int b = a.order[lo];
+    const BlockInfo B = a.m.blocks[b];
+    const long long n3 = (long long)B.n * B.n * B.n;
+    const long long cell = (long long)(item - a.item_start[lo]) * kChunk + threadIdx.x;
+    const Src own = source_of(a, a.fac[b], b);
+    double q[6], w[6];
+    for (int v = 0; v < nv; ++v) q[v] = src_val(own, B.off + v * n3 + cell);
+    c2p(p, q, w);
+    const double Ue = fmax(w[4], w[0] * p.e_floor);
+    const double lr = log10(w[0]), le = log10(Ue / w[0]);
+    const int seed = (p.inv_mode == 1 && a.s.enabled) ? seed_cell_wave(a.s, a.t, lr, le) : -1;
+    int i, j, it;
+    double wr, wT;
+    table_rho(a.t, lr, i, wr);
+    table_invert(a.t, i, wr, le, seed, p.newton_max_iter, j, wT, it);
+    a.jc[B.off / nv + cell] = j;
+  }
+}
+
+// stage-kernel variants offered to the runtime: tile shape (x fastest; all
+// divide blocks of edge >= 8) and waves per SIMD the register budget targets
+#define TDH_TILES(X) X(8, 8, 4, 2) X(16, 4, 4, 2) X(4, 8, 8, 2) X(8, 4, 8, 2) \
+                     X(8, 8, 4, 3) X(16, 4, 4, 3) X(4, 8, 8, 3) X(8, 4, 8, 3)
 
 __global__ void set_window_kernel(double *win, double t, double dt0) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -762,7 +809,7 @@ __global__ void eos_eval_kernel(Phys p, Table t, const double *rho, const double
 // ---------------------------------------------------------------------------
 int num_tiles() {
   int n = 0;
-#define TDH_COUNT(x, y, z) ++n;
+#define TDH_COUNT(x, y, z, o) ++n;
   TDH_TILES(TDH_COUNT)
 #undef TDH_COUNT
   return n;
@@ -770,24 +817,29 @@ int num_tiles() {
 
 void tile_shape(int id, int *dims) {
   int i = 0;
-#define TDH_SHAPE(x, y, z)                 \
-  if (i++ == id) {                         \
-    dims[0] = x; dims[1] = y; dims[2] = z; \
-    return;                                \
+#define TDH_SHAPE(x, y, z, o)                              \
+  if (i++ == id) {                                         \
+    dims[0] = x; dims[1] = y; dims[2] = z; dims[3] = o;    \
+    return;                                                \
   }
   TDH_TILES(TDH_SHAPE)
 #undef TDH_SHAPE
-  dims[0] = dims[1] = dims[2] = 0;
+  dims[0] = dims[1] = dims[2] = dims[3] = 0;
+}
+
+hipError_t launch_seed(const StageArgs &a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(seed_kernel, dim3(grid), dim3(kChunk), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_stage(const StageArgs &a, int tile, int grid, hipStream_t s) {
   int i = 0;
-#define TDH_LAUNCH(x, y, z)                                                             \
-  if (i++ == tile) {                                                                    \
-    if (a.m.nv == 6)                                                                    \
-      hipLaunchKernelGGL((stage_tiled<x, y, z, 6>), dim3(grid), dim3(kChunk), 0, s, a); \
-    else                                                                                \
-      hipLaunchKernelGGL((stage_tiled<x, y, z, 5>), dim3(grid), dim3(kChunk), 0, s, a); \
+#define TDH_LAUNCH(x, y, z, o)                                                             \
+  if (i++ == tile) {                                                                       \
+    if (a.m.nv == 6)                                                                       \
+      hipLaunchKernelGGL((stage_tiled<x, y, z, 6, o>), dim3(grid), dim3(kChunk), 0, s, a); \
+    else                                                                                   \
+      hipLaunchKernelGGL((stage_tiled<x, y, z, 5, o>), dim3(grid), dim3(kChunk), 0, s, a); \
     return hipGetLastError();                                                           \
   }
   TDH_TILES(TDH_LAUNCH)

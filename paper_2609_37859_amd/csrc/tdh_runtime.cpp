@@ -37,6 +37,7 @@ struct tdh_ctx {
 
   // device memory: state in the caller's arena, metadata owned here
   double *Qa = nullptr, *Qb = nullptr, *Qs = nullptr, *imp = nullptr, *bf1 = nullptr, *phi = nullptr;
+  int *jc = nullptr;  // per-cell table cell of the stage input (seeded inversion)
   BlockInfo *d_blocks = nullptr;
   int *d_lmap = nullptr, *d_fac = nullptr, *d_par = nullptr, *d_order = nullptr, *d_item_start = nullptr;
   int *d_cnt_ge = nullptr, *d_cfl_item_block = nullptr, *d_cfl_block_start = nullptr;
@@ -154,6 +155,7 @@ static size_t arena_need(const tdh_config *cfg, const Layout &L) {
   s += 3 * align256(L.total * sizeof(double));   // Qa, Qb, Qs
   s += 2 * align256(L.itotal * sizeof(double));  // impulses, stage-1 boundary fluxes
   if (cfg->grav_kind == 1) s += align256(L.ptotal * sizeof(double));
+  if (cfg->eos_kind == 1) s += align256(L.ncells * sizeof(int));  // seeded-inversion cells
   return s;
 }
 
@@ -275,6 +277,7 @@ static StageArgs base_args(tdh_ctx *c) {
   a.item_start = c->d_item_start;
   a.cnt_ge = c->d_cnt_ge;
   a.win = c->d_win;
+  a.jc = c->jc;
   return a;
 }
 
@@ -384,6 +387,7 @@ extern "C" tdh_status tdh_init_blocks(tdh_ctx *c, const tdh_mesh *m, void *dev_a
   c->imp = (double *)take(L.itotal * sizeof(double));
   c->bf1 = (double *)take(L.itotal * sizeof(double));
   if (c->cfg.grav_kind == 1) c->phi = (double *)take(L.ptotal * sizeof(double));
+  if (c->cfg.eos_kind == 1) c->jc = (int *)take(L.ncells * sizeof(int));
   // metadata
   tdh_status s;
   if ((s = dev_alloc(c, &c->d_blocks, c->nb)) || (s = dev_alloc(c, &c->d_lmap, c->lmap.size())) ||
@@ -569,6 +573,10 @@ static tdh_status collect_timing(tdh_ctx *c) {
 static tdh_status timed_stage(tdh_ctx *c, const StageArgs &a) {
   const bool t = c->timing && !c->capturing;
   tdh_status s;
+  if (c->cfg.eos_kind == 1 && c->cfg.inv_mode != 0) {
+    HIPCHK(c, launch_seed(a, c->grid, c->stream));
+    c->stats.kernel_launches++;
+  }
   if (t && 2 * (c->ev_used + 1) > c->ev.size())
     if ((s = collect_timing(c))) return s;
   if (t) HIPCHK(c, hipEventRecord(c->ev[2 * c->ev_used], c->stream));
@@ -776,7 +784,7 @@ extern "C" tdh_status tdh_get_stats(tdh_ctx *c, tdh_stats *out) {
 }
 
 static bool tile_fits(const tdh_ctx *c, int id) {
-  int d[3];
+  int d[4];
   tile_shape(id, d);
   return d[0] > 0 && c->lat % d[0] == 0 && c->lat % d[1] == 0 && c->lat % d[2] == 0;
 }
@@ -785,7 +793,9 @@ extern "C" int tdh_num_tiles(void) { return num_tiles(); }
 
 extern "C" tdh_status tdh_tile_shape(int id, int *dims) {
   if (!dims || id < 0 || id >= num_tiles()) return fail(nullptr, TDH_EINVAL, "tile id out of range");
-  tile_shape(id, dims);
+  int d[4];
+  tile_shape(id, d);
+  for (int i = 0; i < 4; ++i) dims[i] = d[i];
   return TDH_OK;
 }
 

@@ -335,7 +335,7 @@ def tile_shapes():
     L = lib()
     out = []
     for t in range(L.tdh_num_tiles()):
-        d = (C.c_int * 3)()
+        d = (C.c_int * 4)()
         L.tdh_tile_shape(t, d)
         out.append(tuple(d))
     return out

@@ -507,3 +507,52 @@ def mlp_init_params(seed: int) -> np.ndarray:
     p[192:4288] = rng.normal(0.0, math.sqrt(2.0 / 64.0), 4096)
     p[4352:4416] = rng.normal(0.0, math.sqrt(1.0 / 64.0), 64)
     return p.astype(np.float32)
+
+
+def debris_stream_c5(table: EosTable, regions=(13, 17, 9), rn=32, n_split=301, dxr=0.25, vfr=1e8, dv=3e7,
+                     rho_pk=1e-3, T=1e4, stream_frac=0.3, sig_cells=8.0):
+    """Production-shaped run: 13 x 17 x 9 regions of 32^3 cells at dx = 0.25 Rsun;
+    the 301 regions nearest the stream axis and the black-hole path are split
+    into eight 16^3 blocks (1688 x 32^3 + 2408 x 16^3 = 4096 blocks, 65.2 M
+    cells).  A tidally stretched n = 1.5 stream (ellipsoid with semi-axes
+    0.3 L_x, 8 dx, 8 dx; rho = rho_pk theta^1.5, T = 1e4 K) with a linear
+    velocity spread v_x = dV (x - x_c) / (0.3 L_x) lies in a 1e-10 rho_pk
+    background at rest; a 1e3 Msun point mass starts 20 Rsun from the stream
+    centre and moves at -V_fr along x (uniform frame velocity V_fr); excision
+    radius 4 dx, softening 0.1 dx; outflow boundaries."""
+    dx = dxr * R_SUN
+    rx, ry, rz = regions
+    L = np.array([rx, ry, rz]) * rn * dx
+    c = 0.5 * L
+    bh0 = np.array([c[0], c[1] + 20.0 * R_SUN, c[2]])
+    # split the regions whose centres are nearest the stream axis or the BH path
+    cz, cy, cx = np.meshgrid(np.arange(rz), np.arange(ry), np.arange(rx), indexing="ij")
+    pc = np.stack([(cx + 0.5) * rn * dx, (cy + 0.5) * rn * dx, (cz + 0.5) * rn * dx], -1)
+    d_axis = np.hypot(pc[..., 1] - c[1], pc[..., 2] - c[2]) + np.maximum(np.abs(pc[..., 0] - c[0]) - stream_frac * L[0], 0)
+    d_bh = np.hypot(pc[..., 1] - bh0[1], pc[..., 2] - bh0[2])
+    score = np.minimum(d_axis, d_bh) + 1e-6 * (cx + rx * (cy + ry * cz))  # deterministic ties
+    order = np.argsort(score.ravel(), kind="stable")
+    split = np.zeros(rx * ry * rz, dtype=bool)
+    split[order[:n_split]] = True
+    mesh = mixed_mesh(regions, rn, split.reshape(rz, ry, rx), dx, bc=(1, 1, 1))
+    cfg = Config(eos_kind=1, dual=1, grav_kind=2, n_lat=3, cfl=0.3, eta1=1e-3, eta2=1e-4,
+                 rho_floor=1e-10 * rho_pk * 0.5, p_floor=0.0, e_floor=table.e_floor, merge_frac=0.0,
+                 gm_bh=G_NEWTON * 1e3 * M_SUN, r_soft=0.1 * dx, r_exc=4.0 * dx, bh_x0=tuple(bh0),
+                 v_frame=(vfr, 0.0, 0.0))
+    # specific energy at T on a fine log-density grid (data for the initial state)
+    lg = np.linspace(math.log10(cfg.rho_floor) - 0.1, math.log10(rho_pk) + 0.1, 4096)
+    _, eg = saha_pe(10.0 ** lg, T)
+    a_s = stream_frac * L[0]
+    sig = sig_cells * dx
+
+    def fn(x, y, z):
+        q = ((x - c[0]) / a_s) ** 2 + ((y - c[1]) / sig) ** 2 + ((z - c[2]) / sig) ** 2
+        theta = np.clip(1.0 - q, 0.0, 1.0)
+        rho = np.maximum(rho_pk * theta ** 1.5, 1e-10 * rho_pk)
+        e = 10.0 ** np.interp(np.log10(rho), lg, np.log10(eg))
+        U = rho * e
+        inside = theta > 0
+        vx = np.where(inside, dv * (x - c[0]) / a_s, 0.0)
+        return [rho, rho * vx, 0 * x, 0 * x, U + 0.5 * rho * vx * vx, U]
+
+    return cfg, mesh, pack_state(mesh, cfg.nv, fn)

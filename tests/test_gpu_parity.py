@@ -239,3 +239,42 @@ def test_bench_workload_parity_sampled(tdh, orc, saha):
     ctx.close()
     o, _ = orc.run_sync(cfg, mesh, U, 3, table=saha, dts=dts)
     assert np.all(rel_err(6, mesh, g, o) <= TOL)
+
+
+def test_c3_full_size_lat_window(tdh, orc):
+    """C3 at its full size (256^3 as 512 x 32^3, fixed polytrope potential, N_LAT
+    = 3): the library's levels equal the oracle's assignment on the library's
+    dt_b bit for bit, and one LAT window (batched, graph-captured) equals the
+    oracle's window to 1e-11 with the same block-update count."""
+    cfg, mesh, U, phi, info = W.polytrope_c3()
+    ctx = tdh.Context(cfg, mesh, U, phi=phi)
+    dtb, dt0, lev, L = ctx.reduce_dt()
+    lev_o, L_o, dt0_o = orc.lat_assign(cfg, mesh, dtb)
+    assert np.array_equal(lev, lev_o) and L == L_o and dt0 == dt0_o
+    ctx.run_window(dt0 * 2 ** L, batched=True, graph=True)
+    g = ctx.get_state()
+    st = ctx.stats()
+    ctx.close()
+    o, nupd = orc.lat_window(cfg, mesh, U, lev, dt0, phi=phi)
+    assert st["block_updates"] == nupd
+    err = rel_err(5, mesh, g, o)
+    print("C3 full-size LAT window rel err", err, "updates", nupd, "levels", np.bincount(lev))
+    assert np.all(err <= TOL)
+
+
+def test_c5_shaped_subdomain_lat_window(tdh, orc, saha):
+    """C5-shaped run on a reduced region grid: mixed 16^3/32^3 blocks, Saha
+    table, dual energy, moving point mass with excision, LAT levels from the
+    library's CFL; one window against the oracle."""
+    cfg, mesh, U = W.debris_stream_c5(saha, regions=(4, 3, 2), n_split=6, dxr=1.0)
+    ctx = tdh.Context(cfg, mesh, U, table=saha, inv_mode=2)
+    dtb, dt0, lev, L = ctx.reduce_dt()
+    lev_o, L_o, _ = orc.lat_assign(cfg, mesh, dtb)
+    assert np.array_equal(lev, lev_o)
+    ctx.run_window(dt0 * 2 ** L, batched=True)
+    g = ctx.get_state()
+    ctx.close()
+    o, _ = orc.lat_window(cfg, mesh, U, lev, dt0, table=saha)
+    err = rel_err(6, mesh, g, o)
+    print("C5-shaped window rel err", err, "levels", np.bincount(lev))
+    assert np.all(err <= TOL)
