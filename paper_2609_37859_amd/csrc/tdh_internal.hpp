@@ -37,10 +37,14 @@ struct Phys {
   double bh_x0[3], v_frame[3];
 };
 
+// Tabulated EOS on (log10 rho, log10 T) nodes, packed by density-row pairs:
+// le2[i][j] = (log e[i][j], log e[i+1][j]);
+// pc[i][j] = (log P[i][j], log P[i+1][j], log cs2[i][j], log cs2[i+1][j]).
 struct Table {
   int nrho, nT;
   double lr0, dlr, inv_dlr, lT0, dlT;
-  const double *lP, *le, *lc2;
+  const double2 *le2;
+  const double4 *pc;
 };
 
 constexpr int kMlpParams = 4417;  // W1[64][2], b1[64], W2[64][64], b2[64], W3[64], b3

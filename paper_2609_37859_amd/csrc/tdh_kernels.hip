@@ -92,8 +92,10 @@ __device__ __forceinline__ void table_rho(const Table &t, double lr, int &i, dou
   w = x - ii;
 }
 
-__device__ __forceinline__ double tcol(const double *F, int nT, int i, double w, int j) {
-  return (1.0 - w) * F[i * nT + j] + w * F[(i + 1) * nT + j];
+// log e of column j interpolated between density rows i and i+1 (one 16-byte load)
+__device__ __forceinline__ double tcol_le(const Table &t, int i, double w, int j) {
+  const double2 v = t.le2[i * t.nT + j];
+  return (1.0 - w) * v.x + w * v.y;
 }
 
 // Table cell of a target log e on the density-interpolated column: the largest
@@ -104,7 +106,7 @@ __device__ __forceinline__ double tcol(const double *F, int nT, int i, double w,
 __device__ __forceinline__ void table_invert(const Table &t, int i, double w, double le, int seed, int maxit,
                                              int &jout, double &wT, int &iters) {
   const int nT = t.nT;
-  const double lo_v = tcol(t.le, nT, i, w, 0), hi_v = tcol(t.le, nT, i, w, nT - 1);
+  const double lo_v = tcol_le(t, i, w, 0), hi_v = tcol_le(t, i, w, nT - 1);
   le = fmin(fmax(le, lo_v), hi_v);
   int j = -1;
   double a = 0.0, b = 1.0;
@@ -112,8 +114,8 @@ __device__ __forceinline__ void table_invert(const Table &t, int i, double w, do
   if (seed >= 0) {
     int jj = min(max(seed, 0), nT - 2);
     for (int it = 0; it <= maxit; ++it) {
-      a = tcol(t.le, nT, i, w, jj);
-      b = tcol(t.le, nT, i, w, jj + 1);
+      a = tcol_le(t, i, w, jj);
+      b = tcol_le(t, i, w, jj + 1);
       if (a <= le && (le < b || jj == nT - 2)) { j = jj; iters = it; break; }
       if (it == maxit) break;
       double s = floor((le - a) / (b - a));
@@ -123,20 +125,28 @@ __device__ __forceinline__ void table_invert(const Table &t, int i, double w, do
   }
   if (j < 0) {
     int lo = 0, hi = nT - 1;
+    double vlo = lo_v, vhi = hi_v;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
-      if (tcol(t.le, nT, i, w, mid) <= le) lo = mid; else hi = mid;
+      const double vm = tcol_le(t, i, w, mid);
+      if (vm <= le) { lo = mid; vlo = vm; } else { hi = mid; vhi = vm; }
     }
     j = lo;
-    a = tcol(t.le, nT, i, w, j);
-    b = tcol(t.le, nT, i, w, j + 1);
+    a = vlo;
+    b = hi == lo + 1 ? vhi : tcol_le(t, i, w, j + 1);
   }
   jout = j;
   wT = (le - a) / (b - a);
 }
 
-__device__ __forceinline__ double tbil(const double *F, int nT, int i, double w, int j, double wT) {
-  return (1.0 - wT) * tcol(F, nT, i, w, j) + wT * tcol(F, nT, i, w, j + 1);
+// log P and log c_s^2 at (w, wT) in cell (i, j): two 32-byte loads, each
+// holding both density rows of both fields at one T node
+__device__ __forceinline__ void tbil_pc(const Table &t, int i, double w, int j, double wT, double &lP, double &lc2) {
+  const double4 v0 = t.pc[i * t.nT + j], v1 = t.pc[i * t.nT + j + 1];
+  const double p0 = (1.0 - w) * v0.x + w * v0.y, p1 = (1.0 - w) * v1.x + w * v1.y;
+  const double c0 = (1.0 - w) * v0.z + w * v0.w, c1 = (1.0 - w) * v1.z + w * v1.w;
+  lP = (1.0 - wT) * p0 + wT * p1;
+  lc2 = (1.0 - wT) * c0 + wT * c1;
 }
 
 // Table cell seed from the learned network for this lane's (log rho, log e);
@@ -164,8 +174,10 @@ __device__ __forceinline__ void eos_pc(const Phys &p, const Table &t, double rho
   double w, wT;
   table_rho(t, log10(rho), i, w);
   table_invert(t, i, w, log10(Ue / rho), jseed, p.newton_max_iter, j, wT, it);
-  P = exp10(tbil(t.lP, t.nT, i, w, j, wT));
-  cs = exp10(0.5 * tbil(t.lc2, t.nT, i, w, j, wT));
+  double lP, lc2;
+  tbil_pc(t, i, w, j, wT, lP, lc2);
+  P = exp10(lP);
+  cs = exp10(0.5 * lc2);
   if (jout) *jout = j;
 }
 
@@ -772,7 +784,7 @@ __global__ __launch_bounds__(256) void eos_invert_kernel(Table t, Seed s, int ma
   for (long long wv = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / 64; wv < nw; wv += wstride) {
     const long long q = wv * 64 + l;  // the loop is uniform across the wave
     const bool ok = q < n;
-    const double qlr = ok ? lr[q] : t.lr0, qle = ok ? le[q] : t.le[0];
+    const double qlr = ok ? lr[q] : t.lr0, qle = ok ? le[q] : t.le2[0].x;
     int i, j, it;
     double w, wT;
     table_rho(t, qlr, i, w);

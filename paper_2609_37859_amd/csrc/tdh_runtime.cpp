@@ -436,14 +436,27 @@ extern "C" tdh_status tdh_set_eos_table(tdh_ctx *c, int nrho, int nT, double lr0
     for (int j = 0; j + 1 < nT; ++j)
       if (!(le[(size_t)i * nT + j + 1] > le[(size_t)i * nT + j]))
         return fail(c, TDH_EINVAL, "log e is not increasing in T on row %d", i);
-  const size_t sz = (size_t)nrho * nT;
-  if (!c->d_table || c->tab.nrho * c->tab.nT != (int)sz) {
-    tdh_status s = dev_alloc(c, &c->d_table, 3 * sz);
+  // pack by density-row pairs (see Table in tdh_internal.hpp)
+  const size_t np = (size_t)(nrho - 1) * nT;
+  const size_t pc_off = (2 * np + 3) & ~(size_t)3;  // 32-byte alignment of the double4 records
+  std::vector<double> packed(pc_off + 4 * np);
+  for (int i = 0; i + 1 < nrho; ++i)
+    for (int j = 0; j < nT; ++j) {
+      const size_t a = (size_t)i * nT + j, b = (size_t)(i + 1) * nT + j, q = (size_t)i * nT + j;
+      packed[2 * q] = le[a];
+      packed[2 * q + 1] = le[b];
+      double *pcq = packed.data() + pc_off + 4 * q;
+      pcq[0] = lP[a];
+      pcq[1] = lP[b];
+      pcq[2] = lc2[a];
+      pcq[3] = lc2[b];
+    }
+  if (!c->d_table || c->tab.nrho != nrho || c->tab.nT != nT) {
+    tdh_status s = dev_alloc(c, &c->d_table, pc_off + 4 * np);
     if (s) return s;
   }
-  HIPCHK(c, hipMemcpyAsync(c->d_table, lP, sz * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->d_table + sz, le, sz * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->d_table + 2 * sz, lc2, sz * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_table, packed.data(), packed.size() * sizeof(double), hipMemcpyHostToDevice,
+                           c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->tab.nrho = nrho;
   c->tab.nT = nT;
@@ -452,9 +465,8 @@ extern "C" tdh_status tdh_set_eos_table(tdh_ctx *c, int nrho, int nT, double lr0
   c->tab.inv_dlr = 1.0 / dlr;
   c->tab.lT0 = lT0;
   c->tab.dlT = dlT;
-  c->tab.lP = c->d_table;
-  c->tab.le = c->d_table + sz;
-  c->tab.lc2 = c->d_table + 2 * sz;
+  c->tab.le2 = (const double2 *)c->d_table;
+  c->tab.pc = (const double4 *)(c->d_table + pc_off);
   c->have_table = true;
   for (auto &g : c->graphs) hipGraphExecDestroy(g.second);
   c->graphs.clear();

@@ -167,6 +167,21 @@ class Context:
         self._check(self.L.tdh_init_blocks(self.ctx, C.byref(self._mesh), C.c_void_p(self._arena_ptr), nbytes,
                                            _dp(st), None if ph is None else _dp(ph)), "tdh_init_blocks")
 
+    def _enter(self, *tensors):
+        """Order the library stream after torch's current stream (inputs ready)
+        and keep the tensors alive for the library stream."""
+        cur = self.torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        for t in tensors:
+            t.record_stream(self.stream)
+
+    def _dev64(self, t):
+        return t.to(self.device, self.torch.float64).contiguous()
+
+    def _leave(self):
+        """Order torch's current stream after the library stream (outputs ready)."""
+        self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
     def _check(self, rc, what, ctx=True):
         if rc != 0:
             msg = self.L.tdh_last_error(self.ctx if ctx else None)
@@ -224,8 +239,10 @@ class Context:
         lT = torch.empty(n, dtype=torch.float64, device=self.device)
         j = torch.empty(n, dtype=torch.int32, device=self.device)
         it = torch.empty(n, dtype=torch.int32, device=self.device)
+        self._enter(lr, le, lT, j, it)
         self._check(self.L.tdh_eos_invert_batch(self.ctx, lr.data_ptr(), le.data_ptr(), lT.data_ptr(), j.data_ptr(),
                                                 it.data_ptr(), n, int(mode)), "tdh_eos_invert_batch")
+        self._leave()
         return lT, j, it
 
     def eos_eval(self, rho, U):
@@ -234,8 +251,10 @@ class Context:
         U = U.to(self.device, torch.float64).contiguous()
         P = torch.empty_like(rho)
         cs = torch.empty_like(rho)
+        self._enter(rho, U, P, cs)
         self._check(self.L.tdh_eos_eval_batch(self.ctx, rho.data_ptr(), U.data_ptr(), P.data_ptr(), cs.data_ptr(),
                                               rho.numel()), "tdh_eos_eval_batch")
+        self._leave()
         return P, cs
 
     def set_tile(self, tile_id):
@@ -271,23 +290,30 @@ class Context:
 
     def mlp_train(self, x, lT, steps, batch=4096, lr=1e-3, seed=1):
         """x: device float64 [n, 2] (log10 rho, log10 e); lT: device float64 [n]."""
+        x, lT = self._dev64(x), self._dev64(lT)
         loss = np.zeros(steps, dtype=np.float32)
+        self._enter(x, lT)
         self._check(self.L.tdh_mlp_train(self.ctx, x.data_ptr(), lT.data_ptr(), x.shape[0], int(steps), int(batch),
                                          float(lr), int(seed), loss.ctypes.data_as(C.POINTER(C.c_float))),
                     "tdh_mlp_train")
         return loss
 
     def mlp_loss_grad(self, x, lT):
+        x, lT = self._dev64(x), self._dev64(lT)
         g = np.zeros(4417, dtype=np.float32)
         loss = C.c_float()
+        self._enter(x, lT)
         self._check(self.L.tdh_mlp_loss_grad(self.ctx, x.data_ptr(), lT.data_ptr(), x.shape[0], C.byref(loss),
                                              g.ctypes.data_as(C.POINTER(C.c_float))), "tdh_mlp_loss_grad")
         return loss.value, g
 
     def mlp_forward(self, x):
         torch = self.torch
+        x = self._dev64(x)
         out = torch.empty(x.shape[0], dtype=torch.float64, device=self.device)
+        self._enter(x, out)
         self._check(self.L.tdh_mlp_forward(self.ctx, x.data_ptr(), out.data_ptr(), x.shape[0]), "tdh_mlp_forward")
+        self._leave()
         return out
 
     def mlp_params(self):
