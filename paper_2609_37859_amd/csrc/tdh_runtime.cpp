@@ -43,6 +43,7 @@ struct tdh_ctx {
   int *d_cnt_ge = nullptr, *d_cfl_item_block = nullptr, *d_cfl_block_start = nullptr;
   double *d_cfl_part = nullptr, *d_dtb = nullptr, *d_win = nullptr;
   int cfl_nitems = 0;
+  double *h_dtb = nullptr;  // pinned host copy of the per-block steps
   std::vector<void *> owned;
 
   // EOS table
@@ -197,6 +198,7 @@ extern "C" tdh_status tdh_init(const tdh_config *cfg, void *hip_stream, tdh_ctx 
 extern "C" void tdh_destroy(tdh_ctx *c) {
   if (!c) return;
   for (hipEvent_t e : c->ev) hipEventDestroy(e);
+  if (c->h_dtb) hipHostFree(c->h_dtb);
   for (auto &g : c->graphs) hipGraphExecDestroy(g.second);
   for (void *p : c->owned) hipFree(p);
   delete c;
@@ -310,6 +312,10 @@ static bool tile_fits(const tdh_ctx *c, int id);
 
 // device copies of the level-dependent tables; starts a new window
 static tdh_status install_levels(tdh_ctx *c, const std::vector<int> &lev) {
+  if (c->have_mesh && lev == c->levels) {  // same assignment: the device tables are current
+    c->k = 0;
+    return TDH_OK;
+  }
   c->levels = lev;
   c->Lmax = 0;
   for (int l : lev) c->Lmax = std::max(c->Lmax, l);
@@ -418,6 +424,7 @@ extern "C" tdh_status tdh_init_blocks(tdh_ctx *c, const tdh_mesh *m, void *dev_a
   HIPCHK(c, hipMemcpyAsync(c->Qa, host_state, L.total * sizeof(double), hipMemcpyHostToDevice, c->stream));
   if (c->phi) HIPCHK(c, hipMemcpyAsync(c->phi, host_phi, L.ptotal * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipHostMalloc((void **)&c->h_dtb, c->nb * sizeof(double), hipHostMallocDefault));
   build_adjacency(c);
   if (c->lat < 8) return fail(c, TDH_EINVAL, "blocks must have an edge of at least 8 cells");
   c->tile = 0;
@@ -527,9 +534,9 @@ extern "C" tdh_status tdh_reduce_dt(tdh_ctx *c, double *host_dtb, double *host_d
   HIPCHK(c, launch_cfl(a, c->cfg.cfl, c->t, c->d_cfl_item_block, c->cfl_nitems, c->d_cfl_part, c->nb,
                        c->d_cfl_block_start, c->d_dtb, c->stream));
   c->stats.kernel_launches += 2;
-  std::vector<double> dtb(c->nb);
-  HIPCHK(c, hipMemcpyAsync(dtb.data(), c->d_dtb, c->nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->h_dtb, c->d_dtb, c->nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::vector<double> dtb(c->h_dtb, c->h_dtb + c->nb);
   double dt0;
   std::vector<int> lev = c->cfg.n_lat > 0 ? assign_levels(c, dtb, dt0) : std::vector<int>(c->nb, 0);
   if (c->cfg.n_lat == 0) {
