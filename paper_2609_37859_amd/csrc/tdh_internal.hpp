@@ -24,7 +24,7 @@ struct MeshDev {
   int nx, ny, nz;
   int bc[3];
   double x0[3], dx[3], inv_dx[3];
-  int lat, lx, ly, lz;
+  int lat, lat_shift, lx, ly, lz;  // lattice edge (a power of two) and its log2
   int nv;
   const int *lmap;          // lattice cell -> block
   const BlockInfo *blocks;
@@ -37,7 +37,8 @@ struct Phys {
   double bh_x0[3], v_frame[3];
 };
 
-// Tabulated EOS on (log10 rho, log10 T) nodes, packed by density-row pairs:
+// Tabulated EOS on (log2 rho, log2 T) nodes (converted from log10 at upload; the
+// interpolation weights do not depend on the base), packed by density-row pairs:
 // le2[i][j] = (log e[i][j], log e[i+1][j]);
 // pc[i][j] = (log P[i][j], log P[i+1][j], log cs2[i][j], log cs2[i+1][j]).
 struct Table {
