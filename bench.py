@@ -20,7 +20,6 @@ FP64 oracle on the host, on a bounded number of steps of the same workload,
 and its final state doubles as the accuracy check of the GPU run.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -35,19 +34,13 @@ HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("tdh_kernels.hip", "tdh_internal.hpp"):
-        h.update(open(os.path.join(ROOT, "paper_2609_37859_amd", "csrc", f), "rb").read())
-    return h.hexdigest()[:16]
-
-
 def traffic_from_profiles(workload):
     """HBM bytes per stage launch from the committed counter summary, if it
     was taken on the current kernel source; else None."""
     path = os.path.join(PROFILES, f"stage_traffic_{workload}.json")
     if not os.path.exists(path):
         return None
+    from paper_2609_37859_amd.profile_summary import kernel_source_hash
     d = json.load(open(path))
     if d.get("kernel_hash") != kernel_source_hash():
         return None

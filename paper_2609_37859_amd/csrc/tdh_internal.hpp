@@ -37,8 +37,7 @@ struct Phys {
   double bh_x0[3], v_frame[3];
 };
 
-// Tabulated EOS on (log2 rho, log2 T) nodes (converted from log10 at upload; the
-// interpolation weights do not depend on the base), packed by density-row pairs:
+// Tabulated EOS on (log10 rho, log10 T) nodes, packed by density-row pairs:
 // le2[i][j] = (log e[i][j], log e[i+1][j]);
 // pc[i][j] = (log P[i][j], log P[i+1][j], log cs2[i][j], log cs2[i+1][j]).
 struct Table {

@@ -151,14 +151,9 @@ __device__ __forceinline__ void tbil_pc(const Table &t, int i, double w, int j, 
 
 // Table cell seed from the learned network for this lane's (log rho, log e);
 // every lane of the wave must call it (the hidden layer runs on the matrix cores).
-// The table works in log2 units; the network in log10 units.
-constexpr double kLog10of2 = 0.30102999566398119521373889472449302676818988;
-constexpr double kLog2of10 = 3.32192809488736234787031942948939017586483139;
-
-__device__ __forceinline__ int seed_cell_wave(const Seed &s, const Table &t, double lr2, double le2) {
-  const float y = mlp_wave_forward(s.w, norm01(lr2 * kLog10of2, s.lr_lo, s.lr_hi),
-                                   norm01(le2 * kLog10of2, s.le_lo, s.le_hi));
-  const double lT = (s.lt_lo + 0.5 * ((double)y + 1.0) * (s.lt_hi - s.lt_lo)) * kLog2of10;
+__device__ __forceinline__ int seed_cell_wave(const Seed &s, const Table &t, double lr, double le) {
+  const float y = mlp_wave_forward(s.w, norm01(lr, s.lr_lo, s.lr_hi), norm01(le, s.le_lo, s.le_hi));
+  const double lT = s.lt_lo + 0.5 * ((double)y + 1.0) * (s.lt_hi - s.lt_lo);
   const double x = (lT - t.lT0) / t.dlT;
   if (!(x > 0.0)) return 0;
   if (x > (double)(t.nT - 2)) return t.nT - 2;
@@ -177,12 +172,12 @@ __device__ __forceinline__ void eos_pc(const Phys &p, const Table &t, double rho
   const double Ue = fmax(U, rho * p.e_floor);
   int i, j, it;
   double w, wT;
-  table_rho(t, log2(rho), i, w);
-  table_invert(t, i, w, log2(Ue / rho), jseed, p.newton_max_iter, j, wT, it);
+  table_rho(t, log10(rho), i, w);
+  table_invert(t, i, w, log10(Ue / rho), jseed, p.newton_max_iter, j, wT, it);
   double lP, lc2;
   tbil_pc(t, i, w, j, wT, lP, lc2);
-  P = exp2(lP);
-  cs = exp2(0.5 * lc2);
+  P = exp10(lP);
+  cs = exp10(0.5 * lc2);
   if (jout) *jout = j;
 }
 
@@ -324,8 +319,6 @@ struct TileGeom {
   static constexpr int SLAB = S0 > S1 ? (S0 > S2 ? S0 : S2) : (S1 > S2 ? S1 : S2);
   static constexpr int F0 = (TX + 1) * TY * TZ, F1 = TX * (TY + 1) * TZ, F2 = TX * TY * (TZ + 1);
   static constexpr int NF = F0 > F1 ? (F0 > F2 ? F0 : F2) : (F1 > F2 ? F1 : F2);
-  // threads: enough whole waves that every axis's faces take one round
-  static constexpr int NTH = ((NF + 63) / 64) * 64;
 };
 
 struct TileCtx {
@@ -338,8 +331,7 @@ struct TileCtx {
 };
 
 template <int TX, int TY, int TZ, int NV, int D>
-__device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, double *sW, double *sD, double *sF,
-                                          int *sB,
+__device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, double *sW, double *sF, int *sB,
                                           const int *sJc, const double *qc, const int *cc, const int *lc,
                                           double *rhs, double &divv, double &emax) {
   using G = TileGeom<TX, TY, TZ>;
@@ -356,7 +348,7 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
   const int n = T.B.n;
   const int Nd = D == 0 ? m.nx : (D == 1 ? m.ny : m.nz);
   // stage the slab: tile extended by two cells along D
-  for (int s = tid; s < NS; s += G::NTH) {
+  for (int s = tid; s < NS; s += kChunk) {
     int sc[3] = {s % L0, (s / L0) % L1, s / (L0 * L1)};
     sc[D] -= 2;
     const int g[3] = {T.B.ox + T.to[0] + sc[0], T.B.oy + T.to[1] + sc[1], T.B.oz + T.to[2] + sc[2]};
@@ -371,19 +363,8 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
     sB[s] = (m.bc[D] == 0 || (g[D] >= 0 && g[D] < Nd)) ? nb_ : -1;
   }
   __syncthreads();
-  // van Leer slopes of the staged cells that have both neighbours along D, once per cell
-  for (int s = tid; s < NS; s += G::NTH) {
-    const int sd = D == 0 ? s % L0 : (D == 1 ? (s / L0) % L1 : s / (L0 * L1));
-    if (sd == 0 || sd == (D == 0 ? L0 : (D == 1 ? L1 : L2)) - 1) continue;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const double q0 = sW[v * G::SLAB + s - STR], q1 = sW[v * G::SLAB + s], q2 = sW[v * G::SLAB + s + STR];
-      sD[v * G::SLAB + s] = vanleer(q1 - q0, q2 - q1);
-    }
-  }
-  __syncthreads();
   // every face of the tile along D, once
-  for (int f0 = 0; f0 < NFD; f0 += G::NTH) {
+  for (int f0 = 0; f0 < NFD; f0 += kChunk) {
     if (f0 + (tid & ~63) >= NFD) continue;  // the whole wave is idle this round
     // lanes past the end repeat the last face so the wave stays converged for
     // the network seed; they store nothing
@@ -395,9 +376,10 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
     constexpr int perm[6] = {0, PN, P1, P2, 4, 5};
 #pragma unroll
     for (int vv = 0; vv < NV; ++vv) {
-      const int o = perm[vv] * G::SLAB + s0;
-      wl[vv] = sW[o + STR] + 0.5 * sD[o + STR];
-      wr[vv] = sW[o + 2 * STR] - 0.5 * sD[o + 2 * STR];
+      const double *col = sW + perm[vv] * G::SLAB + s0;
+      const double q0 = col[0], q1 = col[STR], q2 = col[2 * STR], q3 = col[3 * STR];
+      wl[vv] = q1 + 0.5 * vanleer(q1 - q0, q2 - q1);
+      wr[vv] = q2 - 0.5 * vanleer(q2 - q1, q3 - q2);
     }
     double pl, cl, pr, cr;
     int jl = -1, seedl = -1;
@@ -478,7 +460,7 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
   }
   __syncthreads();
   // own cell: divergence, gravity, neighbour energies
-  if (tid < G::TV) {
+  {
     const int flo = cc[0] + F0 * (cc[1] + F1 * cc[2]);
     const int fhi = flo + FSTR;
     const double idx = m.inv_dx[D];
@@ -502,12 +484,10 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
 }
 
 template <int TX, int TY, int TZ, int NV, int OCC>
-__global__ __launch_bounds__((TileGeom<TX, TY, TZ>::NTH)) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
-void stage_tiled(StageArgs a) {
+__global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void stage_tiled(StageArgs a) {
   using G = TileGeom<TX, TY, TZ>;
   static_assert(G::TV == kChunk, "one cell per thread");
   __shared__ double sW[7 * G::SLAB];   // primitives (rho, vx, vy, vz, U_EOS, A) + stage-input E
-  __shared__ double sD[NV * G::SLAB];  // limited slopes of the primitives
   __shared__ double sF[7 * G::NF];     // fluxes (rho, mx, my, mz, E, A) + face velocity
   __shared__ int sB[G::SLAB];          // owning block of a staged cell, -1 beyond an outflow edge
   __shared__ int sJc[kChunk];          // table cell of each tile cell's centre state (seeds)
@@ -539,10 +519,7 @@ void stage_tiled(StageArgs a) {
     T.dtb = T.fb * dt0;
     T.t = a.phase == 1 ? tk : tk + T.dtb;
     T.own = source_of(a, T.fb, T.b);
-    // threads past the tile's cells only stage cells and compute faces
-    const bool has_cell = tid < G::TV;
-    const int tc = has_cell ? tid : 0;
-    const int cc[3] = {tc % TX, (tc / TX) % TY, tc / (TX * TY)};
+    const int cc[3] = {tid % TX, (tid / TX) % TY, tid / (TX * TY)};
     const int lc[3] = {T.to[0] + cc[0], T.to[1] + cc[1], T.to[2] + cc[2]};
     const long long cell = ((long long)lc[2] * n + lc[1]) * n + lc[0];
     double qc[6];
@@ -555,12 +532,11 @@ void stage_tiled(StageArgs a) {
     int jcell = -1;
     if (p.eos_kind == 1 && p.inv_mode != 0) {
       jcell = a.jc[T.B.off / NV + cell];
-      if (has_cell) sJc[tid] = jcell;
+      sJc[tid] = jcell;
     }
-    tile_axis<TX, TY, TZ, NV, 0>(a, T, sW, sD, sF, sB, sJc, qc, cc, lc, rhs, divv, emax);
-    tile_axis<TX, TY, TZ, NV, 1>(a, T, sW, sD, sF, sB, sJc, qc, cc, lc, rhs, divv, emax);
-    tile_axis<TX, TY, TZ, NV, 2>(a, T, sW, sD, sF, sB, sJc, qc, cc, lc, rhs, divv, emax);
-    if (!has_cell) continue;  // no barrier below: the extra threads go on to the next item
+    tile_axis<TX, TY, TZ, NV, 0>(a, T, sW, sF, sB, sJc, qc, cc, lc, rhs, divv, emax);
+    tile_axis<TX, TY, TZ, NV, 1>(a, T, sW, sF, sB, sJc, qc, cc, lc, rhs, divv, emax);
+    tile_axis<TX, TY, TZ, NV, 2>(a, T, sW, sF, sB, sJc, qc, cc, lc, rhs, divv, emax);
     // combine
     const double *Qbase = a.par[T.b] ? a.Qb : a.Qa;
     double qn[6];
@@ -637,7 +613,7 @@ __global__ __launch_bounds__(kChunk) void seed_kernel(StageArgs a) {
     for (int v = 0; v < nv; ++v) q[v] = src_val(own, B.off + v * n3 + cell);
     c2p(p, q, w);
     const double Ue = fmax(w[4], w[0] * p.e_floor);
-    const double lr = log2(w[0]), le = log2(Ue / w[0]);
+    const double lr = log10(w[0]), le = log10(Ue / w[0]);
     const int seed = (p.inv_mode == 1 && a.s.enabled) ? seed_cell_wave(a.s, a.t, lr, le) : -1;
     int i, j, it;
     double wr, wT;
@@ -808,8 +784,7 @@ __global__ __launch_bounds__(256) void eos_invert_kernel(Table t, Seed s, int ma
   for (long long wv = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / 64; wv < nw; wv += wstride) {
     const long long q = wv * 64 + l;  // the loop is uniform across the wave
     const bool ok = q < n;
-    // queries arrive in log10 units; the table works in log2 units
-    const double qlr = ok ? lr[q] * kLog2of10 : t.lr0, qle = ok ? le[q] * kLog2of10 : t.le2[0].x;
+    const double qlr = ok ? lr[q] : t.lr0, qle = ok ? le[q] : t.le2[0].x;
     int i, j, it;
     double w, wT;
     table_rho(t, qlr, i, w);
@@ -824,7 +799,7 @@ __global__ __launch_bounds__(256) void eos_invert_kernel(Table t, Seed s, int ma
     }
     table_invert(t, i, w, qle, seed, maxit, j, wT, it);
     if (ok) {
-      if (lT) lT[q] = (t.lT0 + (j + wT) * t.dlT) * kLog10of2;
+      if (lT) lT[q] = t.lT0 + (j + wT) * t.dlT;
       if (jo) jo[q] = j;
       if (iters) iters[q] = it;
     }
@@ -874,9 +849,9 @@ hipError_t launch_stage(const StageArgs &a, int tile, int grid, hipStream_t s) {
 #define TDH_LAUNCH(x, y, z, o)                                                             \
   if (i++ == tile) {                                                                       \
     if (a.m.nv == 6)                                                                       \
-      hipLaunchKernelGGL((stage_tiled<x, y, z, 6, o>), dim3(grid), dim3(TileGeom<x, y, z>::NTH), 0, s, a); \
-    else                                                                                                 \
-      hipLaunchKernelGGL((stage_tiled<x, y, z, 5, o>), dim3(grid), dim3(TileGeom<x, y, z>::NTH), 0, s, a); \
+      hipLaunchKernelGGL((stage_tiled<x, y, z, 6, o>), dim3(grid), dim3(kChunk), 0, s, a); \
+    else                                                                                   \
+      hipLaunchKernelGGL((stage_tiled<x, y, z, 5, o>), dim3(grid), dim3(kChunk), 0, s, a); \
     return hipGetLastError();                                                           \
   }
   TDH_TILES(TDH_LAUNCH)

@@ -444,21 +444,20 @@ extern "C" tdh_status tdh_set_eos_table(tdh_ctx *c, int nrho, int nT, double lr0
     for (int j = 0; j + 1 < nT; ++j)
       if (!(le[(size_t)i * nT + j + 1] > le[(size_t)i * nT + j]))
         return fail(c, TDH_EINVAL, "log e is not increasing in T on row %d", i);
-  // pack by density-row pairs and convert every logarithm to base 2 (see Table)
-  const double L2 = 3.32192809488736234787031942948939017586483139;  // log2(10)
+  // pack by density-row pairs (see Table in tdh_internal.hpp)
   const size_t np = (size_t)(nrho - 1) * nT;
   const size_t pc_off = (2 * np + 3) & ~(size_t)3;  // 32-byte alignment of the double4 records
   std::vector<double> packed(pc_off + 4 * np);
   for (int i = 0; i + 1 < nrho; ++i)
     for (int j = 0; j < nT; ++j) {
       const size_t a = (size_t)i * nT + j, b = (size_t)(i + 1) * nT + j, q = (size_t)i * nT + j;
-      packed[2 * q] = le[a] * L2;
-      packed[2 * q + 1] = le[b] * L2;
+      packed[2 * q] = le[a];
+      packed[2 * q + 1] = le[b];
       double *pcq = packed.data() + pc_off + 4 * q;
-      pcq[0] = lP[a] * L2;
-      pcq[1] = lP[b] * L2;
-      pcq[2] = lc2[a] * L2;
-      pcq[3] = lc2[b] * L2;
+      pcq[0] = lP[a];
+      pcq[1] = lP[b];
+      pcq[2] = lc2[a];
+      pcq[3] = lc2[b];
     }
   if (!c->d_table || c->tab.nrho != nrho || c->tab.nT != nT) {
     tdh_status s = dev_alloc(c, &c->d_table, pc_off + 4 * np);
@@ -469,11 +468,11 @@ extern "C" tdh_status tdh_set_eos_table(tdh_ctx *c, int nrho, int nT, double lr0
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->tab.nrho = nrho;
   c->tab.nT = nT;
-  c->tab.lr0 = lr0 * L2;
-  c->tab.dlr = dlr * L2;
-  c->tab.inv_dlr = 1.0 / (dlr * L2);
-  c->tab.lT0 = lT0 * L2;
-  c->tab.dlT = dlT * L2;
+  c->tab.lr0 = lr0;
+  c->tab.dlr = dlr;
+  c->tab.inv_dlr = 1.0 / dlr;
+  c->tab.lT0 = lT0;
+  c->tab.dlT = dlT;
   c->tab.le2 = (const double2 *)c->d_table;
   c->tab.pc = (const double4 *)(c->d_table + pc_off);
   c->have_table = true;

@@ -1,0 +1,120 @@
+"""Summaries of rocprofv3 output for the stage kernel.
+
+Reads the CSV files rocprofv3 writes (`--output-format csv`): the kernel
+statistics of a `--kernel-trace --stats` run, and the per-dispatch
+`FETCH_SIZE` / `WRITE_SIZE` counters (KiB) of two `--pmc` runs of the same
+command, plus the same counters for a plain device copy of known size.  The
+copy gives the factor from counter units to HBM bytes for each counter.
+Writes a short text summary (and, with --json, the per-launch HBM bytes and
+the hash of the kernel sources they were taken on).
+
+  python -m paper_2609_37859_amd.profile_summary --stats DIR --fetch DIR --write DIR \
+      --copy-fetch DIR --copy-write DIR --copy-bytes N --kernel stage_tiled --cmd "..." \
+      --out profiles/x.md [--json profiles/x.json]
+"""
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import statistics
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("tdh_kernels.hip", "tdh_internal.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2609_37859_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _one(d, pattern):
+    hits = sorted(glob.glob(os.path.join(d, "**", pattern), recursive=True))
+    if not hits:
+        raise SystemExit(f"no {pattern} under {d}")
+    return hits[0]
+
+
+def kernel_stats(d, kernel):
+    """Rows of the stats file whose name contains `kernel`; the variant with the
+    most calls is the one the run used after tuning."""
+    rows = [r for r in csv.DictReader(open(_one(d, "*kernel_stats.csv"))) if kernel in r["Name"]]
+    if not rows:
+        raise SystemExit(f"kernel {kernel} not in the stats of {d}")
+    rows.sort(key=lambda r: -int(r["Calls"]))
+    return rows
+
+
+def counter_per_dispatch(d, name_exact, counter):
+    vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(_one(d, "*counter_collection.csv")))
+            if r["Kernel_Name"] == name_exact and r["Counter_Name"] == counter]
+    if not vals:
+        raise SystemExit(f"no {counter} for {name_exact} under {d}")
+    return vals
+
+
+def copy_factor(d, counter, nbytes):
+    """HBM bytes per counter unit, from the largest copy dispatch of the calibration run."""
+    best = 0.0
+    for r in csv.DictReader(open(_one(d, "*counter_collection.csv"))):
+        if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == counter:
+            best = max(best, float(r["Counter_Value"]))
+    if best <= 0:
+        raise SystemExit(f"no copy dispatch with {counter} under {d}")
+    return nbytes / best
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--stats", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--copy-fetch")
+    ap.add_argument("--copy-write")
+    ap.add_argument("--copy-bytes", type=float, default=float(1 << 30))
+    ap.add_argument("--kernel", default="stage_tiled")
+    ap.add_argument("--cmd", action="append", default=[], help="command that produced the inputs (repeatable)")
+    ap.add_argument("--title", default="stage kernel")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--json")
+    args = ap.parse_args()
+
+    rows = kernel_stats(args.stats, args.kernel)
+    used = rows[0]
+    lines = [f"# {args.title}", "", "Commands:", ""]
+    lines += [f"    {c}" for c in args.cmd]
+    lines += ["", "Kernel statistics (rocprofv3 --kernel-trace --stats):", "",
+              "| kernel | calls | average ms | min ms | max ms |", "|---|---|---|---|---|"]
+    for r in rows:
+        lines.append(f"| `{r['Name']}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.4f} | "
+                     f"{float(r['MinNs']) / 1e6:.4f} | {float(r['MaxNs']) / 1e6:.4f} |")
+    lines += ["", f"Variant used after tuning: `{used['Name']}`, average {float(used['AverageNs']) / 1e6:.4f} ms "
+                  f"over {used['Calls']} launches.", ""]
+    out = {"kernel": used["Name"], "avg_launch_ms": float(used["AverageNs"]) / 1e6, "kernel_hash": kernel_source_hash()}
+    if args.fetch and args.write and args.copy_fetch and args.copy_write:
+        f_k = copy_factor(args.copy_fetch, "FETCH_SIZE", args.copy_bytes)
+        w_k = copy_factor(args.copy_write, "WRITE_SIZE", args.copy_bytes)
+        fv = counter_per_dispatch(args.fetch, used["Name"], "FETCH_SIZE")
+        wv = counter_per_dispatch(args.write, used["Name"], "WRITE_SIZE")
+        fb, wb = statistics.mean(fv) * f_k, statistics.mean(wv) * w_k
+        lines += ["HBM traffic per launch (counter runs of the same command, copy-calibrated):", "",
+                  f"- FETCH_SIZE: mean {statistics.mean(fv):.1f} KiB over {len(fv)} launches; copy factor "
+                  f"{f_k:.4f} B per unit -> {fb / 1e6:.2f} MB read",
+                  f"- WRITE_SIZE: mean {statistics.mean(wv):.1f} KiB over {len(wv)} launches; copy factor "
+                  f"{w_k:.4f} B per unit -> {wb / 1e6:.2f} MB written",
+                  f"- total {(fb + wb) / 1e6:.2f} MB per launch", ""]
+        out.update({"hbm_read_bytes_per_launch": fb, "hbm_write_bytes_per_launch": wb,
+                    "hbm_bytes_per_launch": fb + wb, "fetch_factor": f_k, "write_factor": w_k})
+    lines.append(f"Kernel source hash: {out['kernel_hash']}")
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    if args.json:
+        with open(args.json, "w") as f:
+            json.dump(out, f, indent=1)
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main()
