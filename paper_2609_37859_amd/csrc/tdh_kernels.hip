@@ -46,9 +46,11 @@ struct Src {
   double w;  // value = (1 - w) A + w B; w in {0, 1/2, 1}
 };
 
+template <bool UNIFORM = false>
 __device__ __forceinline__ Src source_of(const StageArgs &a, int fb, int nb) {
-  const int fn = a.fac[nb];
-  const int pn = a.par[nb];
+  // UNIFORM: nb is the same in every lane; keep the result in scalar registers
+  const int fn = UNIFORM ? __builtin_amdgcn_readfirstlane(a.fac[nb]) : a.fac[nb];
+  const int pn = UNIFORM ? __builtin_amdgcn_readfirstlane(a.par[nb]) : a.par[nb];
   const double *Qend = pn ? a.Qb : a.Qa;   // latest computed state
   const double *Qold = pn ? a.Qa : a.Qb;   // state at the start of that step
   const bool act = (a.k & (fn - 1)) == 0;  // factors are powers of two
@@ -321,6 +323,30 @@ struct TileGeom {
   static constexpr int NF = F0 > F1 ? (F0 > F2 ? F0 : F2) : (F1 > F2 ? F1 : F2);
 };
 
+// The thread index as a value the compiler cannot hoist out of the item loop:
+// every per-thread index below is then recomputed per item (a few integer
+// operations) instead of being held in registers for the kernel's lifetime.
+__device__ __forceinline__ int item_tid() {
+  int t;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
+  return t;
+}
+
+// Per-item values that are the same in every lane, moved to scalar registers
+// (the loads that produce them are vector loads from writable memory).
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ long long uni(long long x) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(unsigned long long)x);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)x >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ BlockInfo uni(const BlockInfo &b) {
+  BlockInfo r;
+  r.n = uni(b.n); r.ox = uni(b.ox); r.oy = uni(b.oy); r.oz = uni(b.oz);
+  r.off = uni(b.off); r.poff = uni(b.poff); r.ioff = uni(b.ioff);
+  return r;
+}
+
 struct TileCtx {
   int b;
   BlockInfo B;
@@ -332,8 +358,7 @@ struct TileCtx {
 
 template <int TX, int TY, int TZ, int NV, int D>
 __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, double *sW, double *sF, int *sB,
-                                          const int *sJc, const double *qc, const int *cc, const int *lc,
-                                          double *rhs, double &divv, double &emax) {
+                                          const int *sJc, double *rhs, double &divv, double &emax) {
   using G = TileGeom<TX, TY, TZ>;
   constexpr int L0 = TX + (D == 0 ? 4 : 0), L1 = TY + (D == 1 ? 4 : 0), L2 = TZ + (D == 2 ? 4 : 0);
   constexpr int NS = L0 * L1 * L2;
@@ -344,10 +369,12 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
   constexpr int PN = 1 + D, P1 = 1 + (D + 1) % 3, P2 = 1 + (D + 2) % 3;
   const Phys &p = a.p;
   const MeshDev &m = a.m;
-  const int tid = threadIdx.x;
+  const int tid = item_tid();
+  const int cc[3] = {tid % TX, (tid / TX) % TY, tid / (TX * TY)};  // own cell in the tile
   const int n = T.B.n;
   const int Nd = D == 0 ? m.nx : (D == 1 ? m.ny : m.nz);
   // stage the slab: tile extended by two cells along D
+#pragma unroll 1
   for (int s = tid; s < NS; s += kChunk) {
     int sc[3] = {s % L0, (s / L0) % L1, s / (L0 * L1)};
     sc[D] -= 2;
@@ -364,6 +391,7 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
   }
   __syncthreads();
   // every face of the tile along D, once
+#pragma unroll 1
   for (int f0 = 0; f0 < NFD; f0 += kChunk) {
     if (f0 + (tid & ~63) >= NFD) continue;  // the whole wave is idle this round
     // lanes past the end repeat the last face so the wave stays converged for
@@ -469,16 +497,24 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
     divv += (sF[6 * G::NF + fhi] - sF[6 * G::NF + flo]) * idx;
     const int sbase = cc[0] + L0 * (cc[1] + L1 * cc[2]);
     emax = fmax(emax, fmax(sW[6 * G::SLAB + sbase + STR], sW[6 * G::SLAB + sbase + 3 * STR]));
+    if (D == 0) emax = fmax(emax, sW[6 * G::SLAB + sbase + 2 * STR]);  // own stage-input E
     if (p.grav_kind) {
+      const int lc[3] = {T.to[0] + cc[0], T.to[1] + cc[1], T.to[2] + cc[2]};
       int im[3] = {lc[0], lc[1], lc[2]}, ip[3] = {lc[0], lc[1], lc[2]};
       im[D] -= 1;
       ip[D] += 1;
       const double pm = phi_at(a, T.B, im[0], im[1], im[2], T.t);
       const double p0 = phi_at(a, T.B, lc[0], lc[1], lc[2], T.t);
       const double pp = phi_at(a, T.B, ip[0], ip[1], ip[2], T.t);
-      rhs[PN] -= qc[IDN] * (pp - pm) / (2.0 * m.dx[D]);
+      rhs[PN] -= sW[sbase + 2 * STR] * (pp - pm) / (2.0 * m.dx[D]);  // own density
       rhs[IEN] -= (sF[IDN * G::NF + fhi] * (pp - p0) + sF[IDN * G::NF + flo] * (p0 - pm)) / (2.0 * m.dx[D]);
     }
+    // Pin the sums here: otherwise the compiler sinks this axis's arithmetic
+    // to the final use and keeps every value read from LDS live through the
+    // remaining axes (tens of registers).
+#pragma unroll
+    for (int v = 0; v < NV; ++v) asm volatile("" : "+v"(rhs[v]));
+    asm volatile("" : "+v"(divv), "+v"(emax));
   }
   __syncthreads();
 }
@@ -491,7 +527,6 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
   __shared__ double sF[7 * G::NF];     // fluxes (rho, mx, my, mz, E, A) + face velocity
   __shared__ int sB[G::SLAB];          // owning block of a staged cell, -1 beyond an outflow edge
   __shared__ int sJc[kChunk];          // table cell of each tile cell's centre state (seeds)
-  const int tid = threadIdx.x;
   const Phys &p = a.p;
   const MeshDev &m = a.m;
   const int a0 = a.cnt_ge[a.Lhi + 1], a1 = a.cnt_ge[a.Llo];
@@ -503,30 +538,28 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
     int lo = a0, hi = a1;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
-      if (a.item_start[mid] <= item) lo = mid; else hi = mid;
+      if (uni(a.item_start[mid]) <= item) lo = mid; else hi = mid;
     }
+    const int tid = item_tid();
     TileCtx T;
-    T.b = a.order[lo];
-    T.B = m.blocks[T.b];
+    T.b = uni(a.order[lo]);
+    T.B = uni(m.blocks[T.b]);
     const int n = T.B.n;
     const long long n3 = (long long)n * n * n;
-    const int tile = item - a.item_start[lo];
+    const int tile = item - uni(a.item_start[lo]);
     const int ntx = n / TX, nty = n / TY;
     T.to[0] = (tile % ntx) * TX;
     T.to[1] = ((tile / ntx) % nty) * TY;
     T.to[2] = (tile / (ntx * nty)) * TZ;
-    T.fb = a.fac[T.b];
+    T.fb = uni(a.fac[T.b]);
     T.dtb = T.fb * dt0;
     T.t = a.phase == 1 ? tk : tk + T.dtb;
-    T.own = source_of(a, T.fb, T.b);
+    T.own = source_of<true>(a, T.fb, T.b);
     const int cc[3] = {tid % TX, (tid / TX) % TY, tid / (TX * TY)};
     const int lc[3] = {T.to[0] + cc[0], T.to[1] + cc[1], T.to[2] + cc[2]};
     const long long cell = ((long long)lc[2] * n + lc[1]) * n + lc[0];
-    double qc[6];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) qc[v] = src_val(T.own, T.B.off + v * n3 + cell);
     double rhs[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    double divv = 0.0, emax = qc[IEN];
+    double divv = 0.0, emax = -INFINITY;
     // seeded inversion: the table cell of each tile cell's centre state (from
     // seed_kernel) starts the face and compression queries
     int jcell = -1;
@@ -534,11 +567,14 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
       jcell = a.jc[T.B.off / NV + cell];
       sJc[tid] = jcell;
     }
-    tile_axis<TX, TY, TZ, NV, 0>(a, T, sW, sF, sB, sJc, qc, cc, lc, rhs, divv, emax);
-    tile_axis<TX, TY, TZ, NV, 1>(a, T, sW, sF, sB, sJc, qc, cc, lc, rhs, divv, emax);
-    tile_axis<TX, TY, TZ, NV, 2>(a, T, sW, sF, sB, sJc, qc, cc, lc, rhs, divv, emax);
-    // combine
-    const double *Qbase = a.par[T.b] ? a.Qb : a.Qa;
+    tile_axis<TX, TY, TZ, NV, 0>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
+    tile_axis<TX, TY, TZ, NV, 1>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
+    tile_axis<TX, TY, TZ, NV, 2>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
+    // combine (the stage input is read again here rather than held through the axes)
+    double qc[6];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) qc[v] = src_val(T.own, T.B.off + v * n3 + cell);
+    const double *Qbase = uni(a.par[T.b]) ? a.Qb : a.Qa;
     double qn[6];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -581,7 +617,7 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
         if (NV > 5) qn[IAX] = uf;
       }
     }
-    double *out = a.phase == 1 ? a.Qs : (a.par[T.b] ? a.Qa : a.Qb);
+    double *out = a.phase == 1 ? a.Qs : (uni(a.par[T.b]) ? a.Qa : a.Qb);
 #pragma unroll
     for (int v = 0; v < NV; ++v) out[T.B.off + v * n3 + cell] = qn[v];
   }
