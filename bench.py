@@ -9,15 +9,19 @@ minimum, global minimum, level assignment) and one RK2 step of every block
 energy update), inputs resident in HBM.
 
 Prints one JSON line.  `value` is the cell-updates/s of the learned form:
-one launch per RK phase for all levels, each face's first table query seeded
-by the learned network (trained first on the GPU by the library's own
-kernels; training time reported, not timed), the second query seeded by the
-first.  The chained form (first query bisected) and the plain form
-(bisection for every query, one launch per level) are reported beside it;
-all three give bit-identical states.  The roofline entry is for the
-stage kernel (HIP events on the library's stream); the CPU baseline is the
-FP64 oracle on the host, on a bounded number of steps of the same workload,
-and its final state doubles as the accuracy check of the GPU run.
+one launch per RK phase for all levels; at the end of each stage the table
+cell of every output state is found by a search started from the learned
+network's prediction (the network runs on the matrix cores inside the stage
+kernel; it is trained first on the GPU by the library's own kernels, training
+time reported, not timed), and that cell seeds the next stage's face and
+compression queries of the cell.  Beside it: the temporal form (searches
+start from the input state's cell), the chained form (a separate pass bisects
+for the cells before each stage) and the plain form (bisection for every
+query, one launch per level); all give bit-identical states.  The roofline
+entry is for the stage kernel (HIP events on the library's stream); the CPU
+baseline is the FP64 oracle on the host, on a bounded number of steps of the
+same workload, and its final state doubles as the accuracy check of the GPU
+run.
 """
 import argparse
 import json
@@ -45,6 +49,17 @@ def traffic_from_profiles(workload):
     if d.get("kernel_hash") != kernel_source_hash():
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+FORMS = {
+    "learned": "batched launches; each stage finds the table cells of its output states by searches started "
+               "from the learned network's prediction; they seed the next stage's face and compression queries",
+    "temporal": "batched launches; each stage finds the table cells of its output states by searches started "
+                "from its input states' cells; they seed the next stage's queries",
+    "chained": "batched launches; before each stage the table cell of every cell's state is bisected; it seeds "
+               "the cell's face and compression queries",
+    "plain": "one launch per level; bisection for every table query",
+}
 
 
 def train_seed(T, W, table, steps=2000, nsamples=1 << 20):
@@ -106,8 +121,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps for the CPU baseline / accuracy check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="learned,chained,plain",
-                    help="comma list of forms to time: learned, chained, plain (the first present is the headline)")
+    ap.add_argument("--forms", default="learned,temporal,chained,plain",
+                    help="comma list of forms to time: learned, temporal, chained, plain (learned is the headline "
+                         "when present)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -157,7 +173,8 @@ def main():
     forms = args.forms.split(",")
     params, train_s, train_loss, seed_err = train_seed(T, W, table)
     res = {}
-    for name, mode, batched in (("learned", 1, True), ("chained", 2, True), ("plain", 0, False)):
+    for name, mode, batched in (("learned", 1, True), ("temporal", 3, True), ("chained", 2, True),
+                                ("plain", 0, False)):
         if name in forms:
             res[name] = run_form(T, W, cfg, mesh, U, table, args.steps, args.warmup, inv_mode=mode, batched=batched,
                                  seed_params=params if mode == 1 else None)
@@ -189,12 +206,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "c2: 128^3 periodic as 64 MeshBlocks of 32^3, Saha H/He table EOS 256x256, dual "
                                "energy, cold Mach-1e7 Gaussian stream, CFL 0.3", "cells": ncell, "nv": nv,
-                   "form": {"learned": "batched launches; each face's first table query seeded by the learned "
-                                       "network, the second by the first",
-                            "chained": "batched launches; first query bisected, second seeded by the first",
-                            "plain": "one launch per level; bisection for every table query"}[head],
+                   "form": FORMS[head],
                    "tile": T.tile_shapes()[tile]},
-        "forms": {k: {"value": rate(k), "ms_per_step": 1e3 * v[0] / args.steps,
+        "forms": {k: {"value": rate(k), "ms_per_step": 1e3 * v[0] / args.steps, "form": FORMS[k],
                       "stage_kernel_ms": v[1] / max(v[2], 1), "tile": T.tile_shapes()[v[4]]} for k, v in res.items()},
         "speedup_vs_plain": (value / plain) if plain else None,
         "learned_seed": {"train_steps": 2000, "batch": 4096, "samples": 1 << 20, "train_seconds": train_s,

@@ -76,9 +76,17 @@ typedef struct {
   double bh_x0[3], v_frame[3]; /* point-mass position at t = 0 and frame velocity */
   int inv_mode;   /* table inversion (every mode gives the same cell, hence the same result):
                      0 bisection for every query;
-                     1 a face's left state seeded by the learned network (tdh_mlp_*), its
-                       right state and the cell's compression query seeded by that cell;
-                     2 as 1 with the left state bisected */
+                     2 before each stage a pass bisects for the table cell of every
+                       cell's stage-input state; that cell seeds the cell's face and
+                       compression queries (a face's right state is seeded by its
+                       left state's cell);
+                     1 as 2, but each stage records the table cells of its output
+                       states for the next stage instead of a pass, their searches
+                       starting from the learned network's prediction (tdh_mlp_*;
+                       from the input state's cell while the network is off);
+                     3 as 1 with every search starting from the input state's cell.
+                     In modes 1 and 3 a pass finds the cells once after a state
+                     upload (with the network in mode 1). */
   int newton_max_iter; /* seeded secant steps before falling back to bisection (>= 0) */
 } tdh_config;
 
@@ -163,6 +171,13 @@ tdh_status tdh_set_time(tdh_ctx *ctx, double t);
 /* Copy the current (synchronised) state to / from host memory. */
 tdh_status tdh_get_state(tdh_ctx *ctx, double *host_state);
 tdh_status tdh_set_state(tdh_ctx *ctx, const double *host_state);
+
+/* Seed table cells held for the current state (tdh_config.inv_mode 3; table
+ * EOS only): host_cells receives one int32 per cell, blocks in order, cells of
+ * a block x fastest; -1 where none is held yet (after a state upload).  The
+ * values only start searches; they never change a result.  Synchronises the
+ * stream.  TDH_ESTATE without a table EOS or inside a window. */
+tdh_status tdh_get_seed_cells(tdh_ctx *ctx, int32_t *host_cells);
 
 /* Batched EOS queries on device arrays of n values (n <= 2^31):
  *   invert: log10 rho, log10 e -> log10 T, table cell j, secant steps taken

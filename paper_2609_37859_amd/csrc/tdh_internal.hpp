@@ -82,7 +82,9 @@ struct StageArgs {
   int k;                    // sub-cycle index in the window (dt0 units)
   int phase;                // 1 or 2
   const double *win;        // device {window start time, finest step dt0}
-  int *jc;                  // table cell of each cell's stage-input state (seeded inversion)
+  int *jc;                  // table cell of each cell's state, one segment per state buffer
+                            // (Qa, Qb, Qs; jn cells each), the seeds of the inversion
+  long long jn;
 };
 
 // host-side launchers (tdh_kernels.hip)

@@ -153,8 +153,10 @@ __device__ __forceinline__ void tbil_pc(const Table &t, int i, double w, int j, 
 
 // Table cell seed from the learned network for this lane's (log rho, log e);
 // every lane of the wave must call it (the hidden layer runs on the matrix cores).
-__device__ __forceinline__ int seed_cell_wave(const Seed &s, const Table &t, double lr, double le) {
-  const float y = mlp_wave_forward(s.w, norm01(lr, s.lr_lo, s.lr_hi), norm01(le, s.le_lo, s.le_hi));
+// lane >= 0: use the lean forward pass with that lane index (see tdh_mlp_dev.hpp)
+__device__ __forceinline__ int seed_cell_wave(const Seed &s, const Table &t, double lr, double le, int lane = -1) {
+  const float x0 = norm01(lr, s.lr_lo, s.lr_hi), x1 = norm01(le, s.le_lo, s.le_hi);
+  const float y = lane >= 0 ? mlp_wave_forward_lean(s.w, x0, x1, lane) : mlp_wave_forward(s.w, x0, x1);
   const double lT = s.lt_lo + 0.5 * ((double)y + 1.0) * (s.lt_hi - s.lt_lo);
   const double x = (lT - t.lT0) / t.dlT;
   if (!(x > 0.0)) return 0;
@@ -347,6 +349,11 @@ __device__ __forceinline__ BlockInfo uni(const BlockInfo &b) {
   return r;
 }
 
+// Segment of the seed cells that belongs to a block's stage input / output
+// buffer (0: Qa, 1: Qb, 2: Qs) given the block's parity.
+__device__ __forceinline__ int jseg_in(const StageArgs &a, int par) { return a.phase == 1 ? par : 2; }
+__device__ __forceinline__ int jseg_out(const StageArgs &a, int par) { return a.phase == 1 ? 2 : 1 - par; }
+
 struct TileCtx {
   int b;
   BlockInfo B;
@@ -519,7 +526,9 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
   __syncthreads();
 }
 
-template <int TX, int TY, int TZ, int NV, int OCC>
+// NET: the learned network starts the output states' table-cell searches (a
+// separate instantiation, so its matrix-core registers burden no other form)
+template <int TX, int TY, int TZ, int NV, int OCC, bool NET>
 __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void stage_tiled(StageArgs a) {
   using G = TileGeom<TX, TY, TZ>;
   static_assert(G::TV == kChunk, "one cell per thread");
@@ -563,8 +572,9 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
     // seeded inversion: the table cell of each tile cell's centre state (from
     // seed_kernel) starts the face and compression queries
     int jcell = -1;
+    const int parb = uni(a.par[T.b]);
     if (p.eos_kind == 1 && p.inv_mode != 0) {
-      jcell = a.jc[T.B.off / NV + cell];
+      jcell = a.jc[jseg_in(a, parb) * a.jn + T.B.off / NV + cell];
       sJc[tid] = jcell;
     }
     tile_axis<TX, TY, TZ, NV, 0>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
@@ -574,7 +584,7 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
     double qc[6];
 #pragma unroll
     for (int v = 0; v < NV; ++v) qc[v] = src_val(T.own, T.B.off + v * n3 + cell);
-    const double *Qbase = uni(a.par[T.b]) ? a.Qb : a.Qa;
+    const double *Qbase = parb ? a.Qb : a.Qa;
     double qn[6];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -617,16 +627,35 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
         if (NV > 5) qn[IAX] = uf;
       }
     }
-    double *out = a.phase == 1 ? a.Qs : (uni(a.par[T.b]) ? a.Qa : a.Qb);
+    double *out = a.phase == 1 ? a.Qs : (parb ? a.Qa : a.Qb);
 #pragma unroll
     for (int v = 0; v < NV; ++v) out[T.B.off + v * n3 + cell] = qn[v];
+    if (p.eos_kind == 1 && (p.inv_mode == 1 || p.inv_mode == 3)) {
+      // The table cell of the output state seeds the next stage's queries of
+      // this cell.  Its search starts from the learned network's prediction
+      // (mode 1; the whole wave takes part, every thread owns a cell) or from
+      // the input state's cell (mode 3).
+      double w[6];
+      c2p(p, qn, w);
+      const double Ue = fmax(w[4], w[0] * p.e_floor);
+      const double lr = log10(w[0]), le = log10(Ue / w[0]);
+      int start = jcell;
+      if constexpr (NET) start = seed_cell_wave(a.s, a.t, lr, le, item_tid() & 63);
+      int i, j, it;
+      double wr, wT;
+      table_rho(a.t, lr, i, wr);
+      table_invert(a.t, i, wr, le, start, p.newton_max_iter, j, wT, it);
+      a.jc[jseg_out(a, parb) * a.jn + T.B.off / NV + cell] = j;
+    }
   }
 }
 
 // Table cell of every active cell's stage-input centre state.  Mode 1 starts
 // the search from the learned network's prediction (its hidden layer on the
 // matrix cores), mode 2 bisects; both end at the same, exact cell, which
-// seeds the stage kernel's face and compression queries.  Blocks hold a
+// seeds the stage kernel's face and compression queries.  Modes 1 and 3 run
+// it once after a state upload; afterwards each stage leaves the cells of its
+// output for the next.  Blocks hold a
 // multiple of 256 cells, so every wave is full when it calls the network.
 __global__ __launch_bounds__(kChunk) void seed_kernel(StageArgs a) {
   const int a0 = a.cnt_ge[a.Lhi + 1], a1 = a.cnt_ge[a.Llo];
@@ -655,14 +684,13 @@ __global__ __launch_bounds__(kChunk) void seed_kernel(StageArgs a) {
     double wr, wT;
     table_rho(a.t, lr, i, wr);
     table_invert(a.t, i, wr, le, seed, p.newton_max_iter, j, wT, it);
-    a.jc[B.off / nv + cell] = j;
+    a.jc[jseg_in(a, a.par[b]) * a.jn + B.off / nv + cell] = j;
   }
 }
 
 // stage-kernel variants offered to the runtime: tile shape (x fastest; all
 // divide blocks of edge >= 8) and waves per SIMD the register budget targets
-#define TDH_TILES(X) X(8, 8, 4, 2) X(16, 4, 4, 2) X(4, 8, 8, 2) X(8, 4, 8, 2) \
-                     X(8, 8, 4, 3) X(16, 4, 4, 3) X(4, 8, 8, 3) X(8, 4, 8, 3)
+#define TDH_TILES(X) X(8, 8, 4, 3) X(16, 4, 4, 3) X(4, 8, 8, 3) X(8, 4, 8, 3) X(16, 4, 4, 2) X(8, 8, 4, 2)
 
 __global__ void set_window_kernel(double *win, double t, double dt0) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -882,13 +910,21 @@ hipError_t launch_seed(const StageArgs &a, int grid, hipStream_t s) {
 
 hipError_t launch_stage(const StageArgs &a, int tile, int grid, hipStream_t s) {
   int i = 0;
-#define TDH_LAUNCH(x, y, z, o)                                                             \
-  if (i++ == tile) {                                                                       \
-    if (a.m.nv == 6)                                                                       \
-      hipLaunchKernelGGL((stage_tiled<x, y, z, 6, o>), dim3(grid), dim3(kChunk), 0, s, a); \
-    else                                                                                   \
-      hipLaunchKernelGGL((stage_tiled<x, y, z, 5, o>), dim3(grid), dim3(kChunk), 0, s, a); \
-    return hipGetLastError();                                                           \
+  // the network variant when it starts the searches (table EOS, mode 1, network on)
+  const bool net = a.p.eos_kind == 1 && a.p.inv_mode == 1 && a.s.enabled;
+#define TDH_LAUNCH(x, y, z, o)                                                                   \
+  if (i++ == tile) {                                                                             \
+    if (net) {                                                                                   \
+      if (a.m.nv == 6)                                                                           \
+        hipLaunchKernelGGL((stage_tiled<x, y, z, 6, o, true>), dim3(grid), dim3(kChunk), 0, s, a); \
+      else                                                                                       \
+        hipLaunchKernelGGL((stage_tiled<x, y, z, 5, o, true>), dim3(grid), dim3(kChunk), 0, s, a); \
+    } else if (a.m.nv == 6) {                                                                    \
+      hipLaunchKernelGGL((stage_tiled<x, y, z, 6, o, false>), dim3(grid), dim3(kChunk), 0, s, a);  \
+    } else {                                                                                     \
+      hipLaunchKernelGGL((stage_tiled<x, y, z, 5, o, false>), dim3(grid), dim3(kChunk), 0, s, a);  \
+    }                                                                                            \
+    return hipGetLastError();                                                                    \
   }
   TDH_TILES(TDH_LAUNCH)
 #undef TDH_LAUNCH

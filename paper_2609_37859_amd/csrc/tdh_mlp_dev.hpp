@@ -108,6 +108,63 @@ __device__ __forceinline__ float mlp_wave_forward(const MlpDev &w, float x0, flo
   return layer3(w, acc);
 }
 
+// The same forward pass (bit for bit) with a lean register footprint, for use
+// inside a larger kernel: one 16-sample tile at a time, and the lane index
+// passed in (an opaque per-item value keeps the weight loads next to their
+// use instead of hoisted into registers for the kernel's lifetime).
+__device__ __forceinline__ float mlp_wave_forward_lean(const MlpDev &w, float x0, float x1, int l) {
+  const float xb0 = round_bf16(x0), xb1 = round_bf16(x1);
+  bf16x8 bop[4][2];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+      bop[nt][kt] = *(const bf16x8 *)(w.w2b + (16 * nt + (l & 15)) * H + 32 * kt + 8 * (l >> 4));
+  const int src = 16 * ((l & 15) >> 2);
+  float y = 0.0f;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    const int q = 16 * mt + (l & 15);
+    const float q0 = __shfl(xb0, q, 64), q1 = __shfl(xb1, q, 64);
+    bf16x8 a[2];
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = 32 * kt + 8 * (l >> 4) + e;
+        float z = w.b1[k];
+        z += from_bf16(w.w1b[2 * k]) * q0;
+        z += from_bf16(w.w1b[2 * k + 1]) * q1;
+        a[kt][e] = to_bf16(fmaxf(z, 0.0f));
+      }
+    f32x4 acc[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], bop[nt][0], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], bop[nt][1], c, 0, 0, 0);
+      acc[nt] = c;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float s = 0.0f;
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        const int o = 16 * nt + (l & 15);
+        const float h = round_bf16(fmaxf(acc[nt][r] + w.b2[o], 0.0f));
+        s += from_bf16(w.w3b[o]) * h;
+      }
+      s += __shfl_xor(s, 1, 64);
+      s += __shfl_xor(s, 2, 64);
+      s += __shfl_xor(s, 4, 64);
+      s += __shfl_xor(s, 8, 64);
+      const float v = __shfl(s, src, 64);
+      if (mt == (l >> 4) && r == (l & 3)) y = v;
+    }
+  }
+  return y + w.b3[0];
+}
+
 __device__ __forceinline__ float norm01(double v, double lo, double hi) {
   return (float)(2.0 * (v - lo) / (hi - lo) - 1.0);
 }

@@ -37,7 +37,8 @@ struct tdh_ctx {
 
   // device memory: state in the caller's arena, metadata owned here
   double *Qa = nullptr, *Qb = nullptr, *Qs = nullptr, *imp = nullptr, *bf1 = nullptr, *phi = nullptr;
-  int *jc = nullptr;  // per-cell table cell of the stage input (seeded inversion)
+  int *jc = nullptr;  // seed table cells: a segment of ncells per state buffer (Qa, Qb, Qs)
+  bool seeds_held = false;  // the current buffers' segments hold the cells of the current state
   BlockInfo *d_blocks = nullptr;
   int *d_lmap = nullptr, *d_fac = nullptr, *d_par = nullptr, *d_order = nullptr, *d_item_start = nullptr;
   int *d_cnt_ge = nullptr, *d_cfl_item_block = nullptr, *d_cfl_block_start = nullptr;
@@ -156,7 +157,7 @@ static size_t arena_need(const tdh_config *cfg, const Layout &L) {
   s += 3 * align256(L.total * sizeof(double));   // Qa, Qb, Qs
   s += 2 * align256(L.itotal * sizeof(double));  // impulses, stage-1 boundary fluxes
   if (cfg->grav_kind == 1) s += align256(L.ptotal * sizeof(double));
-  if (cfg->eos_kind == 1) s += align256(L.ncells * sizeof(int));  // seeded-inversion cells
+  if (cfg->eos_kind == 1) s += align256(3 * L.ncells * sizeof(int));  // seed cells of Qa, Qb, Qs
   return s;
 }
 
@@ -175,7 +176,7 @@ extern "C" tdh_status tdh_init(const tdh_config *cfg, void *hip_stream, tdh_ctx 
   if (cfg->eos_kind < 0 || cfg->eos_kind > 1) return fail(nullptr, TDH_EINVAL, "eos_kind must be 0 or 1");
   if (cfg->grav_kind < 0 || cfg->grav_kind > 2) return fail(nullptr, TDH_EINVAL, "grav_kind must be 0, 1 or 2");
   if (cfg->n_lat < 0 || cfg->n_lat > kMaxLevel) return fail(nullptr, TDH_EINVAL, "n_lat must be in [0, 30]");
-  if (cfg->inv_mode < 0 || cfg->inv_mode > 2) return fail(nullptr, TDH_EINVAL, "inv_mode must be 0, 1 or 2");
+  if (cfg->inv_mode < 0 || cfg->inv_mode > 3) return fail(nullptr, TDH_EINVAL, "inv_mode must be 0, 1, 2 or 3");
   if (cfg->newton_max_iter < 0 || cfg->newton_max_iter > 64)
     return fail(nullptr, TDH_EINVAL, "newton_max_iter must be in [0, 64]");
   if (cfg->eos_kind == 0 && !(cfg->gamma > 1.0)) return fail(nullptr, TDH_EINVAL, "gamma must exceed 1");
@@ -281,6 +282,7 @@ static StageArgs base_args(tdh_ctx *c) {
   a.cnt_ge = c->d_cnt_ge;
   a.win = c->d_win;
   a.jc = c->jc;
+  a.jn = c->ncells;
   return a;
 }
 
@@ -394,7 +396,7 @@ extern "C" tdh_status tdh_init_blocks(tdh_ctx *c, const tdh_mesh *m, void *dev_a
   c->imp = (double *)take(L.itotal * sizeof(double));
   c->bf1 = (double *)take(L.itotal * sizeof(double));
   if (c->cfg.grav_kind == 1) c->phi = (double *)take(L.ptotal * sizeof(double));
-  if (c->cfg.eos_kind == 1) c->jc = (int *)take(L.ncells * sizeof(int));
+  if (c->cfg.eos_kind == 1) c->jc = (int *)take(3 * L.ncells * sizeof(int));
   // metadata
   tdh_status s;
   if ((s = dev_alloc(c, &c->d_blocks, c->nb)) || (s = dev_alloc(c, &c->d_lmap, c->lmap.size())) ||
@@ -423,6 +425,8 @@ extern "C" tdh_status tdh_init_blocks(tdh_ctx *c, const tdh_mesh *m, void *dev_a
   c->par.assign(c->nb, 0);
   HIPCHK(c, hipMemcpyAsync(c->d_par, c->par.data(), c->nb * sizeof(int), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->Qa, host_state, L.total * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  if (c->jc) HIPCHK(c, hipMemsetAsync(c->jc, 0xff, 3 * L.ncells * sizeof(int), c->stream));  // no seeds yet (-1)
+  c->seeds_held = false;
   if (c->phi) HIPCHK(c, hipMemcpyAsync(c->phi, host_phi, L.ptotal * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipHostMalloc((void **)&c->h_dtb, c->nb * sizeof(double), hipHostMallocDefault));
@@ -593,7 +597,7 @@ static tdh_status collect_timing(tdh_ctx *c) {
 static tdh_status timed_stage(tdh_ctx *c, const StageArgs &a) {
   const bool t = c->timing && !c->capturing;
   tdh_status s;
-  if (c->cfg.eos_kind == 1 && c->cfg.inv_mode != 0) {
+  if (c->cfg.eos_kind == 1 && c->cfg.inv_mode == 2) {
     HIPCHK(c, launch_seed(a, c->grid, c->stream));
     c->stats.kernel_launches++;
   }
@@ -606,6 +610,21 @@ static tdh_status timed_stage(tdh_ctx *c, const StageArgs &a) {
     c->ev_used++;
   }
   c->stats.kernel_launches++;
+  return TDH_OK;
+}
+
+// Modes 1 and 3 carry seed cells from stage to stage; after a state upload a
+// pass over every block finds them once (outside any captured graph).
+static tdh_status ensure_seeds(tdh_ctx *c) {
+  if (c->cfg.eos_kind != 1 || !(c->cfg.inv_mode == 1 || c->cfg.inv_mode == 3) || c->seeds_held) return TDH_OK;
+  StageArgs a = base_args(c);
+  a.k = 0;
+  a.phase = 1;
+  a.Llo = 0;
+  a.Lhi = kCntSlots - 2;
+  HIPCHK(c, launch_seed(a, c->grid, c->stream));
+  c->stats.kernel_launches++;
+  c->seeds_held = true;
   return TDH_OK;
 }
 
@@ -672,6 +691,7 @@ extern "C" tdh_status tdh_step_level(tdh_ctx *c, int level, double dt) {
     c->dt_coarse = dt;
     c->dt0 = std::ldexp(dt, -c->Lmax);
     HIPCHK(c, launch_set_window(c->d_win, c->t, c->dt0, c->stream));
+    if ((s = ensure_seeds(c))) return s;
   } else if (std::ldexp(dt, level) != c->dt_coarse) {
     return fail(c, TDH_EINVAL, "dt * 2^level must equal the window's coarse step");
   }
@@ -691,6 +711,7 @@ extern "C" tdh_status tdh_run_window(tdh_ctx *c, double dt_coarse, int batched, 
   c->dt0 = std::ldexp(dt_coarse, -c->Lmax);
   const int nsub = 1 << c->Lmax;
   HIPCHK(c, launch_set_window(c->d_win, c->t, c->dt0, c->stream));
+  if ((s = ensure_seeds(c))) return s;
   if (use_graph) {
     // The graph holds the window's launches for this Lmax; the window time,
     // step and the level-dependent work lists live in device memory, so one
@@ -768,8 +789,27 @@ extern "C" tdh_status tdh_set_state(tdh_ctx *c, const double *host) {
   if ((s = ready(c)) || (s = require_window_boundary(c))) return s;
   if (!host) return fail(c, TDH_EINVAL, "null input");
   HIPCHK(c, hipMemcpyAsync(c->Qa, host, c->total * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  if (c->jc) HIPCHK(c, hipMemsetAsync(c->jc, 0xff, 3 * c->ncells * sizeof(int), c->stream));  // stale seeds go
+  c->seeds_held = false;
   c->par.assign(c->nb, 0);
   HIPCHK(c, hipMemcpyAsync(c->d_par, c->par.data(), c->nb * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_get_seed_cells(tdh_ctx *c, int32_t *host) {
+  CHECK_CTX(c);
+  tdh_status s;
+  if ((s = ready(c))) return s;
+  if (!host) return fail(c, TDH_EINVAL, "null output");
+  if (!c->jc) return fail(c, TDH_ESTATE, "no seed cells without a table EOS");
+  if (c->k != 0) return fail(c, TDH_ESTATE, "seed cells are only defined between windows");
+  for (int b = 0; b < c->nb; ++b) {
+    const long long n = c->blk[4 * b];
+    const long long cell0 = c->binfo[b].off / c->nv;
+    const int *src = c->jc + (size_t)c->par[b] * c->ncells + cell0;  // segment of the current buffer
+    HIPCHK(c, hipMemcpyAsync(host + cell0, src, n * n * n * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return TDH_OK;
 }

@@ -74,6 +74,7 @@ def lib():
         "tdh_set_time": ([ctx, d], st),
         "tdh_get_state": ([ctx, P(d)], st),
         "tdh_set_state": ([ctx, P(d)], st),
+        "tdh_get_seed_cells": ([ctx, P(C.c_int32)], st),
         "tdh_eos_invert_batch": ([ctx, vp, vp, vp, vp, vp, C.c_int64, i], st),
         "tdh_eos_eval_batch": ([ctx, vp, vp, vp, vp, C.c_int64], st),
         "tdh_get_stats": ([ctx, P(tdh_stats)], st),
@@ -225,6 +226,13 @@ class Context:
     def get_state(self):
         out = np.empty(self.mesh.offsets(self.nv)[-1])
         self._check(self.L.tdh_get_state(self.ctx, _dp(out)), "tdh_get_state")
+        return out
+
+    def seed_cells(self):
+        """Seed table cells held for the current state (inv_mode 3), per cell."""
+        out = np.empty(self.mesh.ncells, dtype=np.int32)
+        self._check(self.L.tdh_get_seed_cells(self.ctx, out.ctypes.data_as(C.POINTER(C.c_int32))),
+                    "tdh_get_seed_cells")
         return out
 
     def set_state(self, U):

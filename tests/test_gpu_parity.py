@@ -67,7 +67,7 @@ def test_periodic_conservation_gpu(tdh, orc):
     assert np.all(err <= TOL), err
 
 
-@pytest.mark.parametrize("inv_mode", [0, 2])
+@pytest.mark.parametrize("inv_mode", [0, 2, 3])
 def test_c2_table_dual_energy_20_steps(tdh, orc, saha, inv_mode):
     """C2: 128^3 as 64 blocks of 32^3, Saha table, dual energy, Mach 1e7 stream."""
     cfg, mesh, U = W.stream_c2(saha)
@@ -99,6 +99,45 @@ def test_inversion_modes_agree_bitwise_and_with_oracle(tdh, orc, saha):
     assert same.mean() > 0.999
     assert np.max(np.abs(lTg - lTo)) < 1e-12
     ctx.close()
+
+
+def _centre_cells(ctx, cfg, mesh, g, table):
+    """Exact table cell of every cell's state, from the library's bisection."""
+    import torch
+    off = mesh.offsets(6)
+    lr, le = [], []
+    for b in range(mesh.nblocks):
+        q = g[off[b]:off[b + 1]].reshape(6, -1)
+        K = 0.5 * (q[1] ** 2 + q[2] ** 2 + q[3] ** 2) / q[0]
+        Uc = q[4] - K
+        Ueos = np.where((Uc > 0) & (Uc > cfg.eta1 * q[4]), Uc, q[5])
+        Ue = np.maximum(Ueos, q[0] * table.e_floor)
+        lr.append(np.log10(q[0]))
+        le.append(np.log10(Ue / q[0]))
+    _, j, _ = ctx.eos_invert(torch.from_numpy(np.concatenate(lr)), torch.from_numpy(np.concatenate(le)), mode=0)
+    return j.cpu().numpy()
+
+
+def test_temporal_seeds_track_the_state(tdh, saha):
+    """inv_mode 3: after a state upload no seed is held (-1); after steps the
+    held seeds are the table cells of the current state (up to the odd cell at
+    a bracket edge, where host and device logarithms may round apart), and
+    the state equals the bisection run's bit for bit."""
+    cfg, mesh, U = W.stream_c2(saha, nb=2)
+    ctx = tdh.Context(cfg, mesh, U, table=saha, inv_mode=3)
+    assert np.all(ctx.seed_cells() == -1)
+    tdh.run_sync_steps(ctx, 3, dts=[3e-4] * 3)
+    g = ctx.get_state()
+    seeds = ctx.seed_cells()
+    exact = _centre_cells(ctx, cfg, mesh, g, saha)
+    assert np.mean(seeds == exact) > 0.999, np.mean(seeds == exact)
+    ctx.set_state(U)
+    assert np.all(ctx.seed_cells() == -1)
+    ctx.close()
+    ref = tdh.Context(cfg, mesh, U, table=saha, inv_mode=0)
+    tdh.run_sync_steps(ref, 3, dts=[3e-4] * 3)
+    assert np.array_equal(ref.get_state(), g)
+    ref.close()
 
 
 def test_levels_bit_exact_and_dt_parity(tdh, orc):
@@ -267,10 +306,19 @@ def test_c5_shaped_subdomain_lat_window(tdh, orc, saha):
     table, dual energy, moving point mass with excision, LAT levels from the
     library's CFL; one window against the oracle."""
     cfg, mesh, U = W.debris_stream_c5(saha, regions=(4, 3, 2), n_split=6, dxr=1.0)
-    ctx = tdh.Context(cfg, mesh, U, table=saha, inv_mode=2)
+    outs = []
+    for mode in (2, 3):  # centre cells bisected before each stage / carried from the last stage
+        ctx = tdh.Context(cfg, mesh, U, table=saha, inv_mode=mode)
+        dtb, dt0, lev, L = ctx.reduce_dt()
+        lev_o, L_o, _ = orc.lat_assign(cfg, mesh, dtb)
+        assert np.array_equal(lev, lev_o)
+        ctx.run_window(dt0 * 2 ** L, batched=True)
+        ctx.run_window(dt0 * 2 ** L, batched=True)  # a second window starts from carried seeds
+        outs.append(ctx.get_state())
+        ctx.close()
+    assert np.array_equal(outs[0], outs[1])
+    ctx = tdh.Context(cfg, mesh, U, table=saha, inv_mode=3)
     dtb, dt0, lev, L = ctx.reduce_dt()
-    lev_o, L_o, _ = orc.lat_assign(cfg, mesh, dtb)
-    assert np.array_equal(lev, lev_o)
     ctx.run_window(dt0 * 2 ** L, batched=True)
     g = ctx.get_state()
     ctx.close()
