@@ -153,10 +153,10 @@ __device__ __forceinline__ void tbil_pc(const Table &t, int i, double w, int j, 
 
 // Table cell seed from the learned network for this lane's (log rho, log e);
 // every lane of the wave must call it (the hidden layer runs on the matrix cores).
-// lane >= 0: use the lean forward pass with that lane index (see tdh_mlp_dev.hpp)
+// lane: the lane index if the caller has an opaque one (see tdh_mlp_dev.hpp)
 __device__ __forceinline__ int seed_cell_wave(const Seed &s, const Table &t, double lr, double le, int lane = -1) {
   const float x0 = norm01(lr, s.lr_lo, s.lr_hi), x1 = norm01(le, s.le_lo, s.le_hi);
-  const float y = lane >= 0 ? mlp_wave_forward_lean(s.w, x0, x1, lane) : mlp_wave_forward(s.w, x0, x1);
+  const float y = mlp_wave_forward_fast(s.w, x0, x1, lane >= 0 ? lane : (int)(threadIdx.x & 63));
   const double lT = s.lt_lo + 0.5 * ((double)y + 1.0) * (s.lt_hi - s.lt_lo);
   const double x = (lT - t.lT0) / t.dlT;
   if (!(x > 0.0)) return 0;

@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(MlpDev w, Seed s, cons
     const bool ok = q < n;
     const float x0 = ok ? norm01(in[2 * q], s.lr_lo, s.lr_hi) : 0.0f;
     const float x1 = ok ? norm01(in[2 * q + 1], s.le_lo, s.le_hi) : 0.0f;
-    const float y = mlp_wave_forward(w, x0, x1);
+    const float y = mlp_wave_forward_fast(w, x0, x1, l);
     if (ok) out[q] = s.lt_lo + 0.5 * ((double)y + 1.0) * (s.lt_hi - s.lt_lo);
   }
 }
