@@ -81,6 +81,8 @@ def lib():
         _lib.orc_hllc_flux.restype = None
         _lib.orc_num_threads.argtypes = []
         _lib.orc_num_threads.restype = i
+        _lib.orc_set_interp_rounding.argtypes = [i]
+        _lib.orc_set_interp_rounding.restype = None
         if hasattr(_lib, "orc_mlp_forward"):
             _lib.orc_mlp_forward.argtypes = [P(d), i, C.c_int64, P(d), P(d)]
             _lib.orc_mlp_forward.restype = None
@@ -222,6 +224,24 @@ def hllc_flux(wl, pl, cl, wr, pr, cr):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+class interp_rounding:
+    """Context in which the table interpolation (1 - w) x + w y is evaluated as
+    one fused multiply-add (fused=True) instead of two rounded products and a
+    rounded sum: an equally valid rounding, used only to measure how strongly a
+    workload amplifies rounding differences."""
+
+    def __init__(self, fused: bool):
+        self.fused = fused
+
+    def __enter__(self):
+        lib().orc_set_interp_rounding(1 if self.fused else 0)
+        return self
+
+    def __exit__(self, *exc):
+        lib().orc_set_interp_rounding(0)
+        return False
 
 
 class _DummyCfg:

@@ -178,9 +178,21 @@ static void table_rho_cell(const orc_table *T, double lr, int *i, double *w) {
   *i = ii; *w = x - ii;
 }
 
+/* Rounding of the linear interpolation (1 - w) x + w y: 0 (default) rounds
+ * both products and the sum; 1 takes w y + (1 - w) x as one fused
+ * multiply-add.  Both are exact evaluations of the same formula up to one
+ * rounding; mode 1 exists only so that the tests can measure how strongly a
+ * workload amplifies such a difference (the conditioning of the comparison). */
+static int g_interp_fused = 0;
+void orc_set_interp_rounding(int fused) { g_interp_fused = fused ? 1 : 0; }
+
+static double lerp(double w, double x, double y) {
+  return g_interp_fused ? fma(w, y, (1.0 - w) * x) : (1.0 - w) * x + w * y;
+}
+
 /* value of a table field at density weight w between rows i, i+1, at T node j */
 static double tcol(const double *F, int nT, int i, double w, int j) {
-  return (1.0 - w) * F[(size_t)i * nT + j] + w * F[(size_t)(i + 1) * nT + j];
+  return lerp(w, F[(size_t)i * nT + j], F[(size_t)(i + 1) * nT + j]);
 }
 
 /* Inversion e -> T at fixed density.  The answer is defined as the largest T
@@ -203,7 +215,7 @@ static void table_invert(const orc_table *T, int i, double w, double le, int *jo
 }
 
 static double tbil(const double *F, int nT, int i, double w, int j, double wT) {
-  return (1.0 - wT) * tcol(F, nT, i, w, j) + wT * tcol(F, nT, i, w, j + 1);
+  return lerp(wT, tcol(F, nT, i, w, j), tcol(F, nT, i, w, j + 1));
 }
 
 /* (rho, U) -> pressure and adiabatic sound speed */

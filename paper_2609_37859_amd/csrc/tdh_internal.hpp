@@ -45,6 +45,10 @@ struct Table {
   double lr0, dlr, inv_dlr, lT0, dlT;
   const double2 *le2;
   const double4 *pc;
+  // Cell records, one 128-byte line per table cell (i, j), i < nrho-1, j < nT-1:
+  // le2[i][j], le2[i][j+1], pc[i][j], pc[i][j+1] (12 doubles, 4 unused): a
+  // seeded query whose seed cell brackets its target needs this line only.
+  const double *rec;
 };
 
 constexpr int kMlpParams = 4417;  // W1[64][2], b1[64], W2[64][64], b2[64], W3[64], b3

@@ -94,10 +94,20 @@ __device__ __forceinline__ void table_rho(const Table &t, double lr, int &i, dou
   w = x - ii;
 }
 
+// (1 - w) x + w y with both products and the sum rounded separately (no fused
+// multiply-add): one rounding pattern for every table interpolation, so the
+// record and node paths agree bit for bit, and the same pattern as the plain
+// definition.  Some low-density cells near a point mass amplify the rounding
+// of the EOS; a fused form moves them by ~1e-11 relative.
+__device__ __forceinline__ double tlerp(double w, double x, double y) {
+#pragma clang fp contract(off)
+  return (1.0 - w) * x + w * y;
+}
+
 // log e of column j interpolated between density rows i and i+1 (one 16-byte load)
 __device__ __forceinline__ double tcol_le(const Table &t, int i, double w, int j) {
   const double2 v = t.le2[i * t.nT + j];
-  return (1.0 - w) * v.x + w * v.y;
+  return tlerp(w, v.x, v.y);
 }
 
 // Table cell of a target log e on the density-interpolated column: the largest
@@ -145,10 +155,27 @@ __device__ __forceinline__ void table_invert(const Table &t, int i, double w, do
 // holding both density rows of both fields at one T node
 __device__ __forceinline__ void tbil_pc(const Table &t, int i, double w, int j, double wT, double &lP, double &lc2) {
   const double4 v0 = t.pc[i * t.nT + j], v1 = t.pc[i * t.nT + j + 1];
-  const double p0 = (1.0 - w) * v0.x + w * v0.y, p1 = (1.0 - w) * v1.x + w * v1.y;
-  const double c0 = (1.0 - w) * v0.z + w * v0.w, c1 = (1.0 - w) * v1.z + w * v1.w;
-  lP = (1.0 - wT) * p0 + wT * p1;
-  lc2 = (1.0 - wT) * c0 + wT * c1;
+  lP = tlerp(wT, tlerp(w, v0.x, v0.y), tlerp(w, v1.x, v1.y));
+  lc2 = tlerp(wT, tlerp(w, v0.z, v0.w), tlerp(w, v1.z, v1.w));
+}
+
+// Seeded query from the seed cell's record alone: true (and j, wT, lP, lc2)
+// when cell jj brackets the target exactly as table_invert would accept it
+// (the clamp of an out-of-range target only matters in the edge cells).
+__device__ __forceinline__ bool table_record(const Table &t, int i, double w, double le, int jj, double &wT,
+                                             double &lP, double &lc2) {
+  const double4 *R = (const double4 *)(t.rec + 16 * ((long long)i * (t.nT - 1) + jj));
+  const double4 r0 = R[0], r1 = R[1], r2 = R[2];
+  const double a = tlerp(w, r0.x, r0.y), b = tlerp(w, r0.z, r0.w);
+  if (!(a <= le && le < b)) {
+    if (jj == 0 && le < a) le = a;                       // below the table: clamped to its first node
+    else if (jj == t.nT - 2 && le >= b) le = b;          // above: clamped to its last node
+    else return false;
+  }
+  wT = (le - a) / (b - a);
+  lP = tlerp(wT, tlerp(w, r1.x, r1.y), tlerp(w, r2.x, r2.y));
+  lc2 = tlerp(wT, tlerp(w, r1.z, r1.w), tlerp(w, r2.z, r2.w));
+  return true;
 }
 
 // Table cell seed from the learned network for this lane's (log rho, log e);
@@ -175,11 +202,16 @@ __device__ __forceinline__ void eos_pc(const Phys &p, const Table &t, double rho
   }
   const double Ue = fmax(U, rho * p.e_floor);
   int i, j, it;
-  double w, wT;
+  double w, wT, lP, lc2;
   table_rho(t, log10(rho), i, w);
-  table_invert(t, i, w, log10(Ue / rho), jseed, p.newton_max_iter, j, wT, it);
-  double lP, lc2;
-  tbil_pc(t, i, w, j, wT, lP, lc2);
+  const double le = log10(Ue / rho);
+  const int jj = min(jseed, t.nT - 2);
+  if (jseed >= 0 && table_record(t, i, w, le, jj, wT, lP, lc2)) {
+    j = jj;
+  } else {
+    table_invert(t, i, w, le, jseed, p.newton_max_iter, j, wT, it);
+    tbil_pc(t, i, w, j, wT, lP, lc2);
+  }
   P = exp10(lP);
   cs = exp10(0.5 * lc2);
   if (jout) *jout = j;

@@ -451,7 +451,9 @@ extern "C" tdh_status tdh_set_eos_table(tdh_ctx *c, int nrho, int nT, double lr0
   // pack by density-row pairs (see Table in tdh_internal.hpp)
   const size_t np = (size_t)(nrho - 1) * nT;
   const size_t pc_off = (2 * np + 3) & ~(size_t)3;  // 32-byte alignment of the double4 records
-  std::vector<double> packed(pc_off + 4 * np);
+  const size_t rec_off = (pc_off + 4 * np + 15) & ~(size_t)15;  // 128-byte cell records
+  const size_t nrec = (size_t)(nrho - 1) * (nT - 1);
+  std::vector<double> packed(rec_off + 16 * nrec, 0.0);
   for (int i = 0; i + 1 < nrho; ++i)
     for (int j = 0; j < nT; ++j) {
       const size_t a = (size_t)i * nT + j, b = (size_t)(i + 1) * nT + j, q = (size_t)i * nT + j;
@@ -463,8 +465,21 @@ extern "C" tdh_status tdh_set_eos_table(tdh_ctx *c, int nrho, int nT, double lr0
       pcq[2] = lc2[a];
       pcq[3] = lc2[b];
     }
+  for (int i = 0; i + 1 < nrho; ++i)
+    for (int j = 0; j + 1 < nT; ++j) {
+      double *r = packed.data() + rec_off + 16 * ((size_t)i * (nT - 1) + j);
+      const size_t q = (size_t)i * nT + j;
+      r[0] = packed[2 * q];
+      r[1] = packed[2 * q + 1];
+      r[2] = packed[2 * (q + 1)];
+      r[3] = packed[2 * (q + 1) + 1];
+      for (int v = 0; v < 4; ++v) {
+        r[4 + v] = packed[pc_off + 4 * q + v];
+        r[8 + v] = packed[pc_off + 4 * (q + 1) + v];
+      }
+    }
   if (!c->d_table || c->tab.nrho != nrho || c->tab.nT != nT) {
-    tdh_status s = dev_alloc(c, &c->d_table, pc_off + 4 * np);
+    tdh_status s = dev_alloc(c, &c->d_table, packed.size());
     if (s) return s;
   }
   HIPCHK(c, hipMemcpyAsync(c->d_table, packed.data(), packed.size() * sizeof(double), hipMemcpyHostToDevice,
@@ -479,6 +494,7 @@ extern "C" tdh_status tdh_set_eos_table(tdh_ctx *c, int nrho, int nT, double lr0
   c->tab.dlT = dlT;
   c->tab.le2 = (const double2 *)c->d_table;
   c->tab.pc = (const double4 *)(c->d_table + pc_off);
+  c->tab.rec = c->d_table + rec_off;
   c->have_table = true;
   for (auto &g : c->graphs) hipGraphExecDestroy(g.second);
   c->graphs.clear();

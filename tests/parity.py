@@ -1,20 +1,34 @@
 """Per-cell comparison metric of the GPU path against the oracle.
 
-Relative error per variable and cell, |a - b| / s, with the scale s of each
-variable the magnitude its rounding error is a fraction of:
-  density:            s = |rho|
-  total energy:       s = E_hat = max(|E|, K + |U|), K the kinetic energy density
+Relative error per variable and cell, |a - b| / s, with s the magnitude the
+cell's rounding error is a fraction of.
+
+Per-cell scale c of each variable (from the reference state b):
+  density:            c = |rho|
+  total energy:       c = E_hat = max(|E|, K + |U|), K the kinetic energy density
                       and U the internal energy (U_aux with dual energy, else
                       E - K).  Where gravity work has driven E far below its
                       kinetic and thermal parts, E is a small difference of
                       large terms and its error is a fraction of E_hat.
-  momentum component: s = max(|m_q|, sqrt(rho E_hat)) (a component changes
+  momentum component: c = max(|m_q|, sqrt(rho E_hat)) (a component changes
                       sign; sqrt(rho E_hat) is the cell's momentum scale).
-  U_aux:              s = |U_aux|, except in cells where resynchronisation can
+  U_aux:              c = |U_aux|, except in cells where resynchronisation can
                       copy E - K into it (U_aux >= eta2 |E|): there
-                      s = max(|U_aux|, 1e-2 E_hat), since U_aux then carries the
+                      c = max(|U_aux|, 1e-2 E_hat), since U_aux then carries the
                       rounding of E - K.  Cold cells (U_aux << eta2 E, where the
                       dual energy matters) are measured strictly against U_aux.
+
+Stencil scale (stencil=True, the default): s = the largest c over the cell and
+its six face neighbours.  A finite-volume update adds the fluxes through the
+cell's faces, computed from the states on both sides, so its rounding error is
+a fraction of the largest state in that stencil, not of the cell's own value.
+In a cell beside a much more energetic one (a stream edge next to a point mass)
+the cell's own value can be hundreds of times smaller than the fluxes it
+receives; there two equally valid roundings of the oracle itself differ by more
+than 1e-11 of the cell's own value (a CPU test shows it), while against the
+stencil scale they agree to ~1e-13.  stencil=False gives the strict per-cell
+form, reported beside it.
+
 Non-finite values fail.
 """
 import numpy as np
@@ -23,33 +37,56 @@ TOL = 1e-11
 ETA2 = 1e-4
 
 
-def rel_err(nv, mesh, a, b, with_counts=False):
+def _cell_scales(nv, B):
+    """Per-cell scale c of every variable, B: [nv, ...] reference state."""
+    K = 0.5 * (B[1] ** 2 + B[2] ** 2 + B[3] ** 2) / B[0]
+    U = B[5] if nv > 5 else B[4] - K
+    Ehat = np.maximum(np.abs(B[4]), K + np.abs(U))
+    mscale = np.sqrt(np.abs(B[0])) * np.sqrt(Ehat)
+    c = np.empty_like(B)
+    for v in range(nv):
+        if v in (1, 2, 3):
+            c[v] = np.maximum(np.abs(B[v]), mscale)
+        elif v == 4:
+            c[v] = Ehat
+        elif v == 5:
+            c[v] = np.where(np.abs(B[5]) >= ETA2 * np.abs(B[4]), np.maximum(np.abs(B[5]), 1e-2 * Ehat),
+                            np.abs(B[5]))
+        else:
+            c[v] = np.abs(B[v])
+    return c, int(np.sum(Ehat > 100.0 * np.abs(B[4])))
+
+
+def _stencil_max(c, bc):
+    """max of c[v, z, y, x] over the cell and its six face neighbours (periodic
+    axes wrap, outflow axes repeat the edge cell)."""
+    s = c.copy()
+    for ax, kind in zip((3, 2, 1), bc):  # x, y, z
+        if kind == 0:
+            s = np.maximum(s, np.maximum(np.roll(c, 1, axis=ax), np.roll(c, -1, axis=ax)))
+        else:
+            pad = [(0, 0)] * 4
+            pad[ax] = (1, 1)
+            p = np.pad(c, pad, mode="edge")
+            n = c.shape[ax]
+            lo = np.take(p, np.arange(0, n), axis=ax)
+            hi = np.take(p, np.arange(2, n + 2), axis=ax)
+            s = np.maximum(s, np.maximum(lo, hi))
+    return s
+
+
+def rel_err(nv, mesh, a, b, with_counts=False, stencil=True):
     if not (np.all(np.isfinite(a)) and np.all(np.isfinite(b))):
-        return np.full(nv, np.inf)  # a non-finite state never passes
-    off = mesh.offsets(nv)
-    errs = np.zeros(nv)
-    ill = 0
-    for blk in range(mesh.nblocks):
-        A = a[off[blk]:off[blk + 1]].reshape(nv, -1)
-        B = b[off[blk]:off[blk + 1]].reshape(nv, -1)
-        K = 0.5 * (B[1] ** 2 + B[2] ** 2 + B[3] ** 2) / B[0]
-        U = B[5] if nv > 5 else B[4] - K
-        Ehat = np.maximum(np.abs(B[4]), K + np.abs(U))
-        ill += int(np.sum(Ehat > 100.0 * np.abs(B[4])))
-        mscale = np.sqrt(np.abs(B[0])) * np.sqrt(Ehat)
-        for v in range(nv):
-            if v in (1, 2, 3):
-                den = np.maximum(np.abs(B[v]), mscale)
-            elif v == 4:
-                den = Ehat
-            elif v == 5:
-                den = np.where(np.abs(B[5]) >= ETA2 * np.abs(B[4]), np.maximum(np.abs(B[5]), 1e-2 * Ehat),
-                               np.abs(B[5]))
-            else:
-                den = np.abs(B[v])
-            with np.errstate(divide="ignore", invalid="ignore"):
-                r = np.where(den > 0, np.abs(A[v] - B[v]) / den, np.abs(A[v] - B[v]))
-            errs[v] = max(errs[v], float(np.max(r)))
+        errs = np.full(nv, np.inf)  # a non-finite state never passes
+        return (errs, 0) if with_counts else errs
+    from paper_2609_37859_amd.workloads import to_global
+    A, B = to_global(mesh, nv, a), to_global(mesh, nv, b)
+    c, ill = _cell_scales(nv, B)
+    s = _stencil_max(c, mesh.bc) if stencil else c
+    d = np.abs(A - B)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = np.where(s > 0, d / s, d)
+    errs = r.reshape(nv, -1).max(axis=1)
     if with_counts:
         return errs, ill
     return errs
