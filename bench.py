@@ -22,8 +22,18 @@ entry is for the stage kernel (HIP events on the library's stream); the CPU
 baseline is the FP64 oracle on the host, on a bounded number of steps of the
 same workload, and its final state doubles as the accuracy check of the GPU
 run.
+
+The "lat" object times whole LAT windows (CFL reduction, level assignment,
+2^Lmax sub-cycles) on the full-size polytrope (ideal gas, fixed potential) and
+on the production-shaped mesh (4096 mixed 16^3/32^3 blocks, table EOS, point
+mass): the batched forms (one launch per RK phase for all active levels,
+window captured in a hipGraph) beside the plain form (one launch per level).
+It reports cell-updates/s from the library's update counters and the
+sync-equivalent rate (cells x 2^Lmax per window over the time), which shows
+the work LAT saves.
 """
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -114,6 +124,68 @@ def run_form(T, W, cfg, mesh, U, table, steps, warmup, inv_mode, batched, seed_p
     return el, stage_ms, launches, st, tile
 
 
+def run_lat(T, W, cfg, mesh, U, windows, warmup, inv_mode=0, batched=True, graph=False, table=None, phi=None,
+            seed_params=None):
+    """LAT windows (reduce_dt, level assignment, one window of 2^Lmax sub-cycles)
+    timed end to end; returns rates from the library's own update counters."""
+    import torch
+    ctx = T.Context(cfg, mesh, U, phi=phi, table=table, inv_mode=inv_mode)
+    if seed_params is not None:
+        ctx.mlp_init(seed_params, W.seed_ranges(table))
+        ctx.mlp_enable_seed(True)
+    ctx.autotune(reps=1)
+    for _ in range(warmup):
+        _, dt0, lev, L = ctx.reduce_dt()
+        ctx.run_window(dt0 * 2 ** L, batched=batched, graph=graph)
+    ctx.sync()
+    st0 = ctx.stats()
+    sync_equiv = 0
+    hist = np.zeros(8, dtype=np.int64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(windows):
+        _, dt0, lev, L = ctx.reduce_dt()
+        ctx.run_window(dt0 * 2 ** L, batched=batched, graph=graph)
+        sync_equiv += mesh.ncells * 2 ** L
+        hist[:len(np.bincount(lev))] += np.bincount(lev)
+    ctx.sync()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st1 = ctx.stats()
+    tile = T.tile_shapes()[ctx.get_tile()]
+    ctx.close()
+    cu = st1["cell_updates"] - st0["cell_updates"]
+    bu = st1["block_updates"] - st0["block_updates"]
+    return {"value": cu / el, "sync_equivalent": sync_equiv / el, "ms_per_window": 1e3 * el / windows,
+            "windows": windows, "block_updates": int(bu), "block_updates_sync": int(sync_equiv // mesh.ncells *
+                                                                                      mesh.nblocks),
+            "levels": [int(v) for v in np.trim_zeros(hist, "b")], "tile": tile}
+
+
+def lat_section(T, W, table, seed_params, windows, warmup):
+    """LAT-batched forms beside the plain per-level form on the two LAT workloads."""
+    out = {}
+    cfg, mesh, U, phi, info = W.polytrope_c3()
+    cfg = dataclasses.replace(cfg, merge_frac=0.01)  # performance runs merge sparse top bins
+    out["polytrope"] = {
+        "workload": "256^3 as 512 MeshBlocks of 32^3, n=1.5 polytrope (1 Msun, 1 Rsun) in a 1e-10 atmosphere, fixed "
+                    "potential, ideal gas, N_LAT=3, merge_frac 0.01, outflow",
+        "batched_graph": run_lat(T, W, cfg, mesh, U, windows, warmup, batched=True, graph=True, phi=phi),
+        "plain": run_lat(T, W, cfg, mesh, U, windows, warmup, batched=False, graph=False, phi=phi)}
+    cfg, mesh, U = W.debris_stream_c5(table)
+    cfg = dataclasses.replace(cfg, merge_frac=0.01)
+    out["production"] = {
+        "workload": "4096 MeshBlocks (1688 x 32^3 + 2408 x 16^3, 65.2M cells), Saha table EOS, dual energy, "
+                    "1e3 Msun point mass with excision in a moving frame, debris stream, N_LAT=3, merge_frac 0.01",
+        "learned": run_lat(T, W, cfg, mesh, U, windows, warmup, inv_mode=1, batched=True, graph=True, table=table,
+                           seed_params=seed_params),
+        "temporal": run_lat(T, W, cfg, mesh, U, windows, warmup, inv_mode=3, batched=True, graph=True,
+                            table=table),
+        "plain": run_lat(T, W, cfg, mesh, U, windows, warmup, inv_mode=0, batched=False, graph=False,
+                         table=table)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +196,8 @@ def main():
     ap.add_argument("--forms", default="learned,temporal,chained,plain",
                     help="comma list of forms to time: learned, temporal, chained, plain (learned is the headline "
                          "when present)")
+    ap.add_argument("--lat-windows", type=int, default=3,
+                    help="timed LAT windows per form on the polytrope and production-shaped workloads (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -178,6 +252,7 @@ def main():
         if name in forms:
             res[name] = run_form(T, W, cfg, mesh, U, table, args.steps, args.warmup, inv_mode=mode, batched=batched,
                                  seed_params=params if mode == 1 else None)
+    lat = lat_section(T, W, table, params, args.lat_windows, 1) if args.lat_windows > 0 else None
     head = "learned" if "learned" in res else next(iter(res))
     el, stage_ms, launches, st, tile = res[head]
 
@@ -220,6 +295,7 @@ def main():
                      "kernel": "stage_tiled", "avg_launch_ms": stage_ms / max(launches, 1),
                      "algorithmic_bytes_per_cell_update": 5 * nv * 8},
         "cpu_baseline": cpu,
+        "lat": lat,
     }
     print(json.dumps(out), flush=True)
 

@@ -189,9 +189,14 @@ tdh_status tdh_eos_invert_batch(tdh_ctx *ctx, const double *dev_lrho, const doub
 tdh_status tdh_eos_eval_batch(tdh_ctx *ctx, const double *dev_rho, const double *dev_U, double *dev_P,
                               double *dev_cs, int64_t n);
 
-/* Stage-kernel variants: tdh_num_tiles() of them, id -> (x, y, z) tile edges
- * and the waves per SIMD its register budget targets (host_dims4[4]).  Every
- * variant gives bit-identical results; a tile must divide the smallest block.
+/* Stage-kernel variants: tdh_num_tiles() of them.  id -> host_dims4[4]:
+ *   fused form (one kernel; a workgroup per tile, faces through LDS):
+ *     (x, y, z) tile edges and the waves per SIMD its register budget targets;
+ *     a tile must divide the smallest block;
+ *   split form (a face-flux kernel per axis writing the faces of every active
+ *     block to HBM, then a per-cell update kernel; fits every mesh):
+ *     (0, waves per SIMD of the face kernels, of the update kernel, 0).
+ * Every variant gives bit-identical results.
  * tdh_autotune times one stage over all blocks reps times per fitting shape
  * (state unchanged), keeps the fastest, returns its id and per-shape
  * milliseconds (host_ms [tdh_num_tiles()], -1 where a shape does not fit;

@@ -12,6 +12,9 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions stay off: they are generated from scalar code otherwise
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no multiply-add contraction: every stage-kernel form (and the oracle)
+    # rounds each product and sum on its own, so the forms agree bit for bit
+    "-ffp-contract=off",
     "-Wno-unused-command-line-argument",
 ]
 

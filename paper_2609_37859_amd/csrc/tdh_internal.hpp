@@ -18,6 +18,7 @@ struct BlockInfo {
   long long off;   // offset (doubles) of the block in every state buffer
   long long poff;  // offset of its (n+2)^3 potential
   long long ioff;  // offset of its [6][nv][n^2] face arrays
+  long long foff;  // offset (in faces) of its (n+1) n^2 faces of one axis in the flux arrays
 };
 
 struct MeshDev {
@@ -89,11 +90,16 @@ struct StageArgs {
   int *jc;                  // table cell of each cell's state, one segment per state buffer
                             // (Qa, Qb, Qs; jn cells each), the seeds of the inversion
   long long jn;
+  // split stage form: face fluxes of axis d at flx + d * fstride, per block
+  // [nv + 1][(n+1) n^2] (fluxes, then the face velocity) from its foff
+  double *flx;
+  long long fstride;
+  const int *fitem_start;   // prefix sum of 256-face work items (one axis) over `order`
 };
 
 // host-side launchers (tdh_kernels.hip)
 int num_tiles();
-void tile_shape(int id, int *dims);  // x, y, z edges and waves per SIMD of variant id
+void tile_shape(int id, int *dims);  // x, y, z edges and waves per SIMD of variant id (x = 0: split form)
 hipError_t launch_stage(const StageArgs &a, int tile, int grid, hipStream_t s);
 hipError_t launch_seed(const StageArgs &a, int grid, hipStream_t s);
 hipError_t launch_set_window(double *win, double t, double dt0, hipStream_t s);

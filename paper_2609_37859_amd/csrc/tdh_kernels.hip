@@ -377,7 +377,7 @@ __device__ __forceinline__ long long uni(long long x) {
 __device__ __forceinline__ BlockInfo uni(const BlockInfo &b) {
   BlockInfo r;
   r.n = uni(b.n); r.ox = uni(b.ox); r.oy = uni(b.oy); r.oz = uni(b.oz);
-  r.off = uni(b.off); r.poff = uni(b.poff); r.ioff = uni(b.ioff);
+  r.off = uni(b.off); r.poff = uni(b.poff); r.ioff = uni(b.ioff); r.foff = uni(b.foff);
   return r;
 }
 
@@ -385,6 +385,31 @@ __device__ __forceinline__ BlockInfo uni(const BlockInfo &b) {
 // buffer (0: Qa, 1: Qb, 2: Qs) given the block's parity.
 __device__ __forceinline__ int jseg_in(const StageArgs &a, int par) { return a.phase == 1 ? par : 2; }
 __device__ __forceinline__ int jseg_out(const StageArgs &a, int par) { return a.phase == 1 ? 2 : 1 - par; }
+
+// Work items of a persistent launch, XCD-aware.  Workgroups are dispatched to
+// the eight XCDs round robin (workgroup w on XCD w % 8), so each XCD takes a
+// contiguous share of the items: neighbouring tiles, whose halos overlap,
+// then run under one L2.
+struct ItemRange {
+  int first, end, step;
+};
+__device__ __forceinline__ ItemRange xcd_items(int i0, int i1) {
+  constexpr int kXcd = 8;
+  const int w = (int)blockIdx.x, G = (int)gridDim.x;
+  ItemRange r;
+  if (G < kXcd) {  // too few workgroups to give every XCD some: plain striding
+    r.first = i0 + w;
+    r.end = i1;
+    r.step = G;
+    return r;
+  }
+  const int x = w % kXcd;
+  const int total = i1 - i0, per = (total + kXcd - 1) / kXcd;
+  r.first = i0 + min(total, x * per) + w / kXcd;
+  r.end = i0 + min(total, (x + 1) * per);
+  r.step = G / kXcd + (x < G % kXcd ? 1 : 0);  // workgroups on this XCD
+  return r;
+}
 
 struct TileCtx {
   int b;
@@ -395,6 +420,209 @@ struct TileCtx {
   Src own;
 };
 
+// ---------------------------------------------------------------------------
+// pieces shared by the two stage-kernel forms (so that they agree bit for bit)
+// ---------------------------------------------------------------------------
+// PLM states either side of a face from four cells along the axis (q1 | q2 are
+// the cells left | right of the face)
+__device__ __forceinline__ void plm_face(double q0, double q1, double q2, double q3, double &l, double &r) {
+  l = q1 + 0.5 * vanleer(q1 - q0, q2 - q1);
+  r = q2 - 0.5 * vanleer(q2 - q1, q3 - q2);
+}
+
+// Flux through one face along D from its reconstructed states (rotated:
+// normal velocity first): EOS of both states, HLLC, auxiliary-energy flux and
+// face velocity, the excision rule, and for block-boundary faces the stage-1
+// flux or the time-integrated impulse.  Gf receives the fluxes in conserved
+// order (slots 0..NV-1) and the face velocity (slot 6).
+//   fr: local coordinates of the cell right of the face; nbo: block owning the
+//   cell across a block face (-1 beyond an outflow edge); seedl: seed cell of
+//   the left state (-1: none).
+template <int NV, int D>
+__device__ __forceinline__ void face_flux(const StageArgs &a, const BlockInfo &B, int fb, double t, double dtb,
+                                          const int *fr, const double *wl, const double *wr, int seedl, int nbo,
+                                          double *Gf) {
+  constexpr int PN = 1 + D, P1 = 1 + (D + 1) % 3, P2 = 1 + (D + 2) % 3;
+  const Phys &p = a.p;
+  const MeshDev &m = a.m;
+  const int n = B.n;
+  double pl, cl, pr, cr;
+  int jl = -1;
+  eos_pc(p, a.t, wl[0], wl[4], seedl, pl, cl, &jl);
+  eos_pc(p, a.t, wr[0], wr[4], p.inv_mode == 0 ? -1 : jl, pr, cr);
+  double F[5];
+  hllc(wl, pl, cl, wr, pr, cr, F);
+  double FA = 0.0, vf;
+  {
+    const bool up_left = F[0] >= 0.0;
+    const double ru = up_left ? wl[0] : wr[0];
+    if (NV > 5) FA = F[0] * ((up_left ? wl[5] : wr[5]) / ru);
+    vf = F[0] / ru;
+  }
+  if (p.grav_kind == 2 && p.r_exc > 0.0) {
+    int gl[3] = {B.ox + fr[0], B.oy + fr[1], B.oz + fr[2]};
+    const bool eR = excised(p, m, gl[0], gl[1], gl[2], t);
+    gl[D] -= 1;
+    const bool eL = excised(p, m, gl[0], gl[1], gl[2], t);
+    if (eL != eR) {
+      const bool into = eR ? (F[0] >= 0.0) : (F[0] <= 0.0);
+      if (!into) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) F[v] = 0.0;
+        FA = 0.0;
+        vf = 0.0;
+      }
+    }
+  }
+  Gf[IDN] = F[0];
+  Gf[PN] = F[1];
+  Gf[P1] = F[2];
+  Gf[P2] = F[3];
+  Gf[IEN] = F[4];
+  Gf[5] = FA;
+  Gf[6] = vf;
+  // block-boundary faces: stage-1 flux, then the time-integrated impulse
+  const int bd = fr[D];
+  if (bd == 0 || bd == n) {
+    const int side = bd == n;
+    const int u0 = D == 0 ? fr[1] : fr[0];
+    const int u1 = D == 2 ? fr[1] : fr[2];
+    const long long nn2 = (long long)n * n;
+    const long long base = B.ioff + (long long)(2 * D + side) * NV * nn2 + (long long)u1 * n + u0;
+    // only faces towards a block on another schedule take part in the reflux
+    const int fn = nbo >= 0 ? a.fac[nbo] : fb;
+    if (fn == fb) {
+    } else if (a.phase == 1) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) a.bf1[base + v * nn2] = Gf[v];
+    } else {
+      const double area = m.dx[(D + 1) % 3] * m.dx[(D + 2) % 3];
+      const int fw = fb > fn ? fb : fn;
+      const bool overwrite = (a.k & (fw - 1)) == 0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const long long ix = base + v * nn2;
+        const double Is = 0.5 * (a.bf1[ix] + Gf[v]) * area * dtb;
+        a.imp[ix] = overwrite ? Is : a.imp[ix] + Is;
+      }
+    }
+  }
+}
+
+// One axis's contribution to a cell's right-hand side (divergence, face-
+// velocity divergence, gravity) and the neighbour energies of the resync.
+// Flo / Fhi: the cell's low / high face along D (slots as face_flux); Em, Ep:
+// stage-input E of the neighbours along D; rho: the cell's stage-input density.
+template <int NV, int D>
+__device__ __forceinline__ void axis_update(const StageArgs &a, const BlockInfo &B, double t, const int *lc,
+                                            const double *Flo, const double *Fhi, double rho, double Em, double Ep,
+                                            double *rhs, double &divv, double &emax) {
+  constexpr int PN = 1 + D;
+  const Phys &p = a.p;
+  const MeshDev &m = a.m;
+  const double idx = m.inv_dx[D];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) rhs[v] -= (Fhi[v] - Flo[v]) * idx;
+  divv += (Fhi[6] - Flo[6]) * idx;
+  emax = fmax(emax, fmax(Em, Ep));
+  if (p.grav_kind) {
+    int im[3] = {lc[0], lc[1], lc[2]}, ip[3] = {lc[0], lc[1], lc[2]};
+    im[D] -= 1;
+    ip[D] += 1;
+    const double pm = phi_at(a, B, im[0], im[1], im[2], t);
+    const double p0 = phi_at(a, B, lc[0], lc[1], lc[2], t);
+    const double pp = phi_at(a, B, ip[0], ip[1], ip[2], t);
+    rhs[PN] -= rho * (pp - pm) / (2.0 * m.dx[D]);
+    rhs[IEN] -= (Fhi[IDN] * (pp - p0) + Flo[IDN] * (p0 - pm)) / (2.0 * m.dx[D]);
+  }
+  // Pin the sums here: otherwise the compiler may sink this axis's arithmetic
+  // to the final use and keep its inputs live through the remaining axes.
+#pragma unroll
+  for (int v = 0; v < NV; ++v) asm volatile("" : "+v"(rhs[v]));
+  asm volatile("" : "+v"(divv), "+v"(emax));
+}
+
+// RK combine of one cell and everything after it: compression of U_aux,
+// floors, resynchronisation, excision reset, the store, and (modes 1 and 3)
+// the table cell of the output state for the next stage.
+template <int NV, bool NET>
+__device__ __forceinline__ void finish_cell(const StageArgs &a, const BlockInfo &B, const Src &own, int parb, double dtb,
+                                            double tk, const int *lc, long long cell, int jcell, const double *rhs,
+                                            double divv, double emax) {
+  const Phys &p = a.p;
+  const MeshDev &m = a.m;
+  const long long n3 = (long long)B.n * B.n * B.n;
+  double qc[6];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) qc[v] = src_val(own, B.off + v * n3 + cell);
+  const double *Qbase = parb ? a.Qb : a.Qa;
+  double qn[6];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const double qs = qc[v] + dtb * rhs[v];
+    qn[v] = a.phase == 1 ? qs : 0.5 * Qbase[B.off + v * n3 + cell] + 0.5 * qs;
+  }
+  if (NV > 5) {
+    const double tau = a.phase == 1 ? dtb : 0.5 * dtb;
+    if (p.eos_kind == 0) {
+      qn[IAX] = qn[IAX] * exp(-(p.gamma - 1.0) * divv * tau);
+    } else {
+      double Pa, ca;
+      eos_pc(p, a.t, qc[IDN], qn[IAX], p.inv_mode == 0 ? -1 : jcell, Pa, ca);
+      qn[IAX] = qn[IAX] - Pa * divv * tau;
+    }
+    const double uf = u_floor(p, qn[IDN] > p.rho_floor ? qn[IDN] : p.rho_floor);
+    if (qn[IAX] < uf) qn[IAX] = uf;
+  }
+  if (qn[IDN] < p.rho_floor) qn[IDN] = p.rho_floor;
+  {
+    double w[6];
+    c2p(p, qn, w);
+    const double uf = u_floor(p, qn[IDN]);
+    if (w[4] < uf) {
+      qn[IEN] += uf - w[4];
+      if (NV > 5 && qn[IAX] < uf) qn[IAX] = uf;
+    }
+  }
+  if (NV > 5) {
+    const double K = 0.5 * (qn[IM1] * qn[IM1] + qn[IM2] * qn[IM2] + qn[IM3] * qn[IM3]) / qn[IDN];
+    const double Uc = qn[IEN] - K;
+    if (Uc > 0.0 && Uc > p.eta2 * emax) qn[IAX] = Uc;
+  }
+  if (a.phase == 2 && p.grav_kind == 2 && p.r_exc > 0.0) {
+    if (excised(p, m, B.ox + lc[0], B.oy + lc[1], B.oz + lc[2], tk + dtb)) {
+      const double uf = u_floor(p, p.rho_floor);
+      qn[IDN] = p.rho_floor;
+      qn[IM1] = qn[IM2] = qn[IM3] = 0.0;
+      qn[IEN] = uf;
+      if (NV > 5) qn[IAX] = uf;
+    }
+  }
+  double *out = a.phase == 1 ? a.Qs : (parb ? a.Qa : a.Qb);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) out[B.off + v * n3 + cell] = qn[v];
+  if (p.eos_kind == 1 && (p.inv_mode == 1 || p.inv_mode == 3)) {
+    // The table cell of the output state seeds the next stage's queries of
+    // this cell.  Its search starts from the learned network's prediction
+    // (mode 1; the whole wave takes part, every thread owns a cell) or from
+    // the input state's cell (mode 3).
+    double w[6];
+    c2p(p, qn, w);
+    const double Ue = fmax(w[4], w[0] * p.e_floor);
+    const double lr = log10(w[0]), le = log10(Ue / w[0]);
+    int start = jcell;
+    if constexpr (NET) start = seed_cell_wave(a.s, a.t, lr, le, item_tid() & 63);
+    int i, j, it;
+    double wr, wT;
+    table_rho(a.t, lr, i, wr);
+    table_invert(a.t, i, wr, le, start, p.newton_max_iter, j, wT, it);
+    a.jc[jseg_out(a, parb) * a.jn + B.off / NV + cell] = j;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fused form: one workgroup per tile, faces through LDS
+// ---------------------------------------------------------------------------
 template <int TX, int TY, int TZ, int NV, int D>
 __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, double *sW, double *sF, int *sB,
                                           const int *sJc, double *rhs, double &divv, double &emax) {
@@ -410,7 +638,6 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
   const MeshDev &m = a.m;
   const int tid = item_tid();
   const int cc[3] = {tid % TX, (tid / TX) % TY, tid / (TX * TY)};  // own cell in the tile
-  const int n = T.B.n;
   const int Nd = D == 0 ? m.nx : (D == 1 ? m.ny : m.nz);
   // stage the slab: tile extended by two cells along D
 #pragma unroll 1
@@ -431,12 +658,7 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
   __syncthreads();
   // every face of the tile along D, once
 #pragma unroll 1
-  for (int f0 = 0; f0 < NFD; f0 += kChunk) {
-    if (f0 + (tid & ~63) >= NFD) continue;  // the whole wave is idle this round
-    // lanes past the end repeat the last face so the wave stays converged for
-    // the network seed; they store nothing
-    const bool valid = f0 + tid < NFD;
-    const int f = valid ? f0 + tid : NFD - 1;
+  for (int f = tid; f < NFD; f += kChunk) {
     const int fc[3] = {f % F0, (f / F0) % F1, f / (F0 * F1)};
     const int s0 = fc[0] + L0 * (fc[1] + L1 * fc[2]);  // stencil start (tile cell fd - 2)
     double wl[6], wr[6];
@@ -444,12 +666,9 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
 #pragma unroll
     for (int vv = 0; vv < NV; ++vv) {
       const double *col = sW + perm[vv] * G::SLAB + s0;
-      const double q0 = col[0], q1 = col[STR], q2 = col[2 * STR], q3 = col[3 * STR];
-      wl[vv] = q1 + 0.5 * vanleer(q1 - q0, q2 - q1);
-      wr[vv] = q2 - 0.5 * vanleer(q2 - q1, q3 - q2);
+      plm_face(col[0], col[STR], col[2 * STR], col[3 * STR], wl[vv], wr[vv]);
     }
-    double pl, cl, pr, cr;
-    int jl = -1, seedl = -1;
+    int seedl = -1;
     if (p.eos_kind == 1 && p.inv_mode != 0) {
       // seed the left state from the table cell of the adjacent tile cell's centre
       int tc[3] = {fc[0], fc[1], fc[2]};
@@ -457,103 +676,33 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
       if (tc[D] >= (D == 0 ? TX : (D == 1 ? TY : TZ))) tc[D] -= 1;
       seedl = sJc[tc[0] + TX * (tc[1] + TY * tc[2])];
     }
-    eos_pc(p, a.t, wl[0], wl[4], seedl, pl, cl, &jl);
-    eos_pc(p, a.t, wr[0], wr[4], p.inv_mode == 0 ? -1 : jl, pr, cr);
-    if (!valid) continue;
-    double F[5];
-    hllc(wl, pl, cl, wr, pr, cr, F);
-    double FA = 0.0, vf;
-    {
-      const bool up_left = F[0] >= 0.0;
-      const double ru = up_left ? wl[0] : wr[0];
-      if (NV > 5) FA = F[0] * ((up_left ? wl[5] : wr[5]) / ru);
-      vf = F[0] / ru;
-    }
     const int fr[3] = {T.to[0] + fc[0], T.to[1] + fc[1], T.to[2] + fc[2]};  // cell right of the face
-    if (p.grav_kind == 2 && p.r_exc > 0.0) {
-      int gl[3] = {T.B.ox + fr[0], T.B.oy + fr[1], T.B.oz + fr[2]};
-      const bool eR = excised(p, m, gl[0], gl[1], gl[2], T.t);
-      gl[D] -= 1;
-      const bool eL = excised(p, m, gl[0], gl[1], gl[2], T.t);
-      if (eL != eR) {
-        const bool into = eR ? (F[0] >= 0.0) : (F[0] <= 0.0);
-        if (!into) {
-#pragma unroll
-          for (int v = 0; v < 5; ++v) F[v] = 0.0;
-          FA = 0.0;
-          vf = 0.0;
-        }
-      }
-    }
-    double Gf[6];
-    Gf[IDN] = F[0];
-    Gf[PN] = F[1];
-    Gf[P1] = F[2];
-    Gf[P2] = F[3];
-    Gf[IEN] = F[4];
-    Gf[5] = FA;
+    const int side = fr[D] == T.B.n;
+    const int nbo = (fr[D] == 0 || side) ? sB[s0 + (side ? 2 : 1) * STR] : T.b;  // cell across a block face
+    double Gf[7];
+    face_flux<NV, D>(a, T.B, T.fb, T.t, T.dtb, fr, wl, wr, seedl, nbo, Gf);
 #pragma unroll
     for (int v = 0; v < NV; ++v) sF[v * G::NF + f] = Gf[v];
-    sF[6 * G::NF + f] = vf;
-    // block-boundary faces: stage-1 flux, then the time-integrated impulse
-    const int bd = fr[D];
-    if (bd == 0 || bd == n) {
-      const int side = bd == n;
-      const int u0 = D == 0 ? fr[1] : fr[0];
-      const int u1 = D == 2 ? fr[1] : fr[2];
-      const long long nn2 = (long long)n * n;
-      const long long base = T.B.ioff + (long long)(2 * D + side) * NV * nn2 + (long long)u1 * n + u0;
-      // only faces towards a block on another schedule take part in the reflux
-      const int nbo = sB[s0 + (side ? 2 : 1) * STR];  // cell across the block face
-      const int fn = nbo >= 0 ? a.fac[nbo] : T.fb;
-      if (fn == T.fb) {
-      } else if (a.phase == 1) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) a.bf1[base + v * nn2] = Gf[v];
-      } else {
-        {
-          const double area = m.dx[(D + 1) % 3] * m.dx[(D + 2) % 3];
-          const int fw = T.fb > fn ? T.fb : fn;
-          const bool overwrite = (a.k & (fw - 1)) == 0;
-#pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            const long long ix = base + v * nn2;
-            const double Is = 0.5 * (a.bf1[ix] + Gf[v]) * area * T.dtb;
-            a.imp[ix] = overwrite ? Is : a.imp[ix] + Is;
-          }
-        }
-      }
-    }
+    sF[6 * G::NF + f] = Gf[6];
   }
   __syncthreads();
   // own cell: divergence, gravity, neighbour energies
   {
     const int flo = cc[0] + F0 * (cc[1] + F1 * cc[2]);
     const int fhi = flo + FSTR;
-    const double idx = m.inv_dx[D];
+    double Flo[7], Fhi[7];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) rhs[v] -= (sF[v * G::NF + fhi] - sF[v * G::NF + flo]) * idx;
-    divv += (sF[6 * G::NF + fhi] - sF[6 * G::NF + flo]) * idx;
-    const int sbase = cc[0] + L0 * (cc[1] + L1 * cc[2]);
-    emax = fmax(emax, fmax(sW[6 * G::SLAB + sbase + STR], sW[6 * G::SLAB + sbase + 3 * STR]));
-    if (D == 0) emax = fmax(emax, sW[6 * G::SLAB + sbase + 2 * STR]);  // own stage-input E
-    if (p.grav_kind) {
-      const int lc[3] = {T.to[0] + cc[0], T.to[1] + cc[1], T.to[2] + cc[2]};
-      int im[3] = {lc[0], lc[1], lc[2]}, ip[3] = {lc[0], lc[1], lc[2]};
-      im[D] -= 1;
-      ip[D] += 1;
-      const double pm = phi_at(a, T.B, im[0], im[1], im[2], T.t);
-      const double p0 = phi_at(a, T.B, lc[0], lc[1], lc[2], T.t);
-      const double pp = phi_at(a, T.B, ip[0], ip[1], ip[2], T.t);
-      rhs[PN] -= sW[sbase + 2 * STR] * (pp - pm) / (2.0 * m.dx[D]);  // own density
-      rhs[IEN] -= (sF[IDN * G::NF + fhi] * (pp - p0) + sF[IDN * G::NF + flo] * (p0 - pm)) / (2.0 * m.dx[D]);
+    for (int v = 0; v < NV; ++v) {
+      Flo[v] = sF[v * G::NF + flo];
+      Fhi[v] = sF[v * G::NF + fhi];
     }
-    // Pin the sums here: otherwise the compiler sinks this axis's arithmetic
-    // to the final use and keeps every value read from LDS live through the
-    // remaining axes (tens of registers).
-#pragma unroll
-    for (int v = 0; v < NV; ++v) asm volatile("" : "+v"(rhs[v]));
-    asm volatile("" : "+v"(divv), "+v"(emax));
+    Flo[6] = sF[6 * G::NF + flo];
+    Fhi[6] = sF[6 * G::NF + fhi];
+    const int sbase = cc[0] + L0 * (cc[1] + L1 * cc[2]);
+    if (D == 0) emax = fmax(emax, sW[6 * G::SLAB + sbase + 2 * STR]);  // own stage-input E
+    const int lc[3] = {T.to[0] + cc[0], T.to[1] + cc[1], T.to[2] + cc[2]};
+    axis_update<NV, D>(a, T.B, T.t, lc, Flo, Fhi, sW[sbase + 2 * STR], sW[6 * G::SLAB + sbase + STR],
+                       sW[6 * G::SLAB + sbase + 3 * STR], rhs, divv, emax);
   }
   __syncthreads();
 }
@@ -575,7 +724,8 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
   const int i0 = a.item_start[a0], i1 = a.item_start[a1];
   const double dt0 = a.win[1];
   const double tk = a.win[0] + a.k * dt0;
-  for (int item = i0 + (int)blockIdx.x; item < i1; item += (int)gridDim.x) {
+  const ItemRange R = xcd_items(i0, i1);
+  for (int item = R.first; item < R.end; item += R.step) {
     int lo = a0, hi = a1;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
@@ -586,7 +736,6 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
     T.b = uni(a.order[lo]);
     T.B = uni(m.blocks[T.b]);
     const int n = T.B.n;
-    const long long n3 = (long long)n * n * n;
     const int tile = item - uni(a.item_start[lo]);
     const int ntx = n / TX, nty = n / TY;
     T.to[0] = (tile % ntx) * TX;
@@ -601,8 +750,8 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
     const long long cell = ((long long)lc[2] * n + lc[1]) * n + lc[0];
     double rhs[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double divv = 0.0, emax = -INFINITY;
-    // seeded inversion: the table cell of each tile cell's centre state (from
-    // seed_kernel) starts the face and compression queries
+    // seeded inversion: the table cell of each tile cell's stage-input state
+    // starts the face and compression queries
     int jcell = -1;
     const int parb = uni(a.par[T.b]);
     if (p.eos_kind == 1 && p.inv_mode != 0) {
@@ -612,73 +761,168 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
     tile_axis<TX, TY, TZ, NV, 0>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
     tile_axis<TX, TY, TZ, NV, 1>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
     tile_axis<TX, TY, TZ, NV, 2>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
-    // combine (the stage input is read again here rather than held through the axes)
-    double qc[6];
+    finish_cell<NV, NET>(a, T.B, T.own, parb, T.dtb, tk, lc, cell, jcell, rhs, divv, emax);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// split form: a kernel per axis computes every face flux of the active blocks
+// into the flux arrays (one face per thread, no LDS, no barriers), then one
+// kernel per cell sums them.  Same arithmetic as the fused form, bit for bit.
+// ---------------------------------------------------------------------------
+// Item -> block lookup over a prefix array of the level-sorted block order.
+__device__ __forceinline__ int item_slot(const int *start, int a0, int a1, int item) {
+  int lo = a0, hi = a1;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (uni(start[mid]) <= item) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// face (fi, fj, fk) of axis D: the D-th coordinate in [0, n], the others in
+// [0, n), x fastest
+template <int D>
+__device__ __forceinline__ long long face_index(int n, int i, int j, int k) {
+  const int ex = n + (D == 0), ey = n + (D == 1);
+  return (long long)i + (long long)ex * (j + (long long)ey * k);
+}
+
+template <int NV, int D, int OCC>
+__global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void face_kernel(StageArgs a) {
+  constexpr int PN = 1 + D, P1 = 1 + (D + 1) % 3, P2 = 1 + (D + 2) % 3;
+  const Phys &p = a.p;
+  const MeshDev &m = a.m;
+  const int a0 = a.cnt_ge[a.Lhi + 1], a1 = a.cnt_ge[a.Llo];
+  if (a1 <= a0) return;
+  const int i0 = a.fitem_start[a0], i1 = a.fitem_start[a1];
+  const double dt0 = a.win[1];
+  const double tk = a.win[0] + a.k * dt0;
+  const int Nd = D == 0 ? m.nx : (D == 1 ? m.ny : m.nz);
+  const ItemRange R = xcd_items(i0, i1);
+  for (int item = R.first; item < R.end; item += R.step) {
+    const int lo = item_slot(a.fitem_start, a0, a1, item);
+    const int b = uni(a.order[lo]);
+    const BlockInfo B = uni(m.blocks[b]);
+    const int n = B.n;
+    const long long nf = (long long)(n + 1) * n * n;
+    const long long f = (long long)(item - uni(a.fitem_start[lo])) * kChunk + item_tid();
+    if (f >= nf) continue;
+    const int fb = uni(a.fac[b]);
+    const double dtb = fb * dt0;
+    const double t = a.phase == 1 ? tk : tk + dtb;
+    const Src own = source_of<true>(a, fb, b);
+    const int ex = n + (D == 0), ey = n + (D == 1);
+    const int fr[3] = {(int)(f % ex), (int)((f / ex) % ey), (int)(f / ((long long)ex * ey))};  // cell right of the face
+    // the four cells of the stencil along D: primitives, and the block across a block face
+    double W[4][6], wl[6], wr[6];
+    int nbo = b;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) qc[v] = src_val(T.own, T.B.off + v * n3 + cell);
-    const double *Qbase = parb ? a.Qb : a.Qa;
-    double qn[6];
+    for (int s = 0; s < 4; ++s) {
+      int g[3] = {B.ox + fr[0], B.oy + fr[1], B.oz + fr[2]};
+      g[D] += s - 2;
+      double q[6];
+      int nb_;
+      long long id_;
+      load_q(a, b, B, own, fb, g[0], g[1], g[2], q, &nb_, &id_);
+      c2p(p, q, W[s]);
+      if ((s == 1 && fr[D] == 0) || (s == 2 && fr[D] == n))
+        nbo = (m.bc[D] == 0 || (g[D] >= 0 && g[D] < Nd)) ? nb_ : -1;
+    }
+    constexpr int perm[6] = {0, PN, P1, P2, 4, 5};
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const double qs = qc[v] + T.dtb * rhs[v];
-      qn[v] = a.phase == 1 ? qs : 0.5 * Qbase[T.B.off + v * n3 + cell] + 0.5 * qs;
+    for (int vv = 0; vv < NV; ++vv)
+      plm_face(W[0][perm[vv]], W[1][perm[vv]], W[2][perm[vv]], W[3][perm[vv]], wl[vv], wr[vv]);
+    int seedl = -1;
+    if (p.eos_kind == 1 && p.inv_mode != 0) {
+      // seed the left state from the table cell of the nearest own cell left of the face
+      int tc[3] = {fr[0], fr[1], fr[2]};
+      if (tc[D] > 0) tc[D] -= 1;
+      if (tc[D] >= n) tc[D] = n - 1;
+      const int parb = uni(a.par[b]);
+      seedl = a.jc[jseg_in(a, parb) * a.jn + B.off / NV + ((long long)tc[2] * n + tc[1]) * n + tc[0]];
     }
-    if (NV > 5) {
-      const double tau = a.phase == 1 ? T.dtb : 0.5 * T.dtb;
-      if (p.eos_kind == 0) {
-        qn[IAX] = qn[IAX] * exp(-(p.gamma - 1.0) * divv * tau);
-      } else {
-        double Pa, ca;
-        eos_pc(p, a.t, qc[IDN], qn[IAX], p.inv_mode == 0 ? -1 : jcell, Pa, ca);
-        qn[IAX] = qn[IAX] - Pa * divv * tau;
-      }
-      const double uf = u_floor(p, qn[IDN] > p.rho_floor ? qn[IDN] : p.rho_floor);
-      if (qn[IAX] < uf) qn[IAX] = uf;
-    }
-    if (qn[IDN] < p.rho_floor) qn[IDN] = p.rho_floor;
-    {
-      double w[6];
-      c2p(p, qn, w);
-      const double uf = u_floor(p, qn[IDN]);
-      if (w[4] < uf) {
-        qn[IEN] += uf - w[4];
-        if (NV > 5 && qn[IAX] < uf) qn[IAX] = uf;
-      }
-    }
-    if (NV > 5) {
-      const double K = 0.5 * (qn[IM1] * qn[IM1] + qn[IM2] * qn[IM2] + qn[IM3] * qn[IM3]) / qn[IDN];
-      const double Uc = qn[IEN] - K;
-      if (Uc > 0.0 && Uc > p.eta2 * emax) qn[IAX] = Uc;
-    }
-    if (a.phase == 2 && p.grav_kind == 2 && p.r_exc > 0.0) {
-      if (excised(p, m, T.B.ox + lc[0], T.B.oy + lc[1], T.B.oz + lc[2], tk + T.dtb)) {
-        const double uf = u_floor(p, p.rho_floor);
-        qn[IDN] = p.rho_floor;
-        qn[IM1] = qn[IM2] = qn[IM3] = 0.0;
-        qn[IEN] = uf;
-        if (NV > 5) qn[IAX] = uf;
-      }
-    }
-    double *out = a.phase == 1 ? a.Qs : (parb ? a.Qa : a.Qb);
+    double Gf[7];
+    face_flux<NV, D>(a, B, fb, t, dtb, fr, wl, wr, seedl, nbo, Gf);
+    double *F = a.flx + D * a.fstride + (NV + 1) * B.foff;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) out[T.B.off + v * n3 + cell] = qn[v];
-    if (p.eos_kind == 1 && (p.inv_mode == 1 || p.inv_mode == 3)) {
-      // The table cell of the output state seeds the next stage's queries of
-      // this cell.  Its search starts from the learned network's prediction
-      // (mode 1; the whole wave takes part, every thread owns a cell) or from
-      // the input state's cell (mode 3).
-      double w[6];
-      c2p(p, qn, w);
-      const double Ue = fmax(w[4], w[0] * p.e_floor);
-      const double lr = log10(w[0]), le = log10(Ue / w[0]);
-      int start = jcell;
-      if constexpr (NET) start = seed_cell_wave(a.s, a.t, lr, le, item_tid() & 63);
-      int i, j, it;
-      double wr, wT;
-      table_rho(a.t, lr, i, wr);
-      table_invert(a.t, i, wr, le, start, p.newton_max_iter, j, wT, it);
-      a.jc[jseg_out(a, parb) * a.jn + T.B.off / NV + cell] = j;
+    for (int v = 0; v < NV; ++v) F[v * nf + f] = Gf[v];
+    F[NV * nf + f] = Gf[6];
+  }
+}
+
+// stage-input E of global cell g as the reader sees it
+__device__ __forceinline__ double load_E(const StageArgs &a, int b, const BlockInfo &B, const Src &own, int fb, int gx,
+                                         int gy, int gz) {
+  const MeshDev &m = a.m;
+  gx = wrap_axis(gx, m.nx, m.bc[0]);
+  gy = wrap_axis(gy, m.ny, m.bc[1]);
+  gz = wrap_axis(gz, m.nz, m.bc[2]);
+  const int lx = gx - B.ox, ly = gy - B.oy, lz = gz - B.oz;
+  if ((unsigned)lx < (unsigned)B.n && (unsigned)ly < (unsigned)B.n && (unsigned)lz < (unsigned)B.n) {
+    const long long n3 = (long long)B.n * B.n * B.n;
+    return src_val(own, B.off + IEN * n3 + ((long long)lz * B.n + ly) * B.n + lx);
+  }
+  const int nb = block_of(m, gx, gy, gz);
+  const BlockInfo Bn = m.blocks[nb];
+  const Src s = source_of(a, fb, nb);
+  const long long n3 = (long long)Bn.n * Bn.n * Bn.n;
+  return src_val(s, Bn.off + IEN * n3 + ((long long)(gz - Bn.oz) * Bn.n + (gy - Bn.oy)) * Bn.n + (gx - Bn.ox));
+}
+
+template <int NV, bool NET, int OCC>
+__global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void update_kernel(StageArgs a) {
+  const Phys &p = a.p;
+  const MeshDev &m = a.m;
+  const int a0 = a.cnt_ge[a.Lhi + 1], a1 = a.cnt_ge[a.Llo];
+  if (a1 <= a0) return;
+  const int i0 = a.item_start[a0], i1 = a.item_start[a1];
+  const double dt0 = a.win[1];
+  const double tk = a.win[0] + a.k * dt0;
+  const ItemRange R = xcd_items(i0, i1);
+  for (int item = R.first; item < R.end; item += R.step) {
+    const int lo = item_slot(a.item_start, a0, a1, item);
+    const int b = uni(a.order[lo]);
+    const BlockInfo B = uni(m.blocks[b]);
+    const int n = B.n;
+    const long long n3 = (long long)n * n * n;
+    const long long cell = (long long)(item - uni(a.item_start[lo])) * kChunk + item_tid();
+    const int fb = uni(a.fac[b]);
+    const double dtb = fb * dt0;
+    const double t = a.phase == 1 ? tk : tk + dtb;
+    const Src own = source_of<true>(a, fb, b);
+    const int parb = uni(a.par[b]);
+    const int lc[3] = {(int)(cell % n), (int)((cell / n) % n), (int)(cell / ((long long)n * n))};
+    const int g[3] = {B.ox + lc[0], B.oy + lc[1], B.oz + lc[2]};
+    int jcell = -1;
+    if (p.eos_kind == 1 && p.inv_mode != 0) jcell = a.jc[jseg_in(a, parb) * a.jn + B.off / NV + cell];
+    const double rho = src_val(own, B.off + IDN * n3 + cell);
+    double rhs[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double divv = 0.0;
+    double emax = src_val(own, B.off + IEN * n3 + cell);  // own stage-input E
+    const long long nf = (long long)(n + 1) * n * n;
+#define TDH_AXIS(D)                                                                                         \
+    {                                                                                                       \
+      const double *F = a.flx + D * a.fstride + (NV + 1) * B.foff;                                          \
+      const long long flo = face_index<D>(n, lc[0], lc[1], lc[2]);                                          \
+      const long long fhi = flo + (D == 0 ? 1 : (D == 1 ? (long long)n : (long long)n * n));                \
+      double Flo[7], Fhi[7];                                                                                \
+      _Pragma("unroll") for (int v = 0; v <= NV; ++v) {                                                     \
+        Flo[v == NV ? 6 : v] = F[v * nf + flo];                                                             \
+        Fhi[v == NV ? 6 : v] = F[v * nf + fhi];                                                             \
+      }                                                                                                     \
+      int gm[3] = {g[0], g[1], g[2]}, gp[3] = {g[0], g[1], g[2]};                                           \
+      gm[D] -= 1;                                                                                           \
+      gp[D] += 1;                                                                                           \
+      const double Em = load_E(a, b, B, own, fb, gm[0], gm[1], gm[2]);                                      \
+      const double Ep = load_E(a, b, B, own, fb, gp[0], gp[1], gp[2]);                                      \
+      axis_update<NV, D>(a, B, t, lc, Flo, Fhi, rho, Em, Ep, rhs, divv, emax);                              \
     }
+    TDH_AXIS(0)
+    TDH_AXIS(1)
+    TDH_AXIS(2)
+#undef TDH_AXIS
+    finish_cell<NV, NET>(a, B, own, parb, dtb, tk, lc, cell, jcell, rhs, divv, emax);
   }
 }
 
@@ -695,7 +939,8 @@ __global__ __launch_bounds__(kChunk) void seed_kernel(StageArgs a) {
   const int i0 = a.item_start[a0], i1 = a.item_start[a1];
   const Phys &p = a.p;
   const int nv = a.m.nv;
-  for (int item = i0 + (int)blockIdx.x; item < i1; item += (int)gridDim.x) {
+  const ItemRange R = xcd_items(i0, i1);
+  for (int item = R.first; item < R.end; item += R.step) {
     int lo = a0, hi = a1;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
@@ -915,11 +1160,19 @@ __global__ void eos_eval_kernel(Phys p, Table t, const double *rho, const double
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// split-form variants: waves per SIMD the face and the update kernels' registers target
+#define TDH_SPLITS(X) X(4, 3) X(3, 3) X(5, 4)
+
+// Variant ids: the fused tile shapes of TDH_TILES in order, then the split
+// forms of TDH_SPLITS.
 int num_tiles() {
   int n = 0;
 #define TDH_COUNT(x, y, z, o) ++n;
   TDH_TILES(TDH_COUNT)
 #undef TDH_COUNT
+#define TDH_COUNT2(f, u) ++n;
+  TDH_SPLITS(TDH_COUNT2)
+#undef TDH_COUNT2
   return n;
 }
 
@@ -932,7 +1185,26 @@ void tile_shape(int id, int *dims) {
   }
   TDH_TILES(TDH_SHAPE)
 #undef TDH_SHAPE
-  dims[0] = dims[1] = dims[2] = dims[3] = 0;
+#define TDH_SHAPE2(f, u)                                   \
+  if (i++ == id) {                                         \
+    dims[0] = 0; dims[1] = f; dims[2] = u; dims[3] = 0;    \
+    return;                                                \
+  }
+  TDH_SPLITS(TDH_SHAPE2)
+#undef TDH_SHAPE2
+  dims[0] = dims[1] = dims[2] = dims[3] = -1;
+}
+
+template <int NV, int OF, int OU>
+static hipError_t launch_split(const StageArgs &a, bool net, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((face_kernel<NV, 0, OF>), dim3(grid), dim3(kChunk), 0, s, a);
+  hipLaunchKernelGGL((face_kernel<NV, 1, OF>), dim3(grid), dim3(kChunk), 0, s, a);
+  hipLaunchKernelGGL((face_kernel<NV, 2, OF>), dim3(grid), dim3(kChunk), 0, s, a);
+  if (net)
+    hipLaunchKernelGGL((update_kernel<NV, true, OU>), dim3(grid), dim3(kChunk), 0, s, a);
+  else
+    hipLaunchKernelGGL((update_kernel<NV, false, OU>), dim3(grid), dim3(kChunk), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_seed(const StageArgs &a, int grid, hipStream_t s) {
@@ -960,6 +1232,10 @@ hipError_t launch_stage(const StageArgs &a, int tile, int grid, hipStream_t s) {
   }
   TDH_TILES(TDH_LAUNCH)
 #undef TDH_LAUNCH
+#define TDH_LAUNCH2(f, u)                                                                        \
+  if (i++ == tile) return a.m.nv == 6 ? launch_split<6, f, u>(a, net, grid, s) : launch_split<5, f, u>(a, net, grid, s);
+  TDH_SPLITS(TDH_LAUNCH2)
+#undef TDH_LAUNCH2
   return hipErrorInvalidValue;
 }
 

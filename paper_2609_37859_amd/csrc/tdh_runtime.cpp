@@ -38,10 +38,12 @@ struct tdh_ctx {
   // device memory: state in the caller's arena, metadata owned here
   double *Qa = nullptr, *Qb = nullptr, *Qs = nullptr, *imp = nullptr, *bf1 = nullptr, *phi = nullptr;
   int *jc = nullptr;  // seed table cells: a segment of ncells per state buffer (Qa, Qb, Qs)
+  double *flx = nullptr;  // face fluxes of the split stage form (3 axes)
+  long long ftotal = 0;   // faces of one axis over all blocks
   bool seeds_held = false;  // the current buffers' segments hold the cells of the current state
   BlockInfo *d_blocks = nullptr;
   int *d_lmap = nullptr, *d_fac = nullptr, *d_par = nullptr, *d_order = nullptr, *d_item_start = nullptr;
-  int *d_cnt_ge = nullptr, *d_cfl_item_block = nullptr, *d_cfl_block_start = nullptr;
+  int *d_cnt_ge = nullptr, *d_cfl_item_block = nullptr, *d_cfl_block_start = nullptr, *d_fitem_start = nullptr;
   double *d_cfl_part = nullptr, *d_dtb = nullptr, *d_win = nullptr;
   int cfl_nitems = 0;
   double *h_dtb = nullptr;  // pinned host copy of the per-block steps
@@ -60,7 +62,7 @@ struct tdh_ctx {
   int mlp_steps_done = 0;
 
   // LAT window state
-  std::vector<int> levels, fac, par, order, item_start, cnt_ge;
+  std::vector<int> levels, fac, par, order, item_start, fitem_start, cnt_ge;
   int Lmax = 0;
   int k = 0;                 // next sub-cycle
   double dt_coarse = 0.0, dt0 = 0.0;
@@ -111,8 +113,8 @@ static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 // mesh validation and layout
 // ---------------------------------------------------------------------------
 struct Layout {
-  long long total = 0, ptotal = 0, itotal = 0, ncells = 0;
-  std::vector<long long> off, poff, ioff;
+  long long total = 0, ptotal = 0, itotal = 0, ncells = 0, ftotal = 0;
+  std::vector<long long> off, poff, ioff, foff;
   int lat = 0, nmax = 0;
 };
 
@@ -135,6 +137,7 @@ static const char *mesh_layout(const tdh_config *cfg, const tdh_mesh *m, Layout 
   L.off.resize(m->nblocks);
   L.poff.resize(m->nblocks);
   L.ioff.resize(m->nblocks);
+  L.foff.resize(m->nblocks);
   for (int b = 0; b < m->nblocks; ++b) {
     const long long n = m->blk[4 * b];
     L.off[b] = L.total;
@@ -143,6 +146,8 @@ static const char *mesh_layout(const tdh_config *cfg, const tdh_mesh *m, Layout 
     L.ptotal += (n + 2) * (n + 2) * (n + 2);
     L.ioff[b] = L.itotal;
     L.itotal += 6LL * nv * n * n;
+    L.foff[b] = L.ftotal;
+    L.ftotal += (n + 1) * n * n;
     L.ncells += n * n * n;
   }
   L.lat = lat;
@@ -151,6 +156,7 @@ static const char *mesh_layout(const tdh_config *cfg, const tdh_mesh *m, Layout 
 }
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+static int nv_of(const tdh_config *cfg) { return cfg->dual ? 6 : 5; }
 
 static size_t arena_need(const tdh_config *cfg, const Layout &L) {
   size_t s = 0;
@@ -158,6 +164,7 @@ static size_t arena_need(const tdh_config *cfg, const Layout &L) {
   s += 2 * align256(L.itotal * sizeof(double));  // impulses, stage-1 boundary fluxes
   if (cfg->grav_kind == 1) s += align256(L.ptotal * sizeof(double));
   if (cfg->eos_kind == 1) s += align256(3 * L.ncells * sizeof(int));  // seed cells of Qa, Qb, Qs
+  s += align256(3 * (nv_of(cfg) + 1) * L.ftotal * sizeof(double));  // face fluxes of the split stage form
   return s;
 }
 
@@ -283,6 +290,9 @@ static StageArgs base_args(tdh_ctx *c) {
   a.win = c->d_win;
   a.jc = c->jc;
   a.jn = c->ncells;
+  a.flx = c->flx;
+  a.fstride = (long long)(c->nv + 1) * c->ftotal;
+  a.fitem_start = c->d_fitem_start;
   return a;
 }
 
@@ -328,9 +338,11 @@ static tdh_status install_levels(tdh_ctx *c, const std::vector<int> &lev) {
   for (int b = 0; b < c->nb; ++b) c->order[b] = b;
   std::stable_sort(c->order.begin(), c->order.end(), [&](int x, int y) { return lev[x] > lev[y]; });
   c->item_start.assign(c->nb + 1, 0);
+  c->fitem_start.assign(c->nb + 1, 0);
   for (int i = 0; i < c->nb; ++i) {
     const long long n = c->blk[4 * c->order[i]];
     c->item_start[i + 1] = c->item_start[i] + (int)((n * n * n + kChunk - 1) / kChunk);
+    c->fitem_start[i + 1] = c->fitem_start[i] + (int)(((n + 1) * n * n + kChunk - 1) / kChunk);
   }
   c->cnt_ge.assign(kCntSlots, 0);
   for (int L = 0; L < kCntSlots; ++L)
@@ -340,6 +352,8 @@ static tdh_status install_levels(tdh_ctx *c, const std::vector<int> &lev) {
   HIPCHK(c, hipMemcpyAsync(c->d_order, c->order.data(), c->nb * sizeof(int), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_item_start, c->item_start.data(), (c->nb + 1) * sizeof(int), hipMemcpyHostToDevice,
                            c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_fitem_start, c->fitem_start.data(), (c->nb + 1) * sizeof(int),
+                           hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_cnt_ge, c->cnt_ge.data(), kCntSlots * sizeof(int), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->k = 0;
@@ -384,7 +398,7 @@ extern "C" tdh_status tdh_init_blocks(tdh_ctx *c, const tdh_mesh *m, void *dev_a
   for (int b = 0; b < c->nb; ++b) {
     BlockInfo &B = c->binfo[b];
     B.n = c->blk[4 * b]; B.ox = c->blk[4 * b + 1]; B.oy = c->blk[4 * b + 2]; B.oz = c->blk[4 * b + 3];
-    B.off = L.off[b]; B.poff = L.poff[b]; B.ioff = L.ioff[b];
+    B.off = L.off[b]; B.poff = L.poff[b]; B.ioff = L.ioff[b]; B.foff = L.foff[b];
   }
   c->total = L.total; c->ptotal = L.ptotal; c->itotal = L.itotal; c->ncells = L.ncells;
   // carve the arena
@@ -397,11 +411,14 @@ extern "C" tdh_status tdh_init_blocks(tdh_ctx *c, const tdh_mesh *m, void *dev_a
   c->bf1 = (double *)take(L.itotal * sizeof(double));
   if (c->cfg.grav_kind == 1) c->phi = (double *)take(L.ptotal * sizeof(double));
   if (c->cfg.eos_kind == 1) c->jc = (int *)take(3 * L.ncells * sizeof(int));
+  c->ftotal = L.ftotal;
+  c->flx = (double *)take(3 * (c->nv + 1) * L.ftotal * sizeof(double));
   // metadata
   tdh_status s;
   if ((s = dev_alloc(c, &c->d_blocks, c->nb)) || (s = dev_alloc(c, &c->d_lmap, c->lmap.size())) ||
       (s = dev_alloc(c, &c->d_fac, c->nb)) || (s = dev_alloc(c, &c->d_par, c->nb)) ||
       (s = dev_alloc(c, &c->d_order, c->nb)) || (s = dev_alloc(c, &c->d_item_start, c->nb + 1)) ||
+      (s = dev_alloc(c, &c->d_fitem_start, c->nb + 1)) ||
       (s = dev_alloc(c, &c->d_cnt_ge, kCntSlots)) || (s = dev_alloc(c, &c->d_dtb, c->nb)) ||
       (s = dev_alloc(c, &c->d_win, 2)) ||
       (s = dev_alloc(c, &c->d_cfl_block_start, c->nb + 1)))
@@ -862,6 +879,7 @@ extern "C" tdh_status tdh_get_stats(tdh_ctx *c, tdh_stats *out) {
 static bool tile_fits(const tdh_ctx *c, int id) {
   int d[4];
   tile_shape(id, d);
+  if (d[0] == 0) return d[1] > 0;  // the split form fits every mesh
   return d[0] > 0 && c->lat % d[0] == 0 && c->lat % d[1] == 0 && c->lat % d[2] == 0;
 }
 
