@@ -97,13 +97,16 @@ def train_seed(T, W, table, steps=2000, nsamples=1 << 20):
     return params, secs, float(loss[-1]), q
 
 
-def run_form(T, W, cfg, mesh, U, table, steps, warmup, inv_mode, batched, seed_params=None):
+def run_form(T, W, cfg, mesh, U, table, steps, warmup, inv_mode, batched, seed_params=None, tile=-1):
     import torch
     ctx = T.Context(cfg, mesh, U, table=table, inv_mode=inv_mode)
     if seed_params is not None:
         ctx.mlp_init(seed_params, W.seed_ranges(table))
         ctx.mlp_enable_seed(True)
-    ctx.autotune(reps=2)
+    if tile >= 0:
+        ctx.set_tile(tile)
+    else:
+        ctx.autotune(reps=2)
     for _ in range(warmup):
         _, dt0, lev, L = ctx.reduce_dt()
         ctx.run_window(dt0 * 2 ** L, batched=batched)
@@ -196,7 +199,9 @@ def main():
     ap.add_argument("--forms", default="learned,temporal,chained,plain",
                     help="comma list of forms to time: learned, temporal, chained, plain (learned is the headline "
                          "when present)")
-    ap.add_argument("--lat-windows", type=int, default=3,
+    ap.add_argument("--tile", type=int, default=-1,
+                    help="stage-kernel variant id to use instead of autotuning (profiling runs fix it)")
+    ap.add_argument("--lat-windows", type=int, default=5,
                     help="timed LAT windows per form on the polytrope and production-shaped workloads (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (reference for the HBM byte counters)")
@@ -251,7 +256,7 @@ def main():
                                 ("plain", 0, False)):
         if name in forms:
             res[name] = run_form(T, W, cfg, mesh, U, table, args.steps, args.warmup, inv_mode=mode, batched=batched,
-                                 seed_params=params if mode == 1 else None)
+                                 seed_params=params if mode == 1 else None, tile=args.tile)
     lat = lat_section(T, W, table, params, args.lat_windows, 1) if args.lat_windows > 0 else None
     head = "learned" if "learned" in res else next(iter(res))
     el, stage_ms, launches, st, tile = res[head]

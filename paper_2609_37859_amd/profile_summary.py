@@ -55,6 +55,15 @@ def counter_per_dispatch(d, name_exact, counter):
     return vals
 
 
+def counter_table(d, kernel):
+    """{counter: [values per dispatch]} for the dispatches of `kernel`."""
+    out = {}
+    for r in csv.DictReader(open(_one(d, "*counter_collection.csv"))):
+        if r["Kernel_Name"] == kernel:
+            out.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
 def copy_factor(d, counter, nbytes):
     """HBM bytes per counter unit, from the largest copy dispatch of the calibration run."""
     best = 0.0
@@ -75,6 +84,8 @@ def main():
     ap.add_argument("--copy-write")
     ap.add_argument("--copy-bytes", type=float, default=float(1 << 30))
     ap.add_argument("--kernel", default="stage_tiled")
+    ap.add_argument("--sq", action="append", default=[], help="directory of a --pmc run of SQ counters (repeatable)")
+    ap.add_argument("--cells", type=float, default=0.0, help="cells one launch of the kernel updates (per-cell rates)")
     ap.add_argument("--cmd", action="append", default=[], help="command that produced the inputs (repeatable)")
     ap.add_argument("--title", default="stage kernel")
     ap.add_argument("--out", required=True)
@@ -107,6 +118,17 @@ def main():
                   f"- total {(fb + wb) / 1e6:.2f} MB per launch", ""]
         out.update({"hbm_read_bytes_per_launch": fb, "hbm_write_bytes_per_launch": wb,
                     "hbm_bytes_per_launch": fb + wb, "fetch_factor": f_k, "write_factor": w_k})
+    for d in args.sq:
+        tab = counter_table(d, used["Name"])
+        if not tab:
+            continue
+        lines += [f"SQ counters per launch ({d.rstrip('/').split('/')[-1]}):", ""]
+        for k, v in sorted(tab.items()):
+            mean = statistics.mean(v)
+            per = f", {mean / args.cells:.1f} per cell" if args.cells > 0 else ""
+            lines.append(f"- {k}: mean {mean:.4g} over {len(v)} launches{per}")
+            out.setdefault("sq", {})[k] = mean
+        lines.append("")
     lines.append(f"Kernel source hash: {out['kernel_hash']}")
     with open(args.out, "w") as f:
         f.write("\n".join(lines) + "\n")
