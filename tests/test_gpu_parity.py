@@ -140,6 +140,32 @@ def test_temporal_seeds_track_the_state(tdh, saha):
     ref.close()
 
 
+def test_table_eos_evaluation_matches_oracle(tdh, orc, saha):
+    """P and c_s from (rho, U) over the whole table range and beyond its edges
+    (clamped), against the oracle's evaluation with the C library's log10 and
+    pow: the library's own base-10 logarithm and the table interpolation agree
+    to a few units in the last place (bound 1e-13 relative)."""
+    import torch
+    cfg = W.Config(eos_kind=1, e_floor=saha.e_floor)
+    mesh = W.uniform_mesh(1, 1, 1, 8, 1.0)
+    ctx = tdh.Context(cfg, mesh, W.uniform_state(mesh, W.Config()), table=saha)
+    rng = np.random.default_rng(21)
+    n = 1 << 18
+    lr = rng.uniform(-12.3, 2.3, n)
+    x = W.seed_training_samples(saha, n, 22)
+    le = x[:, 1] + rng.uniform(-0.3, 0.3, n)  # table range and a little beyond
+    rho = 10.0 ** lr
+    U = rho * 10.0 ** le
+    Pg, cg = ctx.eos_eval(torch.from_numpy(rho), torch.from_numpy(U))
+    torch.cuda.synchronize()
+    Po, co = orc.eos_eval(cfg, rho, U, table=saha)
+    ctx.close()
+    eP = np.max(np.abs(Pg.cpu().numpy() / Po - 1))
+    ec = np.max(np.abs(cg.cpu().numpy() / co - 1))
+    print("EOS eval max rel err P", eP, "c_s", ec)
+    assert eP < 1e-13 and ec < 1e-13
+
+
 def test_levels_bit_exact_and_dt_parity(tdh, orc):
     """C3-shaped polytrope (reduced to 4^3 blocks of 16^3): per-block CFL steps
     agree to 1e-13, and the level assignment computed by the library from its
