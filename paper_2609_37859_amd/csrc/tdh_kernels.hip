@@ -352,6 +352,7 @@ struct Nbr {
 };
 
 // load conserved state of global cell g (stage view of the reader), return block info
+template <int NV>
 __device__ __forceinline__ void load_q(const StageArgs &a, int b, const BlockInfo &B, const Src &own, int fb,
                                        int gx, int gy, int gz, double *q, int *nb_out, long long *idx_out) {
   const MeshDev &m = a.m;
@@ -359,11 +360,10 @@ __device__ __forceinline__ void load_q(const StageArgs &a, int b, const BlockInf
   gy = wrap_axis(gy, m.ny, m.bc[1]);
   gz = wrap_axis(gz, m.nz, m.bc[2]);
   const int lx = gx - B.ox, ly = gy - B.oy, lz = gz - B.oz;
-  const int nv = m.nv;
   if ((unsigned)lx < (unsigned)B.n && (unsigned)ly < (unsigned)B.n && (unsigned)lz < (unsigned)B.n) {
     const long long n3 = (long long)B.n * B.n * B.n;
     const long long idx = ((long long)lz * B.n + ly) * B.n + lx;
-    for (int v = 0; v < nv; ++v) q[v] = src_val(own, B.off + v * n3 + idx);
+    _Pragma("unroll") for (int v = 0; v < NV; ++v) q[v] = src_val(own, B.off + v * n3 + idx);
     if (nb_out) { *nb_out = b; *idx_out = idx; }
     return;
   }
@@ -372,7 +372,7 @@ __device__ __forceinline__ void load_q(const StageArgs &a, int b, const BlockInf
   const Src s = source_of(a, fb, nb);
   const long long n3 = (long long)Bn.n * Bn.n * Bn.n;
   const long long idx = ((long long)(gz - Bn.oz) * Bn.n + (gy - Bn.oy)) * Bn.n + (gx - Bn.ox);
-  for (int v = 0; v < nv; ++v) q[v] = src_val(s, Bn.off + v * n3 + idx);
+  _Pragma("unroll") for (int v = 0; v < NV; ++v) q[v] = src_val(s, Bn.off + v * n3 + idx);
   if (nb_out) { *nb_out = nb; *idx_out = idx; }
 }
 
@@ -390,11 +390,26 @@ __device__ __forceinline__ void load_q(const StageArgs &a, int b, const BlockInf
 template <int TX, int TY, int TZ>
 struct TileGeom {
   static constexpr int TV = TX * TY * TZ;
-  static constexpr int S0 = (TX + 4) * TY * TZ, S1 = TX * (TY + 4) * TZ, S2 = TX * TY * (TZ + 4);
-  static constexpr int SLAB = S0 > S1 ? (S0 > S2 ? S0 : S2) : (S1 > S2 ? S1 : S2);
+  static constexpr int A0 = TY * TZ, A1 = TX * TZ, A2 = TX * TY;  // face areas normal to x, y, z
+  static constexpr int AMAX = A0 > A1 ? (A0 > A2 ? A0 : A2) : (A1 > A2 ? A1 : A2);
+  static constexpr int HALO = 4 * AMAX;  // two layers on each side along one axis
   static constexpr int F0 = (TX + 1) * TY * TZ, F1 = TX * (TY + 1) * TZ, F2 = TX * TY * (TZ + 1);
   static constexpr int NF = F0 > F1 ? (F0 > F2 ? F0 : F2) : (F1 > F2 ? F1 : F2);
 };
+
+// LDS slot of the staged cell at tile coordinates (c0, c1, c2), only the D-th of
+// which may lie outside the tile: the tile's own cells first (x fastest), then
+// the halo of axis D as [layer][transverse] with layers -2, -1, T_D, T_D + 1.
+template <int TX, int TY, int TZ, int D>
+__device__ __forceinline__ int cell_slot(int c0, int c1, int c2) {
+  using G = TileGeom<TX, TY, TZ>;
+  constexpr int TD = D == 0 ? TX : (D == 1 ? TY : TZ);
+  constexpr int A = D == 0 ? G::A0 : (D == 1 ? G::A1 : G::A2);
+  const int cd = D == 0 ? c0 : (D == 1 ? c1 : c2);
+  const int u = D == 0 ? c1 + TY * c2 : (D == 1 ? c0 + TX * c2 : c0 + TX * c1);
+  const int layer = cd < 0 ? cd + 2 : cd - TD + 2;
+  return (cd >= 0 && cd < TD) ? c0 + TX * (c1 + TY * c2) : G::TV + layer * A + u;
+}
 
 // The thread index as a value the compiler cannot hoist out of the item loop:
 // every per-thread index below is then recomputed per item (a few integer
@@ -666,58 +681,70 @@ template <int TX, int TY, int TZ, int NV, int D>
 __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, double *sW, double *sF, int *sB,
                                           const int *sJc, double *rhs, double &divv, double &emax) {
   using G = TileGeom<TX, TY, TZ>;
-  constexpr int L0 = TX + (D == 0 ? 4 : 0), L1 = TY + (D == 1 ? 4 : 0), L2 = TZ + (D == 2 ? 4 : 0);
-  constexpr int NS = L0 * L1 * L2;
-  constexpr int STR = D == 0 ? 1 : (D == 1 ? L0 : L0 * L1);
+  constexpr int SW = G::TV + G::HALO;  // stride of one variable in sW
+  constexpr int TD = D == 0 ? TX : (D == 1 ? TY : TZ);
+  constexpr int A = D == 0 ? G::A0 : (D == 1 ? G::A1 : G::A2);
   constexpr int F0 = TX + (D == 0), F1 = TY + (D == 1), F2 = TZ + (D == 2);
   constexpr int NFD = F0 * F1 * F2;
   constexpr int FSTR = D == 0 ? 1 : (D == 1 ? F0 : F0 * F1);
   constexpr int PN = 1 + D, P1 = 1 + (D + 1) % 3, P2 = 1 + (D + 2) % 3;
+  static_assert(4 * A <= kChunk, "one halo cell per thread");
   const Phys &p = a.p;
   const MeshDev &m = a.m;
   const int tid = item_tid();
   const int cc[3] = {tid % TX, (tid / TX) % TY, tid / (TX * TY)};  // own cell in the tile
   const int Nd = D == 0 ? m.nx : (D == 1 ? m.ny : m.nz);
-  // stage the slab: tile extended by two cells along D
-#pragma unroll 1
-  for (int s = tid; s < NS; s += kChunk) {
-    int sc[3] = {s % L0, (s / L0) % L1, s / (L0 * L1)};
-    sc[D] -= 2;
-    const int g[3] = {T.B.ox + T.to[0] + sc[0], T.B.oy + T.to[1] + sc[1], T.B.oz + T.to[2] + sc[2]};
+  // stage the halo along D (the tile's own cells were staged at the item start)
+  if (tid < 4 * A) {
+    const int layer = tid / A, u = tid % A;
+    int c[3];
+    const int cd = layer < 2 ? layer - 2 : TD + layer - 2;
+    if (D == 0) { c[0] = cd; c[1] = u % TY; c[2] = u / TY; }
+    if (D == 1) { c[0] = u % TX; c[1] = cd; c[2] = u / TX; }
+    if (D == 2) { c[0] = u % TX; c[1] = u / TX; c[2] = cd; }
+    const int g[3] = {T.B.ox + T.to[0] + c[0], T.B.oy + T.to[1] + c[1], T.B.oz + T.to[2] + c[2]};
     double q[6], w[6];
     int nb_;
     long long id_;
-    load_q(a, T.b, T.B, T.own, T.fb, g[0], g[1], g[2], q, &nb_, &id_);
+    load_q<NV>(a, T.b, T.B, T.own, T.fb, g[0], g[1], g[2], q, &nb_, &id_);
     c2p(p, q, w);
+    const int slot = G::TV + tid;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) sW[v * G::SLAB + s] = w[v];
-    sW[6 * G::SLAB + s] = q[IEN];
-    sB[s] = (m.bc[D] == 0 || (g[D] >= 0 && g[D] < Nd)) ? nb_ : -1;
+    for (int v = 0; v < NV; ++v) sW[v * SW + slot] = w[v];
+    sW[6 * SW + slot] = q[IEN];
+    sB[tid] = (m.bc[D] == 0 || (g[D] >= 0 && g[D] < Nd)) ? nb_ : -1;
   }
   __syncthreads();
   // every face of the tile along D, once
 #pragma unroll 1
   for (int f = tid; f < NFD; f += kChunk) {
     const int fc[3] = {f % F0, (f / F0) % F1, f / (F0 * F1)};
-    const int s0 = fc[0] + L0 * (fc[1] + L1 * fc[2]);  // stencil start (tile cell fd - 2)
+    int sl[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int c[3] = {fc[0], fc[1], fc[2]};
+      c[D] += k - 2;
+      sl[k] = cell_slot<TX, TY, TZ, D>(c[0], c[1], c[2]);
+    }
     double wl[6], wr[6];
     constexpr int perm[6] = {0, PN, P1, P2, 4, 5};
 #pragma unroll
     for (int vv = 0; vv < NV; ++vv) {
-      const double *col = sW + perm[vv] * G::SLAB + s0;
-      plm_face(col[0], col[STR], col[2 * STR], col[3 * STR], wl[vv], wr[vv]);
+      const double *col = sW + perm[vv] * SW;
+      plm_face(col[sl[0]], col[sl[1]], col[sl[2]], col[sl[3]], wl[vv], wr[vv]);
     }
     int seedl = -1;
     if (p.eos_kind == 1 && p.inv_mode != 0) {
       // seed the left state from the table cell of the adjacent tile cell's centre
       int tc[3] = {fc[0], fc[1], fc[2]};
       if (tc[D] > 0) tc[D] -= 1;
-      if (tc[D] >= (D == 0 ? TX : (D == 1 ? TY : TZ))) tc[D] -= 1;
+      if (tc[D] >= TD) tc[D] -= 1;
       seedl = sJc[tc[0] + TX * (tc[1] + TY * tc[2])];
     }
     const int fr[3] = {T.to[0] + fc[0], T.to[1] + fc[1], T.to[2] + fc[2]};  // cell right of the face
     const int side = fr[D] == T.B.n;
-    const int nbo = (fr[D] == 0 || side) ? sB[s0 + (side ? 2 : 1) * STR] : T.b;  // cell across a block face
+    // block across a block face: a halo cell (layer -1 below, T_D above)
+    const int nbo = (fr[D] == 0 || side) ? sB[(side ? sl[2] : sl[1]) - G::TV] : T.b;
     double Gf[7];
     face_flux<NV, D>(a, T.B, T.fb, T.t, T.dtb, fr, wl, wr, seedl, nbo, Gf);
 #pragma unroll
@@ -737,11 +764,13 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
     }
     Flo[6] = sF[6 * G::NF + flo];
     Fhi[6] = sF[6 * G::NF + fhi];
-    const int sbase = cc[0] + L0 * (cc[1] + L1 * cc[2]);
-    if (D == 0) emax = fmax(emax, sW[6 * G::SLAB + sbase + 2 * STR]);  // own stage-input E
+    int cm[3] = {cc[0], cc[1], cc[2]}, cp[3] = {cc[0], cc[1], cc[2]};
+    cm[D] -= 1;
+    cp[D] += 1;
+    if (D == 0) emax = fmax(emax, sW[6 * SW + tid]);  // own stage-input E
     const int lc[3] = {T.to[0] + cc[0], T.to[1] + cc[1], T.to[2] + cc[2]};
-    axis_update<NV, D>(a, T.B, T.t, lc, Flo, Fhi, sW[sbase + 2 * STR], sW[6 * G::SLAB + sbase + STR],
-                       sW[6 * G::SLAB + sbase + 3 * STR], rhs, divv, emax);
+    axis_update<NV, D>(a, T.B, T.t, lc, Flo, Fhi, sW[tid], sW[6 * SW + cell_slot<TX, TY, TZ, D>(cm[0], cm[1], cm[2])],
+                       sW[6 * SW + cell_slot<TX, TY, TZ, D>(cp[0], cp[1], cp[2])], rhs, divv, emax);
   }
   __syncthreads();
 }
@@ -752,9 +781,10 @@ template <int TX, int TY, int TZ, int NV, int OCC, bool NET>
 __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void stage_tiled(StageArgs a) {
   using G = TileGeom<TX, TY, TZ>;
   static_assert(G::TV == kChunk, "one cell per thread");
-  __shared__ double sW[7 * G::SLAB];   // primitives (rho, vx, vy, vz, U_EOS, A) + stage-input E
+  constexpr int SW = G::TV + G::HALO;
+  __shared__ double sW[7 * SW];        // primitives (rho, vx, vy, vz, U_EOS, A) + stage-input E: own cells, halo
   __shared__ double sF[7 * G::NF];     // fluxes (rho, mx, my, mz, E, A) + face velocity
-  __shared__ int sB[G::SLAB];          // owning block of a staged cell, -1 beyond an outflow edge
+  __shared__ int sB[G::HALO];          // owning block of a halo cell, -1 beyond an outflow edge
   __shared__ int sJc[kChunk];          // table cell of each tile cell's centre state (seeds)
   const Phys &p = a.p;
   const MeshDev &m = a.m;
@@ -775,6 +805,7 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
     T.b = uni(a.order[lo]);
     T.B = uni(m.blocks[T.b]);
     const int n = T.B.n;
+    const long long n3 = (long long)n * n * n;
     const int tile = item - uni(a.item_start[lo]);
     const int ntx = n / TX, nty = n / TY;
     T.to[0] = (tile % ntx) * TX;
@@ -787,6 +818,16 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
     const int cc[3] = {tid % TX, (tid / TX) % TY, tid / (TX * TY)};
     const int lc[3] = {T.to[0] + cc[0], T.to[1] + cc[1], T.to[2] + cc[2]};
     const long long cell = ((long long)lc[2] * n + lc[1]) * n + lc[0];
+    // the tile's own cells, staged once for all three axes
+    {
+      double q[6], w[6];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) q[v] = src_val(T.own, T.B.off + v * n3 + cell);
+      c2p(p, q, w);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sW[v * SW + tid] = w[v];
+      sW[6 * SW + tid] = q[IEN];
+    }
     double rhs[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double divv = 0.0, emax = -INFINITY;
     // seeded inversion: the table cell of each tile cell's stage-input state
@@ -863,7 +904,7 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
       double q[6];
       int nb_;
       long long id_;
-      load_q(a, b, B, own, fb, g[0], g[1], g[2], q, &nb_, &id_);
+      load_q<NV>(a, b, B, own, fb, g[0], g[1], g[2], q, &nb_, &id_);
       c2p(p, q, W[s]);
       if ((s == 1 && fr[D] == 0) || (s == 2 && fr[D] == n))
         nbo = (m.bc[D] == 0 || (g[D] >= 0 && g[D] < Nd)) ? nb_ : -1;
