@@ -95,6 +95,8 @@ struct StageArgs {
   double *flx;
   long long fstride;
   const int *fitem_start;   // prefix sum of 256-face work items (one axis) over `order`
+  const int2 *item_bt;      // per work item (cells): block id, index of the item within its block
+  const int2 *fitem_bt;     // the same for the face items of the split form
 };
 
 // host-side launchers (tdh_kernels.hip)

@@ -795,18 +795,14 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
   const double tk = a.win[0] + a.k * dt0;
   const ItemRange R = xcd_items(i0, i1);
   for (int item = R.first; item < R.end; item += R.step) {
-    int lo = a0, hi = a1;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (uni(a.item_start[mid]) <= item) lo = mid; else hi = mid;
-    }
     const int tid = item_tid();
+    const int2 bt = a.item_bt[item];
     TileCtx T;
-    T.b = uni(a.order[lo]);
+    T.b = uni(bt.x);
     T.B = uni(m.blocks[T.b]);
     const int n = T.B.n;
     const long long n3 = (long long)n * n * n;
-    const int tile = item - uni(a.item_start[lo]);
+    const int tile = uni(bt.y);
     const int ntx = n / TX, nty = n / TY;
     T.to[0] = (tile % ntx) * TX;
     T.to[1] = ((tile / ntx) % nty) * TY;
@@ -850,16 +846,6 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
 // into the flux arrays (one face per thread, no LDS, no barriers), then one
 // kernel per cell sums them.  Same arithmetic as the fused form, bit for bit.
 // ---------------------------------------------------------------------------
-// Item -> block lookup over a prefix array of the level-sorted block order.
-__device__ __forceinline__ int item_slot(const int *start, int a0, int a1, int item) {
-  int lo = a0, hi = a1;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (uni(start[mid]) <= item) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
 // face (fi, fj, fk) of axis D: the D-th coordinate in [0, n], the others in
 // [0, n), x fastest
 template <int D>
@@ -881,12 +867,12 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
   const int Nd = D == 0 ? m.nx : (D == 1 ? m.ny : m.nz);
   const ItemRange R = xcd_items(i0, i1);
   for (int item = R.first; item < R.end; item += R.step) {
-    const int lo = item_slot(a.fitem_start, a0, a1, item);
-    const int b = uni(a.order[lo]);
+    const int2 bt = a.fitem_bt[item];
+    const int b = uni(bt.x);
     const BlockInfo B = uni(m.blocks[b]);
     const int n = B.n;
     const long long nf = (long long)(n + 1) * n * n;
-    const long long f = (long long)(item - uni(a.fitem_start[lo])) * kChunk + item_tid();
+    const long long f = (long long)uni(bt.y) * kChunk + item_tid();
     if (f >= nf) continue;
     const int fb = uni(a.fac[b]);
     const double dtb = fb * dt0;
@@ -961,12 +947,12 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
   const double tk = a.win[0] + a.k * dt0;
   const ItemRange R = xcd_items(i0, i1);
   for (int item = R.first; item < R.end; item += R.step) {
-    const int lo = item_slot(a.item_start, a0, a1, item);
-    const int b = uni(a.order[lo]);
+    const int2 bt = a.item_bt[item];
+    const int b = uni(bt.x);
     const BlockInfo B = uni(m.blocks[b]);
     const int n = B.n;
     const long long n3 = (long long)n * n * n;
-    const long long cell = (long long)(item - uni(a.item_start[lo])) * kChunk + item_tid();
+    const long long cell = (long long)uni(bt.y) * kChunk + item_tid();
     const int fb = uni(a.fac[b]);
     const double dtb = fb * dt0;
     const double t = a.phase == 1 ? tk : tk + dtb;
@@ -1021,15 +1007,11 @@ __global__ __launch_bounds__(kChunk) void seed_kernel(StageArgs a) {
   const int nv = a.m.nv;
   const ItemRange R = xcd_items(i0, i1);
   for (int item = R.first; item < R.end; item += R.step) {
-    int lo = a0, hi = a1;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (a.item_start[mid] <= item) lo = mid; else hi = mid;
-    }
-    const int b = a.order[lo];
+    const int2 bt = a.item_bt[item];
+    const int b = bt.x;
     const BlockInfo B = a.m.blocks[b];
     const long long n3 = (long long)B.n * B.n * B.n;
-    const long long cell = (long long)(item - a.item_start[lo]) * kChunk + threadIdx.x;
+    const long long cell = (long long)bt.y * kChunk + threadIdx.x;
     const Src own = source_of(a, a.fac[b], b);
     double q[6], w[6];
     for (int v = 0; v < nv; ++v) q[v] = src_val(own, B.off + v * n3 + cell);

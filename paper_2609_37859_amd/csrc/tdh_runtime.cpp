@@ -44,6 +44,7 @@ struct tdh_ctx {
   BlockInfo *d_blocks = nullptr;
   int *d_lmap = nullptr, *d_fac = nullptr, *d_par = nullptr, *d_order = nullptr, *d_item_start = nullptr;
   int *d_cnt_ge = nullptr, *d_cfl_item_block = nullptr, *d_cfl_block_start = nullptr, *d_fitem_start = nullptr;
+  int2 *d_item_bt = nullptr, *d_fitem_bt = nullptr;  // per work item: block, item within the block
   double *d_cfl_part = nullptr, *d_dtb = nullptr, *d_win = nullptr;
   int cfl_nitems = 0;
   double *h_dtb = nullptr;  // pinned host copy of the per-block steps
@@ -63,6 +64,7 @@ struct tdh_ctx {
 
   // LAT window state
   std::vector<int> levels, fac, par, order, item_start, fitem_start, cnt_ge;
+  std::vector<int2> item_bt, fitem_bt;
   int Lmax = 0;
   int k = 0;                 // next sub-cycle
   double dt_coarse = 0.0, dt0 = 0.0;
@@ -293,6 +295,8 @@ static StageArgs base_args(tdh_ctx *c) {
   a.flx = c->flx;
   a.fstride = (long long)(c->nv + 1) * c->ftotal;
   a.fitem_start = c->d_fitem_start;
+  a.item_bt = c->d_item_bt;
+  a.fitem_bt = c->d_fitem_bt;
   return a;
 }
 
@@ -353,6 +357,17 @@ static tdh_status install_levels(tdh_ctx *c, const std::vector<int> &lev) {
   HIPCHK(c, hipMemcpyAsync(c->d_item_start, c->item_start.data(), (c->nb + 1) * sizeof(int), hipMemcpyHostToDevice,
                            c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_fitem_start, c->fitem_start.data(), (c->nb + 1) * sizeof(int),
+                           hipMemcpyHostToDevice, c->stream));
+  c->item_bt.resize(c->item_start[c->nb]);
+  c->fitem_bt.resize(c->fitem_start[c->nb]);
+  for (int i = 0; i < c->nb; ++i) {
+    for (int t = c->item_start[i]; t < c->item_start[i + 1]; ++t) c->item_bt[t] = make_int2(c->order[i], t - c->item_start[i]);
+    for (int t = c->fitem_start[i]; t < c->fitem_start[i + 1]; ++t)
+      c->fitem_bt[t] = make_int2(c->order[i], t - c->fitem_start[i]);
+  }
+  HIPCHK(c, hipMemcpyAsync(c->d_item_bt, c->item_bt.data(), c->item_bt.size() * sizeof(int2), hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_fitem_bt, c->fitem_bt.data(), c->fitem_bt.size() * sizeof(int2),
                            hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_cnt_ge, c->cnt_ge.data(), kCntSlots * sizeof(int), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -419,6 +434,8 @@ extern "C" tdh_status tdh_init_blocks(tdh_ctx *c, const tdh_mesh *m, void *dev_a
       (s = dev_alloc(c, &c->d_fac, c->nb)) || (s = dev_alloc(c, &c->d_par, c->nb)) ||
       (s = dev_alloc(c, &c->d_order, c->nb)) || (s = dev_alloc(c, &c->d_item_start, c->nb + 1)) ||
       (s = dev_alloc(c, &c->d_fitem_start, c->nb + 1)) ||
+      (s = dev_alloc(c, &c->d_item_bt, (size_t)(L.ncells / kChunk))) ||
+      (s = dev_alloc(c, &c->d_fitem_bt, (size_t)((L.ftotal + (long long)c->nb * (kChunk - 1)) / kChunk))) ||
       (s = dev_alloc(c, &c->d_cnt_ge, kCntSlots)) || (s = dev_alloc(c, &c->d_dtb, c->nb)) ||
       (s = dev_alloc(c, &c->d_win, 2)) ||
       (s = dev_alloc(c, &c->d_cfl_block_start, c->nb + 1)))
