@@ -677,7 +677,7 @@ __device__ __forceinline__ void finish_cell(const StageArgs &a, const BlockInfo 
 // ---------------------------------------------------------------------------
 // fused form: one workgroup per tile, faces through LDS
 // ---------------------------------------------------------------------------
-template <int TX, int TY, int TZ, int NV, int D>
+template <int TX, int TY, int TZ, int NV, int D, int NT>
 __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, double *sW, double *sF, int *sB,
                                           const int *sJc, double *rhs, double &divv, double &emax) {
   using G = TileGeom<TX, TY, TZ>;
@@ -717,7 +717,7 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
   __syncthreads();
   // every face of the tile along D, once
 #pragma unroll 1
-  for (int f = tid; f < NFD; f += kChunk) {
+  for (int f = tid; f < NFD; f += NT) {
     const int fc[3] = {f % F0, (f / F0) % F1, f / (F0 * F1)};
     int sl[4];
 #pragma unroll
@@ -752,8 +752,9 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
     sF[6 * G::NF + f] = Gf[6];
   }
   __syncthreads();
-  // own cell: divergence, gravity, neighbour energies
-  {
+  // own cell: divergence, gravity, neighbour energies (threads past the tile's
+  // cells only stage and compute faces)
+  if (tid < G::TV) {
     const int flo = cc[0] + F0 * (cc[1] + F1 * cc[2]);
     const int fhi = flo + FSTR;
     double Flo[7], Fhi[7];
@@ -777,10 +778,13 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
 
 // NET: the learned network starts the output states' table-cell searches (a
 // separate instantiation, so its matrix-core registers burden no other form)
-template <int TX, int TY, int TZ, int NV, int OCC, bool NET>
-__global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void stage_tiled(StageArgs a) {
+// NT: threads per workgroup, 256 (one per cell) or 320 (every axis's faces in
+// one round; the last wave only stages and computes faces).
+template <int TX, int TY, int TZ, int NV, int OCC, bool NET, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void stage_tiled(StageArgs a) {
   using G = TileGeom<TX, TY, TZ>;
   static_assert(G::TV == kChunk, "one cell per thread");
+  static_assert(NT == kChunk || NT >= G::NF, "a wide workgroup covers every axis's faces in one round");
   constexpr int SW = G::TV + G::HALO;
   __shared__ double sW[7 * SW];        // primitives (rho, vx, vy, vz, U_EOS, A) + stage-input E: own cells, halo
   __shared__ double sF[7 * G::NF];     // fluxes (rho, mx, my, mz, E, A) + face velocity
@@ -815,7 +819,8 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
     const int lc[3] = {T.to[0] + cc[0], T.to[1] + cc[1], T.to[2] + cc[2]};
     const long long cell = ((long long)lc[2] * n + lc[1]) * n + lc[0];
     // the tile's own cells, staged once for all three axes
-    {
+    const bool has_cell = tid < G::TV;  // uniform per wave
+    if (has_cell) {
       double q[6], w[6];
 #pragma unroll
       for (int v = 0; v < NV; ++v) q[v] = src_val(T.own, T.B.off + v * n3 + cell);
@@ -830,14 +835,14 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
     // starts the face and compression queries
     int jcell = -1;
     const int parb = uni(a.par[T.b]);
-    if (p.eos_kind == 1 && p.inv_mode != 0) {
+    if (has_cell && p.eos_kind == 1 && p.inv_mode != 0) {
       jcell = a.jc[jseg_in(a, parb) * a.jn + T.B.off / NV + cell];
       sJc[tid] = jcell;
     }
-    tile_axis<TX, TY, TZ, NV, 0>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
-    tile_axis<TX, TY, TZ, NV, 1>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
-    tile_axis<TX, TY, TZ, NV, 2>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
-    finish_cell<NV, NET>(a, T.B, T.own, parb, T.dtb, tk, lc, cell, jcell, rhs, divv, emax);
+    tile_axis<TX, TY, TZ, NV, 0, NT>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
+    tile_axis<TX, TY, TZ, NV, 1, NT>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
+    tile_axis<TX, TY, TZ, NV, 2, NT>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
+    if (has_cell) finish_cell<NV, NET>(a, T.B, T.own, parb, T.dtb, tk, lc, cell, jcell, rhs, divv, emax);
   }
 }
 
@@ -1028,8 +1033,12 @@ __global__ __launch_bounds__(kChunk) void seed_kernel(StageArgs a) {
 }
 
 // stage-kernel variants offered to the runtime: tile shape (x fastest; all
-// divide blocks of edge >= 8) and waves per SIMD the register budget targets
-#define TDH_TILES(X) X(8, 8, 4, 3) X(16, 4, 4, 3) X(4, 8, 8, 3) X(8, 4, 8, 3) X(16, 4, 4, 2) X(8, 8, 4, 2)
+// divide blocks of edge >= 8), waves per SIMD the register budget targets,
+// threads per workgroup
+// (320-thread workgroups, every axis's faces in one round, measured 1.6x slower:
+// at 168 registers only two such workgroups fit a CU)
+#define TDH_TILES(X) X(8, 8, 4, 3, 256) X(16, 4, 4, 3, 256) X(4, 8, 8, 3, 256) X(8, 4, 8, 3, 256) \
+                     X(16, 4, 4, 2, 256) X(8, 8, 4, 2, 256)
 
 __global__ void set_window_kernel(double *win, double t, double dt0) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -1229,7 +1238,7 @@ __global__ void eos_eval_kernel(Phys p, Table t, const double *rho, const double
 // forms of TDH_SPLITS.
 int num_tiles() {
   int n = 0;
-#define TDH_COUNT(x, y, z, o) ++n;
+#define TDH_COUNT(x, y, z, o, t) ++n;
   TDH_TILES(TDH_COUNT)
 #undef TDH_COUNT
 #define TDH_COUNT2(f, u) ++n;
@@ -1240,9 +1249,9 @@ int num_tiles() {
 
 void tile_shape(int id, int *dims) {
   int i = 0;
-#define TDH_SHAPE(x, y, z, o)                              \
+#define TDH_SHAPE(x, y, z, o, t)                           \
   if (i++ == id) {                                         \
-    dims[0] = x; dims[1] = y; dims[2] = z; dims[3] = o;    \
+    dims[0] = x; dims[1] = y; dims[2] = z; dims[3] = o + 100 * (t / 64);    \
     return;                                                \
   }
   TDH_TILES(TDH_SHAPE)
@@ -1278,19 +1287,19 @@ hipError_t launch_stage(const StageArgs &a, int tile, int grid, hipStream_t s) {
   int i = 0;
   // the network variant when it starts the searches (table EOS, mode 1, network on)
   const bool net = a.p.eos_kind == 1 && a.p.inv_mode == 1 && a.s.enabled;
-#define TDH_LAUNCH(x, y, z, o)                                                                   \
-  if (i++ == tile) {                                                                             \
-    if (net) {                                                                                   \
-      if (a.m.nv == 6)                                                                           \
-        hipLaunchKernelGGL((stage_tiled<x, y, z, 6, o, true>), dim3(grid), dim3(kChunk), 0, s, a); \
-      else                                                                                       \
-        hipLaunchKernelGGL((stage_tiled<x, y, z, 5, o, true>), dim3(grid), dim3(kChunk), 0, s, a); \
-    } else if (a.m.nv == 6) {                                                                    \
-      hipLaunchKernelGGL((stage_tiled<x, y, z, 6, o, false>), dim3(grid), dim3(kChunk), 0, s, a);  \
-    } else {                                                                                     \
-      hipLaunchKernelGGL((stage_tiled<x, y, z, 5, o, false>), dim3(grid), dim3(kChunk), 0, s, a);  \
-    }                                                                                            \
-    return hipGetLastError();                                                                    \
+#define TDH_LAUNCH(x, y, z, o, t)                                                                   \
+  if (i++ == tile) {                                                                                \
+    if (net) {                                                                                      \
+      if (a.m.nv == 6)                                                                              \
+        hipLaunchKernelGGL((stage_tiled<x, y, z, 6, o, true, t>), dim3(grid), dim3(t), 0, s, a);    \
+      else                                                                                          \
+        hipLaunchKernelGGL((stage_tiled<x, y, z, 5, o, true, t>), dim3(grid), dim3(t), 0, s, a);    \
+    } else if (a.m.nv == 6) {                                                                       \
+      hipLaunchKernelGGL((stage_tiled<x, y, z, 6, o, false, t>), dim3(grid), dim3(t), 0, s, a);     \
+    } else {                                                                                        \
+      hipLaunchKernelGGL((stage_tiled<x, y, z, 5, o, false, t>), dim3(grid), dim3(t), 0, s, a);     \
+    }                                                                                               \
+    return hipGetLastError();                                                                       \
   }
   TDH_TILES(TDH_LAUNCH)
 #undef TDH_LAUNCH
