@@ -48,17 +48,22 @@ HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 
 
-def traffic_from_profiles(workload):
-    """HBM bytes per stage launch from the committed counter summary, if it
-    was taken on the current kernel source; else None."""
+# VALU issue peak: 256 CUs x 4 SIMDs, one wave64 vector instruction per SIMD
+# every 4 cycles (16 lanes; FP64 FMA at this rate is the 78.6 TFLOP/s vector peak)
+VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
+
+
+def counters_from_profiles(workload):
+    """Counter summary of the stage kernel (HBM bytes, SQ counters per launch)
+    if it was taken on the current kernel source; else {}."""
     path = os.path.join(PROFILES, f"stage_traffic_{workload}.json")
     if not os.path.exists(path):
-        return None
+        return {}
     from paper_2609_37859_amd.profile_summary import kernel_source_hash
     d = json.load(open(path))
     if d.get("kernel_hash") != kernel_source_hash():
-        return None
-    return d.get("hbm_bytes_per_launch")
+        return {}
+    return d
 
 
 FORMS = {
@@ -270,7 +275,15 @@ def main():
     # stage 2 reads Q^n and Q^(1) and writes Q^(n+1): 5 nv doubles per cell and step
     bytes_per_step = 5 * nv * 8 * ncell
     achieved = bytes_per_step * args.steps / (stage_ms * 1e-3) / 1e9
-    traffic = traffic_from_profiles("c2")
+    prof = counters_from_profiles("c2")
+    traffic = prof.get("hbm_bytes_per_launch")
+    launch_ms = stage_ms / max(launches, 1)
+    valu = prof.get("sq", {}).get("SQ_INSTS_VALU")
+    valu_issue = None
+    if valu:
+        rate = valu / (launch_ms * 1e-3)
+        valu_issue = {"wave_insts_per_launch": valu, "achieved": rate, "peak": VALU_PEAK_WAVE_INSTS,
+                      "unit": "wave64 VALU instructions/s", "frac": rate / VALU_PEAK_WAVE_INSTS}
     out = {
         "metric": "FP64 cell-updates/s (LAT-batched+MLP-EOS vs plain) at <=1e-11 rel err; % HBM roof",
         "value": value,
@@ -297,8 +310,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": "stage_tiled", "avg_launch_ms": stage_ms / max(launches, 1),
-                     "algorithmic_bytes_per_cell_update": 5 * nv * 8},
+                     "kernel": "stage_tiled", "avg_launch_ms": launch_ms,
+                     "algorithmic_bytes_per_cell_update": 5 * nv * 8,
+                     "valu_issue": valu_issue},
         "cpu_baseline": cpu,
         "lat": lat,
     }

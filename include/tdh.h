@@ -191,9 +191,8 @@ tdh_status tdh_eos_eval_batch(tdh_ctx *ctx, const double *dev_rho, const double 
 
 /* Stage-kernel variants: tdh_num_tiles() of them.  id -> host_dims4[4]:
  *   fused form (one kernel; a workgroup per tile, faces through LDS):
- *     (x, y, z) tile edges and 100 x (waves per workgroup: 4 = one thread
- *     per cell, 5 = every axis's faces in one round) + the waves per SIMD its
- *     register budget targets;
+ *     (x, y, z) tile edges (256 cells, one thread per cell) and the waves
+ *     per SIMD its register budget targets;
  *     a tile must divide the smallest block;
  *   split form (a face-flux kernel per axis writing the faces of every active
  *     block to HBM, then a per-cell update kernel; fits every mesh):

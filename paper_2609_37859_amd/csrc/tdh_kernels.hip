@@ -1251,7 +1251,7 @@ void tile_shape(int id, int *dims) {
   int i = 0;
 #define TDH_SHAPE(x, y, z, o, t)                           \
   if (i++ == id) {                                         \
-    dims[0] = x; dims[1] = y; dims[2] = z; dims[3] = o + 100 * (t / 64);    \
+    dims[0] = x; dims[1] = y; dims[2] = z; dims[3] = o;                      \
     return;                                                \
   }
   TDH_TILES(TDH_SHAPE)
