@@ -50,6 +50,10 @@ struct Table {
   // le2[i][j], le2[i][j+1], pc[i][j], pc[i][j+1] (12 doubles, 4 unused): a
   // seeded query whose seed cell brackets its target needs this line only.
   const double *rec;
+  // Function tables of the lookups' own log10 and 10^x: lg[i] = {2 c_i,
+  // -log10 c_i} with c_i = 1 / (1 + (i + 1/2)/128), i < 128; ex[j] = 2^(j/64), j < 64.
+  const double2 *lg;
+  const double *ex;
 };
 
 constexpr int kMlpParams = 4417;  // W1[64][2], b1[64], W2[64][64], b2[64], W3[64], b3

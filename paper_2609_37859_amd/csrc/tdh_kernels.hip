@@ -192,42 +192,57 @@ __device__ __forceinline__ int seed_cell_wave(const Seed &s, const Table &t, dou
 }
 
 // ---------------------------------------------------------------------------
-// base-10 logarithm for the table lookups (about 2 ulp; the table path takes
-// two per EOS evaluation, and the general-purpose library form costs 105
-// vector instructions against ~60 here)
+// base-10 logarithm and power of ten for the table lookups (the table path
+// takes two of each per EOS evaluation; these cost ~20 vector instructions and
+// one cached load each, against ~105 and ~45 for the general-purpose forms)
 // ---------------------------------------------------------------------------
-// log10 x, x > 0 finite.  x = m 2^e with m in [sqrt(1/2), sqrt(2)); ln m =
-// 2 atanh(s), s = (m - 1)/(m + 1), by the power series of atanh in s^2
-// (|s| <= 0.1716, terms through s^23: truncation < 1e-18 relative);
-// log10 x = e log10(2) + ln(m) log10(e) with log10(2) split into a part whose
-// product with e is exact and a remainder (Cody and Waite's reduction).
-__device__ __forceinline__ double log10_fast(double x) {
+// log10 x, x > 0 normal.  x = u 2^(e-1), u = 2m in [1, 2); with c the tabled
+// reciprocal of the centre of u's 1/128 interval, r = u c - 1 (one fused
+// multiply-add, |r| <= 2^-8) and log10 x = (e-1) log10 2 - log10 c +
+// log10(1 + r), the last by its Taylor series through r^7 (truncation below
+// 3e-21); log10 2 is split into a part whose product with the exponent is
+// exact and a remainder.
+__device__ __forceinline__ double log10_tab(const double2 *lg, double x) {
   int e;
-  double m = frexp(x, &e);                    // m in [1/2, 1)
-  if (m < 0x1.6a09e667f3bcdp-1) {             // below sqrt(1/2)
-    m *= 2.0;
-    e -= 1;
-  }
-  const double f = m - 1.0;                   // exact
-  const double s = f / (m + 1.0);
-  const double z = s * s;
-  double P = 1.0 / 23.0;
-  P = fma(P, z, 1.0 / 21.0);
-  P = fma(P, z, 1.0 / 19.0);
-  P = fma(P, z, 1.0 / 17.0);
-  P = fma(P, z, 1.0 / 15.0);
-  P = fma(P, z, 1.0 / 13.0);
-  P = fma(P, z, 1.0 / 11.0);
-  P = fma(P, z, 1.0 / 9.0);
-  P = fma(P, z, 1.0 / 7.0);
-  P = fma(P, z, 1.0 / 5.0);
-  P = fma(P, z, 1.0 / 3.0);
-  const double lnm = fma(2.0 * s * z, P, 2.0 * s);  // 2s + 2s z P(z)
-  const double de = (double)e;
-  constexpr double L2H = 0x1.3441350800000p-2;     // log10(2), leading 32 bits
-  constexpr double L2L = 0x1.f79fef311f12bp-34;    // log10(2) - L2H
-  constexpr double LOG10E = 0x1.bcb7b1526e50ep-2;
-  return fma(de, L2H, fma(de, L2L, lnm * LOG10E));
+  const double m = frexp(x, &e);                     // [1/2, 1)
+  const int i = (__double2hiint(m) >> 13) & 127;     // leading 7 fraction bits
+  const double2 g = lg[i];                           // {2 c_i, -log10 c_i}
+  const double r = fma(m, g.x, -1.0);
+  constexpr double A = 0x1.bcb7b1526e50ep-2;         // log10(e)
+  double p = A / 7.0;
+  p = fma(p, r, -A / 6.0);
+  p = fma(p, r, A / 5.0);
+  p = fma(p, r, -A / 4.0);
+  p = fma(p, r, A / 3.0);
+  p = fma(p, r, -A / 2.0);
+  p = fma(p, r, A);
+  const double l = fma(p, r, g.y);
+  const double de = (double)(e - 1);
+  constexpr double L2H = 0x1.3441350800000p-2;       // log10(2), leading 32 bits
+  constexpr double L2L = 0x1.f79fef311f12bp-34;      // log10(2) - L2H
+  return fma(de, L2H, fma(de, L2L, l));
+}
+
+// 10^x, |x| < 300.  k = nearest integer to 64 x log2(10); r = x - k log10(2)/64
+// (two-part reduction), 10^x = 2^(k>>6) 2^((k&63)/64) e^(r ln 10) with
+// |r ln 10| <= ln(2)/128 and e^s - 1 by its Taylor series through s^6
+// (truncation below 3e-20).
+__device__ __forceinline__ double exp10_tab(const double *ex, double x) {
+  constexpr double K64 = 0x1.a934f0979a371p+7;       // 64 log2(10)
+  constexpr double L2H = 0x1.3441350800000p-8;       // log10(2)/64, leading 32 bits
+  constexpr double L2L = 0x1.f79fef311f12bp-40;
+  constexpr double LN10 = 0x1.26bb1bbb55516p+1;
+  const double kd = rint(x * K64);
+  const int k = (int)kd;
+  const double s = fma(-kd, L2L, fma(-kd, L2H, x)) * LN10;
+  double p = 1.0 / 720.0;
+  p = fma(p, s, 1.0 / 120.0);
+  p = fma(p, s, 1.0 / 24.0);
+  p = fma(p, s, 1.0 / 6.0);
+  p = fma(p, s, 0.5);
+  p = fma(p, s, 1.0);
+  const double t = ex[k & 63];
+  return ldexp(fma(t, p * s, t), k >> 6);
 }
 
 // (rho, U) -> P, c_s.  jseed: table cell to start from (-1: bisection).
@@ -242,8 +257,8 @@ __device__ __forceinline__ void eos_pc(const Phys &p, const Table &t, double rho
   const double Ue = fmax(U, rho * p.e_floor);
   int i, j, it;
   double w, wT, lP, lc2;
-  table_rho(t, log10_fast(rho), i, w);
-  const double le = log10_fast(Ue / rho);
+  table_rho(t, log10_tab(t.lg, rho), i, w);
+  const double le = log10_tab(t.lg, Ue / rho);
   const int jj = min(jseed, t.nT - 2);
   if (jseed >= 0 && table_record(t, i, w, le, jj, wT, lP, lc2)) {
     j = jj;
@@ -251,8 +266,8 @@ __device__ __forceinline__ void eos_pc(const Phys &p, const Table &t, double rho
     table_invert(t, i, w, le, jseed, p.newton_max_iter, j, wT, it);
     tbil_pc(t, i, w, j, wT, lP, lc2);
   }
-  P = exp10(lP);
-  cs = exp10(0.5 * lc2);
+  P = exp10_tab(t.ex, lP);
+  cs = exp10_tab(t.ex, 0.5 * lc2);
   if (jout) *jout = j;
 }
 
@@ -663,7 +678,7 @@ __device__ __forceinline__ void finish_cell(const StageArgs &a, const BlockInfo 
     double w[6];
     c2p(p, qn, w);
     const double Ue = fmax(w[4], w[0] * p.e_floor);
-    const double lr = log10_fast(w[0]), le = log10_fast(Ue / w[0]);
+    const double lr = log10_tab(a.t.lg, w[0]), le = log10_tab(a.t.lg, Ue / w[0]);
     int start = jcell;
     if constexpr (NET) start = seed_cell_wave(a.s, a.t, lr, le, item_tid() & 63);
     int i, j, it;
@@ -1022,7 +1037,7 @@ __global__ __launch_bounds__(kChunk) void seed_kernel(StageArgs a) {
     for (int v = 0; v < nv; ++v) q[v] = src_val(own, B.off + v * n3 + cell);
     c2p(p, q, w);
     const double Ue = fmax(w[4], w[0] * p.e_floor);
-    const double lr = log10_fast(w[0]), le = log10_fast(Ue / w[0]);
+    const double lr = log10_tab(a.t.lg, w[0]), le = log10_tab(a.t.lg, Ue / w[0]);
     const int seed = (p.inv_mode == 1 && a.s.enabled) ? seed_cell_wave(a.s, a.t, lr, le) : -1;
     int i, j, it;
     double wr, wT;

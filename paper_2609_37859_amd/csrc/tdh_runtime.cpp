@@ -487,7 +487,15 @@ extern "C" tdh_status tdh_set_eos_table(tdh_ctx *c, int nrho, int nT, double lr0
   const size_t pc_off = (2 * np + 3) & ~(size_t)3;  // 32-byte alignment of the double4 records
   const size_t rec_off = (pc_off + 4 * np + 15) & ~(size_t)15;  // 128-byte cell records
   const size_t nrec = (size_t)(nrho - 1) * (nT - 1);
-  std::vector<double> packed(rec_off + 16 * nrec, 0.0);
+  const size_t fn_off = rec_off + 16 * nrec;  // 128-byte aligned
+  std::vector<double> packed(fn_off + 2 * 128 + 64, 0.0);
+  // log10 and 10^x tables, from the host's extended-precision library
+  for (int i = 0; i < 128; ++i) {
+    const double ci = 1.0 / (1.0 + (i + 0.5) / 128.0);
+    packed[fn_off + 2 * i] = 2.0 * ci;
+    packed[fn_off + 2 * i + 1] = (double)-log10l((long double)ci);
+  }
+  for (int j = 0; j < 64; ++j) packed[fn_off + 256 + j] = (double)exp2l((long double)j / 64.0L);
   for (int i = 0; i + 1 < nrho; ++i)
     for (int j = 0; j < nT; ++j) {
       const size_t a = (size_t)i * nT + j, b = (size_t)(i + 1) * nT + j, q = (size_t)i * nT + j;
@@ -529,6 +537,8 @@ extern "C" tdh_status tdh_set_eos_table(tdh_ctx *c, int nrho, int nT, double lr0
   c->tab.le2 = (const double2 *)c->d_table;
   c->tab.pc = (const double4 *)(c->d_table + pc_off);
   c->tab.rec = c->d_table + rec_off;
+  c->tab.lg = (const double2 *)(c->d_table + fn_off);
+  c->tab.ex = c->d_table + fn_off + 256;
   c->have_table = true;
   for (auto &g : c->graphs) hipGraphExecDestroy(g.second);
   c->graphs.clear();
