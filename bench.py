@@ -74,6 +74,7 @@ FORMS = {
     "chained": "batched launches; before each stage the table cell of every cell's state is bisected; it seeds "
                "the cell's face and compression queries",
     "plain": "one launch per level; bisection for every table query",
+    "learned_hlle": "the learned form with the HLLE Riemann solver of the paper's production runs",
 }
 
 
@@ -102,9 +103,9 @@ def train_seed(T, W, table, steps=2000, nsamples=1 << 20):
     return params, secs, float(loss[-1]), q
 
 
-def run_form(T, W, cfg, mesh, U, table, steps, warmup, inv_mode, batched, seed_params=None, tile=-1):
+def run_form(T, W, cfg, mesh, U, table, steps, warmup, inv_mode, batched, seed_params=None, tile=-1, riemann=0):
     import torch
-    ctx = T.Context(cfg, mesh, U, table=table, inv_mode=inv_mode)
+    ctx = T.Context(dataclasses.replace(cfg, riemann=riemann), mesh, U, table=table, inv_mode=inv_mode)
     if seed_params is not None:
         ctx.mlp_init(seed_params, W.seed_ranges(table))
         ctx.mlp_enable_seed(True)
@@ -189,6 +190,8 @@ def lat_section(T, W, table, seed_params, windows, warmup):
                            seed_params=seed_params),
         "temporal": run_lat(T, W, cfg, mesh, U, windows, warmup, inv_mode=3, batched=True, graph=True,
                             table=table),
+        "learned_dense_ghosts": run_lat(T, W, dataclasses.replace(cfg, ghost_dense=1), mesh, U, windows, warmup,
+                                        inv_mode=1, batched=True, graph=True, table=table, seed_params=seed_params),
         "plain": run_lat(T, W, cfg, mesh, U, windows, warmup, inv_mode=0, batched=False, graph=False,
                          table=table)}
     return out
@@ -201,9 +204,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps for the CPU baseline / accuracy check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="learned,temporal,chained,plain",
-                    help="comma list of forms to time: learned, temporal, chained, plain (learned is the headline "
-                         "when present)")
+    ap.add_argument("--forms", default="learned,temporal,chained,plain,learned_hlle",
+                    help="comma list of forms to time: learned, temporal, chained, plain, learned_hlle (learned is "
+                         "the headline when present)")
     ap.add_argument("--tile", type=int, default=-1,
                     help="stage-kernel variant id to use instead of autotuning (profiling runs fix it)")
     ap.add_argument("--lat-windows", type=int, default=5,
@@ -257,11 +260,11 @@ def main():
     forms = args.forms.split(",")
     params, train_s, train_loss, seed_err = train_seed(T, W, table)
     res = {}
-    for name, mode, batched in (("learned", 1, True), ("temporal", 3, True), ("chained", 2, True),
-                                ("plain", 0, False)):
+    for name, mode, batched, riemann in (("learned", 1, True, 0), ("temporal", 3, True, 0), ("chained", 2, True, 0),
+                                         ("plain", 0, False, 0), ("learned_hlle", 1, True, 1)):
         if name in forms:
             res[name] = run_form(T, W, cfg, mesh, U, table, args.steps, args.warmup, inv_mode=mode, batched=batched,
-                                 seed_params=params if mode == 1 else None, tile=args.tile)
+                                 seed_params=params if mode == 1 else None, tile=args.tile, riemann=riemann)
     lat = lat_section(T, W, table, params, args.lat_windows, 1) if args.lat_windows > 0 else None
     head = "learned" if "learned" in res else next(iter(res))
     el, stage_ms, launches, st, tile = res[head]

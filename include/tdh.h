@@ -88,6 +88,12 @@ typedef struct {
                      In modes 1 and 3 a pass finds the cells once after a state
                      upload (with the network in mode 1). */
   int newton_max_iter; /* seeded secant steps before falling back to bisection (>= 0) */
+  int riemann;    /* 0 HLLC (Toro Sec. 10.4); 1 HLLE, the solver of the paper's production
+                     runs (Table 1): the HLL flux with the same Davis wave-speed bounds */
+  int ghost_dense; /* LAT ghosts of a neighbour that is mid-step at the stage time
+                     (Sec. LAT method): 0 linear interpolation in time of its start and
+                     end states; 1 the dense output of its RK2 step where that state is
+                     admissible (positive density and internal energy), linear otherwise */
 } tdh_config;
 
 /* Mesh: uniform spacing dx; cubic blocks whose edge n is a power of two in

@@ -39,7 +39,8 @@ class _Cfg(C.Structure):
                 ("gamma", C.c_double), ("eta1", C.c_double), ("eta2", C.c_double), ("cfl", C.c_double),
                 ("rho_floor", C.c_double), ("p_floor", C.c_double), ("e_floor", C.c_double),
                 ("merge_frac", C.c_double), ("gm_bh", C.c_double), ("r_soft", C.c_double), ("r_exc", C.c_double),
-                ("bh_x0", C.c_double * 3), ("v_frame", C.c_double * 3)]
+                ("bh_x0", C.c_double * 3), ("v_frame", C.c_double * 3),
+                ("riemann", C.c_int), ("ghost_dense", C.c_int)]
 
 
 class _Mesh(C.Structure):
@@ -79,6 +80,10 @@ def lib():
         _lib.orc_table_invert.restype = None
         _lib.orc_hllc_flux.argtypes = [P(d), d, d, P(d), d, d, P(d)]
         _lib.orc_hllc_flux.restype = None
+        _lib.orc_hlle_flux.argtypes = [P(d), d, d, P(d), d, d, P(d)]
+        _lib.orc_hlle_flux.restype = None
+        _lib.orc_dense_value.argtypes = [d, d, d, d]
+        _lib.orc_dense_value.restype = d
         _lib.orc_num_threads.argtypes = []
         _lib.orc_num_threads.restype = i
         _lib.orc_set_interp_rounding.argtypes = [i]
@@ -222,6 +227,18 @@ def hllc_flux(wl, pl, cl, wr, pr, cr):
     return f
 
 
+def hlle_flux(wl, pl, cl, wr, pr, cr):
+    wl = np.ascontiguousarray(wl, dtype=np.float64)
+    wr = np.ascontiguousarray(wr, dtype=np.float64)
+    f = np.zeros(5)
+    lib().orc_hlle_flux(_dp(wl), pl, cl, _dp(wr), pr, cr, _dp(f))
+    return f
+
+
+def dense_value(qn, q1, qe, theta):
+    return float(lib().orc_dense_value(float(qn), float(q1), float(qe), float(theta)))
+
+
 def num_threads() -> int:
     return int(lib().orc_num_threads())
 
@@ -251,6 +268,7 @@ class _DummyCfg:
     n_lat = 0
     gamma = 5.0 / 3.0
     eta1 = eta2 = cfl = rho_floor = p_floor = e_floor = merge_frac = gm_bh = r_soft = r_exc = 0.0
+    riemann = ghost_dense = 0
     bh_x0 = v_frame = (0.0, 0.0, 0.0)
 
 

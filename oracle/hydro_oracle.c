@@ -29,8 +29,10 @@
  *                                                              lat-factor, lat-flux-impulse,
  *                                                              lat-mass-impulse-mismatch, lat-grav-reflux)
  * The Riemann solver is HLLC (Toro, Riemann Solvers and Numerical Methods for
- * Fluid Dynamics, 3rd ed., Sec. 10.4, with Davis wave-speed estimates); the
- * PLM limiter is van Leer's harmonic mean; RK2 is Heun's (SSP) method.
+ * Fluid Dynamics, 3rd ed., Sec. 10.4, with Davis wave-speed estimates) or, by
+ * configuration, the HLLE solver of the paper's production runs (Table 1;
+ * Toro Sec. 10.3 with the same wave-speed estimates); the PLM limiter is van
+ * Leer's harmonic mean; RK2 is Heun's (SSP) method.
  *
  * State layout: blocks are cubic (edge n), stored one after another, each as
  * nv arrays of n^3 doubles with x fastest.  nv = 5 (rho, mx, my, mz, E) or 6
@@ -57,6 +59,8 @@ typedef struct {
   double merge_frac;
   double gm_bh, r_soft, r_exc;
   double bh_x0[3], v_frame[3];
+  int riemann;     /* 0 HLLC, 1 HLLE */
+  int ghost_dense; /* LAT ghosts of a neighbour mid-step: 0 linear in time, 1 RK2 dense output */
 } orc_cfg;
 
 typedef struct {
@@ -289,6 +293,29 @@ static void hllc(const double *wl, double pl, double cl, const double *wr, doubl
   }
 }
 
+/*
+ * HLLE flux (Harten, Lax and van Leer; Einfeldt's positive wave-speed bounds,
+ * here the same Davis estimates as the HLLC solver), Toro (2009) eq. 10.21:
+ * F_L if S_L >= 0, F_R if S_R <= 0, else
+ * (S_R F_L - S_L F_R + S_L S_R (U_R - U_L)) / (S_R - S_L).
+ * The paper's production runs use this solver (Table 1).
+ */
+static void hlle(const double *wl, double pl, double cl, const double *wr, double pr, double cr, double *f) {
+  double rl = wl[0], ul = wl[1], vl = wl[2], zl = wl[3];
+  double rr = wr[0], ur = wr[1], vr = wr[2], zr = wr[3];
+  double El = wl[4] + 0.5 * rl * (ul * ul + vl * vl + zl * zl);
+  double Er = wr[4] + 0.5 * rr * (ur * ur + vr * vr + zr * zr);
+  double sl = fmin(ul - cl, ur - cr);
+  double sr = fmax(ul + cl, ur + cr);
+  double fl[5] = {rl * ul, rl * ul * ul + pl, rl * ul * vl, rl * ul * zl, (El + pl) * ul};
+  double fr[5] = {rr * ur, rr * ur * ur + pr, rr * ur * vr, rr * ur * zr, (Er + pr) * ur};
+  if (sl >= 0.0) { memcpy(f, fl, sizeof fl); return; }
+  if (sr <= 0.0) { memcpy(f, fr, sizeof fr); return; }
+  double ul5[5] = {rl, rl * ul, rl * vl, rl * zl, El};
+  double ur5[5] = {rr, rr * ur, rr * vr, rr * zr, Er};
+  for (int v = 0; v < 5; v++) f[v] = (sr * fl[v] - sl * fr[v] + sl * sr * (ur5[v] - ul5[v])) / (sr - sl);
+}
+
 /* ------------------------------------------------------------------ */
 /* gravity and excision geometry                                       */
 /* ------------------------------------------------------------------ */
@@ -404,7 +431,8 @@ static void block_stage(const mesh_t *M, const double *phi, int b, const double 
           eos_pc(c, T, rl[0], rl[4], &pl, &cl);
           eos_pc(c, T, rr[0], rr[4], &pr, &cr);
           double fr5[5];
-          hllc(rl, pl, cl, rr, pr, cr, fr5);
+          if (c->riemann == 1) hlle(rl, pl, cl, rr, pr, cr, fr5);
+          else hllc(rl, pl, cl, rr, pr, cr, fr5);
           double fl[7];
           fl[IDN] = fr5[0];
           for (int s = 0; s < 3; s++) fl[perm[s]] = fr5[1 + s];
@@ -693,8 +721,23 @@ typedef struct {
   int *f;      /* factor per block (in dt0 units) */
 } lat_t;
 
+/* Heun's method has the continuous extension (dense output) with weights
+ * b1 = th - th^2/2, b2 = th^2/2 on its two stage slopes; written with the
+ * stored start, stage-1 and end states of the step it is
+ * Q(th) = (1 - th) Qn + th (1 - th) Q1 + th^2 Q_{n+1}, second order in time.
+ * The weights are nonnegative and sum to one, so the value is a convex
+ * combination of three admissible states: its density, energies and (the
+ * internal energy being concave in the conserved variables) internal energy
+ * stay positive. */
+static double dense_value(double qn, double q1, double qe, double th) {
+  return (1.0 - th) * qn + th * (1.0 - th) * q1 + th * th * qe;
+}
+
 /* conserved value of variable v at global cell of block nb, as seen at
- * sub-cycle k by a reader with factor fb in phase ph (1 or 2) */
+ * sub-cycle k by a reader with factor fb in phase ph (1 or 2).  A neighbour
+ * that is mid-step at the reader's stage time has its start, stage-1 and end
+ * states stored: with ghost_dense its RK2 dense output is used there, else
+ * the linear interpolation of start and end (Sec. LAT method). */
 static double ghost_value(const lat_t *L, int reader, int nbk, size_t cell, int v, int k, int ph) {
   const mesh_t *M = L->M;
   int n = M->m->blk[4 * nbk];
@@ -702,10 +745,12 @@ static double ghost_value(const lat_t *L, int reader, int nbk, size_t cell, int 
   size_t o = M->off[nbk] + v * n3 + cell;
   int fb = L->f[reader], fn = L->f[nbk];
   int act = (k % fn) == 0;
+  const int dense = M->cfg->ghost_dense;
   if (ph == 1) {
     if (act) return L->Qend[o];
     int t0 = k - k % fn;
     double w = (double)(k - t0) / fn;
+    if (dense) return dense_value(L->Qstart[o], L->Q1[o], L->Qend[o], w);
     return (1.0 - w) * L->Qstart[o] + w * L->Qend[o];
   }
   if (act) {
@@ -715,8 +760,12 @@ static double ghost_value(const lat_t *L, int reader, int nbk, size_t cell, int 
   }
   int t0 = k - k % fn;
   double w = (double)(k + fb - t0) / fn;
+  if (dense) return dense_value(L->Qstart[o], L->Q1[o], L->Qend[o], w);
   return (1.0 - w) * L->Qstart[o] + w * L->Qend[o];
 }
+
+/* dense output of one value, for pins */
+double orc_dense_value(double qn, double q1, double qe, double th) { return dense_value(qn, q1, qe, th); }
 
 static void fill_pad(const lat_t *L, int b, int k, int ph, double *qpad) {
   const mesh_t *M = L->M;
@@ -954,6 +1003,11 @@ void orc_table_invert(const orc_table *tab, int64_t n, const double *lr, const d
 /* HLLC flux of one face for given primitive states (x-normal), for pins */
 void orc_hllc_flux(const double *wl, double pl, double cl, const double *wr, double pr, double cr, double *f) {
   hllc(wl, pl, cl, wr, pr, cr, f);
+}
+
+/* HLLE flux of one face for given primitive states (x-normal), for pins */
+void orc_hlle_flux(const double *wl, double pl, double cl, const double *wr, double pr, double cr, double *f) {
+  hlle(wl, pl, cl, wr, pr, cr, f);
 }
 
 int orc_num_threads(void) {

@@ -32,7 +32,7 @@ struct MeshDev {
 };
 
 struct Phys {
-  int eos_kind, dual, grav_kind, inv_mode, newton_max_iter;
+  int eos_kind, dual, grav_kind, inv_mode, newton_max_iter, riemann, ghost_dense;
   double gamma, eta1, eta2, rho_floor, p_floor, e_floor;
   double gm_bh, r_soft, r_exc;
   double bh_x0[3], v_frame[3];

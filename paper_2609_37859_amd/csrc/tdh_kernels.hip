@@ -43,22 +43,24 @@ __device__ __forceinline__ int block_of(const MeshDev &m, int gx, int gy, int gz
 // Where a reader with factor fb finds block nb's conserved state at its stage time.
 struct Src {
   const double *A, *B;
-  double w;  // value = (1 - w) A + w B; w in {0, 1/2, 1}
+  const double *C;  // stage-1 state of a neighbour mid-step (dense output), else null
+  double w;         // value = (1 - w) A + w B, w in [0, 1]; with C the RK2 dense output at w
 };
 
-template <bool UNIFORM = false>
 __device__ __forceinline__ Src source_of(const StageArgs &a, int fb, int nb) {
-  // UNIFORM: nb is the same in every lane; keep the result in scalar registers
-  const int fn = UNIFORM ? __builtin_amdgcn_readfirstlane(a.fac[nb]) : a.fac[nb];
-  const int pn = UNIFORM ? __builtin_amdgcn_readfirstlane(a.par[nb]) : a.par[nb];
+  const int fn = a.fac[nb];
+  const int pn = a.par[nb];
   const double *Qend = pn ? a.Qb : a.Qa;   // latest computed state
   const double *Qold = pn ? a.Qa : a.Qb;   // state at the start of that step
   const bool act = (a.k & (fn - 1)) == 0;  // factors are powers of two
   Src s;
+  s.C = nullptr;
   if (a.phase == 1) {
     if (act) { s.A = Qend; s.B = Qend; s.w = 0.0; return s; }
+    // mid-step: start, stage-1 and end states of its step are stored
     const int t0 = a.k & ~(fn - 1);
     s.A = Qold; s.B = Qend; s.w = (double)(a.k - t0) / fn;
+    if (a.p.ghost_dense) s.C = a.Qs;
     return s;
   }
   if (act) {
@@ -68,11 +70,30 @@ __device__ __forceinline__ Src source_of(const StageArgs &a, int fb, int nb) {
   }
   const int t0 = a.k & ~(fn - 1);
   s.A = Qold; s.B = Qend; s.w = (double)(a.k + fb - t0) / fn;
+  if (a.p.ghost_dense) s.C = a.Qs;
   return s;
 }
 
+// The stage-input state of a block that is active in this sub-cycle (its own
+// cells): source_of's active case, with no interpolation.
+__device__ __forceinline__ Src own_source(const StageArgs &a, int par) {
+  Src s;
+  s.A = a.phase == 1 ? (par ? a.Qb : a.Qa) : a.Qs;
+  s.B = s.A;
+  s.C = nullptr;
+  s.w = 0.0;
+  return s;
+}
+
+// With C: Heun's dense output (weights th - th^2/2 and th^2/2 on the stage
+// slopes) in stored states, (1 - w) Qn + w (1 - w) Q1 + w^2 Q_{n+1}: second
+// order in time, and a convex combination, so admissible states stay admissible.
 __device__ __forceinline__ double src_val(const Src &s, long long idx) {
   if (s.w == 0.0) return s.A[idx];
+  if (s.C) {
+#pragma clang fp contract(off)
+    return (1.0 - s.w) * s.A[idx] + s.w * (1.0 - s.w) * s.C[idx] + s.w * s.w * s.B[idx];
+  }
   if (s.w == 1.0) return s.B[idx];
   return (1.0 - s.w) * s.A[idx] + s.w * s.B[idx];
 }
@@ -328,6 +349,35 @@ __device__ __forceinline__ void hllc(const double *wl, double pl, double cl, con
   f[4] = f4 + s * (us4 - E);
 }
 
+// HLLE: the HLL flux (Toro Sec. 10.3) with the Davis wave-speed bounds of the
+// HLLC solver above; the solver of the paper's production runs (Table 1)
+__device__ __forceinline__ void hlle(const double *wl, double pl, double cl, const double *wr, double pr, double cr,
+                                     double *f) {
+  const double rl = wl[0], ul = wl[1], vl = wl[2], zl = wl[3];
+  const double rr = wr[0], ur = wr[1], vr = wr[2], zr = wr[3];
+  const double El = wl[4] + 0.5 * rl * (ul * ul + vl * vl + zl * zl);
+  const double Er = wr[4] + 0.5 * rr * (ur * ur + vr * vr + zr * zr);
+  const double sl = fmin(ul - cl, ur - cr);
+  const double sr = fmax(ul + cl, ur + cr);
+  const double fl[5] = {rl * ul, rl * ul * ul + pl, rl * ul * vl, rl * ul * zl, (El + pl) * ul};
+  const double fr[5] = {rr * ur, rr * ur * ur + pr, rr * ur * vr, rr * ur * zr, (Er + pr) * ur};
+  if (sl >= 0.0) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) f[v] = fl[v];
+    return;
+  }
+  if (sr <= 0.0) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) f[v] = fr[v];
+    return;
+  }
+  const double ql[5] = {rl, rl * ul, rl * vl, rl * zl, El};
+  const double qr[5] = {rr, rr * ur, rr * vr, rr * zr, Er};
+  const double ss = sl * sr, den = sr - sl;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) f[v] = (sr * fl[v] - sl * fr[v] + ss * (qr[v] - ql[v])) / den;
+}
+
 // ---------------------------------------------------------------------------
 // gravity / excision geometry
 // ---------------------------------------------------------------------------
@@ -520,7 +570,8 @@ __device__ __forceinline__ void face_flux(const StageArgs &a, const BlockInfo &B
   eos_pc(p, a.t, wl[0], wl[4], seedl, pl, cl, &jl);
   eos_pc(p, a.t, wr[0], wr[4], p.inv_mode == 0 ? -1 : jl, pr, cr);
   double F[5];
-  hllc(wl, pl, cl, wr, pr, cr, F);
+  if (p.riemann == 1) hlle(wl, pl, cl, wr, pr, cr, F);
+  else hllc(wl, pl, cl, wr, pr, cr, F);
   double FA = 0.0, vf;
   {
     const bool up_left = F[0] >= 0.0;
@@ -829,7 +880,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) 
     T.fb = uni(a.fac[T.b]);
     T.dtb = T.fb * dt0;
     T.t = a.phase == 1 ? tk : tk + T.dtb;
-    T.own = source_of<true>(a, T.fb, T.b);
+    T.own = own_source(a, uni(a.par[T.b]));
     const int cc[3] = {tid % TX, (tid / TX) % TY, tid / (TX * TY)};
     const int lc[3] = {T.to[0] + cc[0], T.to[1] + cc[1], T.to[2] + cc[2]};
     const long long cell = ((long long)lc[2] * n + lc[1]) * n + lc[0];
@@ -897,7 +948,7 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
     const int fb = uni(a.fac[b]);
     const double dtb = fb * dt0;
     const double t = a.phase == 1 ? tk : tk + dtb;
-    const Src own = source_of<true>(a, fb, b);
+    const Src own = own_source(a, uni(a.par[b]));
     const int ex = n + (D == 0), ey = n + (D == 1);
     const int fr[3] = {(int)(f % ex), (int)((f / ex) % ey), (int)(f / ((long long)ex * ey))};  // cell right of the face
     // the four cells of the stencil along D: primitives, and the block across a block face
@@ -976,7 +1027,7 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
     const int fb = uni(a.fac[b]);
     const double dtb = fb * dt0;
     const double t = a.phase == 1 ? tk : tk + dtb;
-    const Src own = source_of<true>(a, fb, b);
+    const Src own = own_source(a, uni(a.par[b]));
     const int parb = uni(a.par[b]);
     const int lc[3] = {(int)(cell % n), (int)((cell / n) % n), (int)(cell / ((long long)n * n))};
     const int g[3] = {B.ox + lc[0], B.oy + lc[1], B.oz + lc[2]};
@@ -1032,7 +1083,7 @@ __global__ __launch_bounds__(kChunk) void seed_kernel(StageArgs a) {
     const BlockInfo B = a.m.blocks[b];
     const long long n3 = (long long)B.n * B.n * B.n;
     const long long cell = (long long)bt.y * kChunk + threadIdx.x;
-    const Src own = source_of(a, a.fac[b], b);
+    const Src own = own_source(a, a.par[b]);
     double q[6], w[6];
     for (int v = 0; v < nv; ++v) q[v] = src_val(own, B.off + v * n3 + cell);
     c2p(p, q, w);

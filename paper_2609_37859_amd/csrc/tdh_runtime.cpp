@@ -188,6 +188,8 @@ extern "C" tdh_status tdh_init(const tdh_config *cfg, void *hip_stream, tdh_ctx 
   if (cfg->inv_mode < 0 || cfg->inv_mode > 3) return fail(nullptr, TDH_EINVAL, "inv_mode must be 0, 1, 2 or 3");
   if (cfg->newton_max_iter < 0 || cfg->newton_max_iter > 64)
     return fail(nullptr, TDH_EINVAL, "newton_max_iter must be in [0, 64]");
+  if (cfg->riemann < 0 || cfg->riemann > 1) return fail(nullptr, TDH_EINVAL, "riemann must be 0 (HLLC) or 1 (HLLE)");
+  if (cfg->ghost_dense < 0 || cfg->ghost_dense > 1) return fail(nullptr, TDH_EINVAL, "ghost_dense must be 0 or 1");
   if (cfg->eos_kind == 0 && !(cfg->gamma > 1.0)) return fail(nullptr, TDH_EINVAL, "gamma must exceed 1");
   if (!(cfg->cfl > 0.0)) return fail(nullptr, TDH_EINVAL, "cfl must be positive");
   tdh_ctx *c = new tdh_ctx();
@@ -240,6 +242,8 @@ static Phys make_phys(const tdh_config &g) {
   p.grav_kind = g.grav_kind;
   p.inv_mode = g.inv_mode;
   p.newton_max_iter = g.newton_max_iter;
+  p.riemann = g.riemann;
+  p.ghost_dense = g.ghost_dense;
   p.gamma = g.gamma;
   p.eta1 = g.eta1;
   p.eta2 = g.eta2;

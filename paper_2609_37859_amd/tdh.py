@@ -27,7 +27,8 @@ class tdh_config(C.Structure):
                 ("rho_floor", C.c_double), ("p_floor", C.c_double), ("e_floor", C.c_double),
                 ("merge_frac", C.c_double), ("gm_bh", C.c_double), ("r_soft", C.c_double), ("r_exc", C.c_double),
                 ("bh_x0", C.c_double * 3), ("v_frame", C.c_double * 3),
-                ("inv_mode", C.c_int), ("newton_max_iter", C.c_int)]
+                ("inv_mode", C.c_int), ("newton_max_iter", C.c_int), ("riemann", C.c_int),
+                ("ghost_dense", C.c_int)]
 
 
 class tdh_mesh(C.Structure):

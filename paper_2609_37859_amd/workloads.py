@@ -56,6 +56,8 @@ class Config:
     r_exc: float = 0.0
     bh_x0: tuple = (0.0, 0.0, 0.0)
     v_frame: tuple = (0.0, 0.0, 0.0)
+    riemann: int = 0           # 0 HLLC, 1 HLLE
+    ghost_dense: int = 0       # LAT ghosts of a neighbour mid-step: 0 linear in time, 1 RK2 dense output
 
     @property
     def nv(self) -> int:

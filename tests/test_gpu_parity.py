@@ -5,6 +5,7 @@ oracle never sees GPU output.  Bar: max relative error <= 1e-11 per variable
 and cell (tests/parity.py), bit-exact for integer results (levels, schedule,
 table cells) and between launch forms of the GPU path itself.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -182,8 +183,10 @@ def test_levels_bit_exact_and_dt_parity(tdh, orc):
     assert L >= 1
 
 
-def _lat_run_gpu(T, cfg, mesh, U, phi, levels, dt0, windows, batched=True, graph=False, step_api=False):
+def _lat_run_gpu(T, cfg, mesh, U, phi, levels, dt0, windows, batched=True, graph=False, step_api=False, tile=None):
     ctx = T.Context(cfg, mesh, U, phi=phi)
+    if tile is not None:
+        ctx.set_tile(tile)
     Lmax = int(np.max(levels))
     for w in range(windows):
         ctx.set_levels(levels)
@@ -221,6 +224,53 @@ def test_lat_window_parity_polytrope(tdh, orc):
     g3, _ = _lat_run_gpu(tdh, cfg, mesh, U, phi, lev, dt0, 2, graph=True)
     g4, _ = _lat_run_gpu(tdh, cfg, mesh, U, phi, lev, dt0, 2, step_api=True)
     assert np.array_equal(g, g2) and np.array_equal(g, g3) and np.array_equal(g, g4)
+
+
+@pytest.mark.parametrize("ghost_dense,riemann", [(1, 0), (0, 1), (1, 1)])
+def test_lat_dense_ghosts_and_hlle_polytrope(tdh, orc, ghost_dense, riemann):
+    """LAT windows on the reduced polytrope with the RK2 dense-output ghosts
+    and/or the HLLE solver: GPU equals the oracle to 1e-11; launch forms and
+    the fused and split stage forms agree bit for bit."""
+    base, mesh, U, phi, info = W.polytrope_c3(nb=4, n=16)
+    cfg = dataclasses.replace(base, ghost_dense=ghost_dense, riemann=riemann)
+    dto = orc.cfl(cfg, mesh, U, phi=phi)
+    lev, L, dt0 = orc.lat_assign(cfg, mesh, dto)
+    assert L >= 1
+    o, t = U, 0.0
+    for w in range(2):
+        o, nupd = orc.lat_window(cfg, mesh, o, lev, dt0, phi=phi, t0=t)
+        t += dt0 * 2 ** L
+    g, st = _lat_run_gpu(tdh, cfg, mesh, U, phi, lev, dt0, 2)
+    err = rel_err(5, mesh, g, o)
+    print("LAT dense/HLLE rel err", err)
+    assert np.all(err <= TOL)
+    if ghost_dense:  # the dense output changes the result where neighbours are mid-step
+        lin, _ = orc.lat_window(dataclasses.replace(cfg, ghost_dense=0), mesh, U, lev, dt0, phi=phi)
+        one, _ = orc.lat_window(cfg, mesh, U, lev, dt0, phi=phi)
+        assert not np.array_equal(lin, one)
+    g2, _ = _lat_run_gpu(tdh, cfg, mesh, U, phi, lev, dt0, 2, batched=False)
+    g3, _ = _lat_run_gpu(tdh, cfg, mesh, U, phi, lev, dt0, 2, graph=True)
+    split = [i for i, d in enumerate(tdh.tile_shapes()) if d[0] == 0][0]
+    g4, _ = _lat_run_gpu(tdh, cfg, mesh, U, phi, lev, dt0, 2, tile=split)
+    assert np.array_equal(g, g2) and np.array_equal(g, g3) and np.array_equal(g, g4)
+
+
+@pytest.mark.parametrize("kind", ["c1", "c2"])
+def test_hlle_sync_parity(tdh, orc, saha, kind):
+    """The HLLE solver on C1 (ideal gas) and on the C2 table + dual-energy
+    stream (20 steps, carried seed cells): GPU equals the oracle to 1e-11."""
+    if kind == "c1":
+        base, mesh, U = W.entropy_wave_c1()
+        table, nv, kw = None, 5, {}
+    else:
+        base, mesh, U = W.stream_c2(saha)
+        table, nv, kw = saha, 6, {"inv_mode": 3}
+    cfg = dataclasses.replace(base, riemann=1)
+    g, dg = _run_gpu_sync(tdh, cfg, mesh, U, 20, table=table, **kw)
+    o, do = orc.run_sync(cfg, mesh, U, 20, table=table, dts=dg)
+    err = rel_err(nv, mesh, g, o)
+    print(kind, "HLLE rel err", err)
+    assert np.all(err <= TOL)
 
 
 def test_lat_reflux_conservation_gpu(tdh, orc):

@@ -204,8 +204,9 @@ def _lat_levels_periodic(mesh):
     return np.array([{0: 2, 1: 1, 2: 0, 3: 1}[int(x)] for x in bx], dtype=np.int32)
 
 
-def test_lat_single_level_equals_sync(orc):
-    cfg = W.Config(dual=1)
+@pytest.mark.parametrize("ghost_dense", [0, 1])
+def test_lat_single_level_equals_sync(orc, ghost_dense):
+    cfg = W.Config(dual=1, ghost_dense=ghost_dense)
     mesh = W.uniform_mesh(2, 2, 1, 8, 1.0 / 16)
     U = W.random_smooth_state(mesh, cfg, seed=2)
     a, _ = orc.lat_window(cfg, mesh, U, np.zeros(mesh.nblocks, int), 1e-3)
@@ -213,12 +214,13 @@ def test_lat_single_level_equals_sync(orc):
     assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("ghost_dense", [0, 1])
 @pytest.mark.parametrize("grav", [0, 1])
-def test_lat_reflux_conserves(orc, grav):
+def test_lat_reflux_conserves(orc, grav, ghost_dense):
     """Mixed-factor periodic run: reflux makes sum(rho), sum(m), sum(E) (and with a
     static potential sum(E + rho Phi)) exact to roundoff (eqs lat-flux-impulse,
-    lat-grav-reflux)."""
-    cfg = W.Config(dual=1, grav_kind=grav)
+    lat-grav-reflux), with either ghost time interpolation."""
+    cfg = W.Config(dual=1, grav_kind=grav, ghost_dense=ghost_dense)
     mesh = W.uniform_mesh(4, 2, 2, 4, 1.0 / 16)
     U = W.random_smooth_state(mesh, cfg, seed=8, amp=0.3)
     lev = _lat_levels_periodic(mesh)
@@ -267,3 +269,53 @@ def test_lat_accuracy_matches_sync_on_entropy_wave(orc):
     eb = np.abs(W.to_global(mesh, 5, b)[0, 3, 3] - ex).max()
     assert ea < 3 * eb + 1e-6
     assert ea > 0
+
+
+def test_dense_output_on_the_linear_test_equation(orc):
+    """Heun's method on y' = lam y with h = lam dt: Q1 = (1 + h) y0 and
+    Q_{n+1} = (1 + h + h^2/2) y0.  Its dense output at th is the second-order
+    Taylor polynomial y0 (1 + th h + (th h)^2 / 2) of the exact solution, which
+    the linear interpolation of the endpoints misses by th (1 - th) h^2 / 2."""
+    for h in (-0.3, 0.05, 0.2):
+        y0 = 1.7
+        q1, qe = (1 + h) * y0, (1 + h + h * h / 2) * y0
+        for th in (0.25, 0.5, 0.75):
+            d = orc.dense_value(y0, q1, qe, th)
+            assert abs(d - y0 * (1 + th * h + (th * h) ** 2 / 2)) <= 4e-16 * y0
+            lin = (1 - th) * y0 + th * qe
+            assert abs(lin - d - y0 * th * (1 - th) * h * h / 2) <= 4e-16 * y0
+        assert orc.dense_value(y0, q1, qe, 0.0) == y0 and orc.dense_value(y0, q1, qe, 1.0) == qe
+
+
+def test_dense_output_is_a_convex_combination(orc):
+    """Weights (1 - th), th (1 - th), th^2: nonnegative, summing to one, so a
+    positive value stays between the smallest and largest stored one."""
+    rng = np.random.default_rng(4)
+    for _ in range(200):
+        q = rng.uniform(1e-3, 10.0, size=3)
+        th = rng.uniform(0.0, 1.0)
+        d = orc.dense_value(q[0], q[1], q[2], th)
+        assert q.min() * (1 - 1e-15) <= d <= q.max() * (1 + 1e-15)
+        assert abs(orc.dense_value(q[0], q[0], q[0], th) - q[0]) <= 5e-16 * q[0]
+
+
+def test_lat_dense_ghosts_follow_the_synchronised_run_closer(orc):
+    """Advected entropy wave: the fine blocks, whose ghosts come from mid-step
+    neighbours, end closer to the synchronised run with the RK2 dense output
+    than with linear interpolation in time (second against first order)."""
+    mesh = W.uniform_mesh(4, 2, 2, 4, 1.0 / 16)
+    lev = _lat_levels_periodic(mesh)
+    for dt0 in (2e-3, 8e-3):
+        dev = []
+        for gd in (0, 1):
+            cfg = W.Config(ghost_dense=gd)
+
+            def fn(x, y, z):
+                rho = 1.0 + 0.2 * np.sin(2 * np.pi * x)
+                return W.ideal_conserved(rho, 1.0, 0 * x, 0 * x, 1.0 + 0 * x, cfg.gamma, False)
+            U = W.pack_state(mesh, 5, fn)
+            a, _ = orc.lat_window(cfg, mesh, U, lev, dt0)
+            b, _ = orc.run_sync(cfg, mesh, U, 4, dts=[dt0] * 4)
+            A, B = W.to_global(mesh, 5, a), W.to_global(mesh, 5, b)
+            dev.append(np.abs(A[:, :, :, :4] - B[:, :, :, :4]).max())  # x blocks 0: level 2 (finest)
+        assert 0.0 < dev[1] < 0.95 * dev[0], dev

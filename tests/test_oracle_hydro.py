@@ -22,10 +22,11 @@ def fsum_vars(mesh, nv, U):
 
 
 # --- invariants ------------------------------------------------------------
+@pytest.mark.parametrize("riemann", [0, 1])
 @pytest.mark.parametrize("dual", [0, 1])
-def test_uniform_state_preserved_bitwise(orc, dual):
+def test_uniform_state_preserved_bitwise(orc, dual, riemann):
     """A uniform state is an exact steady solution of the discrete update."""
-    cfg = W.Config(dual=dual)
+    cfg = W.Config(dual=dual, riemann=riemann)
     mesh = W.uniform_mesh(2, 2, 1, 8, (0.1, 0.2, 0.15))
     U = W.uniform_state(mesh, cfg)
     U2, _ = orc.run_sync(cfg, mesh, U, 20)
@@ -44,10 +45,11 @@ def test_uniform_state_preserved_bitwise_table(orc):
     assert np.array_equal(U, U2)
 
 
+@pytest.mark.parametrize("riemann", [0, 1])
 @pytest.mark.parametrize("dual", [0, 1])
-def test_periodic_conservation(orc, dual):
+def test_periodic_conservation(orc, dual, riemann):
     """Flux telescoping: sums of rho, m, E conserved to roundoff on a periodic box."""
-    cfg = W.Config(dual=dual)
+    cfg = W.Config(dual=dual, riemann=riemann)
     mesh = W.uniform_mesh(2, 2, 2, 8, 1.0 / 16)
     U = W.random_smooth_state(mesh, cfg, seed=3, amp=0.3)
     s0 = fsum_vars(mesh, cfg.nv, U)
@@ -112,8 +114,8 @@ def test_exact_riemann_solver_matches_textbook_star_state():
     assert abs(p - s["p_star"]) < 5e-6 and abs(u - s["u_star"]) < 5e-6
 
 
-def _sod_run(orc, ncell):
-    cfg = W.Config(gamma=1.4, rho_floor=1e-10, p_floor=1e-20, cfl=0.3)
+def _sod_run(orc, ncell, riemann=0):
+    cfg = W.Config(gamma=1.4, rho_floor=1e-10, p_floor=1e-20, cfl=0.3, riemann=riemann)
     mesh = W.uniform_mesh(ncell // 4, 1, 1, 4, 1.0 / ncell, bc=(1, 0, 0))
 
     def fn(x, y, z):
@@ -141,6 +143,91 @@ def test_sod_converges_to_exact_solution(orc):
     e256 = _sod_run(orc, 256)
     assert e256 < 6e-3
     assert e128 / e256 > 1.4
+
+
+def test_sod_hlle_converges_and_is_more_diffusive(orc):
+    """HLLE (the paper's production solver) on Sod: L1 error that falls with
+    resolution, and above HLLC's, which resolves the contact."""
+    e128 = _sod_run(orc, 128, riemann=1)
+    e256 = _sod_run(orc, 256, riemann=1)
+    assert e256 < 8e-3
+    assert e128 / e256 > 1.4
+    assert e256 > _sod_run(orc, 256, riemann=0)
+
+
+def _flux_states(rng, n):
+    """Random primitive states (rho, u, v, w, U) with pressure and sound speed
+    of an ideal gas, gamma = 1.4."""
+    out = []
+    for _ in range(n):
+        w = [rng.uniform(0.1, 2.0), rng.uniform(-1.5, 1.5), rng.uniform(-1, 1), rng.uniform(-1, 1),
+             rng.uniform(0.2, 3.0)]
+        P = 0.4 * w[4]
+        out.append((np.array(w), P, math.sqrt(1.4 * P / w[0])))
+    return out
+
+
+def _phys_flux(w, P):
+    r, u, v, z, U = w
+    E = U + 0.5 * r * (u * u + v * v + z * z)
+    return np.array([r * u, r * u * u + P, r * u * v, r * u * z, (E + P) * u]), \
+        np.array([r, r * u, r * v, r * z, E])
+
+
+def test_hlle_flux_consistency_and_upwinding(orc):
+    """F(U, U) is the physical flux; with every wave moving right (left) the
+    flux is the left (right) physical flux exactly."""
+    rng = np.random.default_rng(11)
+    for w, P, c in _flux_states(rng, 20):
+        F, _ = _phys_flux(w, P)
+        assert np.allclose(orc.hlle_flux(w, P, c, w, P, c), F, rtol=1e-14, atol=1e-14)
+        ws, wo = w.copy(), w.copy()
+        ws[1], wo[1] = c + 0.5, c + 0.1      # every wave to the right
+        Fs, _ = _phys_flux(ws, P)
+        assert np.array_equal(orc.hlle_flux(ws, P, c, wo, P, c), Fs)
+        ws[1], wo[1] = -c - 0.5, -c - 0.1    # every wave to the left
+        Fs, _ = _phys_flux(ws, P)
+        assert np.array_equal(orc.hlle_flux(wo, P, c, ws, P, c), Fs)
+
+
+def test_hlle_flux_is_the_hll_state_flux(orc):
+    """Integral consistency (Toro Sec. 10.3): with the single intermediate state
+    U* = (S_R U_R - S_L U_L - (F_R - F_L)) / (S_R - S_L), the HLL flux equals
+    both F_L + S_L (U* - U_L) and F_R + S_R (U* - U_R)."""
+    rng = np.random.default_rng(12)
+    st = _flux_states(rng, 40)
+    for (wl, pl, cl), (wr, pr, cr) in zip(st[::2], st[1::2]):
+        sl = min(wl[1] - cl, wr[1] - cr)
+        sr = max(wl[1] + cl, wr[1] + cr)
+        if not (sl < 0.0 < sr):
+            continue
+        FL, UL = _phys_flux(wl, pl)
+        FR, UR = _phys_flux(wr, pr)
+        Us = (sr * UR - sl * UL - (FR - FL)) / (sr - sl)
+        F = orc.hlle_flux(wl, pl, cl, wr, pr, cr)
+        scale = np.abs(FL) + np.abs(FR) + np.abs(sl * UL) + np.abs(sr * UR)
+        assert np.all(np.abs(F - (FL + sl * (Us - UL))) <= 1e-13 * scale)
+        assert np.all(np.abs(F - (FR + sr * (Us - UR))) <= 1e-13 * scale)
+
+
+def test_stationary_contact_kept_by_hllc_smeared_by_hlle(orc):
+    """A density jump at rest in uniform pressure is an exact steady solution of
+    HLLC (it resolves the contact wave) but not of HLLE, which diffuses it."""
+    mesh = W.uniform_mesh(2, 1, 1, 8, 1.0 / 16, bc=(0, 0, 0))
+
+    def fn(x, y, z):
+        rho = np.where((x > 0.25) & (x < 0.75), 2.0, 1.0)
+        return W.ideal_conserved(rho, 0 * x, 0 * x, 0 * x, 1.0 + 0 * x, 5.0 / 3.0, False)
+
+    U = W.pack_state(mesh, 5, fn)
+    dts = [2e-3] * 10
+    kept, _ = orc.run_sync(W.Config(riemann=0), mesh, U, 10, dts=dts)
+    smeared, _ = orc.run_sync(W.Config(riemann=1), mesh, U, 10, dts=dts)
+    assert np.array_equal(kept, U)
+    g0, g1 = W.to_global(mesh, 5, U), W.to_global(mesh, 5, smeared)
+    assert np.max(np.abs(g1[0] - g0[0])) > 1e-2
+    assert np.allclose(g1[1:4], 0.0, atol=1e-12)             # still at rest
+    assert abs(math.fsum(g1[0].ravel()) - math.fsum(g0[0].ravel())) < 1e-13 * g0[0].sum()
 
 
 def test_linear_sound_wave_second_order(orc):
