@@ -16,7 +16,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["hydro_oracle.c", "mlp_oracle.c"]
+_SOURCES = ["hydro_oracle.c", "mlp_oracle.c", "gravity_oracle.c"]
 
 
 def build(verbose: bool = False) -> str:
@@ -84,6 +84,10 @@ def lib():
         _lib.orc_hlle_flux.restype = None
         _lib.orc_dense_value.argtypes = [d, d, d, d]
         _lib.orc_dense_value.restype = d
+        _lib.orc_mg_levels.argtypes = [i, i, i, P(i)]
+        _lib.orc_mg_levels.restype = i
+        _lib.orc_mg_solve.argtypes = [P(_Mesh), i, P(d), d, i, d, i, P(d), P(d), P(d)]
+        _lib.orc_mg_solve.restype = i
         _lib.orc_num_threads.argtypes = []
         _lib.orc_num_threads.restype = i
         _lib.orc_set_interp_rounding.argtypes = [i]
@@ -237,6 +241,31 @@ def hlle_flux(wl, pl, cl, wr, pr, cr):
 
 def dense_value(qn, q1, qe, theta):
     return float(lib().orc_dense_value(float(qn), float(q1), float(qe), float(theta)))
+
+
+def mg_levels(nx, ny, nz):
+    """Grid dimensions of every multigrid level, finest first."""
+    dims = np.zeros(3 * 24, dtype=np.int32)
+    n = lib().orc_mg_levels(nx, ny, nz, _ip(dims))
+    return [tuple(int(v) for v in dims[3 * l:3 * l + 3]) for l in range(n)]
+
+
+def mg_solve(mesh, nv, U, four_pi_G, max_cycles, tol=0.0, phi_global=None):
+    """Self-gravity potential of state U by multigrid V-cycles (periodic).
+    Returns (phi_global [nz, ny, nx], phi_blocks (per block (n+2)^3), cycles,
+    rms defects before and after each cycle).  phi_global, if given, is the
+    warm start."""
+    k = _Keep(_DummyCfg(), mesh, None)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    warm = phi_global is not None
+    pg = np.zeros((mesh.nz, mesh.ny, mesh.nx)) if not warm else np.array(phi_global, dtype=np.float64, order="C")
+    pb = np.zeros(int(sum((int(n) + 2) ** 3 for n in mesh.blk[:, 0])))
+    defects = np.zeros(max_cycles + 1)
+    c = lib().orc_mg_solve(C.byref(k.mesh), nv, _dp(U), float(four_pi_G), int(max_cycles), float(tol), int(warm),
+                           _dp(pg), _dp(pb), _dp(defects))
+    if c < 0:
+        raise ValueError("the self-gravity solve needs a periodic mesh")
+    return pg, pb, c, defects[:c + 1]
 
 
 def num_threads() -> int:
