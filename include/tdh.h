@@ -178,6 +178,38 @@ tdh_status tdh_set_time(tdh_ctx *ctx, double t);
 tdh_status tdh_get_state(tdh_ctx *ctx, double *host_state);
 tdh_status tdh_set_state(tdh_ctx *ctx, const double *host_state);
 
+/* Self-gravity at a synchronised state (Sec. Self-gravity solver, eqs
+ * selfgrav-poisson, selfgrav-defect): solves A phi = S on the mesh's uniform
+ * grid, A = -lap_h the seven-point operator (neighbours in y and z weighted by
+ * (dx/dy)^2 and (dx/dz)^2, centre 2 (1 + wy + wz)), S = -4 pi G (rho - mean
+ * rho) from the current density, with periodic boundaries, by geometric
+ * multigrid V-cycles (red-black Gauss-Seidel, over-relaxation 1.15, two pre-
+ * and two post-sweeps per level, defect restricted by child means, coarse
+ * correction in full-approximation form, tricubic prolongation, one extra
+ * finest sweep per cycle; the coarsest level gets 2 (nx+ny+nz)^2 sweeps).  The
+ * result, shifted to zero mean, is written into the stored potential that the
+ * hydro update reads (per block (n+2)^3 with one ghost layer), so grav_kind
+ * must be 1.
+ * Requirements: every axis periodic; the levels halve every axis while all
+ * are at least 4, and every level, the coarsest included, has even
+ * dimensions; the coarsest level holds at most 2048 cells (TDH_EINVAL /
+ * TDH_ERANGE otherwise).  Only between windows (TDH_ESTATE).
+ * dev_work: caller-owned device buffer of at least the bytes
+ * tdh_gravity_workspace_bytes returns; its first nx*ny*nz doubles hold the
+ * solution on the global grid ([nz][ny][nx], x fastest), the start of the
+ * next solve when warm != 0 (pass the same buffer again); warm == 0 starts
+ * from zero.  V-cycles run until the root-mean-square defect is <= tol or
+ * max_cycles in [0, 1000] have run (tol 0: exactly max_cycles).
+ * host_cycles (nullable): V-cycles run.  host_defects (nullable,
+ * max_cycles + 1 doubles): the RMS defect before the first and after each
+ * cycle.  Synchronises the stream. */
+tdh_status tdh_gravity_workspace_bytes(tdh_ctx *ctx, size_t *host_bytes);
+tdh_status tdh_gravity_solve(tdh_ctx *ctx, void *dev_work, size_t bytes, double four_pi_G, int max_cycles,
+                             double tol, int warm, int *host_cycles, double *host_defects);
+/* Copy of the stored potential (grav_kind 1): per block (n+2)^3 doubles with
+ * one ghost layer, blocks in order, x fastest.  Synchronises the stream. */
+tdh_status tdh_get_potential(tdh_ctx *ctx, double *host_phi);
+
 /* Seed table cells held for the current state (tdh_config.inv_mode 3; table
  * EOS only): host_cells receives one int32 per cell, blocks in order, cells of
  * a block x fastest; -1 where none is held yet (after a state upload).  The

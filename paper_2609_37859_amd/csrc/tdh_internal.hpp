@@ -104,6 +104,33 @@ struct StageArgs {
 };
 
 // host-side launchers (tdh_kernels.hip)
+// One multigrid level of the self-gravity solve: a dense periodic [nz][ny][nx]
+// grid with x spacing hx (hx2 = hx^2), anisotropy weights wy = (hx/hy)^2,
+// wz = (hx/hz)^2, centre coefficient c0 = 2 (1 + wy + wz); phi, the source,
+// the defect (tmp) and the restricted fine solution (rphi, coarse levels only).
+struct MgLevel {
+  int nx, ny, nz;
+  double hx2, wy, wz, c0;
+  double *phi, *src, *tmp, *rphi;
+};
+constexpr int kMgMaxLevels = 24;
+constexpr int kMgSumParts = 1024;  // workgroups of the deterministic sums
+
+hipError_t mg_launch_gather(const MeshDev &m, const int *par, const double *Qa, const double *Qb, double *rho,
+                            hipStream_t s);
+hipError_t mg_launch_sum(const double *x, long long n, int square, double scale, int op, double *part, double *out,
+                         hipStream_t s);
+hipError_t mg_launch_source(double *src, const double *mean, double four_pi_G, long long n, hipStream_t s);
+hipError_t mg_launch_affine(double *x, const double *shift, double fill, long long n, hipStream_t s);
+hipError_t mg_launch_sweep(const MgLevel &L, hipStream_t s);
+hipError_t mg_launch_defect(const MgLevel &L, hipStream_t s);
+hipError_t mg_launch_restrict(const MgLevel &F, const MgLevel &C, hipStream_t s);
+hipError_t mg_launch_coarse_solve(const MgLevel &C, int sweeps, hipStream_t s);
+hipError_t mg_launch_prolong(const MgLevel &F, const MgLevel &C, hipStream_t s);
+hipError_t mg_launch_scatter(const MeshDev &m, int nblocks, int nmax, const double *phi, double *phib,
+                             hipStream_t s);
+int mg_coarse_max();
+
 int num_tiles();
 void tile_shape(int id, int *dims);  // x, y, z edges and waves per SIMD of variant id (x = 0: split form)
 hipError_t launch_stage(const StageArgs &a, int tile, int grid, hipStream_t s);

@@ -847,6 +847,145 @@ extern "C" tdh_status tdh_get_state(tdh_ctx *c, double *host) {
   return TDH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// self-gravity: multigrid solve into the stored potential (Sec. Self-gravity solver)
+// ---------------------------------------------------------------------------
+namespace {
+struct MgPlan {
+  int nlev = 0;
+  MgLevel lv[kMgMaxLevels];
+  double *part = nullptr, *scal = nullptr;  // sum partials; mean density, defect norm, mean potential
+  size_t bytes = 0;
+};
+}  // namespace
+
+// levels halve every axis while all are even and at least 4; the layout puts the
+// finest potential first (the warm start of the next solve)
+static tdh_status mg_plan(tdh_ctx *c, char *base, MgPlan *P) {
+  if (c->cfg.grav_kind != 1 || !c->phi)
+    return fail(c, TDH_ESTATE, "the self-gravity solve writes the stored potential: grav_kind must be 1");
+  for (int d = 0; d < 3; ++d)
+    if (c->bc[d] != 0) return fail(c, TDH_EINVAL, "the self-gravity solve needs periodic boundaries on every axis");
+  int nx = c->nx, ny = c->ny, nz = c->nz;
+  int nlev = 0;
+  for (;;) {
+    if ((nx & 1) || (ny & 1) || (nz & 1))
+      return fail(c, TDH_EINVAL, "multigrid level %d has an odd dimension (%d x %d x %d)", nlev, nx, ny, nz);
+    MgLevel &L = P->lv[nlev];
+    L.nx = nx; L.ny = ny; L.nz = nz;
+    const double s = (double)(1 << nlev);
+    const double hx = c->dx[0] * s, hy = c->dx[1] * s, hz = c->dx[2] * s;
+    L.hx2 = hx * hx;
+    L.wy = (hx / hy) * (hx / hy);
+    L.wz = (hx / hz) * (hx / hz);
+    L.c0 = 2.0 * (1.0 + L.wy + L.wz);
+    ++nlev;
+    if (nlev == kMgMaxLevels || nx < 4 || ny < 4 || nz < 4) break;
+    nx /= 2; ny /= 2; nz /= 2;
+  }
+  const MgLevel &Cl = P->lv[nlev - 1];
+  if ((long long)Cl.nx * Cl.ny * Cl.nz > mg_coarse_max())
+    return fail(c, TDH_ERANGE, "coarsest multigrid level %d x %d x %d exceeds %d cells", Cl.nx, Cl.ny, Cl.nz,
+                mg_coarse_max());
+  P->nlev = nlev;
+  size_t off = 0;  // doubles
+  auto take = [&](long long n) { double *p = base ? (double *)base + off : nullptr; off += (size_t)((n + 31) & ~31LL); return p; };
+  for (int l = 0; l < nlev; ++l) {
+    MgLevel &L = P->lv[l];
+    const long long n = (long long)L.nx * L.ny * L.nz;
+    L.phi = take(n);
+    L.src = take(n);
+    L.tmp = take(n);
+    L.rphi = l > 0 ? take(n) : nullptr;
+  }
+  P->part = take(kMgSumParts);
+  P->scal = take(4);
+  P->bytes = off * sizeof(double);
+  return TDH_OK;
+}
+
+static hipError_t mg_vcycle(const MgPlan &P, int l, hipStream_t s) {
+  hipError_t e;
+  const MgLevel &L = P.lv[l];
+  if (l == P.nlev - 1) {
+    const int t = L.nx + L.ny + L.nz;
+    return mg_launch_coarse_solve(L, 2 * t * t, s);
+  }
+  const MgLevel &C = P.lv[l + 1];
+  if ((e = mg_launch_sweep(L, s)) || (e = mg_launch_sweep(L, s)) || (e = mg_launch_defect(L, s)) ||
+      (e = mg_launch_restrict(L, C, s)) || (e = mg_vcycle(P, l + 1, s)) || (e = mg_launch_prolong(L, C, s)) ||
+      (e = mg_launch_sweep(L, s)) || (e = mg_launch_sweep(L, s)))
+    return e;
+  return hipSuccess;
+}
+
+extern "C" tdh_status tdh_gravity_workspace_bytes(tdh_ctx *c, size_t *host_bytes) {
+  CHECK_CTX(c);
+  tdh_status st;
+  if ((st = ready(c))) return st;
+  if (!host_bytes) return fail(c, TDH_EINVAL, "null output");
+  MgPlan P;
+  if ((st = mg_plan(c, nullptr, &P))) return st;
+  *host_bytes = P.bytes;
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_gravity_solve(tdh_ctx *c, void *dev_work, size_t bytes, double four_pi_G, int max_cycles,
+                                        double tol, int warm, int *host_cycles, double *host_defects) {
+  CHECK_CTX(c);
+  tdh_status st;
+  if ((st = ready(c)) || (st = require_window_boundary(c))) return st;
+  if (!dev_work) return fail(c, TDH_EINVAL, "null workspace");
+  if (!std::isfinite(four_pi_G) || !(tol >= 0.0) || max_cycles < 0 || max_cycles > 1000)
+    return fail(c, TDH_EINVAL, "four_pi_G must be finite, tol >= 0 and max_cycles in [0, 1000]");
+  MgPlan P;
+  if ((st = mg_plan(c, (char *)dev_work, &P))) return st;
+  if (bytes < P.bytes) return fail(c, TDH_ENOMEM, "workspace of %zu bytes, %zu needed", bytes, P.bytes);
+  const StageArgs a = base_args(c);
+  const MgLevel &F = P.lv[0];
+  const long long N = (long long)F.nx * F.ny * F.nz;
+  const double invN = 1.0 / (double)N;
+  hipStream_t s = c->stream;
+  HIPCHK(c, mg_launch_gather(a.m, c->d_par, c->Qa, c->Qb, F.src, s));
+  HIPCHK(c, mg_launch_sum(F.src, N, 0, invN, 0, P.part, P.scal + 0, s));
+  HIPCHK(c, mg_launch_source(F.src, P.scal + 0, four_pi_G, N, s));
+  if (!warm) HIPCHK(c, mg_launch_affine(F.phi, nullptr, 0.0, N, s));
+  auto norm = [&](double *out) -> hipError_t {
+    hipError_t e;
+    if ((e = mg_launch_defect(F, s)) || (e = mg_launch_sum(F.tmp, N, 1, invN, 1, P.part, P.scal + 1, s))) return e;
+    if ((e = hipMemcpyAsync(out, P.scal + 1, sizeof(double), hipMemcpyDeviceToHost, s))) return e;
+    return hipStreamSynchronize(s);
+  };
+  double d = 0.0;
+  HIPCHK(c, norm(&d));
+  if (host_defects) host_defects[0] = d;
+  int cyc = 0;
+  while (cyc < max_cycles && !(d <= tol)) {
+    HIPCHK(c, mg_vcycle(P, 0, s));
+    HIPCHK(c, mg_launch_sweep(F, s));
+    HIPCHK(c, norm(&d));
+    ++cyc;
+    if (host_defects) host_defects[cyc] = d;
+  }
+  HIPCHK(c, mg_launch_sum(F.phi, N, 0, invN, 0, P.part, P.scal + 2, s));
+  HIPCHK(c, mg_launch_affine(F.phi, P.scal + 2, 0.0, N, s));
+  HIPCHK(c, mg_launch_scatter(a.m, c->nb, c->nmax, F.phi, c->phi, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (host_cycles) *host_cycles = cyc;
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_get_potential(tdh_ctx *c, double *host_phi) {
+  CHECK_CTX(c);
+  tdh_status st;
+  if ((st = ready(c))) return st;
+  if (!host_phi) return fail(c, TDH_EINVAL, "null output");
+  if (!c->phi) return fail(c, TDH_ESTATE, "no stored potential (grav_kind is not 1)");
+  HIPCHK(c, hipMemcpyAsync(host_phi, c->phi, c->ptotal * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return TDH_OK;
+}
+
 extern "C" tdh_status tdh_set_state(tdh_ctx *c, const double *host) {
   CHECK_CTX(c);
   tdh_status s;

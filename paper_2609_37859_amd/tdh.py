@@ -76,6 +76,9 @@ def lib():
         "tdh_get_state": ([ctx, P(d)], st),
         "tdh_set_state": ([ctx, P(d)], st),
         "tdh_get_seed_cells": ([ctx, P(C.c_int32)], st),
+        "tdh_gravity_workspace_bytes": ([ctx, P(C.c_size_t)], st),
+        "tdh_gravity_solve": ([ctx, vp, C.c_size_t, d, i, d, i, P(i), P(d)], st),
+        "tdh_get_potential": ([ctx, P(d)], st),
         "tdh_eos_invert_batch": ([ctx, vp, vp, vp, vp, vp, C.c_int64, i], st),
         "tdh_eos_eval_batch": ([ctx, vp, vp, vp, vp, C.c_int64], st),
         "tdh_get_stats": ([ctx, P(tdh_stats)], st),
@@ -227,6 +230,42 @@ class Context:
     def get_state(self):
         out = np.empty(self.mesh.offsets(self.nv)[-1])
         self._check(self.L.tdh_get_state(self.ctx, _dp(out)), "tdh_get_state")
+        return out
+
+    def gravity_solve(self, four_pi_G, max_cycles, tol=0.0, warm=True):
+        """Self-gravity potential of the current state into the stored potential
+        (multigrid V-cycles, periodic).  The workspace (a device tensor owned
+        here) keeps the solution, the warm start of the next call.  Returns
+        (cycles run, RMS defects before and after each cycle)."""
+        torch = self.torch
+        nbytes = C.c_size_t()
+        self._check(self.L.tdh_gravity_workspace_bytes(self.ctx, C.byref(nbytes)), "tdh_gravity_workspace_bytes")
+        fresh = getattr(self, "_mg_work", None) is None or self._mg_work.numel() < nbytes.value + 256
+        if fresh:
+            self._mg_work = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+            self._mg_work.record_stream(self.stream)
+        ptr = (self._mg_work.data_ptr() + 255) & ~255
+        cyc = C.c_int()
+        defects = np.zeros(max_cycles + 1)
+        self._enter()
+        self._check(self.L.tdh_gravity_solve(self.ctx, C.c_void_p(ptr), nbytes.value, float(four_pi_G),
+                                             int(max_cycles), float(tol), int(warm and not fresh), C.byref(cyc),
+                                             _dp(defects)), "tdh_gravity_solve")
+        return cyc.value, defects[:cyc.value + 1]
+
+    def potential_global(self):
+        """The last solve's potential on the global grid [nz, ny, nx] (device workspace copy)."""
+        m = self.mesh
+        n = m.nx * m.ny * m.nz
+        ptr = (self._mg_work.data_ptr() + 255) & ~255
+        base = self._mg_work.data_ptr()
+        t = self._mg_work[ptr - base:ptr - base + 8 * n].view(self.torch.float64)
+        self.sync()
+        return t.cpu().numpy().reshape(m.nz, m.ny, m.nx).copy()
+
+    def get_potential(self):
+        out = np.empty(int(sum((int(n) + 2) ** 3 for n in self.mesh.blk[:, 0])))
+        self._check(self.L.tdh_get_potential(self.ctx, _dp(out)), "tdh_get_potential")
         return out
 
     def seed_cells(self):

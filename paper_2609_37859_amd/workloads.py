@@ -419,6 +419,22 @@ def high_mach_wave(ncell=64, nt=4, v_adv=1e8, amp=0.1, dual=1):
     return cfg, mesh, pack_state(mesh, cfg.nv, fn)
 
 
+def jeans_wave(nx=64, nt=8, n=8, a=1e-3, lam_ratio=0.8):
+    """Linear Jeans wave along x (Sec. Self-gravity validation, eqs jeans-initial,
+    jeans-analytic), adiabatic: rho = 1 + a cos(kx), P = 1/gamma + c^2 a cos(kx)
+    with c = 1, at rest, wavelength = the box (k = 2 pi), on a periodic
+    nx x nt x nt grid of n^3 blocks; 4 pi G = (lam_ratio k c)^2 puts the mode at
+    lambda / lambda_J = lam_ratio.  Returns (cfg, mesh, U, zero potential,
+    four_pi_G)."""
+    cfg = Config(grav_kind=1, gamma=5.0 / 3.0, cfl=0.3, rho_floor=1e-10, p_floor=1e-12)
+    mesh = uniform_mesh(nx // n, nt // n, nt // n, n, 1.0 / nx)
+    k = 2 * np.pi
+    U = pack_state(mesh, 5, lambda x, y, z: ideal_conserved(1 + a * np.cos(k * x), 0 * x, 0 * x, 0 * x,
+                                                          1 / cfg.gamma + a * np.cos(k * x), cfg.gamma, False))
+    phi0 = pack_potential(mesh, lambda x, y, z: 0 * x)
+    return cfg, mesh, U, phi0, (lam_ratio * k) ** 2
+
+
 def sound_wave(ncell, nt=4, amp=1e-6, gamma=5.0 / 3.0):
     """Linear sound wave along x: rho = 1 + a sin, v = c a sin, P = 1/gamma + c^2 a sin (c = 1)."""
     cfg = Config(eos_kind=0, dual=0, gamma=gamma, cfl=0.3, rho_floor=1e-10, p_floor=1e-20)
