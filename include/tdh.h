@@ -196,9 +196,10 @@ tdh_status tdh_set_state(tdh_ctx *ctx, const double *host_state);
  * TDH_ERANGE otherwise).  Only between windows (TDH_ESTATE).
  * dev_work: caller-owned device buffer of at least the bytes
  * tdh_gravity_workspace_bytes returns; its first nx*ny*nz doubles hold the
- * solution on the global grid ([nz][ny][nx], x fastest), the start of the
- * next solve when warm != 0 (pass the same buffer again); warm == 0 starts
- * from zero.  V-cycles run until the root-mean-square defect is <= tol or
+ * solution on the global grid in red-black order (the cells with i+j+k even
+ * first, then the others, each half [nz][ny][nx/2] with x fastest), the start
+ * of the next solve when warm != 0 (pass the same buffer again); warm == 0
+ * starts from zero.  V-cycles run until the root-mean-square defect is <= tol or
  * max_cycles in [0, 1000] have run (tol 0: exactly max_cycles).
  * host_cycles (nullable): V-cycles run.  host_defects (nullable,
  * max_cycles + 1 doubles): the RMS defect before the first and after each

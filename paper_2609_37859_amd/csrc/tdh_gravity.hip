@@ -13,11 +13,13 @@
 // 2 (nx+ny+nz)^2 sweeps in one workgroup's LDS; one extra finest sweep ends
 // each cycle.
 //
-// Every level is a dense [nz][ny][nx] array (x fastest) with periodic
-// addressing; no ghost cells, so no ghost-fill launches.  Each level has even
-// dimensions, so red (i+j+k even) and black cells are a true 2-colouring and
-// a colour's cells update independently: one thread per cell of the colour,
-// the same values as a sequential sweep.  Levels are HBM-bound stencils
+// Every level is stored in red-black order: the red cells (i+j+k even) first,
+// then the black ones, each colour as [nz][ny][nx/2] with x fastest, and
+// addressed periodically (no ghost cells, so no ghost-fill launches).  Each
+// level has even dimensions, so the colours are a true 2-colouring and a
+// colour's cells update independently: one thread per cell of the colour,
+// the same values as a sequential sweep, reading and writing its colour's
+// half contiguously and its neighbours from the other half.  Levels are HBM-bound stencils
 // (about 24 bytes per cell and sweep at the finest level); coarse levels are
 // launch-bound, which the host keeps cheap by capturing a cycle in a graph.
 // Sums (mean density, defect norm, mean potential) use a fixed grid and a
@@ -33,8 +35,27 @@ constexpr int kMgThreads = 256;
 
 __device__ __forceinline__ int pwrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+__device__ __forceinline__ long long ncell(const MgLevel &L) { return (long long)L.nx * L.ny * L.nz; }
+
+// storage index of cell (i, j, k), offsets of up to two cells wrapped
 __device__ __forceinline__ long long at(const MgLevel &L, int i, int j, int k) {
-  return ((long long)pwrap(k, L.nz) * L.ny + pwrap(j, L.ny)) * L.nx + pwrap(i, L.nx);
+  i = pwrap(i, L.nx);
+  j = pwrap(j, L.ny);
+  k = pwrap(k, L.nz);
+  const long long nat = ((long long)k * L.ny + j) * L.nx + i;
+  return ((i + j + k) & 1) * (ncell(L) >> 1) + (nat >> 1);
+}
+
+// cell of storage index q
+__device__ __forceinline__ void cell_of(const MgLevel &L, long long q, int &i, int &j, int &k) {
+  const long long half = ncell(L) >> 1;
+  const int color = q >= half;
+  const long long r = q - color * half;
+  const int hx = L.nx >> 1;
+  const long long row = r / hx;
+  j = (int)(row % L.ny);
+  k = (int)(row / L.ny);
+  i = 2 * (int)(r % hx) + ((j + k + color) & 1);
 }
 
 // ((x- + x+) + wy (y- + y+)) + wz (z- + z+)
@@ -68,28 +89,20 @@ __device__ __forceinline__ double child_mean(const MgLevel &F, const double *f, 
   return 0.125 * ((a + b) + (c + d));
 }
 
-__device__ __forceinline__ long long ncell(const MgLevel &L) { return (long long)L.nx * L.ny * L.nz; }
-
-// cell (i, j, k) of the t-th cell of colour `color` (nx even)
-__device__ __forceinline__ void color_cell(const MgLevel &L, long long t, int color, int &i, int &j, int &k) {
-  const int hx = L.nx >> 1;
-  const long long row = t / hx;
-  j = (int)(row % L.ny);
-  k = (int)(row / L.ny);
-  i = 2 * (int)(t % hx) + ((j + k + color) & 1);
-}
 
 }  // namespace
 
+// the density of every cell into the finest level's source array
 __global__ __launch_bounds__(kMgThreads) void mg_gather_kernel(MeshDev m, const int *par, const double *Qa,
-                                                                  const double *Qb, double *rho) {
-  const long long n = (long long)m.nx * m.ny * m.nz;
-  for (long long p = blockIdx.x * (long long)kMgThreads + threadIdx.x; p < n; p += (long long)gridDim.x * kMgThreads) {
-    const int i = (int)(p % m.nx), j = (int)((p / m.nx) % m.ny), k = (int)(p / ((long long)m.nx * m.ny));
+                                                                  const double *Qb, MgLevel F) {
+  const long long n = ncell(F);
+  for (long long q = blockIdx.x * (long long)kMgThreads + threadIdx.x; q < n; q += (long long)gridDim.x * kMgThreads) {
+    int i, j, k;
+    cell_of(F, q, i, j, k);
     const int b = m.lmap[((k >> m.lat_shift) * m.ly + (j >> m.lat_shift)) * m.lx + (i >> m.lat_shift)];
     const BlockInfo B = m.blocks[b];
     const double *Q = par[b] ? Qb : Qa;
-    rho[p] = Q[B.off + ((long long)(k - B.oz) * B.n + (j - B.oy)) * B.n + (i - B.ox)];
+    F.src[q] = Q[B.off + ((long long)(k - B.oz) * B.n + (j - B.oy)) * B.n + (i - B.ox)];
   }
 }
 
@@ -144,62 +157,89 @@ __global__ __launch_bounds__(kMgThreads) void mg_affine_kernel(double *x, const 
 __global__ __launch_bounds__(kMgThreads) void mg_rbgs_kernel(MgLevel L, int color) {
   const long long half = ncell(L) >> 1;
   for (long long t = blockIdx.x * (long long)kMgThreads + threadIdx.x; t < half; t += (long long)gridDim.x * kMgThreads) {
+    const long long q = color * half + t;
     int i, j, k;
-    color_cell(L, t, color, i, j, k);
-    const long long p = at(L, i, j, k);
-    L.phi[p] = gs_value(L, L.phi, L.src[p], i, j, k, L.phi[p]);
+    cell_of(L, q, i, j, k);
+    L.phi[q] = gs_value(L, L.phi, L.src[q], i, j, k, L.phi[q]);
   }
 }
 
 __global__ __launch_bounds__(kMgThreads) void mg_defect_kernel(MgLevel L) {
   const long long n = ncell(L);
-  for (long long p = blockIdx.x * (long long)kMgThreads + threadIdx.x; p < n; p += (long long)gridDim.x * kMgThreads) {
-    const int i = (int)(p % L.nx), j = (int)((p / L.nx) % L.ny), k = (int)(p / ((long long)L.nx * L.ny));
-    L.tmp[p] = L.src[p] - apply_A(L, L.phi, i, j, k);
+  for (long long q = blockIdx.x * (long long)kMgThreads + threadIdx.x; q < n; q += (long long)gridDim.x * kMgThreads) {
+    int i, j, k;
+    cell_of(L, q, i, j, k);
+    L.tmp[q] = L.src[q] - apply_A(L, L.phi, i, j, k);
   }
 }
 
 // coarse start R phi (also kept in rphi) and the restricted defect
 __global__ __launch_bounds__(kMgThreads) void mg_restrict_kernel(MgLevel F, MgLevel C) {
   const long long n = ncell(C);
-  for (long long p = blockIdx.x * (long long)kMgThreads + threadIdx.x; p < n; p += (long long)gridDim.x * kMgThreads) {
-    const int i = (int)(p % C.nx), j = (int)((p / C.nx) % C.ny), k = (int)(p / ((long long)C.nx * C.ny));
+  for (long long q = blockIdx.x * (long long)kMgThreads + threadIdx.x; q < n; q += (long long)gridDim.x * kMgThreads) {
+    int i, j, k;
+    cell_of(C, q, i, j, k);
     const double r = child_mean(F, F.phi, i, j, k);
-    C.phi[p] = r;
-    C.rphi[p] = r;
-    C.src[p] = child_mean(F, F.tmp, i, j, k);
+    C.phi[q] = r;
+    C.rphi[q] = r;
+    C.src[q] = child_mean(F, F.tmp, i, j, k);
   }
 }
 
 // coarse source R d + A_c R phi
 __global__ __launch_bounds__(kMgThreads) void mg_coarse_source_kernel(MgLevel C) {
   const long long n = ncell(C);
-  for (long long p = blockIdx.x * (long long)kMgThreads + threadIdx.x; p < n; p += (long long)gridDim.x * kMgThreads) {
-    const int i = (int)(p % C.nx), j = (int)((p / C.nx) % C.ny), k = (int)(p / ((long long)C.nx * C.ny));
-    C.src[p] = C.src[p] + apply_A(C, C.phi, i, j, k);
+  for (long long q = blockIdx.x * (long long)kMgThreads + threadIdx.x; q < n; q += (long long)gridDim.x * kMgThreads) {
+    int i, j, k;
+    cell_of(C, q, i, j, k);
+    C.src[q] = C.src[q] + apply_A(C, C.phi, i, j, k);
   }
 }
 
-// the coarsest level: `sweeps` red-black sweeps in one workgroup's LDS
+// the coarsest level: `sweeps` red-black sweeps in one workgroup's LDS; with at
+// most 2048 cells every thread owns at most one cell of each colour, whose
+// neighbour slots it finds once
 constexpr int kMgCoarseMax = 2048;
 __global__ __launch_bounds__(1024) void mg_coarse_solve_kernel(MgLevel C, int sweeps) {
   __shared__ double sphi[kMgCoarseMax], ssrc[kMgCoarseMax];
-  const int n = (int)ncell(C);
+  const int n = (int)ncell(C), half = n >> 1;
   for (int p = threadIdx.x; p < n; p += 1024) {
     sphi[p] = C.phi[p];
     ssrc[p] = C.src[p];
   }
-  __syncthreads();
-  for (int s = 0; s < sweeps; ++s)
+  const bool own = (int)threadIdx.x < half;
+  int q[2] = {0, 0}, nb[2][6];
+  if (own) {
+#pragma unroll
     for (int color = 0; color < 2; ++color) {
-      for (int t = threadIdx.x; t < (n >> 1); t += 1024) {
-        int i, j, k;
-        color_cell(C, t, color, i, j, k);
-        const int p = (int)at(C, i, j, k);
-        sphi[p] = gs_value(C, sphi, ssrc[p], i, j, k, sphi[p]);
+      int i, j, k;
+      q[color] = color * half + threadIdx.x;
+      cell_of(C, q[color], i, j, k);
+      nb[color][0] = (int)at(C, i - 1, j, k);
+      nb[color][1] = (int)at(C, i + 1, j, k);
+      nb[color][2] = (int)at(C, i, j - 1, k);
+      nb[color][3] = (int)at(C, i, j + 1, k);
+      nb[color][4] = (int)at(C, i, j, k - 1);
+      nb[color][5] = (int)at(C, i, j, k + 1);
+    }
+  }
+  __syncthreads();
+  for (int s = 0; s < sweeps; ++s) {
+#pragma unroll
+    for (int color = 0; color < 2; ++color) {
+      if (own) {
+#pragma clang fp contract(off)
+        const int *g = nb[color];
+        const double sx = sphi[g[0]] + sphi[g[1]];
+        const double sy = sphi[g[2]] + sphi[g[3]];
+        const double sz = sphi[g[4]] + sphi[g[5]];
+        const double nbs = (sx + C.wy * sy) + C.wz * sz;
+        const double gs = (nbs + C.hx2 * ssrc[q[color]]) / C.c0;
+        sphi[q[color]] = (1.0 - kOmegaGS) * sphi[q[color]] + kOmegaGS * gs;
       }
       __syncthreads();
     }
+  }
   for (int p = threadIdx.x; p < n; p += 1024) C.phi[p] = sphi[p];
 }
 
@@ -213,41 +253,72 @@ __global__ __launch_bounds__(kMgThreads) void mg_correction_kernel(MgLevel C) {
 // fine phi += tricubic interpolation of the coarse correction: per axis the
 // cubic through the four nearest coarse centres, weights (-5, 35, 105, -7)/128
 // for the child at -1/4 of its parent (centres parent-2 .. parent+1) and
-// (-7, 105, 35, -5)/128 for the child at +1/4 (parent-1 .. parent+2)
+// (-7, 105, 35, -5)/128 for the child at +1/4 (parent-1 .. parent+2), summed
+// along x, then y, then z.  One thread per coarse cell makes its eight
+// children from the 5 x 5 x 5 coarse neighbourhood they share (125 loads
+// instead of 512), keeping that order of summation for each child.
 __global__ __launch_bounds__(kMgThreads) void mg_prolong_kernel(MgLevel F, MgLevel C) {
-  const double wl[4] = {-5.0 / 128.0, 35.0 / 128.0, 105.0 / 128.0, -7.0 / 128.0};
-  const double wr[4] = {-7.0 / 128.0, 105.0 / 128.0, 35.0 / 128.0, -5.0 / 128.0};
-  const long long n = ncell(F);
-  for (long long p = blockIdx.x * (long long)kMgThreads + threadIdx.x; p < n; p += (long long)gridDim.x * kMgThreads) {
-    const int I = (int)(p % F.nx), J = (int)((p / F.nx) % F.ny), K = (int)(p / ((long long)F.nx * F.ny));
-    const double *wx = (I & 1) ? wr : wl, *wy = (J & 1) ? wr : wl, *wz = (K & 1) ? wr : wl;
-    const int i0 = (I >> 1) - ((I & 1) ? 1 : 2), j0 = (J >> 1) - ((J & 1) ? 1 : 2), k0 = (K >> 1) - ((K & 1) ? 1 : 2);
-    double sz = 0.0;
+  const double w[2][4] = {{-5.0 / 128.0, 35.0 / 128.0, 105.0 / 128.0, -7.0 / 128.0},
+                          {-7.0 / 128.0, 105.0 / 128.0, 35.0 / 128.0, -5.0 / 128.0}};
+  const long long n = ncell(C);
+  for (long long q = blockIdx.x * (long long)kMgThreads + threadIdx.x; q < n; q += (long long)gridDim.x * kMgThreads) {
+    int i, j, k;
+    cell_of(C, q, i, j, k);
+    double Z[2][2][2] = {{{0.0, 0.0}, {0.0, 0.0}}, {{0.0, 0.0}, {0.0, 0.0}}};  // [cz][cy][cx]
+    // coarse offsets -2..2 along each axis; child c (0 left, 1 right) uses offsets c-2 .. c+1
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      double sy = 0.0;
+    for (int oz = 0; oz < 5; ++oz) {
+      double Y[2][2] = {{0.0, 0.0}, {0.0, 0.0}};  // [cy][cx] at this z offset
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        double sx = 0.0;
+      for (int oy = 0; oy < 5; ++oy) {
+        double e[5];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) sx += wx[a] * C.rphi[at(C, i0 + a, j0 + b, k0 + c)];
-        sy += wy[b] * sx;
+        for (int ox = 0; ox < 5; ++ox) e[ox] = C.rphi[at(C, i + ox - 2, j + oy - 2, k + oz - 2)];
+        double X[2];
+#pragma unroll
+        for (int cx = 0; cx < 2; ++cx) {
+          double sx = 0.0;
+#pragma unroll
+          for (int a = 0; a < 4; ++a) sx += w[cx][a] * e[cx + a];
+          X[cx] = sx;
+        }
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy) {
+          const int b = oy - cy;  // this row's place in child cy's stencil
+          if (b < 0 || b > 3) continue;
+#pragma unroll
+          for (int cx = 0; cx < 2; ++cx) Y[cy][cx] += w[cy][b] * X[cx];
+        }
       }
-      sz += wz[c] * sy;
+#pragma unroll
+      for (int cz = 0; cz < 2; ++cz) {
+        const int c = oz - cz;
+        if (c < 0 || c > 3) continue;
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+          for (int cx = 0; cx < 2; ++cx) Z[cz][cy][cx] += w[cz][c] * Y[cy][cx];
+      }
     }
-    F.phi[p] += sz;
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+      for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+        for (int cx = 0; cx < 2; ++cx) {
+          F.phi[at(F, 2 * i + cx, 2 * j + cy, 2 * k + cz)] += Z[cz][cy][cx];
+        }
   }
 }
 
 // the per-block stored potential with one periodic ghost layer; blockIdx.y = block
-__global__ __launch_bounds__(kMgThreads) void mg_scatter_kernel(MeshDev m, const double *phi, double *phib) {
+__global__ __launch_bounds__(kMgThreads) void mg_scatter_kernel(MeshDev m, MgLevel F, double *phib) {
   const BlockInfo B = m.blocks[blockIdx.y];
   const int np = B.n + 2;
   const int tot = np * np * np;
   for (int e = blockIdx.x * kMgThreads + threadIdx.x; e < tot; e += gridDim.x * kMgThreads) {
     const int i = e % np - 1, j = (e / np) % np - 1, k = e / (np * np) - 1;
-    const int gx = pwrap(B.ox + i, m.nx), gy = pwrap(B.oy + j, m.ny), gz = pwrap(B.oz + k, m.nz);
-    phib[B.poff + e] = phi[((long long)gz * m.ny + gy) * m.nx + gx];
+    phib[B.poff + e] = F.phi[at(F, B.ox + i, B.oy + j, B.oz + k)];
   }
 }
 
@@ -259,10 +330,10 @@ static int grid_for(long long n) {
   return (int)(g < 1 ? 1 : (g > 4096 ? 4096 : g));
 }
 
-hipError_t mg_launch_gather(const MeshDev &m, const int *par, const double *Qa, const double *Qb, double *rho,
+hipError_t mg_launch_gather(const MeshDev &m, const int *par, const double *Qa, const double *Qb, const MgLevel &F,
                             hipStream_t s) {
   hipLaunchKernelGGL(mg_gather_kernel, dim3(grid_for((long long)m.nx * m.ny * m.nz)), dim3(kMgThreads), 0, s, m, par,
-                     Qa, Qb, rho);
+                     Qa, Qb, F);
   return hipGetLastError();
 }
 
@@ -310,14 +381,14 @@ hipError_t mg_launch_coarse_solve(const MgLevel &C, int sweeps, hipStream_t s) {
 
 hipError_t mg_launch_prolong(const MgLevel &F, const MgLevel &C, hipStream_t s) {
   hipLaunchKernelGGL(mg_correction_kernel, dim3(grid_for((long long)C.nx * C.ny * C.nz)), dim3(kMgThreads), 0, s, C);
-  hipLaunchKernelGGL(mg_prolong_kernel, dim3(grid_for((long long)F.nx * F.ny * F.nz)), dim3(kMgThreads), 0, s, F, C);
+  hipLaunchKernelGGL(mg_prolong_kernel, dim3(grid_for((long long)C.nx * C.ny * C.nz)), dim3(kMgThreads), 0, s, F, C);
   return hipGetLastError();
 }
 
-hipError_t mg_launch_scatter(const MeshDev &m, int nblocks, int nmax, const double *phi, double *phib, hipStream_t s) {
+hipError_t mg_launch_scatter(const MeshDev &m, int nblocks, int nmax, const MgLevel &F, double *phib, hipStream_t s) {
   const int np = nmax + 2;
   const int gx = (np * np * np + kMgThreads - 1) / kMgThreads;
-  hipLaunchKernelGGL(mg_scatter_kernel, dim3(gx, nblocks), dim3(kMgThreads), 0, s, m, phi, phib);
+  hipLaunchKernelGGL(mg_scatter_kernel, dim3(gx, nblocks), dim3(kMgThreads), 0, s, m, F, phib);
   return hipGetLastError();
 }
 

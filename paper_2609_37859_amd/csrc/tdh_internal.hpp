@@ -104,8 +104,9 @@ struct StageArgs {
 };
 
 // host-side launchers (tdh_kernels.hip)
-// One multigrid level of the self-gravity solve: a dense periodic [nz][ny][nx]
-// grid with x spacing hx (hx2 = hx^2), anisotropy weights wy = (hx/hy)^2,
+// One multigrid level of the self-gravity solve: a periodic nx x ny x nz grid
+// stored in red-black order (red cells, i+j+k even, first; each colour
+// [nz][ny][nx/2], x fastest) with x spacing hx (hx2 = hx^2), anisotropy weights wy = (hx/hy)^2,
 // wz = (hx/hz)^2, centre coefficient c0 = 2 (1 + wy + wz); phi, the source,
 // the defect (tmp) and the restricted fine solution (rphi, coarse levels only).
 struct MgLevel {
@@ -116,7 +117,7 @@ struct MgLevel {
 constexpr int kMgMaxLevels = 24;
 constexpr int kMgSumParts = 1024;  // workgroups of the deterministic sums
 
-hipError_t mg_launch_gather(const MeshDev &m, const int *par, const double *Qa, const double *Qb, double *rho,
+hipError_t mg_launch_gather(const MeshDev &m, const int *par, const double *Qa, const double *Qb, const MgLevel &F,
                             hipStream_t s);
 hipError_t mg_launch_sum(const double *x, long long n, int square, double scale, int op, double *part, double *out,
                          hipStream_t s);
@@ -127,8 +128,7 @@ hipError_t mg_launch_defect(const MgLevel &L, hipStream_t s);
 hipError_t mg_launch_restrict(const MgLevel &F, const MgLevel &C, hipStream_t s);
 hipError_t mg_launch_coarse_solve(const MgLevel &C, int sweeps, hipStream_t s);
 hipError_t mg_launch_prolong(const MgLevel &F, const MgLevel &C, hipStream_t s);
-hipError_t mg_launch_scatter(const MeshDev &m, int nblocks, int nmax, const double *phi, double *phib,
-                             hipStream_t s);
+hipError_t mg_launch_scatter(const MeshDev &m, int nblocks, int nmax, const MgLevel &F, double *phib, hipStream_t s);
 int mg_coarse_max();
 
 int num_tiles();

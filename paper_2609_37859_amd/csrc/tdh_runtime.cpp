@@ -83,6 +83,8 @@ struct tdh_ctx {
 
   // captured windows: key = (Lmax, batched)
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+  // captured multigrid cycles (V-cycle, extra sweep, defect norm): key = workspace
+  std::map<const void *, hipGraphExec_t> mg_graphs;
 };
 
 static thread_local std::string g_err;
@@ -212,6 +214,7 @@ extern "C" void tdh_destroy(tdh_ctx *c) {
   for (hipEvent_t e : c->ev) hipEventDestroy(e);
   if (c->h_dtb) hipHostFree(c->h_dtb);
   for (auto &g : c->graphs) hipGraphExecDestroy(g.second);
+  for (auto &g : c->mg_graphs) hipGraphExecDestroy(g.second);
   for (void *p : c->owned) hipFree(p);
   delete c;
 }
@@ -946,7 +949,7 @@ extern "C" tdh_status tdh_gravity_solve(tdh_ctx *c, void *dev_work, size_t bytes
   const long long N = (long long)F.nx * F.ny * F.nz;
   const double invN = 1.0 / (double)N;
   hipStream_t s = c->stream;
-  HIPCHK(c, mg_launch_gather(a.m, c->d_par, c->Qa, c->Qb, F.src, s));
+  HIPCHK(c, mg_launch_gather(a.m, c->d_par, c->Qa, c->Qb, F, s));
   HIPCHK(c, mg_launch_sum(F.src, N, 0, invN, 0, P.part, P.scal + 0, s));
   HIPCHK(c, mg_launch_source(F.src, P.scal + 0, four_pi_G, N, s));
   if (!warm) HIPCHK(c, mg_launch_affine(F.phi, nullptr, 0.0, N, s));
@@ -959,17 +962,41 @@ extern "C" tdh_status tdh_gravity_solve(tdh_ctx *c, void *dev_work, size_t bytes
   double d = 0.0;
   HIPCHK(c, norm(&d));
   if (host_defects) host_defects[0] = d;
+  // one cycle (V-cycle, the extra finest sweep, the defect norm) is captured
+  // once per workspace and replayed: about a hundred launches, most of them on
+  // levels too small to hide their launch latency
+  auto cycle = [&]() -> hipError_t {
+    hipError_t e;
+    if ((e = mg_vcycle(P, 0, s)) || (e = mg_launch_sweep(F, s)) || (e = mg_launch_defect(F, s)) ||
+        (e = mg_launch_sum(F.tmp, N, 1, invN, 1, P.part, P.scal + 1, s)))
+      return e;
+    return hipSuccess;
+  };
   int cyc = 0;
   while (cyc < max_cycles && !(d <= tol)) {
-    HIPCHK(c, mg_vcycle(P, 0, s));
-    HIPCHK(c, mg_launch_sweep(F, s));
-    HIPCHK(c, norm(&d));
+    auto it = c->mg_graphs.find(dev_work);
+    if (it == c->mg_graphs.end()) {
+      HIPCHK(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      const hipError_t e = cycle();
+      hipGraph_t g;
+      const hipError_t e2 = hipStreamEndCapture(s, &g);
+      if (e != hipSuccess) return hip_fail(c, e, "multigrid cycle capture");
+      HIPCHK(c, e2);
+      hipGraphExec_t ge;
+      const hipError_t e3 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      HIPCHK(c, e3);
+      it = c->mg_graphs.emplace(dev_work, ge).first;
+    }
+    HIPCHK(c, hipGraphLaunch(it->second, s));
+    HIPCHK(c, hipMemcpyAsync(&d, P.scal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
     ++cyc;
     if (host_defects) host_defects[cyc] = d;
   }
   HIPCHK(c, mg_launch_sum(F.phi, N, 0, invN, 0, P.part, P.scal + 2, s));
   HIPCHK(c, mg_launch_affine(F.phi, P.scal + 2, 0.0, N, s));
-  HIPCHK(c, mg_launch_scatter(a.m, c->nb, c->nmax, F.phi, c->phi, s));
+  HIPCHK(c, mg_launch_scatter(a.m, c->nb, c->nmax, F, c->phi, s));
   HIPCHK(c, hipStreamSynchronize(s));
   if (host_cycles) *host_cycles = cyc;
   return TDH_OK;

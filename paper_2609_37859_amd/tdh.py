@@ -254,14 +254,18 @@ class Context:
         return cyc.value, defects[:cyc.value + 1]
 
     def potential_global(self):
-        """The last solve's potential on the global grid [nz, ny, nx] (device workspace copy)."""
+        """The last solve's potential on the global grid [nz, ny, nx] (from the
+        workspace, which holds it in red-black order)."""
         m = self.mesh
         n = m.nx * m.ny * m.nz
         ptr = (self._mg_work.data_ptr() + 255) & ~255
         base = self._mg_work.data_ptr()
         t = self._mg_work[ptr - base:ptr - base + 8 * n].view(self.torch.float64)
         self.sync()
-        return t.cpu().numpy().reshape(m.nz, m.ny, m.nx).copy()
+        raw = t.cpu().numpy()
+        k, j, i = np.meshgrid(np.arange(m.nz), np.arange(m.ny), np.arange(m.nx), indexing="ij")
+        nat = (k * m.ny + j) * m.nx + i
+        return raw[((i + j + k) & 1) * (n // 2) + (nat >> 1)]
 
     def get_potential(self):
         out = np.empty(int(sum((int(n) + 2) ** 3 for n in self.mesh.blk[:, 0])))
