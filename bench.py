@@ -197,6 +197,68 @@ def lat_section(T, W, table, seed_params, windows, warmup):
     return out
 
 
+def mg_bytes_per_cycle(levels):
+    """Algorithmic HBM bytes of one multigrid cycle: per cell of every level but
+    the coarsest, four sweeps (read phi and the source, write phi: 24 B each),
+    the restriction of the solution and of the defect computed on the fly
+    (16 B read, 3 B written per fine cell), the coarse source and correction
+    passes (3 + 3 B per fine cell) and the prolongation (16 B read-modify-write,
+    1 B of coarse reads); on the finest level the extra sweep and the defect
+    norm (24 + 16 B)."""
+    n = [a * b * c for a, b, c in levels]
+    return 138 * sum(n[:-1]) + 40 * n[0]
+
+
+def gravity_section(T, W, cycles, steps):
+    """Self-gravity multigrid on the linear Jeans wave at 256^3 (the paper's
+    Jeans-test grid): time per V-cycle (fixed cycles, warm start) and the
+    coupled update (a solve to an RMS defect of 1e-10 at every step)."""
+    import torch
+    cfg, mesh, U, phi0, fpg = W.jeans_wave(nx=256, nt=256, n=32)
+    ctx = T.Context(cfg, mesh, U, phi=phi0)
+    c0, d0 = ctx.gravity_solve(fpg, 4, warm=False)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c, d = ctx.gravity_solve(fpg, cycles, tol=0.0, warm=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    levels = [(mesh.nx, mesh.ny, mesh.nz)]  # every axis halves while all are at least 4
+    while min(levels[-1]) >= 4:
+        levels.append(tuple(v // 2 for v in levels[-1]))
+    ms = 1e3 * el / cycles
+    nbytes = mg_bytes_per_cycle(levels)
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    # the coupled update: solve (warm, RMS defect <= 1e-10), CFL, one RK2 step
+    for _ in range(2):
+        ctx.gravity_solve(fpg, 20, tol=1e-10, warm=True)
+        _, dt, _, _ = ctx.reduce_dt()
+        ctx.step_level(0, dt)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ncyc = 0
+    for _ in range(steps):
+        k, _ = ctx.gravity_solve(fpg, 20, tol=1e-10, warm=True)
+        ncyc += k
+        _, dt, _, _ = ctx.reduce_dt()
+        ctx.step_level(0, dt)
+    ctx.sync()
+    torch.cuda.synchronize()
+    el2 = time.perf_counter() - t0
+    ctx.close()
+    return {"workload": "256^3 periodic as 512 MeshBlocks of 32^3, linear Jeans wave (lambda/lambda_J = 0.8, "
+                        "amplitude 1e-3), ideal gas gamma 5/3",
+            "levels": levels, "ms_per_vcycle": ms, "vcycles_timed": cycles,
+            "defect_contraction": float((d[-1] / d[0]) ** (1.0 / cycles)) if d[0] > 0 else None,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_vcycle": nbytes},
+            "coupled": {"value": mesh.ncells * steps / el2, "unit": "cell-updates/s", "steps": steps,
+                        "ms_per_step": 1e3 * el2 / steps, "vcycles_per_solve": ncyc / steps,
+                        "form": "per step: multigrid solve to an RMS defect of 1e-10 (warm start), CFL reduction, "
+                                "one RK2 step with the solved potential"}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,6 +273,8 @@ def main():
                     help="stage-kernel variant id to use instead of autotuning (profiling runs fix it)")
     ap.add_argument("--lat-windows", type=int, default=5,
                     help="timed LAT windows per form on the polytrope and production-shaped workloads (0: skip)")
+    ap.add_argument("--gravity-cycles", type=int, default=10,
+                    help="timed multigrid V-cycles on the 256^3 Jeans wave (0: skip the self-gravity section)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -266,6 +330,7 @@ def main():
             res[name] = run_form(T, W, cfg, mesh, U, table, args.steps, args.warmup, inv_mode=mode, batched=batched,
                                  seed_params=params if mode == 1 else None, tile=args.tile, riemann=riemann)
     lat = lat_section(T, W, table, params, args.lat_windows, 1) if args.lat_windows > 0 else None
+    grav = gravity_section(T, W, args.gravity_cycles, 10) if args.gravity_cycles > 0 else None
     head = "learned" if "learned" in res else next(iter(res))
     el, stage_ms, launches, st, tile = res[head]
 
@@ -318,6 +383,7 @@ def main():
                      "valu_issue": valu_issue},
         "cpu_baseline": cpu,
         "lat": lat,
+        "gravity": grav,
     }
     print(json.dumps(out), flush=True)
 

@@ -164,16 +164,34 @@ __global__ __launch_bounds__(kMgThreads) void mg_rbgs_kernel(MgLevel L, int colo
   }
 }
 
-__global__ __launch_bounds__(kMgThreads) void mg_defect_kernel(MgLevel L) {
+__device__ __forceinline__ double defect_at(const MgLevel &L, int i, int j, int k) {
+  return L.src[at(L, i, j, k)] - apply_A(L, L.phi, i, j, k);
+}
+
+// per-workgroup partial sums of the squared defect over the same fixed
+// grid-stride shares as mg_partial_sum_kernel (the defect is not stored)
+__global__ __launch_bounds__(kMgThreads) void mg_defect_sq_partial_kernel(MgLevel L, double *part) {
+  __shared__ double red[kMgThreads];
   const long long n = ncell(L);
+  double s = 0.0;
   for (long long q = blockIdx.x * (long long)kMgThreads + threadIdx.x; q < n; q += (long long)gridDim.x * kMgThreads) {
     int i, j, k;
     cell_of(L, q, i, j, k);
-    L.tmp[q] = L.src[q] - apply_A(L, L.phi, i, j, k);
+    const double d = L.src[q] - apply_A(L, L.phi, i, j, k);
+    s += d * d;
   }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kMgThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// coarse start R phi (also kept in rphi) and the restricted defect
+// coarse start R phi (also kept in rphi) and the restricted defect, the
+// children's defects computed here (the same values and order of summation
+// as a stored defect averaged over the eight children)
 __global__ __launch_bounds__(kMgThreads) void mg_restrict_kernel(MgLevel F, MgLevel C) {
   const long long n = ncell(C);
   for (long long q = blockIdx.x * (long long)kMgThreads + threadIdx.x; q < n; q += (long long)gridDim.x * kMgThreads) {
@@ -182,7 +200,17 @@ __global__ __launch_bounds__(kMgThreads) void mg_restrict_kernel(MgLevel F, MgLe
     const double r = child_mean(F, F.phi, i, j, k);
     C.phi[q] = r;
     C.rphi[q] = r;
-    C.src[q] = child_mean(F, F.tmp, i, j, k);
+    const int I = 2 * i, J = 2 * j, K = 2 * k;
+    double dm;
+    {
+#pragma clang fp contract(off)
+      const double a = defect_at(F, I, J, K) + defect_at(F, I + 1, J, K);
+      const double b = defect_at(F, I, J + 1, K) + defect_at(F, I + 1, J + 1, K);
+      const double c = defect_at(F, I, J, K + 1) + defect_at(F, I + 1, J, K + 1);
+      const double d = defect_at(F, I, J + 1, K + 1) + defect_at(F, I + 1, J + 1, K + 1);
+      dm = 0.125 * ((a + b) + (c + d));
+    }
+    C.src[q] = dm;
   }
 }
 
@@ -361,8 +389,11 @@ hipError_t mg_launch_sweep(const MgLevel &L, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t mg_launch_defect(const MgLevel &L, hipStream_t s) {
-  hipLaunchKernelGGL(mg_defect_kernel, dim3(grid_for((long long)L.nx * L.ny * L.nz)), dim3(kMgThreads), 0, s, L);
+hipError_t mg_launch_defect_norm(const MgLevel &L, double *part, double *out, hipStream_t s) {
+  const long long n = (long long)L.nx * L.ny * L.nz;
+  hipLaunchKernelGGL(mg_defect_sq_partial_kernel, dim3(kMgSumParts), dim3(kMgThreads), 0, s, L, part);
+  hipLaunchKernelGGL(mg_final_sum_kernel, dim3(1), dim3(kMgThreads), 0, s, part, kMgSumParts, 1.0 / (double)n, 1,
+                     out);
   return hipGetLastError();
 }
 

@@ -107,12 +107,13 @@ struct StageArgs {
 // One multigrid level of the self-gravity solve: a periodic nx x ny x nz grid
 // stored in red-black order (red cells, i+j+k even, first; each colour
 // [nz][ny][nx/2], x fastest) with x spacing hx (hx2 = hx^2), anisotropy weights wy = (hx/hy)^2,
-// wz = (hx/hz)^2, centre coefficient c0 = 2 (1 + wy + wz); phi, the source,
-// the defect (tmp) and the restricted fine solution (rphi, coarse levels only).
+// wz = (hx/hz)^2, centre coefficient c0 = 2 (1 + wy + wz); phi, the source and
+// the restricted fine solution (rphi, coarse levels only).  Defects are
+// computed where they are used, never stored.
 struct MgLevel {
   int nx, ny, nz;
   double hx2, wy, wz, c0;
-  double *phi, *src, *tmp, *rphi;
+  double *phi, *src, *rphi;
 };
 constexpr int kMgMaxLevels = 24;
 constexpr int kMgSumParts = 1024;  // workgroups of the deterministic sums
@@ -124,7 +125,7 @@ hipError_t mg_launch_sum(const double *x, long long n, int square, double scale,
 hipError_t mg_launch_source(double *src, const double *mean, double four_pi_G, long long n, hipStream_t s);
 hipError_t mg_launch_affine(double *x, const double *shift, double fill, long long n, hipStream_t s);
 hipError_t mg_launch_sweep(const MgLevel &L, hipStream_t s);
-hipError_t mg_launch_defect(const MgLevel &L, hipStream_t s);
+hipError_t mg_launch_defect_norm(const MgLevel &L, double *part, double *out, hipStream_t s);  // RMS defect
 hipError_t mg_launch_restrict(const MgLevel &F, const MgLevel &C, hipStream_t s);
 hipError_t mg_launch_coarse_solve(const MgLevel &C, int sweeps, hipStream_t s);
 hipError_t mg_launch_prolong(const MgLevel &F, const MgLevel &C, hipStream_t s);

@@ -898,7 +898,6 @@ static tdh_status mg_plan(tdh_ctx *c, char *base, MgPlan *P) {
     const long long n = (long long)L.nx * L.ny * L.nz;
     L.phi = take(n);
     L.src = take(n);
-    L.tmp = take(n);
     L.rphi = l > 0 ? take(n) : nullptr;
   }
   P->part = take(kMgSumParts);
@@ -915,8 +914,7 @@ static hipError_t mg_vcycle(const MgPlan &P, int l, hipStream_t s) {
     return mg_launch_coarse_solve(L, 2 * t * t, s);
   }
   const MgLevel &C = P.lv[l + 1];
-  if ((e = mg_launch_sweep(L, s)) || (e = mg_launch_sweep(L, s)) || (e = mg_launch_defect(L, s)) ||
-      (e = mg_launch_restrict(L, C, s)) || (e = mg_vcycle(P, l + 1, s)) || (e = mg_launch_prolong(L, C, s)) ||
+  if ((e = mg_launch_sweep(L, s)) || (e = mg_launch_sweep(L, s)) || (e = mg_launch_restrict(L, C, s)) || (e = mg_vcycle(P, l + 1, s)) || (e = mg_launch_prolong(L, C, s)) ||
       (e = mg_launch_sweep(L, s)) || (e = mg_launch_sweep(L, s)))
     return e;
   return hipSuccess;
@@ -955,7 +953,7 @@ extern "C" tdh_status tdh_gravity_solve(tdh_ctx *c, void *dev_work, size_t bytes
   if (!warm) HIPCHK(c, mg_launch_affine(F.phi, nullptr, 0.0, N, s));
   auto norm = [&](double *out) -> hipError_t {
     hipError_t e;
-    if ((e = mg_launch_defect(F, s)) || (e = mg_launch_sum(F.tmp, N, 1, invN, 1, P.part, P.scal + 1, s))) return e;
+    if ((e = mg_launch_defect_norm(F, P.part, P.scal + 1, s))) return e;
     if ((e = hipMemcpyAsync(out, P.scal + 1, sizeof(double), hipMemcpyDeviceToHost, s))) return e;
     return hipStreamSynchronize(s);
   };
@@ -967,8 +965,7 @@ extern "C" tdh_status tdh_gravity_solve(tdh_ctx *c, void *dev_work, size_t bytes
   // levels too small to hide their launch latency
   auto cycle = [&]() -> hipError_t {
     hipError_t e;
-    if ((e = mg_vcycle(P, 0, s)) || (e = mg_launch_sweep(F, s)) || (e = mg_launch_defect(F, s)) ||
-        (e = mg_launch_sum(F.tmp, N, 1, invN, 1, P.part, P.scal + 1, s)))
+    if ((e = mg_vcycle(P, 0, s)) || (e = mg_launch_sweep(F, s)) || (e = mg_launch_defect_norm(F, P.part, P.scal + 1, s)))
       return e;
     return hipSuccess;
   };
