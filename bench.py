@@ -53,15 +53,17 @@ PROFILES = os.path.join(ROOT, "profiles")
 VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
 
 
-def counters_from_profiles(workload):
+def counters_from_profiles(workload, family="stage"):
     """Counter summary of the stage kernel (HBM bytes, SQ counters per launch)
-    if it was taken on the current kernel source; else {}."""
-    path = os.path.join(PROFILES, f"stage_traffic_{workload}.json")
+    or of the multigrid kernels (HBM bytes per V-cycle) if it was taken on the
+    current kernel source; else {}."""
+    name = f"stage_traffic_{workload}.json" if family == "stage" else f"multigrid_traffic_{workload}.json"
+    path = os.path.join(PROFILES, name)
     if not os.path.exists(path):
         return {}
     from paper_2609_37859_amd.profile_summary import kernel_source_hash
     d = json.load(open(path))
-    if d.get("kernel_hash") != kernel_source_hash():
+    if d.get("kernel_hash") != kernel_source_hash(family):
         return {}
     return d
 
@@ -229,6 +231,13 @@ def gravity_section(T, W, cycles, steps):
     ms = 1e3 * el / cycles
     nbytes = mg_bytes_per_cycle(levels)
     achieved = nbytes / (ms * 1e-3) / 1e9
+    traffic = None
+    prof = counters_from_profiles("jeans256", family="gravity")
+    if prof.get("hbm_bytes_per_unit"):
+        traffic = prof["hbm_bytes_per_unit"]
+    if steps <= 0:
+        ctx.close()
+        return {"ms_per_vcycle": ms, "vcycles_timed": cycles}
     # the coupled update: solve (warm, RMS defect <= 1e-10), CFL, one RK2 step
     for _ in range(2):
         ctx.gravity_solve(fpg, 20, tol=1e-10, warm=True)
@@ -252,7 +261,8 @@ def gravity_section(T, W, cycles, steps):
             "levels": levels, "ms_per_vcycle": ms, "vcycles_timed": cycles,
             "defect_contraction": float((d[-1] / d[0]) ** (1.0 / cycles)) if d[0] > 0 else None,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_vcycle": nbytes},
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "mg_* (one V-cycle)",
+                         "algorithmic_bytes_per_vcycle": nbytes},
             "coupled": {"value": mesh.ncells * steps / el2, "unit": "cell-updates/s", "steps": steps,
                         "ms_per_step": 1e3 * el2 / steps, "vcycles_per_solve": ncyc / steps,
                         "form": "per step: multigrid solve to an RMS defect of 1e-10 (warm start), CFL reduction, "
@@ -275,6 +285,8 @@ def main():
                     help="timed LAT windows per form on the polytrope and production-shaped workloads (0: skip)")
     ap.add_argument("--gravity-cycles", type=int, default=10,
                     help="timed multigrid V-cycles on the 256^3 Jeans wave (0: skip the self-gravity section)")
+    ap.add_argument("--gravity-steps", type=int, default=10,
+                    help="timed coupled steps (solve + RK2 step) on the 256^3 Jeans wave (0: skip them)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -330,7 +342,7 @@ def main():
             res[name] = run_form(T, W, cfg, mesh, U, table, args.steps, args.warmup, inv_mode=mode, batched=batched,
                                  seed_params=params if mode == 1 else None, tile=args.tile, riemann=riemann)
     lat = lat_section(T, W, table, params, args.lat_windows, 1) if args.lat_windows > 0 else None
-    grav = gravity_section(T, W, args.gravity_cycles, 10) if args.gravity_cycles > 0 else None
+    grav = gravity_section(T, W, args.gravity_cycles, args.gravity_steps) if args.gravity_cycles > 0 else None
     head = "learned" if "learned" in res else next(iter(res))
     el, stage_ms, launches, st, tile = res[head]
 

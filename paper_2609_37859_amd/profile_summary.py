@@ -23,11 +23,62 @@ import statistics
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def kernel_source_hash():
+def kernel_source_hash(family="stage"):
+    """Hash of the sources the counters depend on (stage kernel or multigrid)."""
+    files = ("tdh_kernels.hip", "tdh_internal.hpp") if family == "stage" else ("tdh_gravity.hip", "tdh_internal.hpp")
     h = hashlib.sha256()
-    for f in ("tdh_kernels.hip", "tdh_internal.hpp"):
+    for f in files:
         h.update(open(os.path.join(ROOT, "paper_2609_37859_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
+
+
+def family_summary(args):
+    """Every kernel whose name contains args.family: calls and time, and with
+    counter runs its HBM bytes (total, and per unit of work: the run's
+    total divided by args.units)."""
+    rows = [r for r in csv.DictReader(open(_one(args.stats, "*kernel_stats.csv"))) if args.family in r["Name"]]
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# {args.title}", "", "Commands:", ""] + [f"    {c}" for c in args.cmd]
+    lines += ["", "Kernel statistics (rocprofv3 --kernel-trace --stats):", "",
+              "| kernel | calls | average ms | total ms | HBM read MB (all calls) | HBM written MB (all calls) |",
+              "|---|---|---|---|---|---|"]
+    f_k = copy_factor(args.copy_fetch, "FETCH_SIZE", args.copy_bytes) if args.copy_fetch else None
+    w_k = copy_factor(args.copy_write, "WRITE_SIZE", args.copy_bytes) if args.copy_write else None
+    tot_r = tot_w = 0.0
+    fe = {}
+    wr = {}
+    if args.fetch and f_k:
+        for r in csv.DictReader(open(_one(args.fetch, "*counter_collection.csv"))):
+            if r["Counter_Name"] == "FETCH_SIZE":
+                fe[r["Kernel_Name"]] = fe.get(r["Kernel_Name"], 0.0) + float(r["Counter_Value"]) * f_k
+    if args.write and w_k:
+        for r in csv.DictReader(open(_one(args.write, "*counter_collection.csv"))):
+            if r["Counter_Name"] == "WRITE_SIZE":
+                wr[r["Kernel_Name"]] = wr.get(r["Kernel_Name"], 0.0) + float(r["Counter_Value"]) * w_k
+    total_ms = 0.0
+    for r in rows:
+        rb, wb = fe.get(r["Name"], 0.0), wr.get(r["Name"], 0.0)
+        tot_r += rb
+        tot_w += wb
+        total_ms += float(r["TotalDurationNs"]) / 1e6
+        lines.append(f"| `{r['Name']}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.4f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.3f} | {rb / 1e6:.1f} | {wb / 1e6:.1f} |")
+    out = {"family": args.family, "kernel_hash": kernel_source_hash("gravity"), "total_ms": total_ms}
+    lines += ["", f"All {args.family} kernels: {total_ms:.3f} ms"]
+    if fe:
+        per = (tot_r + tot_w) / max(args.units, 1)
+        lines += [f"HBM traffic (copy-calibrated counters, factors {f_k:.4f} / {w_k:.4f} B per unit): "
+                  f"{tot_r / 1e6:.1f} MB read + {tot_w / 1e6:.1f} MB written; over {args.units} {args.unit_name}: "
+                  f"{per / 1e6:.1f} MB per {args.unit_name[:-1] if args.unit_name.endswith('s') else args.unit_name}"]
+        out.update({"hbm_read_bytes": tot_r, "hbm_write_bytes": tot_w, "units": args.units,
+                    "hbm_bytes_per_unit": per, "ms_per_unit": total_ms / max(args.units, 1)})
+    lines += ["", f"Kernel source hash: {out['kernel_hash']}"]
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    if args.json:
+        with open(args.json, "w") as f:
+            json.dump(out, f, indent=1)
+    print("\n".join(lines))
 
 
 def _one(d, pattern):
@@ -90,7 +141,13 @@ def main():
     ap.add_argument("--title", default="stage kernel")
     ap.add_argument("--out", required=True)
     ap.add_argument("--json")
+    ap.add_argument("--family", help="summarise every kernel whose name contains this (instead of one kernel)")
+    ap.add_argument("--units", type=int, default=1, help="units of work in the run (family mode)")
+    ap.add_argument("--unit-name", default="units")
     args = ap.parse_args()
+    if args.family:
+        family_summary(args)
+        return
 
     rows = kernel_stats(args.stats, args.kernel)
     used = rows[0]
