@@ -182,7 +182,8 @@ tdh_status tdh_set_state(tdh_ctx *ctx, const double *host_state);
  * selfgrav-poisson, selfgrav-defect): solves A phi = S on the mesh's uniform
  * grid, A = -lap_h the seven-point operator (neighbours in y and z weighted by
  * (dx/dy)^2 and (dx/dz)^2, centre 2 (1 + wy + wz)), S = -4 pi G (rho - mean
- * rho) from the current density, with periodic boundaries, by geometric
+ * rho) from the current density (the mean removed in two passes), with
+ * periodic boundaries, by geometric
  * multigrid V-cycles (red-black Gauss-Seidel, over-relaxation 1.15, two pre-
  * and two post-sweeps per level, defect restricted by child means, coarse
  * correction in full-approximation form, tricubic prolongation, one extra

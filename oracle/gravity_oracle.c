@@ -8,7 +8,8 @@
  * with A = -lap_h the positive-definite seven-point operator (eq
  * selfgrav-poisson) and S = -4 pi G (rho - mean rho): on a periodic domain the
  * source must have zero mean, so the mean density is subtracted (the periodic
- * form of the solve; isolated boundaries are not part of this oracle).
+ * form of the solve; isolated boundaries are not part of this oracle), in two
+ * passes as the paper does (the second removes the first's rounding residue).
  * Anisotropic cells enter as the paper states: neighbours in y and z carry
  * weights wy = (dx/dy)^2, wz = (dx/dz)^2 and the centre 2 (1 + wy + wz).
  *
@@ -246,6 +247,11 @@ int orc_mg_solve(const orc_gmesh *m, int nv, const double *U, double four_pi_G, 
   double mean = sum / (double)N;
   for (size_t p = 0; p < N; p++) F->src[p] = -four_pi_G * (rho[p] - mean);
   free(rho);
+  /* a second pass removes the rounding residue of the first from the operator's null space */
+  double s2 = 0.0;
+  for (size_t p = 0; p < N; p++) s2 += F->src[p];
+  double mean2 = s2 / (double)N;
+  for (size_t p = 0; p < N; p++) F->src[p] -= mean2;
   if (warm) memcpy(F->phi, phi_global, N * sizeof(double));
   double d = rms_defect(F);
   if (defects) defects[0] = d;

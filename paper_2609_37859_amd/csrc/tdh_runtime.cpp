@@ -950,6 +950,9 @@ extern "C" tdh_status tdh_gravity_solve(tdh_ctx *c, void *dev_work, size_t bytes
   HIPCHK(c, mg_launch_gather(a.m, c->d_par, c->Qa, c->Qb, F, s));
   HIPCHK(c, mg_launch_sum(F.src, N, 0, invN, 0, P.part, P.scal + 0, s));
   HIPCHK(c, mg_launch_source(F.src, P.scal + 0, four_pi_G, N, s));
+  // a second pass removes the first one's rounding residue from the null space
+  HIPCHK(c, mg_launch_sum(F.src, N, 0, invN, 0, P.part, P.scal + 3, s));
+  HIPCHK(c, mg_launch_affine(F.src, P.scal + 3, 0.0, N, s));
   if (!warm) HIPCHK(c, mg_launch_affine(F.phi, nullptr, 0.0, N, s));
   auto norm = [&](double *out) -> hipError_t {
     hipError_t e;
