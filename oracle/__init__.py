@@ -16,7 +16,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["hydro_oracle.c", "mlp_oracle.c", "gravity_oracle.c"]
+_SOURCES = ["hydro_oracle.c", "mlp_oracle.c", "gravity_oracle.c", "remap_oracle.c"]
 
 
 def build(verbose: bool = False) -> str:
@@ -88,6 +88,12 @@ def lib():
         _lib.orc_mg_levels.restype = i
         _lib.orc_mg_solve.argtypes = [P(_Mesh), i, P(d), d, i, d, i, P(d), P(d), P(d)]
         _lib.orc_mg_solve.restype = i
+        _lib.orc_remap.argtypes = [P(_Cfg), P(_Mesh), P(d), P(_Mesh), P(d), d]
+        _lib.orc_remap.restype = i
+        _lib.orc_galilean_boost.argtypes = [P(_Cfg), P(_Mesh), P(d), P(d), d]
+        _lib.orc_galilean_boost.restype = None
+        _lib.orc_frame_acceleration.argtypes = [P(_Cfg), P(_Mesh), P(d), d, d, P(d)]
+        _lib.orc_frame_acceleration.restype = None
         _lib.orc_num_threads.argtypes = []
         _lib.orc_num_threads.restype = i
         _lib.orc_set_interp_rounding.argtypes = [i]
@@ -266,6 +272,33 @@ def mg_solve(mesh, nv, U, four_pi_G, max_cycles, tol=0.0, phi_global=None):
     if c < 0:
         raise ValueError("the self-gravity solve needs a periodic mesh")
     return pg, pb, c, defects[:c + 1]
+
+
+def remap(cfg, mesh_src, U_src, mesh_dst, t=0.0):
+    """Restart remap of the state U_src on mesh_src onto mesh_dst (cfg: floors,
+    dual energy and excision of the target run).  Returns the target state."""
+    ks = _Keep(cfg, mesh_src, None, need_table=False)
+    kd = _Keep(cfg, mesh_dst, None, need_table=False)
+    U_src = np.ascontiguousarray(U_src, dtype=np.float64)
+    out = np.zeros(int(mesh_dst.offsets(cfg.nv)[-1]))
+    lib().orc_remap(C.byref(ks.cfg), C.byref(ks.mesh), _dp(U_src), C.byref(kd.mesh), _dp(out), float(t))
+    return out
+
+
+def galilean_boost(cfg, mesh, U, V, rho_skip):
+    k = _Keep(cfg, mesh, None, need_table=False)
+    U = np.ascontiguousarray(U, dtype=np.float64).copy()
+    Va = np.ascontiguousarray(V, dtype=np.float64)
+    lib().orc_galilean_boost(C.byref(k.cfg), C.byref(k.mesh), _dp(U), _dp(Va), float(rho_skip))
+    return U
+
+
+def frame_acceleration(cfg, mesh, U, rho_min, t=0.0):
+    k = _Keep(cfg, mesh, None, need_table=False)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    A = np.zeros(3)
+    lib().orc_frame_acceleration(C.byref(k.cfg), C.byref(k.mesh), _dp(U), float(rho_min), float(t), _dp(A))
+    return A
 
 
 def num_threads() -> int:
