@@ -208,6 +208,34 @@ tdh_status tdh_set_state(tdh_ctx *ctx, const double *host_state);
 tdh_status tdh_gravity_workspace_bytes(tdh_ctx *ctx, size_t *host_bytes);
 tdh_status tdh_gravity_solve(tdh_ctx *ctx, void *dev_work, size_t bytes, double four_pi_G, int max_cycles,
                              double tol, int warm, int *host_cycles, double *host_defects);
+/* Restart remap (Sec. Domain remapping of conserved variables, eqs
+ * remap-state-vector, remap-cell-average): dst's state becomes the remap of
+ * src's current state onto dst's mesh, and dst's time src's.  Per target cell:
+ * inside dst's excision sphere at that time (grav_kind 2), the sink state
+ * (rho_floor, 0, U_floor); centre outside src's domain along a non-periodic
+ * axis, the floor state; target grid coincident with the source grid (equal
+ * spacings, origins a whole number of cells apart), the source cell copied;
+ * otherwise the mean over the eight sub-cell midpoints (+-1/4 cell per axis)
+ * of the trilinear interpolant of the source density, momentum and thermal
+ * energy density (U_aux with dual energy on, E - |m|^2/2rho otherwise), with
+ * E rebuilt as U + |m|^2/2rho and U_aux = U (thermal, not total, energy is
+ * carried).  Stencils clamp at non-periodic source edges and wrap across
+ * periodic ones.  Both contexts on the current device with the same number
+ * of variables (TDH_EINVAL), both between windows (TDH_ESTATE); src's stream
+ * is synchronised first, dst's on return.  Seed cells of dst are dropped. */
+tdh_status tdh_remap(tdh_ctx *dst, tdh_ctx *src);
+/* Galilean boost by host_V[3] (eq galilean-boost): m += rho V,
+ * E += m.V + rho |V|^2/2 (with the old m), U_aux unchanged, in every cell with
+ * rho > rho_skip (floor-density cells keep their state).  Between windows;
+ * synchronises the stream. */
+tdh_status tdh_galilean_boost(tdh_ctx *ctx, const double *host_V, double rho_skip);
+/* Frame acceleration (eq frame-acceleration) at the context's time: the
+ * density-weighted mean over cells with rho > rho_min outside the excision
+ * sphere of the point mass's field -GM (r - r_bh) / (|r - r_bh|^2 +
+ * r_soft^2)^(3/2) at the cell centre (uniform cells: the volume cancels; 0 if
+ * no cell counts) into host_A[3].  grav_kind 2 only (TDH_ESTATE).  Sums in a
+ * fixed order; synchronises the stream. */
+tdh_status tdh_frame_acceleration(tdh_ctx *ctx, double rho_min, double *host_A);
 /* Copy of the stored potential (grav_kind 1): per block (n+2)^3 doubles with
  * one ghost layer, blocks in order, x fastest.  Synchronises the stream. */
 tdh_status tdh_get_potential(tdh_ctx *ctx, double *host_phi);

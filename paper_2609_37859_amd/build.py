@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtdh.so")
-SOURCES = ["tdh_kernels.hip", "tdh_mlp.hip", "tdh_gravity.hip", "tdh_runtime.cpp"]
+SOURCES = ["tdh_kernels.hip", "tdh_mlp.hip", "tdh_gravity.hip", "tdh_remap.hip", "tdh_runtime.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

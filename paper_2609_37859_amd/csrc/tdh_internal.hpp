@@ -132,6 +132,16 @@ hipError_t mg_launch_prolong(const MgLevel &F, const MgLevel &C, hipStream_t s);
 hipError_t mg_launch_scatter(const MeshDev &m, int nblocks, int nmax, const MgLevel &F, double *phib, hipStream_t s);
 int mg_coarse_max();
 
+hipError_t launch_remap(const MeshDev &src, const int *src_par, const double *sQa, const double *sQb,
+                        const MeshDev &dst, double *Qd, const Phys &p, double t, int nv, int coincident,
+                        const int *shift, hipStream_t s);
+hipError_t launch_boost(const MeshDev &m, const int *par, double *Qa, double *Qb, int nv, const double *V,
+                        double rho_skip, hipStream_t s);
+hipError_t launch_frame_acceleration(const MeshDev &m, const int *par, const double *Qa, const double *Qb,
+                                     const Phys &p, double t, double rho_min, double *part, double *out,
+                                     hipStream_t s);
+int frame_acceleration_parts();
+
 int num_tiles();
 void tile_shape(int id, int *dims);  // x, y, z edges and waves per SIMD of variant id (x = 0: split form)
 hipError_t launch_stage(const StageArgs &a, int tile, int grid, hipStream_t s);

@@ -85,6 +85,7 @@ struct tdh_ctx {
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
   // captured multigrid cycles (V-cycle, extra sweep, defect norm): key = workspace
   std::map<const void *, hipGraphExec_t> mg_graphs;
+  double *d_facc = nullptr;  // frame-acceleration partial sums and result
 };
 
 static thread_local std::string g_err;
@@ -999,6 +1000,70 @@ extern "C" tdh_status tdh_gravity_solve(tdh_ctx *c, void *dev_work, size_t bytes
   HIPCHK(c, mg_launch_scatter(a.m, c->nb, c->nmax, F, c->phi, s));
   HIPCHK(c, hipStreamSynchronize(s));
   if (host_cycles) *host_cycles = cyc;
+  return TDH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// restart remap, Galilean boost, frame acceleration (Sec. Domain remapping and
+// frame conversion; Sec. Moving-frame dynamics and BH treatment)
+// ---------------------------------------------------------------------------
+extern "C" tdh_status tdh_remap(tdh_ctx *dst, tdh_ctx *src) {
+  CHECK_CTX(dst);
+  CHECK_CTX(src);
+  tdh_status st;
+  if ((st = ready(dst)) || (st = require_window_boundary(dst))) return st;
+  if ((st = ready(src)) || (st = require_window_boundary(src))) return fail(dst, TDH_ESTATE, "source: %s", g_err.c_str());
+  if (dst == src) return fail(dst, TDH_EINVAL, "source and target are the same context");
+  if (dst->nv != src->nv) return fail(dst, TDH_EINVAL, "source and target differ in dual energy (%d vs %d variables)",
+                                      src->nv, dst->nv);
+  // the target grid coincides with the source grid if the spacings are equal and
+  // the origins a whole number of cells apart
+  int coincident = 1, shift[3] = {0, 0, 0};
+  for (int d = 0; d < 3; ++d) {
+    const double sft = (dst->x0[d] - src->x0[d]) / src->dx[d];
+    if (dst->dx[d] != src->dx[d] || sft != std::floor(sft) || std::fabs(sft) > 1e9) coincident = 0;
+    else shift[d] = (int)sft;
+  }
+  HIPCHK(dst, hipStreamSynchronize(src->stream));
+  const StageArgs sa = base_args(src), da = base_args(dst);
+  HIPCHK(dst, launch_remap(sa.m, src->d_par, src->Qa, src->Qb, da.m, dst->Qa, da.p, src->t, dst->nv, coincident, shift,
+                           dst->stream));
+  if (dst->jc) HIPCHK(dst, hipMemsetAsync(dst->jc, 0xff, 3 * dst->ncells * sizeof(int), dst->stream));
+  dst->seeds_held = false;
+  dst->par.assign(dst->nb, 0);
+  HIPCHK(dst, hipMemcpyAsync(dst->d_par, dst->par.data(), dst->nb * sizeof(int), hipMemcpyHostToDevice, dst->stream));
+  HIPCHK(dst, hipStreamSynchronize(dst->stream));
+  dst->t = src->t;
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_galilean_boost(tdh_ctx *c, const double *host_V, double rho_skip) {
+  CHECK_CTX(c);
+  tdh_status st;
+  if ((st = ready(c)) || (st = require_window_boundary(c))) return st;
+  if (!host_V) return fail(c, TDH_EINVAL, "null velocity");
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(host_V[d])) return fail(c, TDH_EINVAL, "velocity must be finite");
+  const StageArgs a = base_args(c);
+  HIPCHK(c, launch_boost(a.m, c->d_par, c->Qa, c->Qb, c->nv, host_V, rho_skip, c->stream));
+  if (c->jc) HIPCHK(c, hipMemsetAsync(c->jc, 0xff, 3 * c->ncells * sizeof(int), c->stream));  // energies moved
+  c->seeds_held = false;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return TDH_OK;
+}
+
+extern "C" tdh_status tdh_frame_acceleration(tdh_ctx *c, double rho_min, double *host_A) {
+  CHECK_CTX(c);
+  tdh_status st;
+  if ((st = ready(c)) || (st = require_window_boundary(c))) return st;
+  if (!host_A) return fail(c, TDH_EINVAL, "null output");
+  if (c->cfg.grav_kind != 2) return fail(c, TDH_ESTATE, "the frame acceleration needs the point mass (grav_kind 2)");
+  if (!c->d_facc && (st = dev_alloc(c, &c->d_facc, (size_t)(4 * frame_acceleration_parts() + 4)))) return st;
+  const StageArgs a = base_args(c);
+  double *part = c->d_facc, *out = c->d_facc + 4 * frame_acceleration_parts();
+  HIPCHK(c, launch_frame_acceleration(a.m, c->d_par, c->Qa, c->Qb, a.p, c->t, rho_min, part, out, c->stream));
+  HIPCHK(c, hipMemcpyAsync(host_A, out, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return TDH_OK;
 }
 

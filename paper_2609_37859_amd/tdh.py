@@ -79,6 +79,9 @@ def lib():
         "tdh_gravity_workspace_bytes": ([ctx, P(C.c_size_t)], st),
         "tdh_gravity_solve": ([ctx, vp, C.c_size_t, d, i, d, i, P(i), P(d)], st),
         "tdh_get_potential": ([ctx, P(d)], st),
+        "tdh_remap": ([ctx, ctx], st),
+        "tdh_galilean_boost": ([ctx, P(d), d], st),
+        "tdh_frame_acceleration": ([ctx, d, P(d)], st),
         "tdh_eos_invert_batch": ([ctx, vp, vp, vp, vp, vp, C.c_int64, i], st),
         "tdh_eos_eval_batch": ([ctx, vp, vp, vp, vp, C.c_int64], st),
         "tdh_get_stats": ([ctx, P(tdh_stats)], st),
@@ -266,6 +269,19 @@ class Context:
         k, j, i = np.meshgrid(np.arange(m.nz), np.arange(m.ny), np.arange(m.nx), indexing="ij")
         nat = (k * m.ny + j) * m.nx + i
         return raw[((i + j + k) & 1) * (n // 2) + (nat >> 1)]
+
+    def remap_from(self, src):
+        """This context's state becomes the restart remap of src's state."""
+        self._check(self.L.tdh_remap(self.ctx, src.ctx), "tdh_remap")
+
+    def galilean_boost(self, V, rho_skip):
+        Va = np.ascontiguousarray(V, dtype=np.float64)
+        self._check(self.L.tdh_galilean_boost(self.ctx, _dp(Va), float(rho_skip)), "tdh_galilean_boost")
+
+    def frame_acceleration(self, rho_min):
+        A = np.zeros(3)
+        self._check(self.L.tdh_frame_acceleration(self.ctx, float(rho_min), _dp(A)), "tdh_frame_acceleration")
+        return A
 
     def get_potential(self):
         out = np.empty(int(sum((int(n) + 2) ** 3 for n in self.mesh.blk[:, 0])))
