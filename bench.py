@@ -9,15 +9,17 @@ minimum, global minimum, level assignment) and one RK2 step of every block
 energy update), inputs resident in HBM.
 
 Prints one JSON line.  `value` is the cell-updates/s of the learned form:
-one launch per RK phase for all levels; at the end of each stage the table
-cell of every output state is found by a search started from the learned
-network's prediction (the network runs on the matrix cores inside the stage
-kernel; it is trained first on the GPU by the library's own kernels, training
-time reported, not timed), and that cell seeds the next stage's face and
-compression queries of the cell.  Beside it: the temporal form (searches
-start from the input state's cell), the chained form (a separate pass bisects
-for the cells before each stage) and the plain form (bisection for every
-query, one launch per level); all give bit-identical states.  The roofline
+one launch per RK phase for all levels; before each stage a pass finds the
+table cell of every cell's state by a search started from the learned
+network's prediction (the network runs on the matrix cores; it is trained
+first on the GPU by the library's own kernels, training time reported, not
+timed), and that cell seeds the stage's face and compression queries of the
+cell.  Beside it: the same with the network inside the stage kernel, seeding
+the next stage from the output states (learned_inkernel), the temporal form
+(searches start from the input state's cell), the chained form (the pass
+bisects), the plain form (bisection for every query, one launch per level)
+and the learned form with the HLLE solver; all but the last give
+bit-identical states.  The roofline
 entry is for the stage kernel (HIP events on the library's stream); the CPU
 baseline is the FP64 oracle on the host, on a bounded number of steps of the
 same workload, and its final state doubles as the accuracy check of the GPU
@@ -30,7 +32,9 @@ mass): the batched forms (one launch per RK phase for all active levels,
 window captured in a hipGraph) beside the plain form (one launch per level).
 It reports cell-updates/s from the library's update counters and the
 sync-equivalent rate (cells x 2^Lmax per window over the time), which shows
-the work LAT saves.
+the work LAT saves.  The "gravity" object times the self-gravity multigrid on
+the 256^3 Jeans wave (V-cycles and the solve-every-step coupled update), the
+"remap" object the restart remap of the 128^3 stream onto a 256^3 grid.
 """
 import argparse
 import dataclasses
@@ -69,8 +73,12 @@ def counters_from_profiles(workload, family="stage"):
 
 
 FORMS = {
-    "learned": "batched launches; each stage finds the table cells of its output states by searches started "
-               "from the learned network's prediction; they seed the next stage's face and compression queries",
+    "learned": "batched launches; before each stage a pass finds the table cell of every cell's state by a "
+               "search started from the learned network's prediction; it seeds the cell's face and "
+               "compression queries",
+    "learned_inkernel": "batched launches; each stage finds the table cells of its output states by searches "
+                        "started from the learned network's prediction inside the stage kernel; they seed the "
+                        "next stage's face and compression queries",
     "temporal": "batched launches; each stage finds the table cells of its output states by searches started "
                 "from its input states' cells; they seed the next stage's queries",
     "chained": "batched launches; before each stage the table cell of every cell's state is bisected; it seeds "
@@ -188,12 +196,12 @@ def lat_section(T, W, table, seed_params, windows, warmup):
     out["production"] = {
         "workload": "4096 MeshBlocks (1688 x 32^3 + 2408 x 16^3, 65.2M cells), Saha table EOS, dual energy, "
                     "1e3 Msun point mass with excision in a moving frame, debris stream, N_LAT=3, merge_frac 0.01",
-        "learned": run_lat(T, W, cfg, mesh, U, windows, warmup, inv_mode=1, batched=True, graph=True, table=table,
+        "learned": run_lat(T, W, cfg, mesh, U, windows, warmup, inv_mode=4, batched=True, graph=True, table=table,
                            seed_params=seed_params),
         "temporal": run_lat(T, W, cfg, mesh, U, windows, warmup, inv_mode=3, batched=True, graph=True,
                             table=table),
         "learned_dense_ghosts": run_lat(T, W, dataclasses.replace(cfg, ghost_dense=1), mesh, U, windows, warmup,
-                                        inv_mode=1, batched=True, graph=True, table=table, seed_params=seed_params),
+                                        inv_mode=4, batched=True, graph=True, table=table, seed_params=seed_params),
         "plain": run_lat(T, W, cfg, mesh, U, windows, warmup, inv_mode=0, batched=False, graph=False,
                          table=table)}
     return out
@@ -305,9 +313,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps for the CPU baseline / accuracy check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="learned,temporal,chained,plain,learned_hlle",
-                    help="comma list of forms to time: learned, temporal, chained, plain, learned_hlle (learned is "
-                         "the headline when present)")
+    ap.add_argument("--forms", default="learned,temporal,chained,plain,learned_hlle,learned_inkernel",
+                    help="comma list of forms to time: learned, temporal, chained, plain, learned_hlle, "
+                         "learned_inkernel (learned is the headline when present)")
     ap.add_argument("--tile", type=int, default=-1,
                     help="stage-kernel variant id to use instead of autotuning (profiling runs fix it)")
     ap.add_argument("--lat-windows", type=int, default=5,
@@ -366,11 +374,12 @@ def main():
     forms = args.forms.split(",")
     params, train_s, train_loss, seed_err = train_seed(T, W, table)
     res = {}
-    for name, mode, batched, riemann in (("learned", 1, True, 0), ("temporal", 3, True, 0), ("chained", 2, True, 0),
-                                         ("plain", 0, False, 0), ("learned_hlle", 1, True, 1)):
+    for name, mode, batched, riemann in (("learned", 4, True, 0), ("temporal", 3, True, 0), ("chained", 2, True, 0),
+                                         ("plain", 0, False, 0), ("learned_hlle", 4, True, 1),
+                                         ("learned_inkernel", 1, True, 0)):
         if name in forms:
             res[name] = run_form(T, W, cfg, mesh, U, table, args.steps, args.warmup, inv_mode=mode, batched=batched,
-                                 seed_params=params if mode == 1 else None, tile=args.tile, riemann=riemann)
+                                 seed_params=params if mode in (1, 4) else None, tile=args.tile, riemann=riemann)
     lat = lat_section(T, W, table, params, args.lat_windows, 1) if args.lat_windows > 0 else None
     grav = gravity_section(T, W, args.gravity_cycles, args.gravity_steps) if args.gravity_cycles > 0 else None
     remap = remap_section(T, W, table, args.remap_reps) if args.remap_reps > 0 else None

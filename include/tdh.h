@@ -84,7 +84,9 @@ typedef struct {
                        states for the next stage instead of a pass, their searches
                        starting from the learned network's prediction (tdh_mlp_*;
                        from the input state's cell while the network is off);
-                     3 as 1 with every search starting from the input state's cell.
+                     3 as 1 with every search starting from the input state's cell;
+                     4 as 2 with the pass's searches starting from the learned
+                       network's prediction (bisection while the network is off).
                      In modes 1 and 3 a pass finds the cells once after a state
                      upload (with the network in mode 1). */
   int newton_max_iter; /* seeded secant steps before falling back to bisection (>= 0) */

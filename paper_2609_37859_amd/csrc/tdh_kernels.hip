@@ -202,9 +202,11 @@ __device__ __forceinline__ bool table_record(const Table &t, int i, double w, do
 // Table cell seed from the learned network for this lane's (log rho, log e);
 // every lane of the wave must call it (the hidden layer runs on the matrix cores).
 // lane: the lane index if the caller has an opaque one (see tdh_mlp_dev.hpp)
+template <bool HOISTED = false>
 __device__ __forceinline__ int seed_cell_wave(const Seed &s, const Table &t, double lr, double le, int lane = -1) {
   const float x0 = norm01(lr, s.lr_lo, s.lr_hi), x1 = norm01(le, s.le_lo, s.le_hi);
-  const float y = mlp_wave_forward_fast(s.w, x0, x1, lane >= 0 ? lane : (int)(threadIdx.x & 63));
+  const int l = lane >= 0 ? lane : (int)(threadIdx.x & 63);
+  const float y = HOISTED ? mlp_wave_forward_hoisted(s.w, x0, x1, l) : mlp_wave_forward_fast(s.w, x0, x1, l);
   const double lT = s.lt_lo + 0.5 * ((double)y + 1.0) * (s.lt_hi - s.lt_lo);
   const double x = (lT - t.lT0) / t.dlT;
   if (!(x > 0.0)) return 0;
@@ -731,7 +733,7 @@ __device__ __forceinline__ void finish_cell(const StageArgs &a, const BlockInfo 
     const double Ue = fmax(w[4], w[0] * p.e_floor);
     const double lr = log10_tab(a.t.lg, w[0]), le = log10_tab(a.t.lg, Ue / w[0]);
     int start = jcell;
-    if constexpr (NET) start = seed_cell_wave(a.s, a.t, lr, le, item_tid() & 63);
+    if constexpr (NET) start = seed_cell_wave<true>(a.s, a.t, lr, le, item_tid() & 63);
     int i, j, it;
     double wr, wT;
     table_rho(a.t, lr, i, wr);
@@ -1070,31 +1072,35 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
 // it once after a state upload; afterwards each stage leaves the cells of its
 // output for the next.  Blocks hold a
 // multiple of 256 cells, so every wave is full when it calls the network.
+template <int NV>
 __global__ __launch_bounds__(kChunk) void seed_kernel(StageArgs a) {
   const int a0 = a.cnt_ge[a.Lhi + 1], a1 = a.cnt_ge[a.Llo];
   if (a1 <= a0) return;
   const int i0 = a.item_start[a0], i1 = a.item_start[a1];
   const Phys &p = a.p;
-  const int nv = a.m.nv;
+  const int nv = NV;
   const ItemRange R = xcd_items(i0, i1);
   for (int item = R.first; item < R.end; item += R.step) {
     const int2 bt = a.item_bt[item];
-    const int b = bt.x;
-    const BlockInfo B = a.m.blocks[b];
+    const int b = uni(bt.x);
+    const BlockInfo B = uni(a.m.blocks[b]);
     const long long n3 = (long long)B.n * B.n * B.n;
-    const long long cell = (long long)bt.y * kChunk + threadIdx.x;
-    const Src own = own_source(a, a.par[b]);
+    const long long cell = (long long)uni(bt.y) * kChunk + threadIdx.x;
+    const int parb = uni(a.par[b]);
+    const Src own = own_source(a, parb);
     double q[6], w[6];
-    for (int v = 0; v < nv; ++v) q[v] = src_val(own, B.off + v * n3 + cell);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) q[v] = src_val(own, B.off + v * n3 + cell);
     c2p(p, q, w);
     const double Ue = fmax(w[4], w[0] * p.e_floor);
     const double lr = log10_tab(a.t.lg, w[0]), le = log10_tab(a.t.lg, Ue / w[0]);
-    const int seed = (p.inv_mode == 1 && a.s.enabled) ? seed_cell_wave(a.s, a.t, lr, le) : -1;
+    const int seed =
+        ((p.inv_mode == 1 || p.inv_mode == 4) && a.s.enabled) ? seed_cell_wave<true>(a.s, a.t, lr, le) : -1;
     int i, j, it;
     double wr, wT;
     table_rho(a.t, lr, i, wr);
     table_invert(a.t, i, wr, le, seed, p.newton_max_iter, j, wT, it);
-    a.jc[jseg_in(a, a.par[b]) * a.jn + B.off / nv + cell] = j;
+    a.jc[jseg_in(a, parb) * a.jn + B.off / nv + cell] = j;
   }
 }
 
@@ -1345,7 +1351,10 @@ static hipError_t launch_split(const StageArgs &a, bool net, int grid, hipStream
 }
 
 hipError_t launch_seed(const StageArgs &a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(seed_kernel, dim3(grid), dim3(kChunk), 0, s, a);
+  if (a.m.nv == 6)
+    hipLaunchKernelGGL(seed_kernel<6>, dim3(grid), dim3(kChunk), 0, s, a);
+  else
+    hipLaunchKernelGGL(seed_kernel<5>, dim3(grid), dim3(kChunk), 0, s, a);
   return hipGetLastError();
 }
 

@@ -176,6 +176,70 @@ __device__ __forceinline__ float mlp_wave_forward_fast(const MlpDev &w, float x0
   return y + w.b3[0];
 }
 
+// The same products and sums as mlp_wave_forward_fast, in an order that loads
+// every weight once per call: layer 1 for all four sample groups first, then
+// each output tile's layer-2 weights serve the four groups.  Needs about 100
+// more registers; for kernels that have them (the seed pass).
+__device__ __forceinline__ float mlp_wave_forward_hoisted(const MlpDev &w, float x0, float x1, int l) {
+  typedef __attribute__((__vector_size__(4 * sizeof(short)))) short bf16x4;
+  const int g = l >> 4, c = l & 15;
+  bf16x8 bx = {0, 0, 0, 0, 0, 0, 0, 0};
+  bx[0] = to_bf16(x0);
+  bx[1] = to_bf16(x1);
+  bf16x8 b2op[4][2];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    const short w1a = w.w1b[2 * (16 * mt + c)], w1c = w.w1b[2 * (16 * mt + c) + 1];
+    const float4 b1 = *(const float4 *)(w.b1 + 16 * mt + 4 * g);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      bf16x8 a1 = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (g == nt) {
+        a1[0] = w1a;
+        a1[1] = w1c;
+      }
+      f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+      z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bx, z, 0, 0, 0);
+      b2op[nt][mt >> 1][4 * (mt & 1) + 0] = to_bf16(fmaxf(z[0] + b1.x, 0.0f));
+      b2op[nt][mt >> 1][4 * (mt & 1) + 1] = to_bf16(fmaxf(z[1] + b1.y, 0.0f));
+      b2op[nt][mt >> 1][4 * (mt & 1) + 2] = to_bf16(fmaxf(z[2] + b1.z, 0.0f));
+      b2op[nt][mt >> 1][4 * (mt & 1) + 3] = to_bf16(fmaxf(z[3] + b1.w, 0.0f));
+    }
+  }
+  float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int mo = 0; mo < 4; ++mo) {
+    bf16x8 a2[2];
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt) {
+      const short *row = w.w2b + (16 * mo + c) * H + 32 * kt + 4 * g;
+      const bf16x4 lo = *(const bf16x4 *)row, hi = *(const bf16x4 *)(row + 16);
+      a2[kt] = bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    }
+    const float4 b2 = *(const float4 *)(w.b2 + 16 * mo + 4 * g);
+    const bf16x4 w3 = *(const bf16x4 *)(w.w3b + 16 * mo + 4 * g);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+      z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[0], b2op[nt][0], z, 0, 0, 0);
+      z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[1], b2op[nt][1], z, 0, 0, 0);
+      s[nt] += from_bf16(w3[0]) * round_bf16(fmaxf(z[0] + b2.x, 0.0f));
+      s[nt] += from_bf16(w3[1]) * round_bf16(fmaxf(z[1] + b2.y, 0.0f));
+      s[nt] += from_bf16(w3[2]) * round_bf16(fmaxf(z[2] + b2.z, 0.0f));
+      s[nt] += from_bf16(w3[3]) * round_bf16(fmaxf(z[3] + b2.w, 0.0f));
+    }
+  }
+  float y = 0.0f;
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    float t = s[nt];
+    t += __shfl_xor(t, 16, 64);
+    t += __shfl_xor(t, 32, 64);
+    if (g == nt) y = t;
+  }
+  return y + w.b3[0];
+}
+
 __device__ __forceinline__ float norm01(double v, double lo, double hi) {
   return (float)(2.0 * (v - lo) / (hi - lo) - 1.0);
 }

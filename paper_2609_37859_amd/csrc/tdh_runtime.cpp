@@ -188,7 +188,7 @@ extern "C" tdh_status tdh_init(const tdh_config *cfg, void *hip_stream, tdh_ctx 
   if (cfg->eos_kind < 0 || cfg->eos_kind > 1) return fail(nullptr, TDH_EINVAL, "eos_kind must be 0 or 1");
   if (cfg->grav_kind < 0 || cfg->grav_kind > 2) return fail(nullptr, TDH_EINVAL, "grav_kind must be 0, 1 or 2");
   if (cfg->n_lat < 0 || cfg->n_lat > kMaxLevel) return fail(nullptr, TDH_EINVAL, "n_lat must be in [0, 30]");
-  if (cfg->inv_mode < 0 || cfg->inv_mode > 3) return fail(nullptr, TDH_EINVAL, "inv_mode must be 0, 1, 2 or 3");
+  if (cfg->inv_mode < 0 || cfg->inv_mode > 4) return fail(nullptr, TDH_EINVAL, "inv_mode must be in [0, 4]");
   if (cfg->newton_max_iter < 0 || cfg->newton_max_iter > 64)
     return fail(nullptr, TDH_EINVAL, "newton_max_iter must be in [0, 64]");
   if (cfg->riemann < 0 || cfg->riemann > 1) return fail(nullptr, TDH_EINVAL, "riemann must be 0 (HLLC) or 1 (HLLE)");
@@ -665,7 +665,7 @@ static tdh_status collect_timing(tdh_ctx *c) {
 static tdh_status timed_stage(tdh_ctx *c, const StageArgs &a) {
   const bool t = c->timing && !c->capturing;
   tdh_status s;
-  if (c->cfg.eos_kind == 1 && c->cfg.inv_mode == 2) {
+  if (c->cfg.eos_kind == 1 && (c->cfg.inv_mode == 2 || c->cfg.inv_mode == 4)) {
     HIPCHK(c, launch_seed(a, c->grid, c->stream));
     c->stats.kernel_launches++;
   }

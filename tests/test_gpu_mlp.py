@@ -137,17 +137,18 @@ def test_corrupted_network_changes_nothing(gctx, saha):
 
 def test_hydro_with_learned_seed_equals_bisection_bitwise(gctx, saha):
     """C2 stream on a 2^3-block mesh: inv_mode 1 (network seed), 2 (bisected
-    centre cells), 3 (centre cells carried between stages) and 0 (bisection)
-    give the same state bit for bit."""
+    centre cells), 3 (centre cells carried between stages), 4 (a pass of
+    network-started searches before each stage) and 0 (bisection) give the same
+    state bit for bit."""
     from paper_2609_37859_amd import tdh as T
     import torch
     _train_seed(gctx, saha, steps=300)
     params = gctx.mlp_params()
     cfg, mesh, U = W.stream_c2(saha, nb=2)
     outs = []
-    for mode in (0, 1, 2, 3):
+    for mode in (0, 1, 2, 3, 4):
         ctx = T.Context(cfg, mesh, U, table=saha, inv_mode=mode)
-        if mode == 1:
+        if mode in (1, 4):
             ctx.mlp_init(params, W.seed_ranges(saha))
             ctx.mlp_enable_seed(True)
         T.run_sync_steps(ctx, 3, dts=[3e-4] * 3)
