@@ -446,7 +446,8 @@ extern "C" tdh_status tdh_init_blocks(tdh_ctx *c, const tdh_mesh *m, void *dev_a
       (s = dev_alloc(c, &c->d_fitem_bt, (size_t)((L.ftotal + (long long)c->nb * (kChunk - 1)) / kChunk))) ||
       (s = dev_alloc(c, &c->d_cnt_ge, kCntSlots)) || (s = dev_alloc(c, &c->d_dtb, c->nb)) ||
       (s = dev_alloc(c, &c->d_win, 2)) ||
-      (s = dev_alloc(c, &c->d_cfl_block_start, c->nb + 1)))
+      (s = dev_alloc(c, &c->d_cfl_block_start, c->nb + 1)) ||
+      (s = dev_alloc(c, &c->d_facc, (size_t)(4 * frame_acceleration_parts() + 4))))
     return s;
   std::vector<int> cstart(c->nb + 1, 0), citem;
   for (int b = 0; b < c->nb; ++b) {
@@ -1058,7 +1059,6 @@ extern "C" tdh_status tdh_frame_acceleration(tdh_ctx *c, double rho_min, double 
   if ((st = ready(c)) || (st = require_window_boundary(c))) return st;
   if (!host_A) return fail(c, TDH_EINVAL, "null output");
   if (c->cfg.grav_kind != 2) return fail(c, TDH_ESTATE, "the frame acceleration needs the point mass (grav_kind 2)");
-  if (!c->d_facc && (st = dev_alloc(c, &c->d_facc, (size_t)(4 * frame_acceleration_parts() + 4)))) return st;
   const StageArgs a = base_args(c);
   double *part = c->d_facc, *out = c->d_facc + 4 * frame_acceleration_parts();
   HIPCHK(c, launch_frame_acceleration(a.m, c->d_par, c->Qa, c->Qb, a.p, c->t, rho_min, part, out, c->stream));
