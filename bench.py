@@ -19,7 +19,9 @@ the next stage from the output states (learned_inkernel), the temporal form
 (searches start from the input state's cell), the chained form (the pass
 bisects), the plain form (bisection for every query, one launch per level)
 and the learned form with the HLLE solver; all but the last give
-bit-identical states.  The roofline
+bit-identical states.  Each form runs --warmup steps, then --repeats timed
+runs of exactly --steps steps each (the state evolving on); its rate is that
+of the median run.  The roofline
 entry is for the stage kernel (HIP events on the library's stream); the CPU
 baseline is the FP64 oracle on the host, on a bounded number of steps of the
 same workload, and its final state doubles as the accuracy check of the GPU
@@ -113,7 +115,11 @@ def train_seed(T, W, table, steps=2000, nsamples=1 << 20):
     return params, secs, float(loss[-1]), q
 
 
-def run_form(T, W, cfg, mesh, U, table, steps, warmup, inv_mode, batched, seed_params=None, tile=-1, riemann=0):
+def run_form(T, W, cfg, mesh, U, table, steps, warmup, inv_mode, batched, seed_params=None, tile=-1, riemann=0,
+             repeats=3):
+    """Time `steps` steps `repeats` times in a row (the state evolves on) and
+    return the median elapsed time: a single host or clock hiccup inside one
+    timed run does not decide the rate."""
     import torch
     ctx = T.Context(dataclasses.replace(cfg, riemann=riemann), mesh, U, table=table, inv_mode=inv_mode)
     if seed_params is not None:
@@ -128,14 +134,17 @@ def run_form(T, W, cfg, mesh, U, table, steps, warmup, inv_mode, batched, seed_p
         ctx.run_window(dt0 * 2 ** L, batched=batched)
     ctx.sync()
     ctx.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        _, dt0, lev, L = ctx.reduce_dt()
-        ctx.run_window(dt0 * 2 ** L, batched=batched)
-    ctx.sync()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    els = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, dt0, lev, L = ctx.reduce_dt()
+            ctx.run_window(dt0 * 2 ** L, batched=batched)
+        ctx.sync()
+        torch.cuda.synchronize()
+        els.append(time.perf_counter() - t0)
+    el = sorted(els)[len(els) // 2]
     stage_ms, launches = ctx.stage_time()
     st = ctx.stats()
     tile = ctx.get_tile()
@@ -311,6 +320,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--repeats", type=int, default=3,
+                    help="timed runs of --steps steps per form; each form reports the median run")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps for the CPU baseline / accuracy check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="learned,temporal,chained,plain,learned_hlle,learned_inkernel",
@@ -379,7 +390,8 @@ def main():
                                          ("learned_inkernel", 1, True, 0)):
         if name in forms:
             res[name] = run_form(T, W, cfg, mesh, U, table, args.steps, args.warmup, inv_mode=mode, batched=batched,
-                                 seed_params=params if mode in (1, 4) else None, tile=args.tile, riemann=riemann)
+                                 seed_params=params if mode in (1, 4) else None, tile=args.tile, riemann=riemann,
+                                 repeats=args.repeats)
     lat = lat_section(T, W, table, params, args.lat_windows, 1) if args.lat_windows > 0 else None
     grav = gravity_section(T, W, args.gravity_cycles, args.gravity_steps) if args.gravity_cycles > 0 else None
     remap = remap_section(T, W, table, args.remap_reps) if args.remap_reps > 0 else None
@@ -411,6 +423,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "repeats": args.repeats,
         "ms_per_step": 1e3 * el / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
