@@ -88,7 +88,10 @@ typedef struct {
                      4 as 2 with the pass's searches starting from the learned
                        network's prediction (bisection while the network is off).
                      In modes 1 and 3 a pass finds the cells once after a state
-                     upload (with the network in mode 1). */
+                     upload (with the network in mode 1).  In modes 2 and 4 the
+                     CFL reduction (tdh_reduce_dt) records the cells of the state
+                     it reduces over (its bisection for c_s finds them), and the
+                     next window's first stage runs without a pass. */
   int newton_max_iter; /* seeded secant steps before falling back to bisection (>= 0) */
   int riemann;    /* 0 HLLC (Toro Sec. 10.4); 1 HLLE, the solver of the paper's production
                      runs (Table 1): the HLL flux with the same Davis wave-speed bounds */
@@ -149,7 +152,9 @@ tdh_status tdh_set_eos_table(tdh_ctx *ctx, int nrho, int nT, double lr0, double 
  * levels of eq lat-factor after bin merging and the one-level neighbour
  * limit; level = Lmax - log2(f_b), level 0 coarsest.  The levels are
  * installed and start a new window.  host_dt_block [nblocks] and
- * host_levels [nblocks] may be NULL.  Synchronises the stream. */
+ * host_levels [nblocks] may be NULL.  With the table EOS in inv_mode 2 or 4
+ * it also records every cell's table cell as the seeds of the next window's
+ * first stage.  Synchronises the stream. */
 tdh_status tdh_reduce_dt(tdh_ctx *ctx, double *host_dt_block, double *host_dt0, int8_t *host_levels,
                          int *host_lmax);
 

@@ -1065,12 +1065,14 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
   }
 }
 
-// Table cell of every active cell's stage-input centre state.  Mode 1 starts
-// the search from the learned network's prediction (its hidden layer on the
-// matrix cores), mode 2 bisects; both end at the same, exact cell, which
-// seeds the stage kernel's face and compression queries.  Modes 1 and 3 run
-// it once after a state upload; afterwards each stage leaves the cells of its
-// output for the next.  Blocks hold a
+// Table cell of every active cell's stage-input centre state.  Modes 1 and 4
+// start the search from the learned network's prediction (its hidden layer on
+// the matrix cores), modes 2 and 3 bisect; all end at the same, exact cell,
+// which seeds the stage kernel's face and compression queries.  Modes 1 and 3
+// run it once after a state upload; afterwards each stage leaves the cells of
+// its output for the next.  Modes 2 and 4 run it before every stage except a
+// window's first when the CFL pass has recorded (bisected) the cells of its
+// state.  Blocks hold a
 // multiple of 256 cells, so every wave is full when it calls the network.
 template <int NV>
 __global__ __launch_bounds__(kChunk) void seed_kernel(StageArgs a) {
@@ -1079,6 +1081,29 @@ __global__ __launch_bounds__(kChunk) void seed_kernel(StageArgs a) {
   const int i0 = a.item_start[a0], i1 = a.item_start[a1];
   const Phys &p = a.p;
   const int nv = NV;
+  const bool net = (p.inv_mode == 1 || p.inv_mode == 4) && a.s.enabled;
+  // the network's weights, staged once per workgroup for all its items
+  __shared__ __align__(16) short s_w2[64 * 64];
+  __shared__ __align__(16) short s_w13[128 + 64];
+  __shared__ __align__(16) float s_b[128 + 4];
+  Seed sd = a.s;
+  sd.w.w2b = s_w2;
+  sd.w.w1b = s_w13;
+  sd.w.w3b = s_w13 + 128;
+  sd.w.b1 = s_b;
+  sd.w.b2 = s_b + 64;
+  sd.w.b3 = s_b + 128;
+  if (net) {
+    const int t = threadIdx.x;
+    const uint4 *w2 = (const uint4 *)a.s.w.w2b;
+    for (int k = t; k < 512; k += kChunk) ((uint4 *)s_w2)[k] = w2[k];
+    if (t < 16) ((uint4 *)s_w13)[t] = ((const uint4 *)a.s.w.w1b)[t];
+    else if (t < 24) ((uint4 *)s_w13)[t] = ((const uint4 *)a.s.w.w3b)[t - 16];
+    else if (t < 40) ((uint4 *)s_b)[t - 24] = ((const uint4 *)a.s.w.b1)[t - 24];
+    else if (t < 56) ((uint4 *)s_b)[t - 24] = ((const uint4 *)a.s.w.b2)[t - 40];
+    else if (t == 56) s_b[128] = a.s.w.b3[0];
+    __syncthreads();
+  }
   const ItemRange R = xcd_items(i0, i1);
   for (int item = R.first; item < R.end; item += R.step) {
     const int2 bt = a.item_bt[item];
@@ -1094,8 +1119,7 @@ __global__ __launch_bounds__(kChunk) void seed_kernel(StageArgs a) {
     c2p(p, q, w);
     const double Ue = fmax(w[4], w[0] * p.e_floor);
     const double lr = log10_tab(a.t.lg, w[0]), le = log10_tab(a.t.lg, Ue / w[0]);
-    const int seed =
-        ((p.inv_mode == 1 || p.inv_mode == 4) && a.s.enabled) ? seed_cell_wave<true>(a.s, a.t, lr, le) : -1;
+    const int seed = net ? seed_cell_wave<true>(sd, a.t, lr, le) : -1;
     int i, j, it;
     double wr, wT;
     table_rho(a.t, lr, i, wr);
@@ -1194,45 +1218,54 @@ __device__ __forceinline__ double wave_min(double v) {
   return v;
 }
 
+// In modes 2 and 4 (table EOS) the pass also records each cell's table cell
+// (found by bisection) in its block's current segment: the seeds of the
+// window's first stage, so no seed pass runs before it.
+template <int NV>
 __global__ __launch_bounds__(kChunk) void cfl_items_kernel(StageArgs a, double t, const int *item_block,
                                                            const int *block_item_start, int nitems, double *part) {
   __shared__ double red[kChunk / 64];
   const MeshDev &m = a.m;
   const Phys &p = a.p;
-  const int nv = m.nv;
+  const int nv = NV;
+  const bool rec = p.eos_kind == 1 && (p.inv_mode == 2 || p.inv_mode == 4) && a.jc != nullptr;
   for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
-    const int b = item_block[item];
-    const BlockInfo B = m.blocks[b];
+    const int b = uni(item_block[item]);
+    const BlockInfo B = uni(m.blocks[b]);
     const int n = B.n;
     const long long n3 = (long long)n * n * n;
-    const long long cell = (long long)(item - block_item_start[b]) * kChunk + threadIdx.x;
+    const long long cell = (long long)uni(item - block_item_start[b]) * kChunk + threadIdx.x;
+    const bool inside = cell < n3;
+    const long long cq = inside ? cell : n3 - 1;
+    const int parb = uni(a.par[b]);
+    const double *Q = parb ? a.Qb : a.Qa;
+    double q[6], w[6];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) q[v] = Q[B.off + v * n3 + cq];
+    c2p(p, q, w);
+    double P, cs;
+    int j = -1;
+    eos_pc(p, a.t, w[0], w[4], -1, P, cs, &j);
+    if (rec && inside) a.jc[(long long)parb * a.jn + B.off / nv + cell] = j;
     double best = INFINITY;
-    if (cell < n3) {
-      const int ci = (int)(cell % n), cj = (int)((cell / n) % n), ck = (int)(cell / ((long long)n * n));
-      const bool exc = p.grav_kind == 2 && p.r_exc > 0.0 && excised(p, m, B.ox + ci, B.oy + cj, B.oz + ck, t);
-      if (!exc) {
-        const double *Q = a.par[b] ? a.Qb : a.Qa;
-        double q[6], w[6];
-        for (int v = 0; v < nv; ++v) q[v] = Q[B.off + v * n3 + cell];
-        c2p(p, q, w);
-        double P, cs;
-        eos_pc(p, a.t, w[0], w[4], -1, P, cs);
-        for (int d = 0; d < 3; ++d) best = fmin(best, m.dx[d] / (fabs(w[1 + d]) + cs));
-        // source-term limit: sqrt(dx_min / |g|) with g the centred potential gradient
-        if (p.grav_kind) {
-          double g2 = 0.0;
-          const int lc[3] = {ci, cj, ck};
-          for (int d = 0; d < 3; ++d) {
-            int ip[3] = {lc[0], lc[1], lc[2]}, im[3] = {lc[0], lc[1], lc[2]};
-            ip[d] += 1;
-            im[d] -= 1;
-            const double gd = (phi_at(a, B, ip[0], ip[1], ip[2], t) - phi_at(a, B, im[0], im[1], im[2], t)) /
-                              (2.0 * m.dx[d]);
-            g2 += gd * gd;
-          }
-          const double dmin = fmin(m.dx[0], fmin(m.dx[1], m.dx[2]));
-          if (g2 > 0.0) best = fmin(best, sqrt(dmin / sqrt(g2)));
+    const int ci = (int)(cq % n), cj = (int)((cq / n) % n), ck = (int)(cq / ((long long)n * n));
+    const bool exc = p.grav_kind == 2 && p.r_exc > 0.0 && excised(p, m, B.ox + ci, B.oy + cj, B.oz + ck, t);
+    if (inside && !exc) {
+      for (int d = 0; d < 3; ++d) best = fmin(best, m.dx[d] / (fabs(w[1 + d]) + cs));
+      // source-term limit: sqrt(dx_min / |g|) with g the centred potential gradient
+      if (p.grav_kind) {
+        double g2 = 0.0;
+        const int lc[3] = {ci, cj, ck};
+        for (int d = 0; d < 3; ++d) {
+          int ip[3] = {lc[0], lc[1], lc[2]}, im[3] = {lc[0], lc[1], lc[2]};
+          ip[d] += 1;
+          im[d] -= 1;
+          const double gd = (phi_at(a, B, ip[0], ip[1], ip[2], t) - phi_at(a, B, im[0], im[1], im[2], t)) /
+                            (2.0 * m.dx[d]);
+          g2 += gd * gd;
         }
+        const double dmin = fmin(m.dx[0], fmin(m.dx[1], m.dx[2]));
+        if (g2 > 0.0) best = fmin(best, sqrt(dmin / sqrt(g2)));
       }
     }
     best = wave_min(best);
@@ -1247,12 +1280,16 @@ __global__ __launch_bounds__(kChunk) void cfl_items_kernel(StageArgs a, double t
   }
 }
 
+// one wave per block: its lanes stride the block's item minima (a min is exact
+// in any order)
 __global__ void cfl_blocks_kernel(const double *part, const int *block_item_start, int nblocks, double cfl,
                                   double *dtb) {
-  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nblocks; b += gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x & 63, wpb = blockDim.x >> 6;
+  for (int b = blockIdx.x * wpb + (threadIdx.x >> 6); b < nblocks; b += gridDim.x * wpb) {
     double r = INFINITY;
-    for (int i = block_item_start[b]; i < block_item_start[b + 1]; ++i) r = fmin(r, part[i]);
-    dtb[b] = cfl * r;
+    for (int i = block_item_start[b] + lane; i < block_item_start[b + 1]; i += 64) r = fmin(r, part[i]);
+    r = wave_min(r);
+    if (lane == 0) dtb[b] = cfl * r;
   }
 }
 
@@ -1403,12 +1440,16 @@ hipError_t launch_reflux(const StageArgs &a, int lc, int dir, int nmax, int grid
 hipError_t launch_cfl(const StageArgs &a, double cfl, double t, const int *item_block, int nitems, double *part,
                       int nblocks, const int *block_item_start, double *dtb, hipStream_t s) {
   const int grid = nitems < 4096 ? nitems : 4096;
-  hipLaunchKernelGGL(cfl_items_kernel, dim3(grid), dim3(kChunk), 0, s, a, t, item_block, block_item_start, nitems,
-                     part);
+  if (a.m.nv == 6)
+    hipLaunchKernelGGL(cfl_items_kernel<6>, dim3(grid), dim3(kChunk), 0, s, a, t, item_block, block_item_start,
+                       nitems, part);
+  else
+    hipLaunchKernelGGL(cfl_items_kernel<5>, dim3(grid), dim3(kChunk), 0, s, a, t, item_block, block_item_start,
+                       nitems, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(cfl_blocks_kernel, dim3((nblocks + 255) / 256), dim3(256), 0, s, part, block_item_start,
-                     nblocks, cfl, dtb);
+  const int bgrid = (nblocks + 3) / 4 < 1024 ? (nblocks + 3) / 4 : 1024;
+  hipLaunchKernelGGL(cfl_blocks_kernel, dim3(bgrid), dim3(256), 0, s, part, block_item_start, nblocks, cfl, dtb);
   return hipGetLastError();
 }
 

@@ -106,138 +106,149 @@ __device__ __forceinline__ float mlp_wave_forward(const MlpDev &w, float x0, flo
   return layer3(w, acc);
 }
 
-// Inference forward pass with every layer but the output on the matrix cores.
-// Each lane passes its own sample's normalised inputs and gets its output.
-// The hidden activations are kept transposed, H1^T[k][q] (hidden unit x
-// sample), and the hidden units are numbered so that the output tile of the
-// first product is, lane by lane, the operand the second product needs:
-//   layer 1, tile (mt, nt): A = W1 rows 16 mt.. placed in the K slots of lane
-//     group nt (zero elsewhere), B = every lane's own (x0, x1) in its slots
-//     e = 0, 1; D holds z1[h = 16 mt + 4 (l/16) + r][q = 16 nt + l%16];
+// Inference forward pass with all three layers on the matrix cores.  Each lane
+// passes its own sample's normalised inputs and gets its output.  The hidden
+// activations are kept transposed (unit x sample), and the units are numbered
+// so that each product's output tile is, lane by lane, the operand the next
+// product needs:
+//   layer 1, tile (mt, nt): A = W1 rows 16 mt.. in slots e = 0, 1 of every
+//     lane group, B = the own (x0, x1) of lane group nt's lanes in those slots
+//     (zero in the other groups), accumulator = b1; D holds
+//     z1[h = 16 mt + 4 (l/16) + r][q = 16 nt + l%16];
 //   layer 2, tile (mo, nt): B for K tile kt is this lane's D of layer-1 tiles
-//     mt = 2 kt, 2 kt + 1 (after bias, ReLU, bf16), i.e. contraction slot
+//     mt = 2 kt, 2 kt + 1 (after ReLU and bf16), i.e. contraction slot
 //     kappa = 32 kt + 8 (l/16) + e holds hidden unit
-//     h = 16 (2 kt + e/4) + 4 (l/16) + e%4; A = W2 with its columns in that order;
-//     D holds z2[o = 16 mo + 4 (l/16) + r][q = 16 nt + l%16];
-//   layer 3 sums w3[o] h2 over this lane's 16 outputs, then over the four lane
-//     groups.
-// Same function as mlp_wave_forward (bf16 operands, fp32 sums and biases); the
-// fp32 sums are taken in another order.  l: the lane index (an opaque per-item
-// value inside a larger kernel keeps the weight loads next to their use).
-__device__ __forceinline__ float mlp_wave_forward_fast(const MlpDev &w, float x0, float x1, int l) {
-  typedef __attribute__((__vector_size__(4 * sizeof(short)))) short bf16x4;
-  const int g = l >> 4, c = l & 15;
-  bf16x8 bx = {0, 0, 0, 0, 0, 0, 0, 0};
-  bx[0] = to_bf16(x0);
-  bx[1] = to_bf16(x1);
-  float y = 0.0f;
-#pragma unroll
-  for (int nt = 0; nt < 4; ++nt) {
-    // layer 1 for samples 16 nt .. 16 nt + 15, hidden layer in layer-2 B layout
-    bf16x8 b2op[2];
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-      bf16x8 a1 = {0, 0, 0, 0, 0, 0, 0, 0};
-      if (g == nt) {
-        a1[0] = w.w1b[2 * (16 * mt + c)];
-        a1[1] = w.w1b[2 * (16 * mt + c) + 1];
-      }
-      f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-      z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bx, z, 0, 0, 0);
-      const float4 b1 = *(const float4 *)(w.b1 + 16 * mt + 4 * g);
-      b2op[mt >> 1][4 * (mt & 1) + 0] = to_bf16(fmaxf(z[0] + b1.x, 0.0f));
-      b2op[mt >> 1][4 * (mt & 1) + 1] = to_bf16(fmaxf(z[1] + b1.y, 0.0f));
-      b2op[mt >> 1][4 * (mt & 1) + 2] = to_bf16(fmaxf(z[2] + b1.z, 0.0f));
-      b2op[mt >> 1][4 * (mt & 1) + 3] = to_bf16(fmaxf(z[3] + b1.w, 0.0f));
-    }
-    // layer 2 and the output layer
-    float s = 0.0f;
-#pragma unroll
-    for (int mo = 0; mo < 4; ++mo) {
-      f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-      for (int kt = 0; kt < 2; ++kt) {
-        const short *row = w.w2b + (16 * mo + c) * H + 32 * kt + 4 * g;
-        const bf16x4 lo = *(const bf16x4 *)row, hi = *(const bf16x4 *)(row + 16);
-        const bf16x8 a2 = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-        z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b2op[kt], z, 0, 0, 0);
-      }
-      const float4 b2 = *(const float4 *)(w.b2 + 16 * mo + 4 * g);
-      const bf16x4 w3 = *(const bf16x4 *)(w.w3b + 16 * mo + 4 * g);
-      s += from_bf16(w3[0]) * round_bf16(fmaxf(z[0] + b2.x, 0.0f));
-      s += from_bf16(w3[1]) * round_bf16(fmaxf(z[1] + b2.y, 0.0f));
-      s += from_bf16(w3[2]) * round_bf16(fmaxf(z[2] + b2.z, 0.0f));
-      s += from_bf16(w3[3]) * round_bf16(fmaxf(z[3] + b2.w, 0.0f));
-    }
-    s += __shfl_xor(s, 16, 64);
-    s += __shfl_xor(s, 32, 64);
-    if (g == nt) y = s;  // this lane's own sample is 16 nt + l%16 = l
-  }
-  return y + w.b3[0];
+//     h = 16 (2 kt + e/4) + 4 (l/16) + e%4; A = W2 with its columns in that
+//     order; accumulator = b2; D holds z2[o = 16 mo + 4 (l/16) + r][q = 16 nt + l%16];
+//   layer 3, tile nt: B is built from the layer-2 tiles as layer 2's B from
+//     layer 1's; every row of A holds w3 in that contraction order and the
+//     accumulator is b3, so every row of D holds the outputs of samples
+//     16 nt .. 16 nt + 15, and lane l takes its own from tile nt = l/16.
+// The products of bf16 operands are exact in fp32; the sums, biases included,
+// are fp32 in the matrix cores' order (mlp_wave_forward adds the bias after
+// the products).  Every lane of the wave must call it.
+typedef __attribute__((__vector_size__(4 * sizeof(short)))) short bf16x4;
+
+// ReLU and bf16 of a D-layout tile into half `hi` of a B operand.  Rounding to
+// nearest keeps the sign, so the ReLU is taken after it, on pairs of bf16 bit
+// patterns as 16-bit integers (negative values, -0 included, have the sign
+// bit set and become +0; the rest are unchanged): relu(bf16(z)) = bf16(relu(z)).
+__device__ __forceinline__ void relu_to_operand(const f32x4 &z, bf16x8 &b, int hi) {
+  typedef short s16x2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 b16x2 __attribute__((ext_vector_type(2)));
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  const s16x2 zero = {0, 0};
+  const s16x2 p = __builtin_elementwise_max(
+      __builtin_bit_cast(s16x2, __builtin_convertvector(f32x2{z[0], z[1]}, b16x2)), zero);
+  const s16x2 q = __builtin_elementwise_max(
+      __builtin_bit_cast(s16x2, __builtin_convertvector(f32x2{z[2], z[3]}, b16x2)), zero);
+  b[4 * hi + 0] = p.x;
+  b[4 * hi + 1] = p.y;
+  b[4 * hi + 2] = q.x;
+  b[4 * hi + 3] = q.y;
 }
 
-// The same products and sums as mlp_wave_forward_fast, in an order that loads
-// every weight once per call: layer 1 for all four sample groups first, then
-// each output tile's layer-2 weights serve the four groups.  Needs about 100
-// more registers; for kernels that have them (the seed pass).
-__device__ __forceinline__ float mlp_wave_forward_hoisted(const MlpDev &w, float x0, float x1, int l) {
-  typedef __attribute__((__vector_size__(4 * sizeof(short)))) short bf16x4;
+// 8 values of a 64-vector in the contraction order above (K tile kt, lane group g)
+__device__ __forceinline__ bf16x8 permuted_row(const short *v, int kt, int g) {
+  const bf16x4 lo = *(const bf16x4 *)(v + 32 * kt + 4 * g), hi = *(const bf16x4 *)(v + 32 * kt + 16 + 4 * g);
+  return bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+}
+
+__device__ __forceinline__ f32x4 bias_tile(const float *b, int t, int g) {
+  const float4 v = *(const float4 *)(b + 16 * t + 4 * g);
+  return f32x4{v.x, v.y, v.z, v.w};
+}
+
+// layer-1 operands: A = the two input weights of hidden unit 16 mt + l%16 in
+// slots e = 0, 1 of every lane group; B for sample group nt = this lane's own
+// (x0, x1) in those slots in lane group nt and zero in the others, so the
+// contraction over the four groups picks the samples 16 nt .. 16 nt + 15
+__device__ __forceinline__ bf16x8 layer1_weights(const MlpDev &w, int mt, int c) {
+  const uint32_t v = *(const uint32_t *)(w.w1b + 2 * (16 * mt + c));
+  return __builtin_bit_cast(bf16x8, uint4{v, 0u, 0u, 0u});
+}
+__device__ __forceinline__ bf16x8 layer1_inputs(uint32_t xpair, int nt, int g) {
+  return __builtin_bit_cast(bf16x8, uint4{g == nt ? xpair : 0u, 0u, 0u, 0u});
+}
+__device__ __forceinline__ uint32_t input_pair(float x0, float x1) {
+  return (uint32_t)(uint16_t)to_bf16(x0) | ((uint32_t)(uint16_t)to_bf16(x1) << 16);
+}
+
+// l: the lane index (an opaque per-item value inside a larger kernel keeps the
+// weight loads next to their use).  One sample group at a time: few registers.
+__device__ __forceinline__ float mlp_wave_forward_fast(const MlpDev &w, float x0, float x1, int l) {
   const int g = l >> 4, c = l & 15;
-  bf16x8 bx = {0, 0, 0, 0, 0, 0, 0, 0};
-  bx[0] = to_bf16(x0);
-  bx[1] = to_bf16(x1);
-  bf16x8 b2op[4][2];
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-    const short w1a = w.w1b[2 * (16 * mt + c)], w1c = w.w1b[2 * (16 * mt + c) + 1];
-    const float4 b1 = *(const float4 *)(w.b1 + 16 * mt + 4 * g);
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      bf16x8 a1 = {0, 0, 0, 0, 0, 0, 0, 0};
-      if (g == nt) {
-        a1[0] = w1a;
-        a1[1] = w1c;
-      }
-      f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-      z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bx, z, 0, 0, 0);
-      b2op[nt][mt >> 1][4 * (mt & 1) + 0] = to_bf16(fmaxf(z[0] + b1.x, 0.0f));
-      b2op[nt][mt >> 1][4 * (mt & 1) + 1] = to_bf16(fmaxf(z[1] + b1.y, 0.0f));
-      b2op[nt][mt >> 1][4 * (mt & 1) + 2] = to_bf16(fmaxf(z[2] + b1.z, 0.0f));
-      b2op[nt][mt >> 1][4 * (mt & 1) + 3] = to_bf16(fmaxf(z[3] + b1.w, 0.0f));
-    }
-  }
-  float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-  for (int mo = 0; mo < 4; ++mo) {
-    bf16x8 a2[2];
-#pragma unroll
-    for (int kt = 0; kt < 2; ++kt) {
-      const short *row = w.w2b + (16 * mo + c) * H + 32 * kt + 4 * g;
-      const bf16x4 lo = *(const bf16x4 *)row, hi = *(const bf16x4 *)(row + 16);
-      a2[kt] = bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-    }
-    const float4 b2 = *(const float4 *)(w.b2 + 16 * mo + 4 * g);
-    const bf16x4 w3 = *(const bf16x4 *)(w.w3b + 16 * mo + 4 * g);
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-      z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[0], b2op[nt][0], z, 0, 0, 0);
-      z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[1], b2op[nt][1], z, 0, 0, 0);
-      s[nt] += from_bf16(w3[0]) * round_bf16(fmaxf(z[0] + b2.x, 0.0f));
-      s[nt] += from_bf16(w3[1]) * round_bf16(fmaxf(z[1] + b2.y, 0.0f));
-      s[nt] += from_bf16(w3[2]) * round_bf16(fmaxf(z[2] + b2.z, 0.0f));
-      s[nt] += from_bf16(w3[3]) * round_bf16(fmaxf(z[3] + b2.w, 0.0f));
-    }
-  }
+  const uint32_t xp = input_pair(x0, x1);
+  const float b3 = w.b3[0];
   float y = 0.0f;
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
-    float t = s[nt];
-    t += __shfl_xor(t, 16, 64);
-    t += __shfl_xor(t, 32, 64);
-    if (g == nt) y = t;
+    bf16x8 b2op[2], b3op[2];
+    const bf16x8 bx = layer1_inputs(xp, nt, g);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      const f32x4 z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(layer1_weights(w, mt, c), bx, bias_tile(w.b1, mt, g), 0,
+                                                              0, 0);
+      relu_to_operand(z, b2op[mt >> 1], mt & 1);
+    }
+#pragma unroll
+    for (int mo = 0; mo < 4; ++mo) {
+      f32x4 z = bias_tile(w.b2, mo, g);
+#pragma unroll
+      for (int kt = 0; kt < 2; ++kt)
+        z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(permuted_row(w.w2b + (16 * mo + c) * H, kt, g), b2op[kt], z,
+                                                    0, 0, 0);
+      relu_to_operand(z, b3op[mo >> 1], mo & 1);
+    }
+    f32x4 z3 = {b3, b3, b3, b3};
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+      z3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(permuted_row(w.w3b, kt, g), b3op[kt], z3, 0, 0, 0);
+    if (g == nt) y = z3[0];  // this lane's own sample is 16 nt + l%16 = l
   }
-  return y + w.b3[0];
+  return y;
+}
+
+// The same products and sums as mlp_wave_forward_fast (bit for bit), in an
+// order that loads every weight once per call: layer 1 for all four sample
+// groups first, then each output tile's layer-2 weights serve the four groups.
+// Needs more registers; for kernels that have them.
+__device__ __forceinline__ float mlp_wave_forward_hoisted(const MlpDev &w, float x0, float x1, int l) {
+  const int g = l >> 4, c = l & 15;
+  const uint32_t xp = input_pair(x0, x1);
+  bf16x8 b2op[4][2], b3op[4][2];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    const f32x4 b1 = bias_tile(w.b1, mt, g);
+    const bf16x8 a1 = layer1_weights(w, mt, c);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const f32x4 z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, layer1_inputs(xp, nt, g), b1, 0, 0, 0);
+      relu_to_operand(z, b2op[nt][mt >> 1], mt & 1);
+    }
+  }
+#pragma unroll
+  for (int mo = 0; mo < 4; ++mo) {
+    const bf16x8 a2[2] = {permuted_row(w.w2b + (16 * mo + c) * H, 0, g), permuted_row(w.w2b + (16 * mo + c) * H, 1, g)};
+    const f32x4 b2 = bias_tile(w.b2, mo, g);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      f32x4 z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[0], b2op[nt][0], b2, 0, 0, 0);
+      z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[1], b2op[nt][1], z, 0, 0, 0);
+      relu_to_operand(z, b3op[nt][mo >> 1], mo & 1);
+    }
+  }
+  const bf16x8 a3[2] = {permuted_row(w.w3b, 0, g), permuted_row(w.w3b, 1, g)};
+  const float b3 = w.b3[0];
+  float y = 0.0f;
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    f32x4 z3 = {b3, b3, b3, b3};
+    z3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3[0], b3op[nt][0], z3, 0, 0, 0);
+    z3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3[1], b3op[nt][1], z3, 0, 0, 0);
+    if (g == nt) y = z3[0];
+  }
+  return y;
 }
 
 __device__ __forceinline__ float norm01(double v, double lo, double hi) {

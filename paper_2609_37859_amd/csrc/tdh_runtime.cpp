@@ -41,6 +41,7 @@ struct tdh_ctx {
   double *flx = nullptr;  // face fluxes of the split stage form (3 axes)
   long long ftotal = 0;   // faces of one axis over all blocks
   bool seeds_held = false;  // the current buffers' segments hold the cells of the current state
+  bool cfl_seeds = false;   // modes 2, 4: the CFL pass recorded them and no stage has run since
   BlockInfo *d_blocks = nullptr;
   int *d_lmap = nullptr, *d_fac = nullptr, *d_par = nullptr, *d_order = nullptr, *d_item_start = nullptr;
   int *d_cnt_ge = nullptr, *d_cfl_item_block = nullptr, *d_cfl_block_start = nullptr, *d_fitem_start = nullptr;
@@ -470,6 +471,7 @@ extern "C" tdh_status tdh_init_blocks(tdh_ctx *c, const tdh_mesh *m, void *dev_a
   HIPCHK(c, hipMemcpyAsync(c->Qa, host_state, L.total * sizeof(double), hipMemcpyHostToDevice, c->stream));
   if (c->jc) HIPCHK(c, hipMemsetAsync(c->jc, 0xff, 3 * L.ncells * sizeof(int), c->stream));  // no seeds yet (-1)
   c->seeds_held = false;
+  c->cfl_seeds = false;
   if (c->phi) HIPCHK(c, hipMemcpyAsync(c->phi, host_phi, L.ptotal * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipHostMalloc((void **)&c->h_dtb, c->nb * sizeof(double), hipHostMallocDefault));
@@ -549,6 +551,8 @@ extern "C" tdh_status tdh_set_eos_table(tdh_ctx *c, int nrho, int nT, double lr0
   c->tab.lg = (const double2 *)(c->d_table + fn_off);
   c->tab.ex = c->d_table + fn_off + 256;
   c->have_table = true;
+  c->seeds_held = false;  // cells of another table
+  c->cfl_seeds = false;
   for (auto &g : c->graphs) hipGraphExecDestroy(g.second);
   c->graphs.clear();
   return TDH_OK;
@@ -608,6 +612,7 @@ extern "C" tdh_status tdh_reduce_dt(tdh_ctx *c, double *host_dtb, double *host_d
   HIPCHK(c, launch_cfl(a, c->cfg.cfl, c->t, c->d_cfl_item_block, c->cfl_nitems, c->d_cfl_part, c->nb,
                        c->d_cfl_block_start, c->d_dtb, c->stream));
   c->stats.kernel_launches += 2;
+  c->cfl_seeds = c->cfg.eos_kind == 1 && (c->cfg.inv_mode == 2 || c->cfg.inv_mode == 4);
   HIPCHK(c, hipMemcpyAsync(c->h_dtb, c->d_dtb, c->nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   std::vector<double> dtb(c->h_dtb, c->h_dtb + c->nb);
@@ -666,7 +671,7 @@ static tdh_status collect_timing(tdh_ctx *c) {
 static tdh_status timed_stage(tdh_ctx *c, const StageArgs &a) {
   const bool t = c->timing && !c->capturing;
   tdh_status s;
-  if (c->cfg.eos_kind == 1 && (c->cfg.inv_mode == 2 || c->cfg.inv_mode == 4)) {
+  if (c->cfg.eos_kind == 1 && (c->cfg.inv_mode == 2 || c->cfg.inv_mode == 4) && !(a.k == 0 && a.phase == 1)) {
     HIPCHK(c, launch_seed(a, c->grid, c->stream));
     c->stats.kernel_launches++;
   }
@@ -682,10 +687,19 @@ static tdh_status timed_stage(tdh_ctx *c, const StageArgs &a) {
   return TDH_OK;
 }
 
-// Modes 1 and 3 carry seed cells from stage to stage; after a state upload a
-// pass over every block finds them once (outside any captured graph).
+// Seeds of a window's first stage.  Modes 1 and 3 carry seed cells from stage
+// to stage; after a state upload a pass over every block finds them once.
+// Modes 2 and 4 take them from the CFL pass when it ran on this state, else
+// from a pass over every block here.  Outside any captured graph, so a
+// window's graph never holds its first seed pass.
 static tdh_status ensure_seeds(tdh_ctx *c) {
-  if (c->cfg.eos_kind != 1 || !(c->cfg.inv_mode == 1 || c->cfg.inv_mode == 3) || c->seeds_held) return TDH_OK;
+  if (c->cfg.eos_kind != 1) return TDH_OK;
+  const bool carried = c->cfg.inv_mode == 1 || c->cfg.inv_mode == 3;
+  const bool per_stage = c->cfg.inv_mode == 2 || c->cfg.inv_mode == 4;
+  if (!(carried && !c->seeds_held) && !(per_stage && !c->cfl_seeds)) {
+    c->cfl_seeds = false;  // consumed by this window
+    return TDH_OK;
+  }
   StageArgs a = base_args(c);
   a.k = 0;
   a.phase = 1;
@@ -693,7 +707,8 @@ static tdh_status ensure_seeds(tdh_ctx *c) {
   a.Lhi = kCntSlots - 2;
   HIPCHK(c, launch_seed(a, c->grid, c->stream));
   c->stats.kernel_launches++;
-  c->seeds_held = true;
+  if (carried) c->seeds_held = true;
+  c->cfl_seeds = false;
   return TDH_OK;
 }
 
@@ -1031,6 +1046,7 @@ extern "C" tdh_status tdh_remap(tdh_ctx *dst, tdh_ctx *src) {
                            dst->stream));
   if (dst->jc) HIPCHK(dst, hipMemsetAsync(dst->jc, 0xff, 3 * dst->ncells * sizeof(int), dst->stream));
   dst->seeds_held = false;
+  dst->cfl_seeds = false;
   dst->par.assign(dst->nb, 0);
   HIPCHK(dst, hipMemcpyAsync(dst->d_par, dst->par.data(), dst->nb * sizeof(int), hipMemcpyHostToDevice, dst->stream));
   HIPCHK(dst, hipStreamSynchronize(dst->stream));
@@ -1049,6 +1065,7 @@ extern "C" tdh_status tdh_galilean_boost(tdh_ctx *c, const double *host_V, doubl
   HIPCHK(c, launch_boost(a.m, c->d_par, c->Qa, c->Qb, c->nv, host_V, rho_skip, c->stream));
   if (c->jc) HIPCHK(c, hipMemsetAsync(c->jc, 0xff, 3 * c->ncells * sizeof(int), c->stream));  // energies moved
   c->seeds_held = false;
+  c->cfl_seeds = false;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return TDH_OK;
 }
@@ -1086,6 +1103,7 @@ extern "C" tdh_status tdh_set_state(tdh_ctx *c, const double *host) {
   HIPCHK(c, hipMemcpyAsync(c->Qa, host, c->total * sizeof(double), hipMemcpyHostToDevice, c->stream));
   if (c->jc) HIPCHK(c, hipMemsetAsync(c->jc, 0xff, 3 * c->ncells * sizeof(int), c->stream));  // stale seeds go
   c->seeds_held = false;
+  c->cfl_seeds = false;
   c->par.assign(c->nb, 0);
   HIPCHK(c, hipMemcpyAsync(c->d_par, c->par.data(), c->nb * sizeof(int), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -155,3 +155,43 @@ def test_hydro_with_learned_seed_equals_bisection_bitwise(gctx, saha):
         outs.append(ctx.get_state())
         ctx.close()
     assert all(np.array_equal(outs[0], o) for o in outs[1:])
+
+
+def test_cfl_pass_records_the_first_stage_seeds(gctx, saha):
+    """Modes 2 and 4: the CFL reduction records the table cell of every cell of
+    the current state (the cells its bisection for the sound speed finds), so
+    the window's first stage needs no seed pass;
+    steps driven by the CFL step equal the bisection run bit for bit, also
+    after a state upload between the reduction and the step (the recorded
+    cells are then dropped)."""
+    from paper_2609_37859_amd import tdh as T
+    _train_seed(gctx, saha, steps=300)
+    params = gctx.mlp_params()
+    cfg, mesh, U = W.stream_c2(saha, nb=2)
+    from tests.test_gpu_parity import _centre_cells
+    outs, dts, cells = [], [], {}
+    for mode in (0, 2, 4):
+        ctx = T.Context(cfg, mesh, U, table=saha, inv_mode=mode)
+        if mode == 4:
+            ctx.mlp_init(params, W.seed_ranges(saha))
+            ctx.mlp_enable_seed(True)
+        assert np.all(ctx.seed_cells() == -1)
+        ctx.reduce_dt()
+        if mode:
+            cells[mode] = ctx.seed_cells()
+        else:
+            assert np.all(ctx.seed_cells() == -1)  # mode 0 records nothing
+        used = list(T.run_sync_steps(ctx, 3))
+        g = ctx.get_state()
+        ctx.reduce_dt()
+        ctx.set_state(U)          # recorded cells of g dropped with the upload
+        used += list(T.run_sync_steps(ctx, 1, dts=[3e-4]))
+        outs.append((g, ctx.get_state()))
+        dts.append(used)
+        ctx.close()
+    assert np.array_equal(cells[2], cells[4])
+    exact = _centre_cells(gctx, cfg, mesh, U, saha)
+    assert np.mean(cells[2] == exact) > 0.999, np.mean(cells[2] == exact)
+    for o, d in zip(outs[1:], dts[1:]):
+        assert d == dts[0]
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
