@@ -40,6 +40,16 @@ __device__ __forceinline__ int block_of(const MeshDev &m, int gx, int gy, int gz
   return m.lmap[((gz >> m.lat_shift) * m.ly + (gy >> m.lat_shift)) * m.lx + (gx >> m.lat_shift)];
 }
 
+// Physics switches of the stage path.  PK = 0 reads them from Phys at run time;
+// PK = 1 and 2 fix them at compile time for the table EOS with dual energy, no
+// gravity and linearly interpolated LAT ghosts, with HLLC (1) or HLLE (2), so
+// the compiler drops the other paths and the registers they would hold.
+template <int PK> __device__ __forceinline__ int k_eos(const Phys &p) { return PK ? 1 : p.eos_kind; }
+template <int PK> __device__ __forceinline__ int k_dual(const Phys &p) { return PK ? 1 : p.dual; }
+template <int PK> __device__ __forceinline__ int k_grav(const Phys &p) { return PK ? 0 : p.grav_kind; }
+template <int PK> __device__ __forceinline__ int k_riemann(const Phys &p) { return PK ? PK - 1 : p.riemann; }
+template <int PK> __device__ __forceinline__ int k_dense(const Phys &p) { return PK ? 0 : p.ghost_dense; }
+
 // Where a reader with factor fb finds block nb's conserved state at its stage time.
 struct Src {
   const double *A, *B;
@@ -47,6 +57,7 @@ struct Src {
   double w;         // value = (1 - w) A + w B, w in [0, 1]; with C the RK2 dense output at w
 };
 
+template <int PK = 0>
 __device__ __forceinline__ Src source_of(const StageArgs &a, int fb, int nb) {
   const int fn = a.fac[nb];
   const int pn = a.par[nb];
@@ -60,7 +71,7 @@ __device__ __forceinline__ Src source_of(const StageArgs &a, int fb, int nb) {
     // mid-step: start, stage-1 and end states of its step are stored
     const int t0 = a.k & ~(fn - 1);
     s.A = Qold; s.B = Qend; s.w = (double)(a.k - t0) / fn;
-    if (a.p.ghost_dense) s.C = a.Qs;
+    if (k_dense<PK>(a.p)) s.C = a.Qs;
     return s;
   }
   if (act) {
@@ -70,7 +81,7 @@ __device__ __forceinline__ Src source_of(const StageArgs &a, int fb, int nb) {
   }
   const int t0 = a.k & ~(fn - 1);
   s.A = Qold; s.B = Qend; s.w = (double)(a.k + fb - t0) / fn;
-  if (a.p.ghost_dense) s.C = a.Qs;
+  if (k_dense<PK>(a.p)) s.C = a.Qs;
   return s;
 }
 
@@ -101,8 +112,9 @@ __device__ __forceinline__ double src_val(const Src &s, long long idx) {
 // ---------------------------------------------------------------------------
 // equation of state
 // ---------------------------------------------------------------------------
+template <int PK = 0>
 __device__ __forceinline__ double u_floor(const Phys &p, double rho) {
-  return p.eos_kind == 0 ? p.p_floor / (p.gamma - 1.0) : rho * p.e_floor;
+  return k_eos<PK>(p) == 0 ? p.p_floor / (p.gamma - 1.0) : rho * p.e_floor;
 }
 
 __device__ __forceinline__ void table_rho(const Table &t, double lr, int &i, double &w) {
@@ -269,9 +281,10 @@ __device__ __forceinline__ double exp10_tab(const double *ex, double x) {
 }
 
 // (rho, U) -> P, c_s.  jseed: table cell to start from (-1: bisection).
+template <int PK = 0>
 __device__ __forceinline__ void eos_pc(const Phys &p, const Table &t, double rho, double U, int jseed, double &P,
                                        double &cs, int *jout = nullptr) {
-  if (p.eos_kind == 0) {
+  if (k_eos<PK>(p) == 0) {
     const double Ue = fmax(U, u_floor(p, rho));
     P = (p.gamma - 1.0) * Ue;
     cs = sqrt(p.gamma * P / rho);
@@ -297,13 +310,14 @@ __device__ __forceinline__ void eos_pc(const Phys &p, const Table &t, double rho
 // ---------------------------------------------------------------------------
 // cell primitives and the Riemann problem
 // ---------------------------------------------------------------------------
+template <int PK = 0>
 __device__ __forceinline__ void c2p(const Phys &p, const double *q, double *w) {
   const double rho = q[IDN];
   const double inv = 1.0 / rho;
   const double K = 0.5 * (q[IM1] * q[IM1] + q[IM2] * q[IM2] + q[IM3] * q[IM3]) * inv;
   const double Uc = q[IEN] - K;
   double Ueos = Uc;
-  if (p.dual) {
+  if (k_dual<PK>(p)) {
     if (!(Uc > 0.0 && Uc > p.eta1 * q[IEN])) Ueos = q[IAX];
     w[5] = q[IAX];
   }
@@ -392,8 +406,9 @@ __device__ __forceinline__ double phi_point(const Phys &p, const MeshDev &m, int
   return -p.gm_bh / sqrt(dx * dx + dy * dy + dz * dz + p.r_soft * p.r_soft);
 }
 
+template <int PK = 0>
 __device__ __forceinline__ bool excised(const Phys &p, const MeshDev &m, int gx, int gy, int gz, double t) {
-  if (p.grav_kind != 2 || !(p.r_exc > 0.0)) return false;
+  if (k_grav<PK>(p) != 2 || !(p.r_exc > 0.0)) return false;
   const double dx = cell_x(m, 0, gx) - (p.bh_x0[0] - p.v_frame[0] * t);
   const double dy = cell_x(m, 1, gy) - (p.bh_x0[1] - p.v_frame[1] * t);
   const double dz = cell_x(m, 2, gz) - (p.bh_x0[2] - p.v_frame[2] * t);
@@ -401,8 +416,9 @@ __device__ __forceinline__ bool excised(const Phys &p, const MeshDev &m, int gx,
 }
 
 // potential at local offset (i,j,k) in [-1, n] of block B
+template <int PK = 0>
 __device__ __forceinline__ double phi_at(const StageArgs &a, const BlockInfo &B, int i, int j, int k, double t) {
-  if (a.p.grav_kind == 1) {
+  if (k_grav<PK>(a.p) == 1) {
     const int np = B.n + 2;
     return a.phi[B.poff + ((long long)(k + 1) * np + (j + 1)) * np + (i + 1)];
   }
@@ -419,7 +435,7 @@ struct Nbr {
 };
 
 // load conserved state of global cell g (stage view of the reader), return block info
-template <int NV>
+template <int NV, int PK = 0>
 __device__ __forceinline__ void load_q(const StageArgs &a, int b, const BlockInfo &B, const Src &own, int fb,
                                        int gx, int gy, int gz, double *q, int *nb_out, long long *idx_out) {
   const MeshDev &m = a.m;
@@ -436,7 +452,7 @@ __device__ __forceinline__ void load_q(const StageArgs &a, int b, const BlockInf
   }
   const int nb = block_of(m, gx, gy, gz);
   const BlockInfo Bn = m.blocks[nb];
-  const Src s = source_of(a, fb, nb);
+  const Src s = source_of<PK>(a, fb, nb);
   const long long n3 = (long long)Bn.n * Bn.n * Bn.n;
   const long long idx = ((long long)(gz - Bn.oz) * Bn.n + (gy - Bn.oy)) * Bn.n + (gx - Bn.ox);
   _Pragma("unroll") for (int v = 0; v < NV; ++v) q[v] = src_val(s, Bn.off + v * n3 + idx);
@@ -559,7 +575,7 @@ __device__ __forceinline__ void plm_face(double q0, double q1, double q2, double
 //   fr: local coordinates of the cell right of the face; nbo: block owning the
 //   cell across a block face (-1 beyond an outflow edge); seedl: seed cell of
 //   the left state (-1: none).
-template <int NV, int D>
+template <int NV, int D, int PK = 0>
 __device__ __forceinline__ void face_flux(const StageArgs &a, const BlockInfo &B, int fb, double t, double dtb,
                                           const int *fr, const double *wl, const double *wr, int seedl, int nbo,
                                           double *Gf) {
@@ -569,10 +585,10 @@ __device__ __forceinline__ void face_flux(const StageArgs &a, const BlockInfo &B
   const int n = B.n;
   double pl, cl, pr, cr;
   int jl = -1;
-  eos_pc(p, a.t, wl[0], wl[4], seedl, pl, cl, &jl);
-  eos_pc(p, a.t, wr[0], wr[4], p.inv_mode == 0 ? -1 : jl, pr, cr);
+  eos_pc<PK>(p, a.t, wl[0], wl[4], seedl, pl, cl, &jl);
+  eos_pc<PK>(p, a.t, wr[0], wr[4], p.inv_mode == 0 ? -1 : jl, pr, cr);
   double F[5];
-  if (p.riemann == 1) hlle(wl, pl, cl, wr, pr, cr, F);
+  if (k_riemann<PK>(p) == 1) hlle(wl, pl, cl, wr, pr, cr, F);
   else hllc(wl, pl, cl, wr, pr, cr, F);
   double FA = 0.0, vf;
   {
@@ -581,11 +597,11 @@ __device__ __forceinline__ void face_flux(const StageArgs &a, const BlockInfo &B
     if (NV > 5) FA = F[0] * ((up_left ? wl[5] : wr[5]) / ru);
     vf = F[0] / ru;
   }
-  if (p.grav_kind == 2 && p.r_exc > 0.0) {
+  if (k_grav<PK>(p) == 2 && p.r_exc > 0.0) {
     int gl[3] = {B.ox + fr[0], B.oy + fr[1], B.oz + fr[2]};
-    const bool eR = excised(p, m, gl[0], gl[1], gl[2], t);
+    const bool eR = excised<PK>(p, m, gl[0], gl[1], gl[2], t);
     gl[D] -= 1;
-    const bool eL = excised(p, m, gl[0], gl[1], gl[2], t);
+    const bool eL = excised<PK>(p, m, gl[0], gl[1], gl[2], t);
     if (eL != eR) {
       const bool into = eR ? (F[0] >= 0.0) : (F[0] <= 0.0);
       if (!into) {
@@ -635,7 +651,7 @@ __device__ __forceinline__ void face_flux(const StageArgs &a, const BlockInfo &B
 // velocity divergence, gravity) and the neighbour energies of the resync.
 // Flo / Fhi: the cell's low / high face along D (slots as face_flux); Em, Ep:
 // stage-input E of the neighbours along D; rho: the cell's stage-input density.
-template <int NV, int D>
+template <int NV, int D, int PK = 0>
 __device__ __forceinline__ void axis_update(const StageArgs &a, const BlockInfo &B, double t, const int *lc,
                                             const double *Flo, const double *Fhi, double rho, double Em, double Ep,
                                             double *rhs, double &divv, double &emax) {
@@ -647,13 +663,13 @@ __device__ __forceinline__ void axis_update(const StageArgs &a, const BlockInfo 
   for (int v = 0; v < NV; ++v) rhs[v] -= (Fhi[v] - Flo[v]) * idx;
   divv += (Fhi[6] - Flo[6]) * idx;
   emax = fmax(emax, fmax(Em, Ep));
-  if (p.grav_kind) {
+  if (k_grav<PK>(p)) {
     int im[3] = {lc[0], lc[1], lc[2]}, ip[3] = {lc[0], lc[1], lc[2]};
     im[D] -= 1;
     ip[D] += 1;
-    const double pm = phi_at(a, B, im[0], im[1], im[2], t);
-    const double p0 = phi_at(a, B, lc[0], lc[1], lc[2], t);
-    const double pp = phi_at(a, B, ip[0], ip[1], ip[2], t);
+    const double pm = phi_at<PK>(a, B, im[0], im[1], im[2], t);
+    const double p0 = phi_at<PK>(a, B, lc[0], lc[1], lc[2], t);
+    const double pp = phi_at<PK>(a, B, ip[0], ip[1], ip[2], t);
     rhs[PN] -= rho * (pp - pm) / (2.0 * m.dx[D]);
     rhs[IEN] -= (Fhi[IDN] * (pp - p0) + Flo[IDN] * (p0 - pm)) / (2.0 * m.dx[D]);
   }
@@ -667,7 +683,7 @@ __device__ __forceinline__ void axis_update(const StageArgs &a, const BlockInfo 
 // RK combine of one cell and everything after it: compression of U_aux,
 // floors, resynchronisation, excision reset, the store, and (modes 1 and 3)
 // the table cell of the output state for the next stage.
-template <int NV, bool NET>
+template <int NV, bool NET, int PK = 0>
 __device__ __forceinline__ void finish_cell(const StageArgs &a, const BlockInfo &B, const Src &own, int parb, double dtb,
                                             double tk, const int *lc, long long cell, int jcell, const double *rhs,
                                             double divv, double emax) {
@@ -686,21 +702,21 @@ __device__ __forceinline__ void finish_cell(const StageArgs &a, const BlockInfo 
   }
   if (NV > 5) {
     const double tau = a.phase == 1 ? dtb : 0.5 * dtb;
-    if (p.eos_kind == 0) {
+    if (k_eos<PK>(p) == 0) {
       qn[IAX] = qn[IAX] * exp(-(p.gamma - 1.0) * divv * tau);
     } else {
       double Pa, ca;
-      eos_pc(p, a.t, qc[IDN], qn[IAX], p.inv_mode == 0 ? -1 : jcell, Pa, ca);
+      eos_pc<PK>(p, a.t, qc[IDN], qn[IAX], p.inv_mode == 0 ? -1 : jcell, Pa, ca);
       qn[IAX] = qn[IAX] - Pa * divv * tau;
     }
-    const double uf = u_floor(p, qn[IDN] > p.rho_floor ? qn[IDN] : p.rho_floor);
+    const double uf = u_floor<PK>(p, qn[IDN] > p.rho_floor ? qn[IDN] : p.rho_floor);
     if (qn[IAX] < uf) qn[IAX] = uf;
   }
   if (qn[IDN] < p.rho_floor) qn[IDN] = p.rho_floor;
   {
     double w[6];
-    c2p(p, qn, w);
-    const double uf = u_floor(p, qn[IDN]);
+    c2p<PK>(p, qn, w);
+    const double uf = u_floor<PK>(p, qn[IDN]);
     if (w[4] < uf) {
       qn[IEN] += uf - w[4];
       if (NV > 5 && qn[IAX] < uf) qn[IAX] = uf;
@@ -711,9 +727,9 @@ __device__ __forceinline__ void finish_cell(const StageArgs &a, const BlockInfo 
     const double Uc = qn[IEN] - K;
     if (Uc > 0.0 && Uc > p.eta2 * emax) qn[IAX] = Uc;
   }
-  if (a.phase == 2 && p.grav_kind == 2 && p.r_exc > 0.0) {
-    if (excised(p, m, B.ox + lc[0], B.oy + lc[1], B.oz + lc[2], tk + dtb)) {
-      const double uf = u_floor(p, p.rho_floor);
+  if (a.phase == 2 && k_grav<PK>(p) == 2 && p.r_exc > 0.0) {
+    if (excised<PK>(p, m, B.ox + lc[0], B.oy + lc[1], B.oz + lc[2], tk + dtb)) {
+      const double uf = u_floor<PK>(p, p.rho_floor);
       qn[IDN] = p.rho_floor;
       qn[IM1] = qn[IM2] = qn[IM3] = 0.0;
       qn[IEN] = uf;
@@ -723,13 +739,13 @@ __device__ __forceinline__ void finish_cell(const StageArgs &a, const BlockInfo 
   double *out = a.phase == 1 ? a.Qs : (parb ? a.Qa : a.Qb);
 #pragma unroll
   for (int v = 0; v < NV; ++v) out[B.off + v * n3 + cell] = qn[v];
-  if (p.eos_kind == 1 && (p.inv_mode == 1 || p.inv_mode == 3)) {
+  if (k_eos<PK>(p) == 1 && (p.inv_mode == 1 || p.inv_mode == 3)) {
     // The table cell of the output state seeds the next stage's queries of
     // this cell.  Its search starts from the learned network's prediction
     // (mode 1; the whole wave takes part, every thread owns a cell) or from
     // the input state's cell (mode 3).
     double w[6];
-    c2p(p, qn, w);
+    c2p<PK>(p, qn, w);
     const double Ue = fmax(w[4], w[0] * p.e_floor);
     const double lr = log10_tab(a.t.lg, w[0]), le = log10_tab(a.t.lg, Ue / w[0]);
     int start = jcell;
@@ -745,7 +761,7 @@ __device__ __forceinline__ void finish_cell(const StageArgs &a, const BlockInfo 
 // ---------------------------------------------------------------------------
 // fused form: one workgroup per tile, faces through LDS
 // ---------------------------------------------------------------------------
-template <int TX, int TY, int TZ, int NV, int D, int NT>
+template <int TX, int TY, int TZ, int NV, int D, int NT, int PK>
 __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, double *sW, double *sF, int *sB,
                                           const int *sJc, double *rhs, double &divv, double &emax) {
   using G = TileGeom<TX, TY, TZ>;
@@ -774,8 +790,8 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
     double q[6], w[6];
     int nb_;
     long long id_;
-    load_q<NV>(a, T.b, T.B, T.own, T.fb, g[0], g[1], g[2], q, &nb_, &id_);
-    c2p(p, q, w);
+    load_q<NV, PK>(a, T.b, T.B, T.own, T.fb, g[0], g[1], g[2], q, &nb_, &id_);
+    c2p<PK>(p, q, w);
     const int slot = G::TV + tid;
 #pragma unroll
     for (int v = 0; v < NV; ++v) sW[v * SW + slot] = w[v];
@@ -802,7 +818,7 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
       plm_face(col[sl[0]], col[sl[1]], col[sl[2]], col[sl[3]], wl[vv], wr[vv]);
     }
     int seedl = -1;
-    if (p.eos_kind == 1 && p.inv_mode != 0) {
+    if (k_eos<PK>(p) == 1 && p.inv_mode != 0) {
       // seed the left state from the table cell of the adjacent tile cell's centre
       int tc[3] = {fc[0], fc[1], fc[2]};
       if (tc[D] > 0) tc[D] -= 1;
@@ -814,7 +830,7 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
     // block across a block face: a halo cell (layer -1 below, T_D above)
     const int nbo = (fr[D] == 0 || side) ? sB[(side ? sl[2] : sl[1]) - G::TV] : T.b;
     double Gf[7];
-    face_flux<NV, D>(a, T.B, T.fb, T.t, T.dtb, fr, wl, wr, seedl, nbo, Gf);
+    face_flux<NV, D, PK>(a, T.B, T.fb, T.t, T.dtb, fr, wl, wr, seedl, nbo, Gf);
 #pragma unroll
     for (int v = 0; v < NV; ++v) sF[v * G::NF + f] = Gf[v];
     sF[6 * G::NF + f] = Gf[6];
@@ -838,7 +854,7 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
     cp[D] += 1;
     if (D == 0) emax = fmax(emax, sW[6 * SW + tid]);  // own stage-input E
     const int lc[3] = {T.to[0] + cc[0], T.to[1] + cc[1], T.to[2] + cc[2]};
-    axis_update<NV, D>(a, T.B, T.t, lc, Flo, Fhi, sW[tid], sW[6 * SW + cell_slot<TX, TY, TZ, D>(cm[0], cm[1], cm[2])],
+    axis_update<NV, D, PK>(a, T.B, T.t, lc, Flo, Fhi, sW[tid], sW[6 * SW + cell_slot<TX, TY, TZ, D>(cm[0], cm[1], cm[2])],
                        sW[6 * SW + cell_slot<TX, TY, TZ, D>(cp[0], cp[1], cp[2])], rhs, divv, emax);
   }
   __syncthreads();
@@ -846,9 +862,10 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
 
 // NET: the learned network starts the output states' table-cell searches (a
 // separate instantiation, so its matrix-core registers burden no other form)
+// PK: physics switches (read at run time, or fixed: see k_eos)
 // NT: threads per workgroup, 256 (one per cell) or 320 (every axis's faces in
 // one round; the last wave only stages and computes faces).
-template <int TX, int TY, int TZ, int NV, int OCC, bool NET, int NT>
+template <int TX, int TY, int TZ, int NV, int OCC, bool NET, int NT, int PK>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void stage_tiled(StageArgs a) {
   using G = TileGeom<TX, TY, TZ>;
   static_assert(G::TV == kChunk, "one cell per thread");
@@ -892,7 +909,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) 
       double q[6], w[6];
 #pragma unroll
       for (int v = 0; v < NV; ++v) q[v] = src_val(T.own, T.B.off + v * n3 + cell);
-      c2p(p, q, w);
+      c2p<PK>(p, q, w);
 #pragma unroll
       for (int v = 0; v < NV; ++v) sW[v * SW + tid] = w[v];
       sW[6 * SW + tid] = q[IEN];
@@ -903,14 +920,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) 
     // starts the face and compression queries
     int jcell = -1;
     const int parb = uni(a.par[T.b]);
-    if (has_cell && p.eos_kind == 1 && p.inv_mode != 0) {
+    if (has_cell && k_eos<PK>(p) == 1 && p.inv_mode != 0) {
       jcell = a.jc[jseg_in(a, parb) * a.jn + T.B.off / NV + cell];
       sJc[tid] = jcell;
     }
-    tile_axis<TX, TY, TZ, NV, 0, NT>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
-    tile_axis<TX, TY, TZ, NV, 1, NT>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
-    tile_axis<TX, TY, TZ, NV, 2, NT>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
-    if (has_cell) finish_cell<NV, NET>(a, T.B, T.own, parb, T.dtb, tk, lc, cell, jcell, rhs, divv, emax);
+    tile_axis<TX, TY, TZ, NV, 0, NT, PK>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
+    tile_axis<TX, TY, TZ, NV, 1, NT, PK>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
+    tile_axis<TX, TY, TZ, NV, 2, NT, PK>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
+    if (has_cell) finish_cell<NV, NET, PK>(a, T.B, T.own, parb, T.dtb, tk, lc, cell, jcell, rhs, divv, emax);
   }
 }
 
@@ -1399,17 +1416,25 @@ hipError_t launch_stage(const StageArgs &a, int tile, int grid, hipStream_t s) {
   int i = 0;
   // the network variant when it starts the searches (table EOS, mode 1, network on)
   const bool net = a.p.eos_kind == 1 && a.p.inv_mode == 1 && a.s.enabled;
+  // physics switches fixed at compile time where the configuration allows
+  const int kind = (!net && a.p.eos_kind == 1 && a.p.dual && a.m.nv == 6 && a.p.grav_kind == 0 && !a.p.ghost_dense)
+                       ? (a.p.riemann == 1 ? 2 : 1)
+                       : 0;
 #define TDH_LAUNCH(x, y, z, o, t)                                                                   \
   if (i++ == tile) {                                                                                \
-    if (net) {                                                                                      \
+    if (kind == 1)                                                                                  \
+      hipLaunchKernelGGL((stage_tiled<x, y, z, 6, o, false, t, 1>), dim3(grid), dim3(t), 0, s, a);  \
+    else if (kind == 2)                                                                             \
+      hipLaunchKernelGGL((stage_tiled<x, y, z, 6, o, false, t, 2>), dim3(grid), dim3(t), 0, s, a);  \
+    else if (net) {                                                                                 \
       if (a.m.nv == 6)                                                                              \
-        hipLaunchKernelGGL((stage_tiled<x, y, z, 6, o, true, t>), dim3(grid), dim3(t), 0, s, a);    \
+        hipLaunchKernelGGL((stage_tiled<x, y, z, 6, o, true, t, 0>), dim3(grid), dim3(t), 0, s, a); \
       else                                                                                          \
-        hipLaunchKernelGGL((stage_tiled<x, y, z, 5, o, true, t>), dim3(grid), dim3(t), 0, s, a);    \
+        hipLaunchKernelGGL((stage_tiled<x, y, z, 5, o, true, t, 0>), dim3(grid), dim3(t), 0, s, a); \
     } else if (a.m.nv == 6) {                                                                       \
-      hipLaunchKernelGGL((stage_tiled<x, y, z, 6, o, false, t>), dim3(grid), dim3(t), 0, s, a);     \
+      hipLaunchKernelGGL((stage_tiled<x, y, z, 6, o, false, t, 0>), dim3(grid), dim3(t), 0, s, a);  \
     } else {                                                                                        \
-      hipLaunchKernelGGL((stage_tiled<x, y, z, 5, o, false, t>), dim3(grid), dim3(t), 0, s, a);     \
+      hipLaunchKernelGGL((stage_tiled<x, y, z, 5, o, false, t, 0>), dim3(grid), dim3(t), 0, s, a);  \
     }                                                                                               \
     return hipGetLastError();                                                                       \
   }
