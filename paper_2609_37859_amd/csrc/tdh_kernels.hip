@@ -41,14 +41,16 @@ __device__ __forceinline__ int block_of(const MeshDev &m, int gx, int gy, int gz
 }
 
 // Physics switches of the stage path.  PK = 0 reads them from Phys at run time;
-// PK = 1 and 2 fix them at compile time for the table EOS with dual energy, no
-// gravity and linearly interpolated LAT ghosts, with HLLC (1) or HLLE (2), so
-// the compiler drops the other paths and the registers they would hold.
-template <int PK> __device__ __forceinline__ int k_eos(const Phys &p) { return PK ? 1 : p.eos_kind; }
-template <int PK> __device__ __forceinline__ int k_dual(const Phys &p) { return PK ? 1 : p.dual; }
-template <int PK> __device__ __forceinline__ int k_grav(const Phys &p) { return PK ? 0 : p.grav_kind; }
-template <int PK> __device__ __forceinline__ int k_riemann(const Phys &p) { return PK ? PK - 1 : p.riemann; }
-template <int PK> __device__ __forceinline__ int k_dense(const Phys &p) { return PK ? 0 : p.ghost_dense; }
+// otherwise they are fixed at compile time, PK = physics_code(p), so the
+// compiler drops the other paths and the registers they would hold.
+__host__ __device__ constexpr int physics_code(int eos, int dual, int grav, int riemann, int dense) {
+  return 1 + eos + 2 * dual + 4 * grav + 16 * riemann + 32 * dense;
+}
+template <int PK> __device__ __forceinline__ int k_eos(const Phys &p) { return PK ? (PK - 1) & 1 : p.eos_kind; }
+template <int PK> __device__ __forceinline__ int k_dual(const Phys &p) { return PK ? ((PK - 1) >> 1) & 1 : p.dual; }
+template <int PK> __device__ __forceinline__ int k_grav(const Phys &p) { return PK ? ((PK - 1) >> 2) & 3 : p.grav_kind; }
+template <int PK> __device__ __forceinline__ int k_riemann(const Phys &p) { return PK ? ((PK - 1) >> 4) & 1 : p.riemann; }
+template <int PK> __device__ __forceinline__ int k_dense(const Phys &p) { return PK ? ((PK - 1) >> 5) & 1 : p.ghost_dense; }
 
 // Where a reader with factor fb finds block nb's conserved state at its stage time.
 struct Src {
@@ -1412,21 +1414,31 @@ hipError_t launch_seed(const StageArgs &a, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Configurations with a stage kernel of their own (physics_code): the table
+// EOS with dual energy and no gravity (HLLC, HLLE), the same about a point
+// mass (linear and dense-output LAT ghosts), and the ideal gas in a fixed
+// potential; the rest run the kernel that reads the switches.
+#define TDH_KINDS(X) X(physics_code(1, 1, 0, 0, 0), 6) X(physics_code(1, 1, 0, 1, 0), 6) \
+                     X(physics_code(1, 1, 2, 0, 0), 6) X(physics_code(1, 1, 2, 0, 1), 6) \
+                     X(physics_code(0, 0, 1, 0, 0), 5)
+
 hipError_t launch_stage(const StageArgs &a, int tile, int grid, hipStream_t s) {
   int i = 0;
   // the network variant when it starts the searches (table EOS, mode 1, network on)
   const bool net = a.p.eos_kind == 1 && a.p.inv_mode == 1 && a.s.enabled;
-  // physics switches fixed at compile time where the configuration allows
-  const int kind = (!net && a.p.eos_kind == 1 && a.p.dual && a.m.nv == 6 && a.p.grav_kind == 0 && !a.p.ghost_dense)
-                       ? (a.p.riemann == 1 ? 2 : 1)
-                       : 0;
+  const int code = net || a.m.nv != 5 + (a.p.dual ? 1 : 0)
+                       ? 0
+                       : physics_code(a.p.eos_kind, a.p.dual ? 1 : 0, a.p.grav_kind, a.p.riemann, a.p.ghost_dense);
+#define TDH_KIND_LAUNCH(c, nv)                                                                      \
+  if (code == (c)) {                                                                                \
+    hipLaunchKernelGGL((stage_tiled<X_, Y_, Z_, nv, O_, false, T_, (c)>), dim3(grid), dim3(T_), 0, s, a); \
+    return hipGetLastError();                                                                       \
+  }
 #define TDH_LAUNCH(x, y, z, o, t)                                                                   \
   if (i++ == tile) {                                                                                \
-    if (kind == 1)                                                                                  \
-      hipLaunchKernelGGL((stage_tiled<x, y, z, 6, o, false, t, 1>), dim3(grid), dim3(t), 0, s, a);  \
-    else if (kind == 2)                                                                             \
-      hipLaunchKernelGGL((stage_tiled<x, y, z, 6, o, false, t, 2>), dim3(grid), dim3(t), 0, s, a);  \
-    else if (net) {                                                                                 \
+    constexpr int X_ = x, Y_ = y, Z_ = z, O_ = o, T_ = t;                                           \
+    TDH_KINDS(TDH_KIND_LAUNCH)                                                                      \
+    if (net) {                                                                                      \
       if (a.m.nv == 6)                                                                              \
         hipLaunchKernelGGL((stage_tiled<x, y, z, 6, o, true, t, 0>), dim3(grid), dim3(t), 0, s, a); \
       else                                                                                          \
@@ -1440,6 +1452,7 @@ hipError_t launch_stage(const StageArgs &a, int tile, int grid, hipStream_t s) {
   }
   TDH_TILES(TDH_LAUNCH)
 #undef TDH_LAUNCH
+#undef TDH_KIND_LAUNCH
 #define TDH_LAUNCH2(f, u)                                                                        \
   if (i++ == tile) return a.m.nv == 6 ? launch_split<6, f, u>(a, net, grid, s) : launch_split<5, f, u>(a, net, grid, s);
   TDH_SPLITS(TDH_LAUNCH2)
