@@ -411,3 +411,24 @@ def test_c5_shaped_subdomain_lat_window(tdh, orc, saha):
     print("C5-shaped window rel err", err, "per-cell scale", strict, "levels", np.bincount(lev),
           "cells with E << its parts", ill)
     assert np.all(err <= TOL)
+
+
+def test_c5_shaped_dense_ghosts_window(tdh, orc, saha):
+    """The C5-shaped sub-domain with the RK2 dense-output ghosts (the
+    compiled table-EOS, point-mass, dense-ghost kind): one LAT window against
+    the oracle, and a visible difference from the linear ghosts."""
+    cfg, mesh, U = W.debris_stream_c5(saha, regions=(4, 3, 2), n_split=6, dxr=1.0)
+    cfg = dataclasses.replace(cfg, ghost_dense=1)
+    ctx = tdh.Context(cfg, mesh, U, table=saha, inv_mode=2)
+    dtb, dt0, lev, L = ctx.reduce_dt()
+    assert L > 0
+    ctx.run_window(dt0 * 2 ** L, batched=True)
+    g = ctx.get_state()
+    ctx.close()
+    o, _ = orc.lat_window(cfg, mesh, U, lev, dt0, table=saha)
+    err = rel_err(6, mesh, g, o)
+    lin, _ = orc.lat_window(dataclasses.replace(cfg, ghost_dense=0), mesh, U, lev, dt0, table=saha)
+    print("C5-shaped dense-ghost window rel err", err, "levels", np.bincount(lev),
+          "max |dense - linear|", np.max(np.abs(o - lin)))
+    assert np.all(err <= TOL)
+    assert not np.array_equal(o, lin)
