@@ -90,10 +90,15 @@ FORMS = {
 }
 
 
-def train_seed(T, W, table, steps=2000, nsamples=1 << 20):
+def train_seed(T, W, table, steps=2000, nsamples=1 << 20, nquery=1 << 24):
     """Train the learned seed on the GPU with the library's kernels: 2^20
-    samples, labels from the library's table inversion.  Returns (params,
-    seconds, final loss, median |dlogT| of the prediction on fresh queries)."""
+    samples, labels from the library's table inversion.  Then evaluate it on
+    2^24 fresh queries of the same distribution: |dlogT| percentiles of the
+    prediction, the histogram of secant steps of the seeded searches (-1: the
+    seed did not lead to the bracketing cell within the step limit and
+    bisection decided), and the time per query of the batched inversion with
+    and without the seed (same cells, checked).  Returns (params, seconds,
+    final loss, evaluation dict)."""
     import torch
     cfg = W.Config(eos_kind=1, e_floor=table.e_floor)
     mesh = W.uniform_mesh(1, 1, 1, 8, 1.0)
@@ -105,13 +110,33 @@ def train_seed(T, W, table, steps=2000, nsamples=1 << 20):
     t0 = time.perf_counter()
     loss = ctx.mlp_train(x, lT, steps=steps, batch=4096, lr=1e-3, seed=1)
     secs = time.perf_counter() - t0
-    xq = torch.from_numpy(W.seed_training_samples(table, 1 << 20, 3)).cuda()
-    lq, _, _ = ctx.eos_invert(xq[:, 0].contiguous(), xq[:, 1].contiguous(), mode=0)
+    xq = torch.from_numpy(W.seed_training_samples(table, nquery, 3)).cuda()
+    qr, qe = xq[:, 0].contiguous(), xq[:, 1].contiguous()
+    lq, j0, _ = ctx.eos_invert(qr, qe, mode=0)
     err = (ctx.mlp_forward(xq) - lq).abs().cpu().numpy()
-    params = ctx.mlp_params()
-    ctx.close()
     q = {f"p{p}": float(np.percentile(err, p)) for p in (50, 90, 99, 99.99)}
     q["max"] = float(err.max())
+    ctx.mlp_enable_seed(True)
+    ns = {}
+    for mode in (0, 1):
+        ctx.eos_invert(qr, qe, mode=mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            out = ctx.eos_invert(qr, qe, mode=mode)
+        torch.cuda.synchronize()
+        ns[mode] = 1e9 * (time.perf_counter() - t0) / (5 * nquery)
+    l1, j1, it1 = out
+    if not (torch.equal(j0, j1) and torch.equal(lq, l1)):
+        raise SystemExit("seeded inversion differs from the table-only one")
+    hist = np.bincount(it1.cpu().numpy().astype(np.int64) + 1)
+    q["queries"] = nquery
+    q["secant_steps_histogram"] = {str(k - 1): int(v) for k, v in enumerate(hist) if v}
+    q["bisection_fallback_rate"] = float(hist[0]) / nquery
+    q["ns_per_query_table_only"] = ns[0]
+    q["ns_per_query_seeded"] = ns[1]
+    params = ctx.mlp_params()
+    ctx.close()
     return params, secs, float(loss[-1]), q
 
 
@@ -413,9 +438,9 @@ def main():
     valu = prof.get("sq", {}).get("SQ_INSTS_VALU")
     valu_issue = None
     if valu:
-        rate = valu / (launch_ms * 1e-3)
-        valu_issue = {"wave_insts_per_launch": valu, "achieved": rate, "peak": VALU_PEAK_WAVE_INSTS,
-                      "unit": "wave64 VALU instructions/s", "frac": rate / VALU_PEAK_WAVE_INSTS}
+        issue = valu / (launch_ms * 1e-3)
+        valu_issue = {"wave_insts_per_launch": valu, "achieved": issue, "peak": VALU_PEAK_WAVE_INSTS,
+                      "unit": "wave64 VALU instructions/s", "frac": issue / VALU_PEAK_WAVE_INSTS}
     out = {
         "metric": "FP64 cell-updates/s (LAT-batched+MLP-EOS vs plain) at <=1e-11 rel err; % HBM roof",
         "value": value,
@@ -438,7 +463,7 @@ def main():
                       "stage_kernel_ms": v[1] / max(v[2], 1), "tile": T.tile_shapes()[v[4]]} for k, v in res.items()},
         "speedup_vs_plain": (value / plain) if plain else None,
         "learned_seed": {"train_steps": 2000, "batch": 4096, "samples": 1 << 20, "train_seconds": train_s,
-                         "final_loss": train_loss, "abs_dlogT_percentiles": seed_err},
+                         "final_loss": train_loss, "evaluation": seed_err},
         "max_rel_err_vs_oracle": acc,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
