@@ -431,10 +431,12 @@ def main():
     # algorithmic HBM bytes of the stage kernel: stage 1 reads Q^n and writes Q^(1),
     # stage 2 reads Q^n and Q^(1) and writes Q^(n+1): 5 nv doubles per cell and step
     bytes_per_step = 5 * nv * 8 * ncell
-    achieved = bytes_per_step * args.steps / (stage_ms * 1e-3) / 1e9
+    # per launch (two launches per step on this single-level workload) over the
+    # average launch duration of every timed run
+    launch_ms = stage_ms / max(launches, 1)
+    achieved = 0.5 * bytes_per_step / (launch_ms * 1e-3) / 1e9
     prof = counters_from_profiles("c2")
     traffic = prof.get("hbm_bytes_per_launch")
-    launch_ms = stage_ms / max(launches, 1)
     valu = prof.get("sq", {}).get("SQ_INSTS_VALU")
     valu_issue = None
     if valu:
