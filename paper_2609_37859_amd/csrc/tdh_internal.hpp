@@ -101,6 +101,10 @@ struct StageArgs {
   const int *fitem_start;   // prefix sum of 256-face work items (one axis) over `order`
   const int2 *item_bt;      // per work item (cells): block id, index of the item within its block
   const int2 *fitem_bt;     // the same for the face items of the split form
+  // CFL partial minima the fused form's second stage leaves for every tile of
+  // its output state, at cfl_part[cfl_start[b] + tile] (null: not taken)
+  double *cfl_part;
+  const int *cfl_start;
 };
 
 // host-side launchers (tdh_kernels.hip)
@@ -149,6 +153,9 @@ hipError_t launch_seed(const StageArgs &a, int grid, hipStream_t s);
 hipError_t launch_set_window(double *win, double t, double dt0, hipStream_t s);
 hipError_t launch_commit(const int *order, const int *cnt_ge, int lmin, int *par, hipStream_t s);
 hipError_t launch_reflux(const StageArgs &a, int lc, int dir, int nmax, int grid, hipStream_t s);  // a.k = completing index
+hipError_t launch_cfl_blocks(const double *part, int nblocks, const int *block_item_start, double cfl, double *dtb,
+                             hipStream_t s);
+bool tile_is_fused(int id);
 hipError_t launch_cfl(const StageArgs &a, double cfl, double t, const int *item_block, int nitems,
                       double *part, int nblocks, const int *block_item_start, double *dtb, hipStream_t s);
 hipError_t launch_eos_invert(const Table &t, const Seed &s, int newton_max_iter, const double *lr, const double *le,

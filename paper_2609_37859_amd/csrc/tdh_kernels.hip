@@ -682,13 +682,21 @@ __device__ __forceinline__ void axis_update(const StageArgs &a, const BlockInfo 
   asm volatile("" : "+v"(divv), "+v"(emax));
 }
 
+__device__ __forceinline__ double wave_min(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 // RK combine of one cell and everything after it: compression of U_aux,
 // floors, resynchronisation, excision reset, the store, and (modes 1 and 3)
 // the table cell of the output state for the next stage.
+//   cflv (stage 2 of the fused form, a.cfl_part set): receives the cell's CFL
+//   limit of its output state, computed as the CFL reduction does; in modes 2
+//   and 4 that state's table cell is recorded as the next stage's seed.
 template <int NV, bool NET, int PK = 0>
 __device__ __forceinline__ void finish_cell(const StageArgs &a, const BlockInfo &B, const Src &own, int parb, double dtb,
                                             double tk, const int *lc, long long cell, int jcell, const double *rhs,
-                                            double divv, double emax) {
+                                            double divv, double emax, double *cflv = nullptr) {
   const Phys &p = a.p;
   const MeshDev &m = a.m;
   const long long n3 = (long long)B.n * B.n * B.n;
@@ -757,6 +765,32 @@ __device__ __forceinline__ void finish_cell(const StageArgs &a, const BlockInfo 
     table_rho(a.t, lr, i, wr);
     table_invert(a.t, i, wr, le, start, p.newton_max_iter, j, wT, it);
     a.jc[jseg_out(a, parb) * a.jn + B.off / NV + cell] = j;
+  }
+  if (cflv && a.cfl_part && a.phase == 2) {
+    double w[6];
+    c2p<PK>(p, qn, w);
+    double P, cs;
+    int jo = -1;
+    eos_pc<PK>(p, a.t, w[0], w[4], (k_eos<PK>(p) == 1 && p.inv_mode != 0) ? jcell : -1, P, cs, &jo);
+    double best = INFINITY;
+    for (int d = 0; d < 3; ++d) best = fmin(best, m.dx[d] / (fabs(w[1 + d]) + cs));
+    if (k_grav<PK>(p)) {
+      const double t = tk + dtb;
+      double g2 = 0.0;
+      for (int d = 0; d < 3; ++d) {
+        int ip[3] = {lc[0], lc[1], lc[2]}, im[3] = {lc[0], lc[1], lc[2]};
+        ip[d] += 1;
+        im[d] -= 1;
+        const double gd = (phi_at<PK>(a, B, ip[0], ip[1], ip[2], t) - phi_at<PK>(a, B, im[0], im[1], im[2], t)) /
+                          (2.0 * m.dx[d]);
+        g2 += gd * gd;
+      }
+      const double dmin = fmin(m.dx[0], fmin(m.dx[1], m.dx[2]));
+      if (g2 > 0.0) best = fmin(best, sqrt(dmin / sqrt(g2)));
+    }
+    *cflv = best;
+    if (k_eos<PK>(p) == 1 && (p.inv_mode == 2 || p.inv_mode == 4))
+      a.jc[jseg_out(a, parb) * a.jn + B.off / NV + cell] = jo;
   }
 }
 
@@ -877,6 +911,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) 
   __shared__ double sF[7 * G::NF];     // fluxes (rho, mx, my, mz, E, A) + face velocity
   __shared__ int sB[G::HALO];          // owning block of a halo cell, -1 beyond an outflow edge
   __shared__ int sJc[kChunk];          // table cell of each tile cell's centre state (seeds)
+  __shared__ double sRed[NT / 64];     // per-wave CFL minima
   const Phys &p = a.p;
   const MeshDev &m = a.m;
   const int a0 = a.cnt_ge[a.Lhi + 1], a1 = a.cnt_ge[a.Llo];
@@ -929,7 +964,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) 
     tile_axis<TX, TY, TZ, NV, 0, NT, PK>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
     tile_axis<TX, TY, TZ, NV, 1, NT, PK>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
     tile_axis<TX, TY, TZ, NV, 2, NT, PK>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
-    if (has_cell) finish_cell<NV, NET, PK>(a, T.B, T.own, parb, T.dtb, tk, lc, cell, jcell, rhs, divv, emax);
+    double cflv = INFINITY;
+    if (has_cell) finish_cell<NV, NET, PK>(a, T.B, T.own, parb, T.dtb, tk, lc, cell, jcell, rhs, divv, emax, &cflv);
+    if (a.cfl_part && a.phase == 2) {  // the tile's CFL minimum for the next reduction
+      cflv = wave_min(cflv);
+      if ((tid & 63) == 0) sRed[tid >> 6] = cflv;
+      __syncthreads();
+      if (tid == 0) {
+        double r = sRed[0];
+        for (int w = 1; w < NT / 64; ++w) r = fmin(r, sRed[w]);
+        a.cfl_part[a.cfl_start[T.b] + tile] = r;
+      }
+    }
   }
 }
 
@@ -1232,10 +1278,6 @@ __global__ void reflux_kernel(StageArgs a, int lc, int dir, int nmax) {
 // ---------------------------------------------------------------------------
 // CFL step: per-item minimum, then per-block minimum
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_min(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-  return v;
-}
 
 // In modes 2 and 4 (table EOS) the pass also records each cell's table cell
 // (found by bisection) in its block's current segment: the seeds of the
@@ -1458,6 +1500,21 @@ hipError_t launch_stage(const StageArgs &a, int tile, int grid, hipStream_t s) {
   TDH_SPLITS(TDH_LAUNCH2)
 #undef TDH_LAUNCH2
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_cfl_blocks(const double *part, int nblocks, const int *block_item_start, double cfl, double *dtb,
+                             hipStream_t s) {
+  const int bgrid = (nblocks + 3) / 4 < 1024 ? (nblocks + 3) / 4 : 1024;
+  hipLaunchKernelGGL(cfl_blocks_kernel, dim3(bgrid), dim3(256), 0, s, part, block_item_start, nblocks, cfl, dtb);
+  return hipGetLastError();
+}
+
+bool tile_is_fused(int id) {
+  int n = 0;
+#define TDH_COUNT(x, y, z, o, t) ++n;
+  TDH_TILES(TDH_COUNT)
+#undef TDH_COUNT
+  return id >= 0 && id < n;
 }
 
 hipError_t launch_set_window(double *win, double t, double dt0, hipStream_t s) {

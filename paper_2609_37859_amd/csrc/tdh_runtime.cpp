@@ -42,6 +42,7 @@ struct tdh_ctx {
   long long ftotal = 0;   // faces of one axis over all blocks
   bool seeds_held = false;  // the current buffers' segments hold the cells of the current state
   bool cfl_seeds = false;   // modes 2, 4: the CFL pass recorded them and no stage has run since
+  bool cfl_parts = false;   // the last window's second stages left every tile's CFL minimum of this state
   BlockInfo *d_blocks = nullptr;
   int *d_lmap = nullptr, *d_fac = nullptr, *d_par = nullptr, *d_order = nullptr, *d_item_start = nullptr;
   int *d_cnt_ge = nullptr, *d_cfl_item_block = nullptr, *d_cfl_block_start = nullptr, *d_fitem_start = nullptr;
@@ -306,6 +307,9 @@ static StageArgs base_args(tdh_ctx *c) {
   a.fitem_start = c->d_fitem_start;
   a.item_bt = c->d_item_bt;
   a.fitem_bt = c->d_fitem_bt;
+  // the point mass moves, so its CFL term needs the reduction's own time
+  a.cfl_part = c->cfg.grav_kind != 2 ? c->d_cfl_part : nullptr;
+  a.cfl_start = c->d_cfl_block_start;
   return a;
 }
 
@@ -472,6 +476,7 @@ extern "C" tdh_status tdh_init_blocks(tdh_ctx *c, const tdh_mesh *m, void *dev_a
   if (c->jc) HIPCHK(c, hipMemsetAsync(c->jc, 0xff, 3 * L.ncells * sizeof(int), c->stream));  // no seeds yet (-1)
   c->seeds_held = false;
   c->cfl_seeds = false;
+  c->cfl_parts = false;
   if (c->phi) HIPCHK(c, hipMemcpyAsync(c->phi, host_phi, L.ptotal * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipHostMalloc((void **)&c->h_dtb, c->nb * sizeof(double), hipHostMallocDefault));
@@ -553,6 +558,7 @@ extern "C" tdh_status tdh_set_eos_table(tdh_ctx *c, int nrho, int nT, double lr0
   c->have_table = true;
   c->seeds_held = false;  // cells of another table
   c->cfl_seeds = false;
+  c->cfl_parts = false;
   for (auto &g : c->graphs) hipGraphExecDestroy(g.second);
   c->graphs.clear();
   return TDH_OK;
@@ -609,10 +615,15 @@ extern "C" tdh_status tdh_reduce_dt(tdh_ctx *c, double *host_dtb, double *host_d
   tdh_status s;
   if ((s = ready(c)) || (s = require_window_boundary(c))) return s;
   StageArgs a = base_args(c);
-  HIPCHK(c, launch_cfl(a, c->cfg.cfl, c->t, c->d_cfl_item_block, c->cfl_nitems, c->d_cfl_part, c->nb,
-                       c->d_cfl_block_start, c->d_dtb, c->stream));
-  c->stats.kernel_launches += 2;
-  c->cfl_seeds = c->cfg.eos_kind == 1 && (c->cfg.inv_mode == 2 || c->cfg.inv_mode == 4);
+  if (c->cfl_parts) {  // the last window's second stages left the tile minima of this state
+    HIPCHK(c, launch_cfl_blocks(c->d_cfl_part, c->nb, c->d_cfl_block_start, c->cfg.cfl, c->d_dtb, c->stream));
+    c->stats.kernel_launches += 1;
+  } else {
+    HIPCHK(c, launch_cfl(a, c->cfg.cfl, c->t, c->d_cfl_item_block, c->cfl_nitems, c->d_cfl_part, c->nb,
+                         c->d_cfl_block_start, c->d_dtb, c->stream));
+    c->stats.kernel_launches += 2;
+    c->cfl_seeds = c->cfg.eos_kind == 1 && (c->cfg.inv_mode == 2 || c->cfg.inv_mode == 4);
+  }
   HIPCHK(c, hipMemcpyAsync(c->h_dtb, c->d_dtb, c->nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   std::vector<double> dtb(c->h_dtb, c->h_dtb + c->nb);
@@ -696,6 +707,7 @@ static tdh_status ensure_seeds(tdh_ctx *c) {
   if (c->cfg.eos_kind != 1) return TDH_OK;
   const bool carried = c->cfg.inv_mode == 1 || c->cfg.inv_mode == 3;
   const bool per_stage = c->cfg.inv_mode == 2 || c->cfg.inv_mode == 4;
+  c->cfl_parts = false;  // this window's second stages overwrite them
   if (!(carried && !c->seeds_held) && !(per_stage && !c->cfl_seeds)) {
     c->cfl_seeds = false;  // consumed by this window
     return TDH_OK;
@@ -709,6 +721,7 @@ static tdh_status ensure_seeds(tdh_ctx *c) {
   c->stats.kernel_launches++;
   if (carried) c->seeds_held = true;
   c->cfl_seeds = false;
+  c->cfl_parts = false;
   return TDH_OK;
 }
 
@@ -759,6 +772,10 @@ static void account_subcycle(tdh_ctx *c, int k) {
 }
 
 static void finish_window(tdh_ctx *c) {
+  // a fused-form window leaves the CFL minima of its output state and, in modes
+  // 2 and 4, that state's table cells (every block's last second stage is in it)
+  c->cfl_parts = c->cfg.grav_kind != 2 && tile_is_fused(c->tile);
+  c->cfl_seeds = c->cfl_parts && c->cfg.eos_kind == 1 && (c->cfg.inv_mode == 2 || c->cfg.inv_mode == 4);
   c->t = c->t + c->dt_coarse;
   c->k = 0;
   c->stats.windows++;
@@ -1015,6 +1032,7 @@ extern "C" tdh_status tdh_gravity_solve(tdh_ctx *c, void *dev_work, size_t bytes
   HIPCHK(c, mg_launch_affine(F.phi, P.scal + 2, 0.0, N, s));
   HIPCHK(c, mg_launch_scatter(a.m, c->nb, c->nmax, F, c->phi, s));
   HIPCHK(c, hipStreamSynchronize(s));
+  c->cfl_parts = false;  // the CFL's gravity term changed with the potential
   if (host_cycles) *host_cycles = cyc;
   return TDH_OK;
 }
@@ -1047,6 +1065,7 @@ extern "C" tdh_status tdh_remap(tdh_ctx *dst, tdh_ctx *src) {
   if (dst->jc) HIPCHK(dst, hipMemsetAsync(dst->jc, 0xff, 3 * dst->ncells * sizeof(int), dst->stream));
   dst->seeds_held = false;
   dst->cfl_seeds = false;
+  dst->cfl_parts = false;
   dst->par.assign(dst->nb, 0);
   HIPCHK(dst, hipMemcpyAsync(dst->d_par, dst->par.data(), dst->nb * sizeof(int), hipMemcpyHostToDevice, dst->stream));
   HIPCHK(dst, hipStreamSynchronize(dst->stream));
@@ -1066,6 +1085,7 @@ extern "C" tdh_status tdh_galilean_boost(tdh_ctx *c, const double *host_V, doubl
   if (c->jc) HIPCHK(c, hipMemsetAsync(c->jc, 0xff, 3 * c->ncells * sizeof(int), c->stream));  // energies moved
   c->seeds_held = false;
   c->cfl_seeds = false;
+  c->cfl_parts = false;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return TDH_OK;
 }
@@ -1104,6 +1124,7 @@ extern "C" tdh_status tdh_set_state(tdh_ctx *c, const double *host) {
   if (c->jc) HIPCHK(c, hipMemsetAsync(c->jc, 0xff, 3 * c->ncells * sizeof(int), c->stream));  // stale seeds go
   c->seeds_held = false;
   c->cfl_seeds = false;
+  c->cfl_parts = false;
   c->par.assign(c->nb, 0);
   HIPCHK(c, hipMemcpyAsync(c->d_par, c->par.data(), c->nb * sizeof(int), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -432,3 +432,46 @@ def test_c5_shaped_dense_ghosts_window(tdh, orc, saha):
           "max |dense - linear|", np.max(np.abs(o - lin)))
     assert np.all(err <= TOL)
     assert not np.array_equal(o, lin)
+
+
+@pytest.mark.parametrize("case", ["c2_mode2", "c2_mode4_hlle", "polytrope_lat", "polytrope_lat_split_tile"])
+def test_cfl_from_the_second_stage_equals_the_reduction(tdh, orc, saha, case):
+    """After a window of the fused form the CFL reduction takes the minima its
+    second stages left; they equal, bit for bit, what the reduction computes
+    from the state itself (the same state uploaded again, which drops them),
+    levels included, and in modes 2 and 4 the recorded table cells equal the
+    reduction's.  A split-form variant leaves none and the reduction runs."""
+    table = None
+    phi = None
+    if case.startswith("c2"):
+        cfg, mesh, U = W.stream_c2(saha, nb=2)
+        table = saha
+        mode = 2 if case == "c2_mode2" else 4
+        if case.endswith("hlle"):
+            cfg = dataclasses.replace(cfg, riemann=1)
+        kw = dict(table=table, inv_mode=mode)
+    else:
+        cfg, mesh, U, phi, _ = W.polytrope_c3(nb=4, n=16)
+        kw = dict(phi=phi)
+    ctx = tdh.Context(cfg, mesh, U, **kw)
+    if case == "polytrope_lat_split_tile":
+        ctx.set_tile(len([t for t in tdh.tile_shapes() if t[0] > 0]))  # the first split form
+    for w in range(3):
+        dtb, dt0, lev, L = ctx.reduce_dt()
+        if w == 0:
+            g0 = ctx.get_state()
+            dto = orc.cfl(cfg, mesh, g0, table=table, phi=phi)
+            assert np.all(np.abs(dtb / dto - 1) < 1e-13)
+        ctx.run_window(dt0 * 2 ** L, batched=True)
+        cells_after = ctx.seed_cells() if table is not None else None
+        f_dtb, f_dt0, f_lev, f_L = ctx.reduce_dt()
+        cells_fused = ctx.seed_cells() if table is not None else None
+        g = ctx.get_state()
+        ctx.set_state(g)
+        k_dtb, k_dt0, k_lev, k_L = ctx.reduce_dt()
+        assert np.array_equal(f_dtb, k_dtb) and f_dt0 == k_dt0 and np.array_equal(f_lev, k_lev) and f_L == k_L
+        if table is not None:
+            assert np.array_equal(cells_fused, ctx.seed_cells())
+            assert np.array_equal(cells_after, cells_fused)
+    print(case, "levels", np.bincount(k_lev), "dt0", k_dt0)
+    ctx.close()
