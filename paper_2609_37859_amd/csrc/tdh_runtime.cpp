@@ -266,6 +266,15 @@ static Phys make_phys(const tdh_config &g) {
   return p;
 }
 
+// The second stage leaves the CFL minima of its output state on single-level
+// runs with the table EOS and no point mass: under LAT a block completes
+// several times per window and only the last counts, the ideal gas's separate
+// reduction is cheaper than the stage's extra work, and the point mass's term
+// moves with time (the reduction takes the host's time).
+static bool stage_cfl(const tdh_ctx *c) {
+  return c->cfg.eos_kind == 1 && c->cfg.n_lat == 0 && c->cfg.grav_kind != 2;
+}
+
 static StageArgs base_args(tdh_ctx *c) {
   StageArgs a{};
   a.m.nx = c->nx;
@@ -307,8 +316,7 @@ static StageArgs base_args(tdh_ctx *c) {
   a.fitem_start = c->d_fitem_start;
   a.item_bt = c->d_item_bt;
   a.fitem_bt = c->d_fitem_bt;
-  // the point mass moves, so its CFL term needs the reduction's own time
-  a.cfl_part = c->cfg.grav_kind != 2 ? c->d_cfl_part : nullptr;
+  a.cfl_part = stage_cfl(c) ? c->d_cfl_part : nullptr;
   a.cfl_start = c->d_cfl_block_start;
   return a;
 }
@@ -774,7 +782,7 @@ static void account_subcycle(tdh_ctx *c, int k) {
 static void finish_window(tdh_ctx *c) {
   // a fused-form window leaves the CFL minima of its output state and, in modes
   // 2 and 4, that state's table cells (every block's last second stage is in it)
-  c->cfl_parts = c->cfg.grav_kind != 2 && tile_is_fused(c->tile);
+  c->cfl_parts = stage_cfl(c) && tile_is_fused(c->tile);
   c->cfl_seeds = c->cfl_parts && c->cfg.eos_kind == 1 && (c->cfg.inv_mode == 2 || c->cfg.inv_mode == 4);
   c->t = c->t + c->dt_coarse;
   c->k = 0;
