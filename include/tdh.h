@@ -154,7 +154,11 @@ tdh_status tdh_set_eos_table(tdh_ctx *ctx, int nrho, int nT, double lr0, double 
  * installed and start a new window.  host_dt_block [nblocks] and
  * host_levels [nblocks] may be NULL.  With the table EOS in inv_mode 2 or 4
  * it also records every cell's table cell as the seeds of the next window's
- * first stage.  Synchronises the stream. */
+ * first stage.  On single-level table-EOS runs without the point mass, after a
+ * window of a fused stage variant, it reduces the per-tile minima that the
+ * window's second stages computed from their output states (the same values;
+ * any other change of the state makes it read the state again).
+ * Synchronises the stream. */
 tdh_status tdh_reduce_dt(tdh_ctx *ctx, double *host_dt_block, double *host_dt0, int8_t *host_levels,
                          int *host_lmax);
 
