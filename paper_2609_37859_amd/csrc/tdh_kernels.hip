@@ -1468,11 +1468,23 @@ hipError_t launch_stage(const StageArgs &a, int tile, int grid, hipStream_t s) {
   int i = 0;
   // the network variant when it starts the searches (table EOS, mode 1, network on)
   const bool net = a.p.eos_kind == 1 && a.p.inv_mode == 1 && a.s.enabled;
-  const int code = net || a.m.nv != 5 + (a.p.dual ? 1 : 0)
+  const int code = a.m.nv != 5 + (a.p.dual ? 1 : 0)
                        ? 0
                        : physics_code(a.p.eos_kind, a.p.dual ? 1 : 0, a.p.grav_kind, a.p.riemann, a.p.ghost_dense);
+  // the network variant has a kernel of its own for the table EOS without gravity (HLLC)
+  if (net && code == physics_code(1, 1, 0, 0, 0)) {
+#define TDH_NET_LAUNCH(x, y, z, o, t)                                                                            \
+    if (i++ == tile) {                                                                                           \
+      hipLaunchKernelGGL((stage_tiled<x, y, z, 6, o, true, t, physics_code(1, 1, 0, 0, 0)>), dim3(grid), dim3(t), \
+                         0, s, a);                                                                               \
+      return hipGetLastError();                                                                                  \
+    }
+    TDH_TILES(TDH_NET_LAUNCH)
+#undef TDH_NET_LAUNCH
+    i = 0;
+  }
 #define TDH_KIND_LAUNCH(c, nv)                                                                      \
-  if (code == (c)) {                                                                                \
+  if (!net && code == (c)) {                                                                        \
     hipLaunchKernelGGL((stage_tiled<X_, Y_, Z_, nv, O_, false, T_, (c)>), dim3(grid), dim3(T_), 0, s, a); \
     return hipGetLastError();                                                                       \
   }
