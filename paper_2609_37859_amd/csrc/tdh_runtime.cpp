@@ -267,12 +267,13 @@ static Phys make_phys(const tdh_config &g) {
 }
 
 // The second stage leaves the CFL minima of its output state on single-level
-// runs with the table EOS and no point mass: under LAT a block completes
-// several times per window and only the last counts, the ideal gas's separate
-// reduction is cheaper than the stage's extra work, and the point mass's term
-// moves with time (the reduction takes the host's time).
+// runs with the table EOS and no point mass: under LAT (also levels a caller
+// installs) the reflux after a sub-cycle still corrects blocks that have
+// completed, the ideal gas's separate reduction is cheaper than the stage's
+// extra work, and the point mass's term moves with time (the reduction takes
+// the host's time).
 static bool stage_cfl(const tdh_ctx *c) {
-  return c->cfg.eos_kind == 1 && c->cfg.n_lat == 0 && c->cfg.grav_kind != 2;
+  return c->cfg.eos_kind == 1 && c->cfg.n_lat == 0 && c->Lmax == 0 && c->cfg.grav_kind != 2;
 }
 
 static StageArgs base_args(tdh_ctx *c) {

@@ -485,3 +485,22 @@ def test_cfl_from_the_second_stage_equals_the_reduction(tdh, orc, saha, case):
                 assert np.array_equal(cells_after, cells_fused)
     print(case, "levels", np.bincount(k_lev), "dt0", k_dt0)
     ctx.close()
+
+
+def test_cfl_after_a_window_on_caller_levels(tdh, orc, saha):
+    """Levels installed by the caller on a run configured without LAT: the
+    window refluxes completed blocks, so the reduction reads the state again
+    and equals, bit for bit, the reduction of the same state uploaded anew."""
+    cfg, mesh, U = W.stream_c2(saha, nb=2)
+    ctx = tdh.Context(cfg, mesh, U, table=saha, inv_mode=2)
+    dtb, dt0, lev, L = ctx.reduce_dt()
+    assert L == 0
+    levels = np.zeros(mesh.nblocks, dtype=np.int8)
+    levels[::2] = 1
+    ctx.set_levels(levels)
+    ctx.run_window(dt0, batched=True)
+    f = ctx.reduce_dt()
+    ctx.set_state(ctx.get_state())
+    k = ctx.reduce_dt()
+    assert np.array_equal(f[0], k[0]) and f[1] == k[1]
+    ctx.close()
