@@ -105,6 +105,7 @@ struct StageArgs {
   // its output state, at cfl_part[cfl_start[b] + tile] (null: not taken)
   double *cfl_part;
   const int *cfl_start;
+  int lmax;                 // finest level of the window (0: every block on one schedule)
 };
 
 // host-side launchers (tdh_kernels.hip)

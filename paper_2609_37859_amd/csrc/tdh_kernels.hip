@@ -42,15 +42,18 @@ __device__ __forceinline__ int block_of(const MeshDev &m, int gx, int gy, int gz
 
 // Physics switches of the stage path.  PK = 0 reads them from Phys at run time;
 // otherwise they are fixed at compile time, PK = physics_code(p), so the
-// compiler drops the other paths and the registers they would hold.
-__host__ __device__ constexpr int physics_code(int eos, int dual, int grav, int riemann, int dense) {
-  return 1 + eos + 2 * dual + 4 * grav + 16 * riemann + 32 * dense;
+// compiler drops the other paths and the registers they would hold.  multi = 0
+// marks a window without levels: every neighbour is on the reader's schedule,
+// so ghosts need no time interpolation and faces no impulses.
+__host__ __device__ constexpr int physics_code(int eos, int dual, int grav, int riemann, int dense, int multi) {
+  return 1 + eos + 2 * dual + 4 * grav + 16 * riemann + 32 * dense + 64 * multi;
 }
 template <int PK> __device__ __forceinline__ int k_eos(const Phys &p) { return PK ? (PK - 1) & 1 : p.eos_kind; }
 template <int PK> __device__ __forceinline__ int k_dual(const Phys &p) { return PK ? ((PK - 1) >> 1) & 1 : p.dual; }
 template <int PK> __device__ __forceinline__ int k_grav(const Phys &p) { return PK ? ((PK - 1) >> 2) & 3 : p.grav_kind; }
 template <int PK> __device__ __forceinline__ int k_riemann(const Phys &p) { return PK ? ((PK - 1) >> 4) & 1 : p.riemann; }
 template <int PK> __device__ __forceinline__ int k_dense(const Phys &p) { return PK ? ((PK - 1) >> 5) & 1 : p.ghost_dense; }
+template <int PK> __host__ __device__ constexpr bool k_multi() { return PK ? ((PK - 1) >> 6) & 1 : true; }
 
 // Where a reader with factor fb finds block nb's conserved state at its stage time.
 struct Src {
@@ -61,6 +64,14 @@ struct Src {
 
 template <int PK = 0>
 __device__ __forceinline__ Src source_of(const StageArgs &a, int fb, int nb) {
+  if constexpr (!k_multi<PK>()) {  // one schedule: the neighbour's stage input, as the reader's own
+    Src s;
+    s.A = a.phase == 1 ? (a.par[nb] ? a.Qb : a.Qa) : a.Qs;
+    s.B = s.A;
+    s.C = nullptr;
+    s.w = 0.0;
+    return s;
+  }
   const int fn = a.fac[nb];
   const int pn = a.par[nb];
   const double *Qend = pn ? a.Qb : a.Qa;   // latest computed state
@@ -623,7 +634,7 @@ __device__ __forceinline__ void face_flux(const StageArgs &a, const BlockInfo &B
   Gf[6] = vf;
   // block-boundary faces: stage-1 flux, then the time-integrated impulse
   const int bd = fr[D];
-  if (bd == 0 || bd == n) {
+  if (k_multi<PK>() && (bd == 0 || bd == n)) {
     const int side = bd == n;
     const int u0 = D == 0 ? fr[1] : fr[0];
     const int u1 = D == 2 ? fr[1] : fr[2];
@@ -1457,12 +1468,13 @@ hipError_t launch_seed(const StageArgs &a, int grid, hipStream_t s) {
 }
 
 // Configurations with a stage kernel of their own (physics_code): the table
-// EOS with dual energy and no gravity (HLLC, HLLE), the same about a point
-// mass (linear and dense-output LAT ghosts), and the ideal gas in a fixed
-// potential; the rest run the kernel that reads the switches.
-#define TDH_KINDS(X) X(physics_code(1, 1, 0, 0, 0), 6) X(physics_code(1, 1, 0, 1, 0), 6) \
-                     X(physics_code(1, 1, 2, 0, 0), 6) X(physics_code(1, 1, 2, 0, 1), 6) \
-                     X(physics_code(0, 0, 1, 0, 0), 5)
+// EOS with dual energy and no gravity (HLLC, HLLE) in windows without levels,
+// the same about a point mass under LAT (linear and dense-output ghosts), and
+// the ideal gas in a fixed potential under LAT; the rest run the kernel that
+// reads the switches.
+#define TDH_KINDS(X) X(physics_code(1, 1, 0, 0, 0, 0), 6) X(physics_code(1, 1, 0, 1, 0, 0), 6) \
+                     X(physics_code(1, 1, 2, 0, 0, 1), 6) X(physics_code(1, 1, 2, 0, 1, 1), 6) \
+                     X(physics_code(0, 0, 1, 0, 0, 1), 5)
 
 hipError_t launch_stage(const StageArgs &a, int tile, int grid, hipStream_t s) {
   int i = 0;
@@ -1470,12 +1482,13 @@ hipError_t launch_stage(const StageArgs &a, int tile, int grid, hipStream_t s) {
   const bool net = a.p.eos_kind == 1 && a.p.inv_mode == 1 && a.s.enabled;
   const int code = a.m.nv != 5 + (a.p.dual ? 1 : 0)
                        ? 0
-                       : physics_code(a.p.eos_kind, a.p.dual ? 1 : 0, a.p.grav_kind, a.p.riemann, a.p.ghost_dense);
+                       : physics_code(a.p.eos_kind, a.p.dual ? 1 : 0, a.p.grav_kind, a.p.riemann, a.p.ghost_dense,
+                                      a.lmax > 0 ? 1 : 0);
   // the network variant has a kernel of its own for the table EOS without gravity (HLLC)
-  if (net && code == physics_code(1, 1, 0, 0, 0)) {
+  if (net && code == physics_code(1, 1, 0, 0, 0, 0)) {
 #define TDH_NET_LAUNCH(x, y, z, o, t)                                                                            \
     if (i++ == tile) {                                                                                           \
-      hipLaunchKernelGGL((stage_tiled<x, y, z, 6, o, true, t, physics_code(1, 1, 0, 0, 0)>), dim3(grid), dim3(t), \
+      hipLaunchKernelGGL((stage_tiled<x, y, z, 6, o, true, t, physics_code(1, 1, 0, 0, 0, 0)>), dim3(grid), dim3(t), \
                          0, s, a);                                                                               \
       return hipGetLastError();                                                                                  \
     }

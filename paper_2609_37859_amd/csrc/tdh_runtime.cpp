@@ -319,6 +319,7 @@ static StageArgs base_args(tdh_ctx *c) {
   a.fitem_bt = c->d_fitem_bt;
   a.cfl_part = stage_cfl(c) ? c->d_cfl_part : nullptr;
   a.cfl_start = c->d_cfl_block_start;
+  a.lmax = c->Lmax;
   return a;
 }
 
@@ -1226,9 +1227,12 @@ extern "C" tdh_status tdh_autotune(tdh_ctx *c, int reps, int *host_best, float *
   if ((s = ready(c)) || (s = require_window_boundary(c))) return s;
   if (reps < 1 || reps > 100) return fail(c, TDH_EINVAL, "reps must be in [1, 100]");
   const std::vector<int> saved = c->levels;
+  const int saved_lmax = c->Lmax;
   if ((s = install_levels(c, std::vector<int>(c->nb, 0)))) return s;
   HIPCHK(c, launch_set_window(c->d_win, c->t, c->dt_coarse > 0.0 ? c->dt_coarse : 1e-30, c->stream));
   StageArgs a = base_args(c);
+  a.lmax = saved_lmax;  // time the kernel the current levels' windows run
+  a.cfl_part = nullptr;
   a.k = 0;
   a.phase = 1;
   a.Llo = 0;
