@@ -504,3 +504,28 @@ def test_cfl_after_a_window_on_caller_levels(tdh, orc, saha):
     k = ctx.reduce_dt()
     assert np.array_equal(f[0], k[0]) and f[1] == k[1]
     ctx.close()
+
+
+def test_c5_full_size_lat_window(tdh, orc, saha):
+    """The production-shaped workload at full size (4096 blocks, 65.2 M cells,
+    Saha table, dual energy, moving point mass with excision, N_LAT = 3,
+    merge_frac 0.01) in the benchmark's launch configuration (batched launches
+    replayed from a captured graph): the levels from the library's CFL equal
+    the oracle's assignment bit for bit, and one window equals the oracle's
+    within 1e-11 per cell."""
+    import time
+    cfg, mesh, U = W.debris_stream_c5(saha)
+    cfg = dataclasses.replace(cfg, merge_frac=0.01)
+    ctx = tdh.Context(cfg, mesh, U, table=saha, inv_mode=2)
+    dtb, dt0, lev, L = ctx.reduce_dt()
+    lev_o, L_o, dt0_o = orc.lat_assign(cfg, mesh, dtb)
+    assert np.array_equal(lev, lev_o) and L == L_o and dt0 == dt0_o
+    ctx.run_window(dt0 * 2 ** L, batched=True, graph=True)
+    g = ctx.get_state()
+    ctx.close()
+    t0 = time.perf_counter()
+    o, _ = orc.lat_window(cfg, mesh, U, lev, dt0, table=saha)
+    err = rel_err(6, mesh, g, o)
+    print("C5 full-size window: levels", np.bincount(lev), "oracle seconds", round(time.perf_counter() - t0, 1),
+          "rel err", err, flush=True)
+    assert np.all(err <= TOL)
