@@ -54,6 +54,10 @@ template <int PK> __device__ __forceinline__ int k_grav(const Phys &p) { return 
 template <int PK> __device__ __forceinline__ int k_riemann(const Phys &p) { return PK ? ((PK - 1) >> 4) & 1 : p.riemann; }
 template <int PK> __device__ __forceinline__ int k_dense(const Phys &p) { return PK ? ((PK - 1) >> 5) & 1 : p.ghost_dense; }
 template <int PK> __host__ __device__ constexpr bool k_multi() { return PK ? ((PK - 1) >> 6) & 1 : true; }
+// compiled point-mass kinds keep each staged cell's potential and excision
+// flag in LDS: every cell's value serves its own and its neighbours' terms
+// (a stored potential is one cached load, not worth the LDS)
+template <int PK> __host__ __device__ constexpr bool k_gcache() { return PK && (((PK - 1) >> 2) & 3) == 2; }
 
 // Where a reader with factor fb finds block nb's conserved state at its stage time.
 struct Src {
@@ -591,7 +595,7 @@ __device__ __forceinline__ void plm_face(double q0, double q1, double q2, double
 template <int NV, int D, int PK = 0>
 __device__ __forceinline__ void face_flux(const StageArgs &a, const BlockInfo &B, int fb, double t, double dtb,
                                           const int *fr, const double *wl, const double *wr, int seedl, int nbo,
-                                          double *Gf) {
+                                          double *Gf, int excl = -1, int excr = -1) {
   constexpr int PN = 1 + D, P1 = 1 + (D + 1) % 3, P2 = 1 + (D + 2) % 3;
   const Phys &p = a.p;
   const MeshDev &m = a.m;
@@ -612,9 +616,9 @@ __device__ __forceinline__ void face_flux(const StageArgs &a, const BlockInfo &B
   }
   if (k_grav<PK>(p) == 2 && p.r_exc > 0.0) {
     int gl[3] = {B.ox + fr[0], B.oy + fr[1], B.oz + fr[2]};
-    const bool eR = excised<PK>(p, m, gl[0], gl[1], gl[2], t);
+    const bool eR = excr >= 0 ? excr != 0 : excised<PK>(p, m, gl[0], gl[1], gl[2], t);
     gl[D] -= 1;
-    const bool eL = excised<PK>(p, m, gl[0], gl[1], gl[2], t);
+    const bool eL = excl >= 0 ? excl != 0 : excised<PK>(p, m, gl[0], gl[1], gl[2], t);
     if (eL != eR) {
       const bool into = eR ? (F[0] >= 0.0) : (F[0] <= 0.0);
       if (!into) {
@@ -667,7 +671,7 @@ __device__ __forceinline__ void face_flux(const StageArgs &a, const BlockInfo &B
 template <int NV, int D, int PK = 0>
 __device__ __forceinline__ void axis_update(const StageArgs &a, const BlockInfo &B, double t, const int *lc,
                                             const double *Flo, const double *Fhi, double rho, double Em, double Ep,
-                                            double *rhs, double &divv, double &emax) {
+                                            double *rhs, double &divv, double &emax, const double *phis = nullptr) {
   constexpr int PN = 1 + D;
   const Phys &p = a.p;
   const MeshDev &m = a.m;
@@ -680,9 +684,9 @@ __device__ __forceinline__ void axis_update(const StageArgs &a, const BlockInfo 
     int im[3] = {lc[0], lc[1], lc[2]}, ip[3] = {lc[0], lc[1], lc[2]};
     im[D] -= 1;
     ip[D] += 1;
-    const double pm = phi_at<PK>(a, B, im[0], im[1], im[2], t);
-    const double p0 = phi_at<PK>(a, B, lc[0], lc[1], lc[2], t);
-    const double pp = phi_at<PK>(a, B, ip[0], ip[1], ip[2], t);
+    const double pm = phis ? phis[0] : phi_at<PK>(a, B, im[0], im[1], im[2], t);
+    const double p0 = phis ? phis[1] : phi_at<PK>(a, B, lc[0], lc[1], lc[2], t);
+    const double pp = phis ? phis[2] : phi_at<PK>(a, B, ip[0], ip[1], ip[2], t);
     rhs[PN] -= rho * (pp - pm) / (2.0 * m.dx[D]);
     rhs[IEN] -= (Fhi[IDN] * (pp - p0) + Flo[IDN] * (p0 - pm)) / (2.0 * m.dx[D]);
   }
@@ -810,7 +814,8 @@ __device__ __forceinline__ void finish_cell(const StageArgs &a, const BlockInfo 
 // ---------------------------------------------------------------------------
 template <int TX, int TY, int TZ, int NV, int D, int NT, int PK>
 __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, double *sW, double *sF, int *sB,
-                                          const int *sJc, double *rhs, double &divv, double &emax) {
+                                          const int *sJc, double *rhs, double &divv, double &emax, double *sPhi,
+                                          unsigned char *sExc) {
   using G = TileGeom<TX, TY, TZ>;
   constexpr int SW = G::TV + G::HALO;  // stride of one variable in sW
   constexpr int TD = D == 0 ? TX : (D == 1 ? TY : TZ);
@@ -844,6 +849,13 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
     for (int v = 0; v < NV; ++v) sW[v * SW + slot] = w[v];
     sW[6 * SW + slot] = q[IEN];
     sB[tid] = (m.bc[D] == 0 || (g[D] >= 0 && g[D] < Nd)) ? nb_ : -1;
+    if constexpr (k_gcache<PK>()) {
+      if (layer == 1 || layer == 2) {  // the cells next to the tile: the only halo the terms need
+        const int l0 = T.to[0] + c[0], l1 = T.to[1] + c[1], l2 = T.to[2] + c[2];
+        sPhi[slot] = phi_at<PK>(a, T.B, l0, l1, l2, T.t);
+        sExc[slot] = excised<PK>(p, m, g[0], g[1], g[2], T.t) ? 1 : 0;
+      }
+    }
   }
   __syncthreads();
   // every face of the tile along D, once
@@ -877,7 +889,10 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
     // block across a block face: a halo cell (layer -1 below, T_D above)
     const int nbo = (fr[D] == 0 || side) ? sB[(side ? sl[2] : sl[1]) - G::TV] : T.b;
     double Gf[7];
-    face_flux<NV, D, PK>(a, T.B, T.fb, T.t, T.dtb, fr, wl, wr, seedl, nbo, Gf);
+    if constexpr (k_gcache<PK>())
+      face_flux<NV, D, PK>(a, T.B, T.fb, T.t, T.dtb, fr, wl, wr, seedl, nbo, Gf, sExc[sl[1]], sExc[sl[2]]);
+    else
+      face_flux<NV, D, PK>(a, T.B, T.fb, T.t, T.dtb, fr, wl, wr, seedl, nbo, Gf);
 #pragma unroll
     for (int v = 0; v < NV; ++v) sF[v * G::NF + f] = Gf[v];
     sF[6 * G::NF + f] = Gf[6];
@@ -901,8 +916,14 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
     cp[D] += 1;
     if (D == 0) emax = fmax(emax, sW[6 * SW + tid]);  // own stage-input E
     const int lc[3] = {T.to[0] + cc[0], T.to[1] + cc[1], T.to[2] + cc[2]};
-    axis_update<NV, D, PK>(a, T.B, T.t, lc, Flo, Fhi, sW[tid], sW[6 * SW + cell_slot<TX, TY, TZ, D>(cm[0], cm[1], cm[2])],
-                       sW[6 * SW + cell_slot<TX, TY, TZ, D>(cp[0], cp[1], cp[2])], rhs, divv, emax);
+    const int sm = cell_slot<TX, TY, TZ, D>(cm[0], cm[1], cm[2]), sp = cell_slot<TX, TY, TZ, D>(cp[0], cp[1], cp[2]);
+    if constexpr (k_gcache<PK>()) {
+      const double phis[3] = {sPhi[sm], sPhi[tid], sPhi[sp]};
+      axis_update<NV, D, PK>(a, T.B, T.t, lc, Flo, Fhi, sW[tid], sW[6 * SW + sm], sW[6 * SW + sp], rhs, divv, emax,
+                             phis);
+    } else {
+      axis_update<NV, D, PK>(a, T.B, T.t, lc, Flo, Fhi, sW[tid], sW[6 * SW + sm], sW[6 * SW + sp], rhs, divv, emax);
+    }
   }
   __syncthreads();
 }
@@ -923,6 +944,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) 
   __shared__ int sB[G::HALO];          // owning block of a halo cell, -1 beyond an outflow edge
   __shared__ int sJc[kChunk];          // table cell of each tile cell's centre state (seeds)
   __shared__ double sRed[NT / 64];     // per-wave CFL minima
+  constexpr int GC = k_gcache<PK>() ? SW : 1;
+  __shared__ double sPhi[GC];          // potential of the staged cells (compiled gravity kinds)
+  __shared__ unsigned char sExc[GC];   // their excision flags
   const Phys &p = a.p;
   const MeshDev &m = a.m;
   const int a0 = a.cnt_ge[a.Lhi + 1], a1 = a.cnt_ge[a.Llo];
@@ -961,6 +985,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) 
 #pragma unroll
       for (int v = 0; v < NV; ++v) sW[v * SW + tid] = w[v];
       sW[6 * SW + tid] = q[IEN];
+      if constexpr (k_gcache<PK>()) {
+        sPhi[tid] = phi_at<PK>(a, T.B, lc[0], lc[1], lc[2], T.t);
+        sExc[tid] = excised<PK>(p, m, T.B.ox + lc[0], T.B.oy + lc[1], T.B.oz + lc[2], T.t) ? 1 : 0;
+      }
     }
     double rhs[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double divv = 0.0, emax = -INFINITY;
@@ -972,9 +1000,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) 
       jcell = a.jc[jseg_in(a, parb) * a.jn + T.B.off / NV + cell];
       sJc[tid] = jcell;
     }
-    tile_axis<TX, TY, TZ, NV, 0, NT, PK>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
-    tile_axis<TX, TY, TZ, NV, 1, NT, PK>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
-    tile_axis<TX, TY, TZ, NV, 2, NT, PK>(a, T, sW, sF, sB, sJc, rhs, divv, emax);
+    tile_axis<TX, TY, TZ, NV, 0, NT, PK>(a, T, sW, sF, sB, sJc, rhs, divv, emax, sPhi, sExc);
+    tile_axis<TX, TY, TZ, NV, 1, NT, PK>(a, T, sW, sF, sB, sJc, rhs, divv, emax, sPhi, sExc);
+    tile_axis<TX, TY, TZ, NV, 2, NT, PK>(a, T, sW, sF, sB, sJc, rhs, divv, emax, sPhi, sExc);
     double cflv = INFINITY;
     if (has_cell) finish_cell<NV, NET, PK>(a, T.B, T.own, parb, T.dtb, tk, lc, cell, jcell, rhs, divv, emax, &cflv);
     if (a.cfl_part && a.phase == 2) {  // the tile's CFL minimum for the next reduction
