@@ -90,7 +90,7 @@ typedef struct {
                      In modes 1 and 3 a pass finds the cells once after a state
                      upload (with the network in mode 1).  In modes 2 and 4 the
                      CFL reduction (tdh_reduce_dt) records the cells of the state
-                     it reduces over (its bisection for c_s finds them), and the
+                     it reduces over (its search for c_s finds them), and the
                      next window's first stage runs without a pass. */
   int newton_max_iter; /* seeded secant steps before falling back to bisection (>= 0) */
   int riemann;    /* 0 HLLC (Toro Sec. 10.4); 1 HLLE, the solver of the paper's production

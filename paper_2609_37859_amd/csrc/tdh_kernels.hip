@@ -1318,9 +1318,9 @@ __global__ void reflux_kernel(StageArgs a, int lc, int dir, int nmax) {
 // CFL step: per-item minimum, then per-block minimum
 // ---------------------------------------------------------------------------
 
-// In modes 2 and 4 (table EOS) the pass also records each cell's table cell
-// (found by bisection) in its block's current segment: the seeds of the
-// window's first stage, so no seed pass runs before it.
+// In modes 2 and 4 (table EOS) the pass also records each cell's table cell in
+// its block's current segment: the seeds of the window's first stage, so no
+// seed pass runs before it.
 template <int NV>
 __global__ __launch_bounds__(kChunk) void cfl_items_kernel(StageArgs a, double t, const int *item_block,
                                                            const int *block_item_start, int nitems, double *part) {
@@ -1343,10 +1343,14 @@ __global__ __launch_bounds__(kChunk) void cfl_items_kernel(StageArgs a, double t
 #pragma unroll
     for (int v = 0; v < NV; ++v) q[v] = Q[B.off + v * n3 + cq];
     c2p(p, q, w);
+    // the search starts from the cell the state's segment holds (carried, or
+    // left by an earlier state of the block; -1 where none: bisection)
+    const long long js = (long long)parb * a.jn + B.off / nv + cq;
+    const int start = (p.eos_kind == 1 && p.inv_mode != 0 && a.jc) ? a.jc[js] : -1;
     double P, cs;
     int j = -1;
-    eos_pc(p, a.t, w[0], w[4], -1, P, cs, &j);
-    if (rec && inside) a.jc[(long long)parb * a.jn + B.off / nv + cell] = j;
+    eos_pc(p, a.t, w[0], w[4], start, P, cs, &j);
+    if (rec && inside) a.jc[js] = j;
     double best = INFINITY;
     const int ci = (int)(cq % n), cj = (int)((cq / n) % n), ck = (int)(cq / ((long long)n * n));
     const bool exc = p.grav_kind == 2 && p.r_exc > 0.0 && excised(p, m, B.ox + ci, B.oy + cj, B.oz + ck, t);
