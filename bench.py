@@ -9,12 +9,14 @@ minimum, global minimum, level assignment) and one RK2 step of every block
 energy update), inputs resident in HBM.
 
 Prints one JSON line.  `value` is the cell-updates/s of the learned form:
-one launch per RK phase for all levels; before each stage a pass finds the
-table cell of every cell's state by a search started from the learned
+one launch per RK phase for all levels; before the second stage a pass finds
+the table cell of every cell's state by a search started from the learned
 network's prediction (the network runs on the matrix cores; it is trained
 first on the GPU by the library's own kernels, training time reported, not
 timed), and that cell seeds the stage's face and compression queries of the
-cell.  Beside it: the same with the network inside the stage kernel, seeding
+cell; the first stage takes the cells the previous step's second stage (or
+the CFL reduction) recorded, and after a step the reduction reduces the CFL
+minima that step's second stage left.  Beside it: the same with the network inside the stage kernel, seeding
 the next stage from the output states (learned_inkernel), the temporal form
 (searches start from the input state's cell), the chained form (the pass
 bisects), the plain form (bisection for every query, one launch per level)
