@@ -77,16 +77,17 @@ def counters_from_profiles(workload, family="stage"):
 
 
 FORMS = {
-    "learned": "batched launches; before each stage a pass finds the table cell of every cell's state by a "
-               "search started from the learned network's prediction; it seeds the cell's face and "
-               "compression queries",
+    "learned": "batched launches; before the second stage a pass finds the table cell of every cell's state by "
+               "a search started from the learned network's prediction; it seeds the cell's face and "
+               "compression queries (the first stage takes the cells the last second stage recorded)",
     "learned_inkernel": "batched launches; each stage finds the table cells of its output states by searches "
                         "started from the learned network's prediction inside the stage kernel; they seed the "
                         "next stage's face and compression queries",
     "temporal": "batched launches; each stage finds the table cells of its output states by searches started "
                 "from its input states' cells; they seed the next stage's queries",
-    "chained": "batched launches; before each stage the table cell of every cell's state is bisected; it seeds "
-               "the cell's face and compression queries",
+    "chained": "batched launches; before the second stage the table cell of every cell's state is bisected; it "
+               "seeds the cell's face and compression queries (the first stage takes the cells the last second "
+               "stage recorded)",
     "plain": "one launch per level; bisection for every table query",
     "learned_hlle": "the learned form with the HLLE Riemann solver of the paper's production runs",
 }
