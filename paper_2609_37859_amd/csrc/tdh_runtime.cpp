@@ -1231,7 +1231,8 @@ extern "C" tdh_status tdh_autotune(tdh_ctx *c, int reps, int *host_best, float *
   if ((s = install_levels(c, std::vector<int>(c->nb, 0)))) return s;
   HIPCHK(c, launch_set_window(c->d_win, c->t, c->dt_coarse > 0.0 ? c->dt_coarse : 1e-30, c->stream));
   StageArgs a = base_args(c);
-  a.lmax = saved_lmax;  // time the kernel the current levels' windows run
+  // time the kernel the run's windows will use: with levels when LAT is configured
+  a.lmax = std::max(saved_lmax, c->cfg.n_lat > 0 ? 1 : 0);
   a.cfl_part = nullptr;
   a.k = 0;
   a.phase = 1;
