@@ -189,7 +189,7 @@ def run_lat(T, W, cfg, mesh, U, windows, warmup, inv_mode=0, batched=True, graph
     if seed_params is not None:
         ctx.mlp_init(seed_params, W.seed_ranges(table))
         ctx.mlp_enable_seed(True)
-    ctx.autotune(reps=1)
+    ctx.autotune(reps=3)
     for _ in range(warmup):
         _, dt0, lev, L = ctx.reduce_dt()
         ctx.run_window(dt0 * 2 ** L, batched=batched, graph=graph)
