@@ -1,44 +1,41 @@
 #!/usr/bin/env python3
 """Benchmark of the MeshBlock hydro update on one MI355X.
 
-Workload: a 128^3 periodic domain as 64 MeshBlocks of 32^3 cells with the
-Saha H/He table EOS and dual energy (cold Mach-1e7 Gaussian stream), FP64.
-One step = one pass of the whole hot path: the CFL reduction (per-block
-minimum, global minimum, level assignment) and one RK2 step of every block
-(two stage launches with PLM, table EOS inversion, HLLC, divergence, dual
-energy update), inputs resident in HBM.
+Headline workload: the production-shaped run, 4096 MeshBlocks (1688 x 32^3 +
+2408 x 16^3, 65.2 M cells, FP64) with the Saha H/He table EOS, dual energy, a
+moving 1e3 Msun point mass with excision, and localized adaptive time stepping
+over four levels (N_LAT = 3, sparse top bins merged below 1 % of the blocks).
+One step = one LAT window, one pass of the whole hot path: the CFL reduction
+(per-block steps, global minimum, level assignment with merge and neighbour
+limit) and the window's 2^Lmax sub-cycles of RK2 stages (PLM, seeded table
+inversion, HLLC, divergence, gravity, dual-energy update, excision), the
+delayed flux corrections and the level bookkeeping, inputs resident in HBM.
 
-Prints one JSON line.  `value` is the cell-updates/s of the learned form:
-one launch per RK phase for all levels; before the second stage a pass finds
-the table cell of every cell's state by a search started from the learned
-network's prediction (the network runs on the matrix cores; it is trained
-first on the GPU by the library's own kernels, training time reported, not
-timed), and that cell seeds the stage's face and compression queries of the
-cell; the first stage takes the cells the previous step's second stage (or
-the CFL reduction) recorded, and after a step the reduction reduces the CFL
-minima that step's second stage left.  Beside it: the same with the network inside the stage kernel, seeding
-the next stage from the output states (learned_inkernel), the temporal form
-(searches start from the input state's cell), the chained form (the pass
-bisects), the plain form (bisection for every query, one launch per level)
-and the learned form with the HLLE solver; all but the last give
-bit-identical states.  Each form runs --warmup steps, then --repeats timed
-runs of exactly --steps steps each (the state evolving on); its rate is that
-of the median run.  The roofline
-entry is for the stage kernel (HIP events on the library's stream); the CPU
-baseline is the FP64 oracle on the host, on a bounded number of steps of the
-same workload, and its final state doubles as the accuracy check of the GPU
-run.
+Prints one JSON line.  `value` is the cell-updates/s of the learned form: all
+active levels in one launch per RK phase, the window replayed from a captured
+hipGraph, and before each stage but a window's first a pass that finds the
+table cell of every active cell's state by a search started from the learned
+network's prediction (the network is trained first on the GPU by the
+library's own kernels; training time reported, not timed).  Beside it: the
+plain form (one launch per level, bisection for every table query, no graph).
+Both give the same bits.  Each form runs --warmup windows, then --repeats
+timed runs of exactly --steps windows; its rate is that of the median run,
+from the library's own update counters.  The roofline entry is the stage
+kernel of the learned form: after the timed runs the same form runs --steps
+windows once more without graph replay, every stage launch bracketed by HIP
+events on the library's stream; 240 algorithmic bytes per cell-update over the
+summed launch time.  The CPU baseline is the FP64 oracle on the host on the
+512-block sub-domain of the same run (5.3 M cells) over two windows, with its
+own CFL steps and levels (single-thread rate on the first window beside it);
+the GPU headline form runs the same two windows from the same initial state,
+and the two end states give max_rel_err_vs_oracle.
 
-The "lat" object times whole LAT windows (CFL reduction, level assignment,
-2^Lmax sub-cycles) on the full-size polytrope (ideal gas, fixed potential) and
-on the production-shaped mesh (4096 mixed 16^3/32^3 blocks, table EOS, point
-mass): the batched forms (one launch per RK phase for all active levels,
-window captured in a hipGraph) beside the plain form (one launch per level).
-It reports cell-updates/s from the library's update counters and the
-sync-equivalent rate (cells x 2^Lmax per window over the time), which shows
-the work LAT saves.  The "gravity" object times the self-gravity multigrid on
-the 256^3 Jeans wave (V-cycles and the solve-every-step coupled update), the
-"remap" object the restart remap of the 128^3 stream onto a 256^3 grid.
+Secondary objects: "c2" times the 128^3 table-EOS stream (64 x 32^3, single
+level) in six inversion forms with its own stage-kernel roofline, "lat" the
+256^3 polytrope (ideal gas, fixed potential, LAT) batched beside per-level,
+"learned_seed" the network's training and evaluation, "gravity" the
+self-gravity multigrid on the 256^3 Jeans wave, "remap" the restart remap of
+the 128^3 stream onto 256^3.
 """
 import argparse
 import dataclasses
@@ -218,30 +215,223 @@ def run_lat(T, W, cfg, mesh, U, windows, warmup, inv_mode=0, batched=True, graph
             "levels": [int(v) for v in np.trim_zeros(hist, "b")], "tile": tile}
 
 
-def lat_section(T, W, table, seed_params, windows, warmup):
-    """LAT-batched forms beside the plain per-level form on the two LAT workloads."""
-    out = {}
+def lat_section(T, W, windows, warmup):
+    """The polytrope (ideal gas, fixed potential, LAT): batched launches replayed
+    from a graph beside one launch per level."""
     cfg, mesh, U, phi, info = W.polytrope_c3()
     cfg = dataclasses.replace(cfg, merge_frac=0.01)  # performance runs merge sparse top bins
-    out["polytrope"] = {
+    return {
         "workload": "256^3 as 512 MeshBlocks of 32^3, n=1.5 polytrope (1 Msun, 1 Rsun) in a 1e-10 atmosphere, fixed "
                     "potential, ideal gas, N_LAT=3, merge_frac 0.01, outflow",
         "batched_graph": run_lat(T, W, cfg, mesh, U, windows, warmup, batched=True, graph=True, phi=phi),
         "plain": run_lat(T, W, cfg, mesh, U, windows, warmup, batched=False, graph=False, phi=phi)}
+
+
+C5_WORKLOAD = ("production-shaped: 4096 MeshBlocks (1688 x 32^3 + 2408 x 16^3, 65.2M cells), Saha H/He table EOS "
+               "256x256, dual energy, 1e3 Msun point mass with excision in a moving frame, debris stream, LAT "
+               "N_LAT=3, merge_frac 0.01, CFL 0.3, outflow")
+
+C5_FORMS = {
+    "learned": "LAT-batched (all active levels in one launch per RK phase, window replayed from a hipGraph); "
+               "before each stage but a window's first, a pass finds every active cell's table cell by a search "
+               "started from the learned network's prediction (the window's first stage takes the cells the CFL "
+               "reduction found); the cell seeds the cell's face and compression queries",
+    "plain": "one launch per level per RK phase, no graph; bisection for every table query",
+}
+
+
+def _timed_windows(ctx, windows, graph, batched=True):
+    """`windows` LAT windows (CFL reduction, level assignment, window), timed
+    end to end; returns (seconds, cell updates, block updates, sync-equivalent
+    cell updates, level histogram)."""
+    import torch
+    st0 = ctx.stats()
+    sync_equiv = 0
+    hist = np.zeros(8, dtype=np.int64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(windows):
+        _, dt0, lev, L = ctx.reduce_dt()
+        ctx.run_window(dt0 * 2 ** L, batched=batched, graph=graph)
+        sync_equiv += ctx.mesh.ncells * 2 ** L
+        h = np.bincount(lev)
+        hist[:len(h)] += h
+    ctx.sync()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st1 = ctx.stats()
+    return (el, st1["cell_updates"] - st0["cell_updates"], st1["block_updates"] - st0["block_updates"], sync_equiv,
+            hist)
+
+
+def c5_section(T, W, table, params, forms, windows, warmup, repeats, tile):
+    """The headline: the production-shaped LAT workload in the learned and the
+    plain form.  Returns {form: result}; the learned form adds the stage
+    kernel's launch timing from a pass of `windows` windows without graph
+    replay (HIP events around every stage launch)."""
     cfg, mesh, U = W.debris_stream_c5(table)
     cfg = dataclasses.replace(cfg, merge_frac=0.01)
-    out["production"] = {
-        "workload": "4096 MeshBlocks (1688 x 32^3 + 2408 x 16^3, 65.2M cells), Saha table EOS, dual energy, "
-                    "1e3 Msun point mass with excision in a moving frame, debris stream, N_LAT=3, merge_frac 0.01",
-        "learned": run_lat(T, W, cfg, mesh, U, windows, warmup, inv_mode=4, batched=True, graph=True, table=table,
-                           seed_params=seed_params),
-        "temporal": run_lat(T, W, cfg, mesh, U, windows, warmup, inv_mode=3, batched=True, graph=True,
-                            table=table),
-        "learned_dense_ghosts": run_lat(T, W, dataclasses.replace(cfg, ghost_dense=1), mesh, U, windows, warmup,
-                                        inv_mode=4, batched=True, graph=True, table=table, seed_params=seed_params),
-        "plain": run_lat(T, W, cfg, mesh, U, windows, warmup, inv_mode=0, batched=False, graph=False,
-                         table=table)}
+    out = {}
+    for name, mode, batched, graph in (("learned", 4, True, True), ("plain", 0, False, False)):
+        if name not in forms:
+            continue
+        ctx = T.Context(cfg, mesh, U, table=table, inv_mode=mode)
+        if mode == 4:
+            ctx.mlp_init(params, W.seed_ranges(table))
+            ctx.mlp_enable_seed(True)
+        if tile >= 0:
+            ctx.set_tile(tile)
+        else:
+            ctx.autotune(reps=3)
+        for _ in range(warmup):
+            _, dt0, lev, L = ctx.reduce_dt()
+            ctx.run_window(dt0 * 2 ** L, batched=batched, graph=graph)
+        ctx.sync()
+        runs = sorted((_timed_windows(ctx, windows, graph, batched) for _ in range(repeats)), key=lambda r: r[0])
+        el, cu, bu, se, hist = runs[len(runs) // 2]
+        r = {"value": cu / el, "ms_per_window": 1e3 * el / windows, "windows": windows, "repeats": repeats,
+             "sync_equivalent": se / el, "block_updates": int(bu),
+             "block_updates_sync": int(se // mesh.ncells * mesh.nblocks),
+             "levels": [int(v) for v in np.trim_zeros(hist, "b")], "tile": T.tile_shapes()[ctx.get_tile()],
+             "form": C5_FORMS[name]}
+        if name == "learned":
+            ctx.set_timing(True)
+            el2, cu2, _, _, _ = _timed_windows(ctx, windows, graph=False, batched=batched)
+            stage_ms, launches = ctx.stage_time()
+            r["timing_pass"] = {"windows": windows, "cell_updates": int(cu2), "stage_kernel_ms": stage_ms,
+                                "stage_launches": int(launches), "ms_per_window": 1e3 * el2 / windows}
+        ctx.close()
+        out[name] = r
     return out
+
+
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def c5_oracle_section(T, W, table, params, windows=2, single_thread=True, tile=-1):
+    """The 512-block sub-domain of the production-shaped run: the oracle over
+    `windows` windows with its own CFL steps and levels (timed on the host's
+    threads; the first window again on one thread), and the GPU headline form
+    over the same windows from the same initial state.  Returns (cpu_baseline,
+    accuracy dict)."""
+    import oracle
+    from tests.parity import rel_err
+    cfg, mesh, U = W.debris_stream_c5(table, box=W.C5_SUBDOMAIN_512)
+    cfg = dataclasses.replace(cfg, merge_frac=0.01)
+    t0 = time.perf_counter()
+    o, info, bu, cu = oracle.run_lat(cfg, mesh, U, windows, table=table)
+    cpu_s = time.perf_counter() - t0
+    cpu = {"value": cu / cpu_s, "unit": "cell-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"{windows} LAT windows of the 512-block sub-domain of the production-shaped run "
+                     f"({mesh.ncells} cells: 112 x 32^3 + 400 x 16^3; {cu} cell-updates, {bu} block updates), "
+                     f"own CFL steps and levels, {cpu_s:.1f} s",
+           "host_cpu": host_cpu_model()}
+    if single_thread:
+        with oracle.threads(1):
+            t1 = time.perf_counter()
+            _, _, _, cu1 = oracle.run_lat(cfg, mesh, U, 1, table=table)
+            s1 = time.perf_counter() - t1
+        cpu["single_thread"] = {"value": cu1 / s1, "cores": 1, "sample": f"the first window ({cu1} cell-updates), "
+                                                                         f"{s1:.1f} s"}
+    ctx = T.Context(cfg, mesh, U, table=table, inv_mode=4)
+    ctx.mlp_init(params, W.seed_ranges(table))
+    ctx.mlp_enable_seed(True)
+    if tile >= 0:
+        ctx.set_tile(tile)
+    else:
+        ctx.autotune(reps=2)
+    lev_equal = True
+    dt_rel = 0.0
+    for w in range(windows):
+        _, dt0, lev, L = ctx.reduce_dt()
+        lev_o, L_o, dt0_o, _ = info[w]
+        lev_equal &= bool(np.array_equal(lev, lev_o)) and L == L_o
+        dt_rel = max(dt_rel, abs(dt0 / dt0_o - 1))
+        ctx.run_window(dt0 * 2 ** L, batched=True, graph=True)
+    g = ctx.get_state()
+    ctx.close()
+    stencil = rel_err(cfg.nv, mesh, g, o, stencil=True)
+    strict = rel_err(cfg.nv, mesh, g, o, stencil=False)
+    acc = {"max_rel_err_vs_oracle": float(np.max(stencil)), "max_rel_err_vs_oracle_strict": float(np.max(strict)),
+           "per_variable_stencil": [float(v) for v in stencil], "per_variable_strict": [float(v) for v in strict],
+           "levels_bit_exact": lev_equal, "max_dt0_rel_diff": dt_rel,
+           "case": f"512-block sub-domain, {windows} windows, learned form (mode 4, network, batched, graph)"}
+    return cpu, acc
+
+
+def _query_eval(ctx, lr, le, reps=5):
+    """Seeded (network start) against table-only inversion of device queries:
+    |dlogT| percentiles of the network's prediction, secant-step histogram,
+    bisection fallback rate, time per query of each (same cells, checked)."""
+    import torch
+    n = lr.numel()
+    l0, j0, _ = ctx.eos_invert(lr, le, mode=0)
+    err = (ctx.mlp_forward(torch.stack([lr, le], 1)) - l0).abs().cpu().numpy()
+    q = {f"p{p}": float(np.percentile(err, p)) for p in (50, 90, 99, 99.99)}
+    q["max"] = float(err.max())
+    ns = {}
+    for mode in (0, 1):
+        ctx.eos_invert(lr, le, mode=mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = ctx.eos_invert(lr, le, mode=mode)
+        torch.cuda.synchronize()
+        ns[mode] = 1e9 * (time.perf_counter() - t0) / (reps * n)
+    l1, j1, it1 = out
+    if not (torch.equal(j0, j1) and torch.equal(l0, l1)):
+        raise SystemExit("seeded inversion differs from the table-only one")
+    hist = np.bincount(it1.cpu().numpy().astype(np.int64) + 1)
+    q.update({"queries": n, "secant_steps_histogram": {str(k - 1): int(v) for k, v in enumerate(hist) if v},
+              "bisection_fallback_rate": float(hist[0]) / n, "ns_per_query_table_only": ns[0],
+              "ns_per_query_seeded": ns[1], "seeded_over_table_only": ns[1] / ns[0]})
+    return q
+
+
+def seed_eval_section(T, W, table, params, windows=2):
+    """Where the learned seed is evaluated beyond its training distribution:
+    (1) every cell state of the polytrope run with the Saha table (the n = 1.5
+    star of the LAT workload with the table EOS, initial internal energy from
+    the Saha temperature at the polytrope's pressure), taken after each of
+    `windows` LAT windows, as inversion queries; (2) a table of the paper's
+    size (640 x 640 nodes over the same ranges), with a network trained on it
+    by the same recipe, on 2^24 queries of its training distribution."""
+    import torch
+    cfg, mesh, U, phi, _ = W.polytrope_c3_saha(table)
+    ctx = T.Context(cfg, mesh, U, phi=phi, table=table, inv_mode=4)
+    ctx.mlp_init(params, W.seed_ranges(table))
+    ctx.mlp_enable_seed(True)
+    lrs, les = [], []
+    for _ in range(windows):
+        _, dt0, lev, L = ctx.reduce_dt()
+        ctx.run_window(dt0 * 2 ** L, batched=True, graph=True)
+        g = torch.from_numpy(ctx.get_state()).cuda()
+        off = mesh.offsets(cfg.nv)
+        for b in range(mesh.nblocks):
+            n3 = int(mesh.blk[b, 0]) ** 3
+            blk = g[off[b]:off[b + 1]].view(cfg.nv, n3)
+            rho = blk[0]
+            ke = 0.5 * (blk[1] ** 2 + blk[2] ** 2 + blk[3] ** 2) / rho
+            u = torch.clamp(blk[4] - ke, min=rho * table.e_floor)
+            lrs.append(torch.log10(rho))
+            les.append(torch.log10(u / rho))
+    poly = _query_eval(ctx, torch.cat(lrs).contiguous(), torch.cat(les).contiguous())
+    poly["case"] = (f"every cell state (log rho, log e) of the 256^3 polytrope run with the Saha table after each of "
+                    f"{windows} LAT windows (learned form)")
+    ctx.close()
+    big = W.saha_table(nrho=640, nT=640)
+    p2, secs, loss, q2 = train_seed(T, W, big)
+    q2.update({"case": "640 x 640 Saha table (the paper's table size), network trained on it (2000 Adam steps, "
+                       "batch 4096, 2^20 samples), 2^24 queries of the training distribution",
+               "train_seconds": secs, "final_loss": loss})
+    return {"polytrope_saha": poly, "table_640": q2}
 
 
 def mg_bytes_per_cycle(levels):
@@ -343,27 +533,85 @@ def remap_section(T, W, table, reps):
                          "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes": nbytes}}
 
 
+def c2_section(T, W, table, params, forms, steps, warmup, repeats, tile, cpu_steps):
+    """The 128^3 table-EOS stream in six inversion forms (single level, one
+    step = CFL reduction + RK2 step), with the stage kernel's roofline, and its
+    accuracy check against the oracle (each side with its own CFL steps)."""
+    cfg, mesh, U = W.stream_c2(table)
+    ncell, nv = mesh.ncells, cfg.nv
+    res = {}
+    for name, mode, batched, riemann in (("learned", 4, True, 0), ("temporal", 3, True, 0), ("chained", 2, True, 0),
+                                         ("plain", 0, False, 0), ("learned_hlle", 4, True, 1),
+                                         ("learned_inkernel", 1, True, 0)):
+        if name in forms:
+            res[name] = run_form(T, W, cfg, mesh, U, table, steps, warmup, inv_mode=mode, batched=batched,
+                                 seed_params=params if mode in (1, 4) else None, tile=tile, riemann=riemann,
+                                 repeats=repeats)
+    if not res:
+        return None
+    head = "learned" if "learned" in res else next(iter(res))
+    el, stage_ms, launches, st, _ = res[head]
+
+    def rate(name):
+        return ncell * steps / res[name][0] if name in res else None
+
+    # stage 1 reads Q^n and writes Q^(1), stage 2 reads Q^n and Q^(1) and writes
+    # Q^(n+1): 5 nv doubles per cell and step, two launches per step
+    launch_ms = stage_ms / max(launches, 1)
+    achieved = 0.5 * 5 * nv * 8 * ncell / (launch_ms * 1e-3) / 1e9
+    prof = counters_from_profiles("c2")
+    out = {"workload": "128^3 periodic as 64 MeshBlocks of 32^3, Saha H/He table EOS 256x256, dual energy, cold "
+                       "Mach-1e7 Gaussian stream, CFL 0.3, single level", "cells": ncell,
+           "forms": {k: {"value": rate(k), "ms_per_step": 1e3 * v[0] / steps, "form": FORMS[k],
+                         "stage_kernel_ms": v[1] / max(v[2], 1), "tile": T.tile_shapes()[v[4]]}
+                     for k, v in res.items()},
+           "speedup_vs_plain": rate(head) / rate("plain") if "plain" in res else None,
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": prof.get("hbm_bytes_per_launch"),
+                        "kernel": "stage_tiled", "avg_launch_ms": launch_ms,
+                        "algorithmic_bytes_per_launch": 0.5 * 5 * nv * 8 * ncell}}
+    if cpu_steps > 0:
+        import oracle
+        from tests.parity import rel_err
+        ctx = T.Context(cfg, mesh, U, table=table, inv_mode=4)
+        ctx.mlp_init(params, W.seed_ranges(table))
+        ctx.mlp_enable_seed(True)
+        T.run_sync_steps(ctx, cpu_steps)
+        g = ctx.get_state()
+        ctx.close()
+        t0 = time.perf_counter()
+        o, _ = oracle.run_sync(cfg, mesh, U, cpu_steps, table=table)
+        cpu_s = time.perf_counter() - t0
+        out["max_rel_err_vs_oracle"] = float(np.max(rel_err(nv, mesh, g, o, stencil=False)))
+        out["oracle"] = {"value": ncell * cpu_steps / cpu_s, "cores": oracle.num_threads(),
+                         "sample": f"{cpu_steps} RK2 steps of the full 128^3 workload (own CFL steps), {cpu_s:.1f} s"}
+    return out
+
+
+SECTIONS = "c5,c5_oracle,c2,lat,seed_eval,gravity,remap"
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=20, help="timed LAT windows per run of the headline forms "
+                                                          "(timed steps per run of the c2 forms)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--repeats", type=int, default=3,
-                    help="timed runs of --steps steps per form; each form reports the median run")
-    ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps for the CPU baseline / accuracy check")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="learned,temporal,chained,plain,learned_hlle,learned_inkernel",
-                    help="comma list of forms to time: learned, temporal, chained, plain, learned_hlle, "
-                         "learned_inkernel (learned is the headline when present)")
+                    help="timed runs of --steps windows per form; each form reports the median run")
+    ap.add_argument("--sections", default=SECTIONS, help=f"comma list out of {SECTIONS}")
+    ap.add_argument("--forms", default="learned,plain,temporal,chained,learned_hlle,learned_inkernel",
+                    help="forms to time (headline: learned, plain; c2 also: temporal, chained, learned_hlle, "
+                         "learned_inkernel)")
     ap.add_argument("--tile", type=int, default=-1,
                     help="stage-kernel variant id to use instead of autotuning (profiling runs fix it)")
-    ap.add_argument("--lat-windows", type=int, default=5,
-                    help="timed LAT windows per form on the polytrope and production-shaped workloads (0: skip)")
-    ap.add_argument("--gravity-cycles", type=int, default=10,
-                    help="timed multigrid V-cycles on the 256^3 Jeans wave (0: skip the self-gravity section)")
-    ap.add_argument("--gravity-steps", type=int, default=10,
-                    help="timed coupled steps (solve + RK2 step) on the 256^3 Jeans wave (0: skip them)")
-    ap.add_argument("--remap-reps", type=int, default=5, help="timed restart remaps (0: skip the remap section)")
+    ap.add_argument("--oracle-windows", type=int, default=2, help="windows of the oracle on the 512-block sub-domain")
+    ap.add_argument("--no-single-thread", action="store_true", help="skip the single-thread oracle window")
+    ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps of the c2 accuracy check (0: skip)")
+    ap.add_argument("--lat-windows", type=int, default=5, help="timed windows per form on the polytrope")
+    ap.add_argument("--gravity-cycles", type=int, default=10, help="timed multigrid V-cycles on the 256^3 Jeans wave")
+    ap.add_argument("--gravity-steps", type=int, default=10, help="timed coupled steps on the 256^3 Jeans wave")
+    ap.add_argument("--remap-reps", type=int, default=5, help="timed restart remaps")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -386,66 +634,48 @@ def main():
     from paper_2609_37859_amd import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     T.lib()
+    sections = set(args.sections.split(","))
+    forms = args.forms.split(",")
+
+    def note(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     table = W.saha_table()
-    cfg, mesh, U = W.stream_c2(table)
-    ncell = mesh.ncells
-    nv = cfg.nv
-
-    # accuracy check and CPU baseline on the same bounded sample
-    acc = None
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        from tests.parity import rel_err
-        ctx = T.Context(cfg, mesh, U, table=table, inv_mode=2)
-        dts = T.run_sync_steps(ctx, args.cpu_steps)
-        g = ctx.get_state()
-        ctx.close()
-        t0 = time.perf_counter()
-        o, _ = oracle.run_sync(cfg, mesh, U, args.cpu_steps, table=table, dts=dts)
-        cpu_s = time.perf_counter() - t0
-        acc = float(np.max(rel_err(nv, mesh, g, o)))
-        cpu = {"value": ncell * args.cpu_steps / cpu_s, "unit": "cell-updates/s", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": f"{args.cpu_steps} RK2 steps of the full 128^3 workload (GPU step sizes), {cpu_s:.1f} s"}
-
-    forms = args.forms.split(",")
     params, train_s, train_loss, seed_err = train_seed(T, W, table)
-    res = {}
-    for name, mode, batched, riemann in (("learned", 4, True, 0), ("temporal", 3, True, 0), ("chained", 2, True, 0),
-                                         ("plain", 0, False, 0), ("learned_hlle", 4, True, 1),
-                                         ("learned_inkernel", 1, True, 0)):
-        if name in forms:
-            res[name] = run_form(T, W, cfg, mesh, U, table, args.steps, args.warmup, inv_mode=mode, batched=batched,
-                                 seed_params=params if mode in (1, 4) else None, tile=args.tile, riemann=riemann,
-                                 repeats=args.repeats)
-    lat = lat_section(T, W, table, params, args.lat_windows, 1) if args.lat_windows > 0 else None
-    grav = gravity_section(T, W, args.gravity_cycles, args.gravity_steps) if args.gravity_cycles > 0 else None
-    remap = remap_section(T, W, table, args.remap_reps) if args.remap_reps > 0 else None
-    head = "learned" if "learned" in res else next(iter(res))
-    el, stage_ms, launches, st, tile = res[head]
+    note(f"network trained in {train_s:.2f} s")
+    c5 = c5_section(T, W, table, params, forms, args.steps, args.warmup, args.repeats, args.tile) \
+        if "c5" in sections else {}
+    note("headline forms timed")
+    cpu, acc = (c5_oracle_section(T, W, table, params, args.oracle_windows, not args.no_single_thread, args.tile)
+                if "c5_oracle" in sections else (None, None))
+    note("oracle sub-domain done")
+    c2 = c2_section(T, W, table, params, forms, args.steps, args.warmup, args.repeats, args.tile, args.cpu_steps) \
+        if "c2" in sections else None
+    lat = lat_section(T, W, args.lat_windows, 1) if "lat" in sections and args.lat_windows > 0 else None
+    seed_eval = seed_eval_section(T, W, table, params) if "seed_eval" in sections else None
+    grav = gravity_section(T, W, args.gravity_cycles, args.gravity_steps) \
+        if "gravity" in sections and args.gravity_cycles > 0 else None
+    remap = remap_section(T, W, table, args.remap_reps) if "remap" in sections and args.remap_reps > 0 else None
 
-    def rate(name):
-        return ncell * args.steps / res[name][0] if name in res else None
-
-    value = rate(head)
-    plain = rate("plain")
-    # algorithmic HBM bytes of the stage kernel: stage 1 reads Q^n and writes Q^(1),
-    # stage 2 reads Q^n and Q^(1) and writes Q^(n+1): 5 nv doubles per cell and step
-    bytes_per_step = 5 * nv * 8 * ncell
-    # per launch (two launches per step on this single-level workload) over the
-    # average launch duration of every timed run
-    launch_ms = stage_ms / max(launches, 1)
-    achieved = 0.5 * bytes_per_step / (launch_ms * 1e-3) / 1e9
-    prof = counters_from_profiles("c2")
-    traffic = prof.get("hbm_bytes_per_launch")
-    valu = prof.get("sq", {}).get("SQ_INSTS_VALU")
-    valu_issue = None
-    if valu:
-        issue = valu / (launch_ms * 1e-3)
-        valu_issue = {"wave_insts_per_launch": valu, "achieved": issue, "peak": VALU_PEAK_WAVE_INSTS,
-                      "unit": "wave64 VALU instructions/s", "frac": issue / VALU_PEAK_WAVE_INSTS}
+    head = c5.get("learned")
+    plain = c5.get("plain")
+    roof = None
+    if head and "timing_pass" in head:
+        tp = head["timing_pass"]
+        bpc = 5 * 6 * 8  # stage 1 reads Q^n, writes Q^(1); stage 2 reads both, writes Q^(n+1): 5 nv doubles
+        launch_ms = tp["stage_kernel_ms"] / max(tp["stage_launches"], 1)
+        alg_per_launch = bpc * tp["cell_updates"] / max(tp["stage_launches"], 1)
+        achieved = alg_per_launch / (launch_ms * 1e-3) / 1e9
+        prof = counters_from_profiles("c5")
+        valu = prof.get("sq", {}).get("SQ_INSTS_VALU")
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": prof.get("hbm_bytes_per_launch"),
+                "kernel": "stage_tiled", "avg_launch_ms": launch_ms, "launches": tp["stage_launches"],
+                "algorithmic_bytes_per_launch": alg_per_launch, "algorithmic_bytes_per_cell_update": bpc,
+                "valu_issue": ({"wave_insts_per_launch": valu, "achieved": valu / (launch_ms * 1e-3),
+                                "peak": VALU_PEAK_WAVE_INSTS, "unit": "wave64 VALU instructions/s",
+                                "frac": valu / (launch_ms * 1e-3) / VALU_PEAK_WAVE_INSTS} if valu else None)}
+    value = head["value"] if head else None
     out = {
         "metric": "FP64 cell-updates/s (LAT-batched+MLP-EOS vs plain) at <=1e-11 rel err; % HBM roof",
         "value": value,
@@ -454,29 +684,24 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "repeats": args.repeats,
-        "ms_per_step": 1e3 * el / args.steps,
+        "ms_per_step": head["ms_per_window"] if head else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "c2: 128^3 periodic as 64 MeshBlocks of 32^3, Saha H/He table EOS 256x256, dual "
-                               "energy, cold Mach-1e7 Gaussian stream, CFL 0.3", "cells": ncell, "nv": nv,
-                   "form": FORMS[head],
-                   "tile": T.tile_shapes()[tile]},
-        "forms": {k: {"value": rate(k), "ms_per_step": 1e3 * v[0] / args.steps, "form": FORMS[k],
-                      "stage_kernel_ms": v[1] / max(v[2], 1), "tile": T.tile_shapes()[v[4]]} for k, v in res.items()},
-        "speedup_vs_plain": (value / plain) if plain else None,
-        "learned_seed": {"train_steps": 2000, "batch": 4096, "samples": 1 << 20, "train_seconds": train_s,
-                         "final_loss": train_loss, "evaluation": seed_err},
-        "max_rel_err_vs_oracle": acc,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic,
-                     "kernel": "stage_tiled", "avg_launch_ms": launch_ms,
-                     "algorithmic_bytes_per_cell_update": 5 * nv * 8,
-                     "valu_issue": valu_issue},
+        "config": {"workload": C5_WORKLOAD, "step": "one LAT window (CFL reduction, level assignment, 2^Lmax "
+                                                     "sub-cycles)", "cells": 65175552, "blocks": 4096, "nv": 6,
+                   "form": C5_FORMS["learned"], "tile": head["tile"] if head else None},
+        "forms": c5,
+        "speedup_vs_plain": (value / plain["value"]) if head and plain else None,
+        "max_rel_err_vs_oracle": acc["max_rel_err_vs_oracle"] if acc else None,
+        "accuracy": acc,
+        "roofline": roof,
         "cpu_baseline": cpu,
+        "learned_seed": {"train_steps": 2000, "batch": 4096, "samples": 1 << 20, "train_seconds": train_s,
+                         "final_loss": train_loss, "evaluation": seed_err, "beyond_training": seed_eval},
+        "c2": c2,
         "lat": lat,
         "gravity": grav,
         "remap": remap,

@@ -316,6 +316,13 @@ tdh_status tdh_mlp_train(tdh_ctx *ctx, const double *dev_in, const double *dev_l
                          float lr, uint64_t seed, float *host_loss);
 tdh_status tdh_mlp_loss_grad(tdh_ctx *ctx, const double *dev_in, const double *dev_lT, int64_t n, float *host_loss,
                              float *host_grad);
+/* One Adam step (beta 0.9/0.999, eps 1e-8, bias corrections with the step
+ * counter, which advances by one; no learning-rate decay) from a caller-given
+ * gradient host_grad [4417] (fp32, parameter order of tdh_mlp_init) at
+ * learning rate lr > 0, on the fp32 master parameters; the bf16 copies the
+ * kernels read are refreshed.  For training loops the caller drives.
+ * Synchronises the stream. */
+tdh_status tdh_mlp_adam_step(tdh_ctx *ctx, const float *host_grad, float lr);
 tdh_status tdh_mlp_forward(tdh_ctx *ctx, const double *dev_in, double *dev_lT, int64_t n);
 tdh_status tdh_mlp_get_params(tdh_ctx *ctx, float *host_params);
 tdh_status tdh_mlp_enable_seed(tdh_ctx *ctx, int on);

@@ -96,6 +96,8 @@ def lib():
         _lib.orc_frame_acceleration.restype = None
         _lib.orc_num_threads.argtypes = []
         _lib.orc_num_threads.restype = i
+        _lib.orc_set_num_threads.argtypes = [i]
+        _lib.orc_set_num_threads.restype = None
         _lib.orc_set_interp_rounding.argtypes = [i]
         _lib.orc_set_interp_rounding.restype = None
         if hasattr(_lib, "orc_mlp_forward"):
@@ -303,6 +305,42 @@ def frame_acceleration(cfg, mesh, U, rho_min, t=0.0):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+class threads:
+    """Context in which the oracle's loops over blocks use n threads (timing)."""
+
+    def __init__(self, n: int):
+        self.n = n
+
+    def __enter__(self):
+        self.prev = num_threads()
+        lib().orc_set_num_threads(int(self.n))
+        return self
+
+    def __exit__(self, *exc):
+        lib().orc_set_num_threads(self.prev)
+        return False
+
+
+def run_lat(cfg, mesh, U, windows, table=None, phi=None, t0=0.0):
+    """`windows` LAT windows, each starting with the oracle's own CFL steps and
+    level assignment (eq lat-base-dt, eq lat-factor).  Returns (U, per-window
+    list of (levels, Lmax, dt0, dt_block), block updates, cell updates)."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    t = float(t0)
+    info = []
+    bu = cu = 0
+    n3 = mesh.block_cells()
+    for _ in range(windows):
+        dtb = cfl(cfg, mesh, U, table=table, t=t, phi=phi)
+        lev, L, dt0 = lat_assign(cfg, mesh, dtb)
+        U, nb = lat_window(cfg, mesh, U, lev, dt0, table=table, phi=phi, t0=t)
+        info.append((lev, L, dt0, dtb))
+        bu += nb
+        cu += int(np.sum((2 ** lev.astype(np.int64)) * n3))
+        t += dt0 * 2 ** L
+    return U, info, bu, cu
 
 
 class interp_rounding:

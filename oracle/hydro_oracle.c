@@ -1017,3 +1017,13 @@ int orc_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Threads the parallel loops over blocks use from now on (timing runs only;
+   every thread count gives the same result, since blocks are independent). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}

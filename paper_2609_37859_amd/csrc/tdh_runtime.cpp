@@ -1376,6 +1376,25 @@ extern "C" tdh_status tdh_mlp_train(tdh_ctx *c, const double *dev_in, const doub
   return TDH_OK;
 }
 
+extern "C" tdh_status tdh_mlp_adam_step(tdh_ctx *c, const float *host_grad, float lr) {
+  CHECK_CTX(c);
+  if (!c->have_mlp) return fail(c, TDH_ESTATE, "call tdh_mlp_init first");
+  if (!host_grad) return fail(c, TDH_EINVAL, "null gradient");
+  if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(c, TDH_EINVAL, "lr must be positive and finite");
+  if (c->mlp_steps_done >= kMlpMaxSteps) return fail(c, TDH_ERANGE, "more than 2^20 Adam steps");
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  HIPCHK(c, hipMemcpyAsync(c->d_mgrad, host_grad, kMlpParams * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  const int t = ++c->mlp_steps_done;
+  const float c1 = (float)(1.0 - std::pow((double)b1, t)), c2 = (float)(1.0 - std::pow((double)b2, t));
+  HIPCHK(c, mlp_launch_adam(c->d_mw, c->d_mm, c->d_mv, c->d_mgrad, lr, b1, b2, eps, c1, c2, c->stream));
+  MlpDev &w = c->seed.w;
+  HIPCHK(c, mlp_launch_pack(c->d_mw, (short *)w.w1b, (short *)w.w2b, (short *)w.w2tb, (short *)w.w3b, (float *)w.b1,
+                            (float *)w.b2, (float *)w.b3, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  invalidate_graphs(c);
+  return TDH_OK;
+}
+
 extern "C" tdh_status tdh_mlp_loss_grad(tdh_ctx *c, const double *dev_in, const double *dev_lT, int64_t n,
                                         float *host_loss, float *host_grad) {
   CHECK_CTX(c);

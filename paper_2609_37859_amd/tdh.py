@@ -100,6 +100,7 @@ def lib():
         "tdh_mlp_forward": ([ctx, vp, vp, C.c_int64], st),
         "tdh_mlp_loss_grad": ([ctx, vp, vp, C.c_int64, P(C.c_float), P(C.c_float)], st),
         "tdh_mlp_enable_seed": ([ctx, i], st),
+        "tdh_mlp_adam_step": ([ctx, P(C.c_float), C.c_float], st),
     }
     for name, (args, res) in sig.items():
         if hasattr(L, name):
@@ -374,6 +375,12 @@ class Context:
         self._check(self.L.tdh_mlp_loss_grad(self.ctx, x.data_ptr(), lT.data_ptr(), x.shape[0], C.byref(loss),
                                              g.ctypes.data_as(C.POINTER(C.c_float))), "tdh_mlp_loss_grad")
         return loss.value, g
+
+    def mlp_adam_step(self, grad, lr):
+        g = np.ascontiguousarray(grad, dtype=np.float32)
+        assert g.size == 4417
+        self._check(self.L.tdh_mlp_adam_step(self.ctx, g.ctypes.data_as(C.POINTER(C.c_float)), float(lr)),
+                    "tdh_mlp_adam_step")
 
     def mlp_forward(self, x):
         torch = self.torch

@@ -405,6 +405,40 @@ def polytrope_c3(nb=8, n=32, mass=M_SUN, radius=R_SUN, npoly=1.5):
     return cfg, mesh, pack_state(mesh, cfg.nv, fn), pack_potential(mesh, phi), info
 
 
+def polytrope_c3_saha(table: EosTable, nb=8, n=32, mass=M_SUN, radius=R_SUN, npoly=1.5):
+    """The polytrope of polytrope_c3 (same mesh, density, pressure and fixed
+    potential) with the Saha H/He EOS: at every radius the temperature whose
+    Saha pressure equals the polytrope's pressure (bisection in log T, clamped
+    to the table's range), and the internal energy density rho e(rho, T) there;
+    cells take the values of their centre's radius.  Dual energy off."""
+    cfg0, mesh, _, phi, info = polytrope_c3(nb, n, mass, radius, npoly)
+    xi, th, xi1, om = lane_emden(npoly)
+    a = info["a"]
+    rho_c, P_c, K = info["rho_c"], info["P_c"], info["K"]
+    r = np.linspace(0.0, 2.0 * math.sqrt(3.0) * radius, 8193)
+    t = np.interp(r / a, xi, th, right=0.0)
+    rho = np.maximum(rho_c * t ** npoly, 1e-10 * rho_c)
+    P = np.maximum(K * rho_c ** (1.0 + 1.0 / npoly) * t ** (npoly + 1.0), 1e-12 * P_c)
+    lo = np.full(r.shape, table.lT0)
+    hi = np.full(r.shape, table.lT0 + (table.nT - 1) * table.dlT)
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        p_mid, _ = saha_pe(rho, 10.0 ** mid)
+        up = p_mid < P
+        lo = np.where(up, mid, lo)
+        hi = np.where(up, hi, mid)
+    _, e = saha_pe(rho, 10.0 ** (0.5 * (lo + hi)))
+    U_r = rho * e
+    cfg = dataclasses.replace(cfg0, eos_kind=1, e_floor=table.e_floor, p_floor=0.0)
+
+    def fn(x, y, z):
+        rr = np.sqrt(x * x + y * y + z * z)
+        d = np.interp(rr, r, rho)
+        return [d, 0.0 * x, 0.0 * x, 0.0 * x, np.interp(rr, r, U_r)]
+
+    return cfg, mesh, pack_state(mesh, cfg.nv, fn), phi, info
+
+
 def high_mach_wave(ncell=64, nt=4, v_adv=1e8, amp=0.1, dual=1):
     """Periodic entropy wave with rho_bar = P = 1 advected at V = 1e8 along x
     (gamma = 5/3, Mach ~7.75e7); blocks of nt^3 cells, uniform in y and z."""
@@ -527,8 +561,16 @@ def mlp_init_params(seed: int) -> np.ndarray:
     return p.astype(np.float32)
 
 
+# Region box (x0, x1, y0, y1, z0, z1) of the production-shaped run's 13 x 17 x 9
+# region grid that holds 512 blocks (112 x 32^3 + 400 x 16^3, 5.3 M cells): the
+# full z extent, y from 4 to 13 (the stream axis at y = 8.5 and the black hole
+# at y = 11 regions) and the two x regions about the centre.  Its timing sample
+# for the CPU oracle and its parity case.
+C5_SUBDOMAIN_512 = (5, 7, 4, 13, 0, 9)
+
+
 def debris_stream_c5(table: EosTable, regions=(13, 17, 9), rn=32, n_split=301, dxr=0.25, vfr=1e8, dv=3e7,
-                     rho_pk=1e-3, T=1e4, stream_frac=0.3, sig_cells=8.0):
+                     rho_pk=1e-3, T=1e4, stream_frac=0.3, sig_cells=8.0, box=None):
     """Production-shaped run: 13 x 17 x 9 regions of 32^3 cells at dx = 0.25 Rsun;
     the 301 regions nearest the stream axis and the black-hole path are split
     into eight 16^3 blocks (1688 x 32^3 + 2408 x 16^3 = 4096 blocks, 65.2 M
@@ -537,7 +579,11 @@ def debris_stream_c5(table: EosTable, regions=(13, 17, 9), rn=32, n_split=301, d
     velocity spread v_x = dV (x - x_c) / (0.3 L_x) lies in a 1e-10 rho_pk
     background at rest; a 1e3 Msun point mass starts 20 Rsun from the stream
     centre and moves at -V_fr along x (uniform frame velocity V_fr); excision
-    radius 4 dx, softening 0.1 dx; outflow boundaries."""
+    radius 4 dx, softening 0.1 dx; outflow boundaries.
+
+    box = (x0, x1, y0, y1, z0, z1) keeps only those regions of the region grid
+    (the same cells, split decisions, coordinates and initial data as in the
+    whole run), with outflow boundaries at the box faces."""
     dx = dxr * R_SUN
     rx, ry, rz = regions
     L = np.array([rx, ry, rz]) * rn * dx
@@ -552,7 +598,13 @@ def debris_stream_c5(table: EosTable, regions=(13, 17, 9), rn=32, n_split=301, d
     order = np.argsort(score.ravel(), kind="stable")
     split = np.zeros(rx * ry * rz, dtype=bool)
     split[order[:n_split]] = True
-    mesh = mixed_mesh(regions, rn, split.reshape(rz, ry, rx), dx, bc=(1, 1, 1))
+    split = split.reshape(rz, ry, rx)
+    if box is None:
+        mesh = mixed_mesh(regions, rn, split, dx, bc=(1, 1, 1))
+    else:
+        x0, x1, y0, y1, z0, z1 = box
+        mesh = mixed_mesh((x1 - x0, y1 - y0, z1 - z0), rn, split[z0:z1, y0:y1, x0:x1], dx,
+                          x0=(x0 * rn * dx, y0 * rn * dx, z0 * rn * dx), bc=(1, 1, 1))
     cfg = Config(eos_kind=1, dual=1, grav_kind=2, n_lat=3, cfl=0.3, eta1=1e-3, eta2=1e-4,
                  rho_floor=1e-10 * rho_pk * 0.5, p_floor=0.0, e_floor=table.e_floor, merge_frac=0.0,
                  gm_bh=G_NEWTON * 1e3 * M_SUN, r_soft=0.1 * dx, r_exc=4.0 * dx, bh_x0=tuple(bh0),

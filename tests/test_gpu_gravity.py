@@ -113,8 +113,8 @@ def test_jeans_wave_coupled_to_the_hydro_update(tdh, orc):
         pg, pb, _, _ = orc.mg_solve(mesh, 5, o, fpg, 20, tol=1e-12, phi_global=pg)
         dto = orc.cfl(cfg, mesh, o, phi=pb, t=t).min()
         assert abs(dt / dto - 1) < 1e-13
-        o, _ = orc.run_sync(cfg, mesh, o, 1, phi=pb, dts=[dt], t0=t)
-        t += dt
+        o, _ = orc.run_sync(cfg, mesh, o, 1, phi=pb, dts=[dto], t0=t)
+        t += dto
     g = ctx.get_state()
     err = rel_err(5, mesh, g, o)
     print("Jeans coupled rel err", err)

@@ -65,6 +65,13 @@ def test_forward_and_gradient_exact_on_dyadic_data(gctx, orc):
 
 
 def test_gradient_matches_oracle_on_random_data(gctx, orc):
+    """Random weights and inputs: the GPU accumulates in fp32 in the matrix
+    cores' order, the oracle exactly, so a hidden activation whose fp32 sum
+    lies within fp32 rounding of a bf16 rounding boundary can round one bf16
+    step apart (a flip, ~2^-16 of the roundings).  Element by element: every
+    sample's output and every gradient component agree to fp32 accumulation
+    accuracy except a bounded number touched by flips, and those stay within
+    the effect of a few flips."""
     import torch
     rng = np.random.default_rng(12)
     n = 4096
@@ -81,13 +88,47 @@ def test_gradient_matches_oracle_on_random_data(gctx, orc):
     yo = orc.mlp_forward(p, xs, round_bf16=True)
     yg = gctx.mlp_forward(torch.from_numpy(raw).cuda()).cpu().numpy()
     yg_n = 2 * (yg - lt_lo) / (lt_hi - lt_lo) - 1
-    d = np.abs(yg_n - yo) / np.maximum(np.abs(yo), 1e-2)
-    assert np.mean(d < 1e-5) > 0.99 and d.max() < 2e-2
+    dy = np.abs(yg_n - yo)
+    ys = np.abs(yo).max()
+    off_y = dy > 1e-5 * ys                 # outputs a flip reached
+    print("forward: samples beyond fp32 accuracy", int(off_y.sum()), "of", n, "max", dy.max() / ys)
+    assert off_y.sum() <= n // 100
+    assert dy.max() <= 2e-2 * ys           # a few bf16 steps of one hidden unit
     loss_g, grad_g = gctx.mlp_loss_grad(torch.from_numpy(raw).cuda(), torch.from_numpy(lT).cuda())
     loss_o, grad_o = orc.mlp_loss_grad(p, xs, tn_seen, round_bf16=True)
     assert abs(loss_g / loss_o - 1) < 1e-4
-    rel = np.linalg.norm(grad_g - grad_o) / np.linalg.norm(grad_o)
-    assert rel < 1e-3, rel
+    gs = np.abs(grad_o).max()
+    dg = np.abs(grad_g - grad_o)
+    off_g = dg > 1e-5 * gs
+    print("gradient: components beyond fp32 accuracy", int(off_g.sum()), "of", grad_o.size, "max", dg.max() / gs)
+    assert off_g.sum() <= grad_o.size // 100
+    assert dg.max() <= 1e-3 * gs
+
+
+def test_adam_step_matches_oracle(gctx, orc):
+    """One and ten Adam steps from the same test-drawn gradients: the GPU's
+    fp32 master weights equal the oracle's fp64 Adam element by element within
+    fp32 rounding of each step (two units in the last place of the weight plus
+    2^-18 of the step size, per step)."""
+    rng = np.random.default_rng(14)
+    p0 = rng.normal(0, 0.3, orc.N_PARAMS).astype(np.float32)
+    gctx.mlp_init(p0, RANGES)
+    w = p0.astype(np.float64)
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    lr = 1e-3
+    for k in range(1, 11):
+        g = rng.normal(0, 1, orc.N_PARAMS).astype(np.float32)
+        g[::37] *= np.float32(1e-5)                   # small components, where eps matters
+        gctx.mlp_adam_step(g, lr)
+        orc.mlp_adam(w, m, v, g.astype(np.float64), k, lr)
+        if k in (1, 10):
+            pg = gctx.mlp_params().astype(np.float64)
+            tol = k * (2.0 ** -22 * np.abs(w) + 2.0 ** -18 * lr)
+            d = np.abs(pg - w)
+            print("Adam step", k, "max |gpu - oracle| / tol", (d / tol).max())
+            assert np.all(d <= tol)
+            assert np.all(np.abs(pg - p0) > 0)      # every weight moved
 
 
 def _train_seed(ctx, saha, steps=2000, n=1 << 20, seed=1):

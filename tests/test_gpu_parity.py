@@ -1,8 +1,11 @@
 """GPU path (libtdh through its C ABI) against the CPU oracle.
 
 Both sides get the same seeded synthetic inputs from the input module; the
-oracle never sees GPU output.  Bar: max relative error <= 1e-11 per variable
-and cell (tests/parity.py), bit-exact for integer results (levels, schedule,
+oracle never sees GPU output: it takes its own CFL steps and LAT levels (or
+steps and levels the test fixes for both).  Bar: max relative error <= 1e-11
+per variable and cell against the cell's own scale (tests/parity.py; on the
+point-mass workloads the stencil-scale form and the oracle's own rounding
+spread, point_mass_bar), bit-exact for integer results (levels, schedule,
 table cells) and between launch forms of the GPU path itself.
 """
 import dataclasses
@@ -12,7 +15,7 @@ import numpy as np
 import pytest
 
 from paper_2609_37859_amd import workloads as W
-from tests.parity import TOL, rel_err
+from tests.parity import TOL, point_mass_bar, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -27,12 +30,58 @@ def tdh():
     return T
 
 
-def _run_gpu_sync(T, cfg, mesh, U, nsteps, table=None, phi=None, dts=None, **kw):
+def _run_gpu_sync(T, cfg, mesh, U, nsteps, table=None, phi=None, dts=None, seed_params=None, **kw):
     ctx = T.Context(cfg, mesh, U, phi=phi, table=table, **kw)
+    if seed_params is not None:
+        ctx.mlp_init(seed_params, W.seed_ranges(table))
+        ctx.mlp_enable_seed(True)
     used = T.run_sync_steps(ctx, nsteps, dts)
     out = ctx.get_state()
     ctx.close()
     return out, used
+
+
+@pytest.fixture(scope="module")
+def seed_params(tdh, saha):
+    """The learned seed trained on the GPU by the library's kernels (C4 recipe,
+    600 Adam steps)."""
+    import torch
+    cfg = W.Config(eos_kind=1, e_floor=saha.e_floor)
+    mesh = W.uniform_mesh(1, 1, 1, 8, 1.0)
+    ctx = tdh.Context(cfg, mesh, W.uniform_state(mesh, W.Config()), table=saha)
+    x = torch.from_numpy(W.seed_training_samples(saha, 1 << 20, 1)).cuda()
+    lT, _, _ = ctx.eos_invert(x[:, 0].contiguous(), x[:, 1].contiguous(), mode=0)
+    ctx.mlp_init(W.mlp_init_params(2), W.seed_ranges(saha))
+    ctx.mlp_train(x, lT, steps=600, batch=4096, lr=1e-3, seed=1)
+    p = ctx.mlp_params()
+    ctx.close()
+    return p
+
+
+def _gpu_lat_windows(T, cfg, mesh, U, windows, table=None, phi=None, graph=True, seed_params=None, **kw):
+    """`windows` LAT windows with the library's own CFL steps and levels;
+    returns (state, per-window (dt_block, dt0, levels, Lmax), stats)."""
+    ctx = T.Context(cfg, mesh, U, phi=phi, table=table, **kw)
+    if seed_params is not None:
+        ctx.mlp_init(seed_params, W.seed_ranges(table))
+        ctx.mlp_enable_seed(True)
+    info = []
+    for _ in range(windows):
+        dtb, dt0, lev, L = ctx.reduce_dt()
+        info.append((dtb, dt0, lev, L))
+        ctx.run_window(dt0 * 2 ** L, batched=True, graph=graph)
+    out, st = ctx.get_state(), ctx.stats()
+    ctx.close()
+    return out, info, st
+
+
+def _check_windows(g_info, o_info):
+    """Per window: the library's dt_b within 1e-13 of the oracle's, and its
+    levels equal to the oracle's own assignment bit for bit."""
+    for (dtb, dt0, lev, L), (lev_o, L_o, dt0_o, dtb_o) in zip(g_info, o_info):
+        assert np.max(np.abs(dtb / dtb_o - 1)) < 1e-13
+        assert abs(dt0 / dt0_o - 1) < 1e-13
+        assert L == L_o and np.array_equal(lev, lev_o), np.nonzero(lev != lev_o)
 
 
 def test_c1_entropy_wave_20_steps(tdh, orc):
@@ -60,7 +109,8 @@ def test_periodic_conservation_gpu(tdh, orc):
     mesh = W.uniform_mesh(2, 2, 2, 16, 1.0 / 32)
     U = W.random_smooth_state(mesh, cfg, seed=3, amp=0.3)
     g, dts = _run_gpu_sync(tdh, cfg, mesh, U, 10)
-    o, _ = orc.run_sync(cfg, mesh, U, 10, dts=dts)
+    o, dto = orc.run_sync(cfg, mesh, U, 10)
+    assert np.max(np.abs(dts / dto - 1)) < 1e-13
     G0, G1 = W.to_global(mesh, 6, U), W.to_global(mesh, 6, g)
     for v in (0, 4):
         assert abs(math.fsum(G1[v].ravel()) - math.fsum(G0[v].ravel())) <= 1e-14 * math.fsum(G0[v].ravel())
@@ -68,15 +118,26 @@ def test_periodic_conservation_gpu(tdh, orc):
     assert np.all(err <= TOL), err
 
 
-@pytest.mark.parametrize("inv_mode", [0, 2, 3])
-def test_c2_table_dual_energy_20_steps(tdh, orc, saha, inv_mode):
-    """C2: 128^3 as 64 blocks of 32^3, Saha table, dual energy, Mach 1e7 stream."""
+@pytest.fixture(scope="module")
+def c2_oracle(orc, saha):
     cfg, mesh, U = W.stream_c2(saha)
-    g, dg = _run_gpu_sync(tdh, cfg, mesh, U, 20, table=saha, inv_mode=inv_mode)
     o, do = orc.run_sync(cfg, mesh, U, 20, table=saha)
+    return cfg, mesh, U, o, do
+
+
+@pytest.mark.parametrize("inv_mode", [0, 1, 2, 3, 4])
+def test_c2_table_dual_energy_20_steps(tdh, c2_oracle, saha, seed_params, inv_mode):
+    """C2 at full size: 128^3 as 64 blocks of 32^3, Saha table, dual energy,
+    Mach 1e7 stream, 20 steps with each side's own CFL steps, in every
+    inversion form: bisection (0), the network inside the stage kernel (1),
+    a bisection pass (2), carried cells (3), a network-started pass (4, the
+    benchmark's learned form); 1 and 4 with the network trained on the GPU."""
+    cfg, mesh, U, o, do = c2_oracle
+    net = seed_params if inv_mode in (1, 4) else None
+    g, dg = _run_gpu_sync(tdh, cfg, mesh, U, 20, table=saha, inv_mode=inv_mode, seed_params=net)
     assert np.max(np.abs(dg / do - 1)) < 1e-13
     err = rel_err(6, mesh, g, o)
-    print("C2 rel err per variable", err)
+    print("C2 mode", inv_mode, "rel err per variable", err)
     assert np.all(err <= TOL)
 
 
@@ -169,16 +230,20 @@ def test_table_eos_evaluation_matches_oracle(tdh, orc, saha):
 
 def test_levels_bit_exact_and_dt_parity(tdh, orc):
     """C3-shaped polytrope (reduced to 4^3 blocks of 16^3): per-block CFL steps
-    agree to 1e-13, and the level assignment computed by the library from its
-    own dt_b equals the oracle's assignment on the same dt_b bit for bit."""
+    agree to 1e-13, and the library's level assignment from its own dt_b
+    equals the oracle's assignment from the oracle's dt_b bit for bit (no
+    block's ratio dt_b / dt0 lies within 1e-12 of a power of two, where the two
+    roundings could decide apart)."""
     cfg, mesh, U, phi, info = W.polytrope_c3(nb=4, n=16)
     ctx = tdh.Context(cfg, mesh, U, phi=phi)
     dtb, dt0, lev, L = ctx.reduce_dt()
     ctx.close()
     dto = orc.cfl(cfg, mesh, U, phi=phi)
     assert np.max(np.abs(dtb / dto - 1)) < 1e-13
-    lev_o, L_o, dt0_o = orc.lat_assign(cfg, mesh, dtb)
-    assert L == L_o and dt0 == dt0_o
+    lev_o, L_o, dt0_o = orc.lat_assign(cfg, mesh, dto)
+    r = dto / dt0_o
+    assert np.all(np.abs(r / 2.0 ** np.floor(np.log2(r)) - 1) > 1e-12)
+    assert L == L_o and abs(dt0 / dt0_o - 1) < 1e-13
     assert np.array_equal(lev, lev_o)
     assert L >= 1
 
@@ -267,7 +332,8 @@ def test_hlle_sync_parity(tdh, orc, saha, kind):
         table, nv, kw = saha, 6, {"inv_mode": 3}
     cfg = dataclasses.replace(base, riemann=1)
     g, dg = _run_gpu_sync(tdh, cfg, mesh, U, 20, table=table, **kw)
-    o, do = orc.run_sync(cfg, mesh, U, 20, table=table, dts=dg)
+    o, do = orc.run_sync(cfg, mesh, U, 20, table=table)
+    assert np.max(np.abs(dg / do - 1)) < 1e-13
     err = rel_err(nv, mesh, g, o)
     print(kind, "HLLE rel err", err)
     assert np.all(err <= TOL)
@@ -291,8 +357,11 @@ def test_high_mach_wave_gpu(tdh, orc):
     """Dual-energy entropy wave at Mach ~7.7e7 (blocks of 16^3): GPU = oracle."""
     cfg, mesh, U = W.high_mach_wave(ncell=64, nt=16, dual=1)
     g, dts = _run_gpu_sync(tdh, cfg, mesh, U, 30)
-    o, _ = orc.run_sync(cfg, mesh, U, 30, dts=dts)
-    assert np.all(rel_err(6, mesh, g, o) <= TOL)
+    o, dto = orc.run_sync(cfg, mesh, U, 30)
+    assert np.max(np.abs(dts / dto - 1)) < 1e-13
+    err = rel_err(6, mesh, g, o)
+    print("high-Mach wave rel err", err)
+    assert np.all(err <= TOL)
 
 
 def test_mixed_block_sizes_point_mass_excision(tdh, orc, saha):
@@ -325,9 +394,11 @@ def test_mixed_block_sizes_point_mass_excision(tdh, orc, saha):
     dts = [orc.cfl(cfg, mesh, U, table=saha).min()] * 6
     g, _ = _run_gpu_sync(tdh, cfg, mesh, U, 6, table=saha, dts=dts)
     o, _ = orc.run_sync(cfg, mesh, U, 6, table=saha, dts=dts)
-    err = rel_err(6, mesh, g, o)
-    print("mixed rel err", err)
-    assert np.all(err <= TOL)
+    with orc.interp_rounding(True):
+        o2, _ = orc.run_sync(cfg, mesh, U, 6, table=saha, dts=dts)
+    ok, rep = point_mass_bar(6, mesh, g, o, o2)
+    print("mixed blocks, point mass:", rep)
+    assert ok
 
 
 def test_all_tiles_bitwise_equal(tdh, orc, saha):
@@ -359,79 +430,92 @@ def test_bench_workload_parity_sampled(tdh, orc, saha):
     dts = tdh.run_sync_steps(ctx, 3)
     g = ctx.get_state()
     ctx.close()
-    o, _ = orc.run_sync(cfg, mesh, U, 3, table=saha, dts=dts)
+    o, dto = orc.run_sync(cfg, mesh, U, 3, table=saha)
+    assert np.max(np.abs(dts / dto - 1)) < 1e-13
     assert np.all(rel_err(6, mesh, g, o) <= TOL)
 
 
-def test_c3_full_size_lat_window(tdh, orc):
-    """C3 at its full size (256^3 as 512 x 32^3, fixed polytrope potential, N_LAT
-    = 3): the library's levels equal the oracle's assignment on the library's
-    dt_b bit for bit, and one LAT window (batched, graph-captured) equals the
-    oracle's window to 1e-11 with the same block-update count."""
+def test_c3_full_size_eight_windows(tdh, orc):
+    """C3 at its full size (256^3 as 512 x 32^3, fixed polytrope potential,
+    N_LAT = 3) over 8 coarse steps, each side with its own CFL steps and level
+    assignment: every window's levels equal bit for bit, dt_b within 1e-13, the
+    block-update count equal, and the end state within 1e-11 (batched launches
+    replayed from a captured graph)."""
+    import time
     cfg, mesh, U, phi, info = W.polytrope_c3()
-    ctx = tdh.Context(cfg, mesh, U, phi=phi)
-    dtb, dt0, lev, L = ctx.reduce_dt()
-    lev_o, L_o, dt0_o = orc.lat_assign(cfg, mesh, dtb)
-    assert np.array_equal(lev, lev_o) and L == L_o and dt0 == dt0_o
-    ctx.run_window(dt0 * 2 ** L, batched=True, graph=True)
-    g = ctx.get_state()
-    st = ctx.stats()
-    ctx.close()
-    o, nupd = orc.lat_window(cfg, mesh, U, lev, dt0, phi=phi)
-    assert st["block_updates"] == nupd
+    g, g_info, st = _gpu_lat_windows(tdh, cfg, mesh, U, 8, phi=phi)
+    t0 = time.perf_counter()
+    o, o_info, bu, cu = orc.run_lat(cfg, mesh, U, 8, phi=phi)
+    _check_windows(g_info, o_info)
+    assert st["block_updates"] == bu and st["cell_updates"] == cu
     err = rel_err(5, mesh, g, o)
-    print("C3 full-size LAT window rel err", err, "updates", nupd, "levels", np.bincount(lev))
+    print("C3 full size, 8 windows: rel err", err, "updates", bu, "levels", [np.bincount(i[0]) for i in o_info],
+          "oracle s", round(time.perf_counter() - t0, 1), flush=True)
     assert np.all(err <= TOL)
+
+
+def _c5_reduced(saha):
+    return W.debris_stream_c5(saha, regions=(4, 3, 2), n_split=6, dxr=1.0)
 
 
 def test_c5_shaped_subdomain_lat_window(tdh, orc, saha):
     """C5-shaped run on a reduced region grid: mixed 16^3/32^3 blocks, Saha
-    table, dual energy, moving point mass with excision, LAT levels from the
-    library's CFL; one window against the oracle."""
-    cfg, mesh, U = W.debris_stream_c5(saha, regions=(4, 3, 2), n_split=6, dxr=1.0)
+    table, dual energy, moving point mass with excision, LAT levels from each
+    side's own CFL; two windows in modes 2 and 3 (bitwise equal), against the
+    oracle's two windows."""
+    cfg, mesh, U = _c5_reduced(saha)
     outs = []
     for mode in (2, 3):  # centre cells bisected before each stage / carried from the last stage
-        ctx = tdh.Context(cfg, mesh, U, table=saha, inv_mode=mode)
-        dtb, dt0, lev, L = ctx.reduce_dt()
-        lev_o, L_o, _ = orc.lat_assign(cfg, mesh, dtb)
-        assert np.array_equal(lev, lev_o)
-        ctx.run_window(dt0 * 2 ** L, batched=True)
-        ctx.run_window(dt0 * 2 ** L, batched=True)  # a second window starts from carried seeds
-        outs.append(ctx.get_state())
-        ctx.close()
-    assert np.array_equal(outs[0], outs[1])
-    ctx = tdh.Context(cfg, mesh, U, table=saha, inv_mode=3)
-    dtb, dt0, lev, L = ctx.reduce_dt()
-    ctx.run_window(dt0 * 2 ** L, batched=True)
-    g = ctx.get_state()
-    ctx.close()
-    o, _ = orc.lat_window(cfg, mesh, U, lev, dt0, table=saha)
-    err, ill = rel_err(6, mesh, g, o, with_counts=True)
-    strict = rel_err(6, mesh, g, o, stencil=False)
-    print("C5-shaped window rel err", err, "per-cell scale", strict, "levels", np.bincount(lev),
-          "cells with E << its parts", ill)
-    assert np.all(err <= TOL)
+        g, g_info, _ = _gpu_lat_windows(tdh, cfg, mesh, U, 2, table=saha, inv_mode=mode, graph=False)
+        outs.append((g, g_info))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    o, o_info, _, _ = orc.run_lat(cfg, mesh, U, 2, table=saha)
+    _check_windows(outs[0][1], o_info)
+    with orc.interp_rounding(True):
+        o2, _, _, _ = orc.run_lat(cfg, mesh, U, 2, table=saha)
+    ok, rep = point_mass_bar(6, mesh, outs[0][0], o, o2)
+    print("C5-shaped reduced, 2 windows:", rep, "levels", [np.bincount(i[0]) for i in o_info])
+    assert ok
 
 
 def test_c5_shaped_dense_ghosts_window(tdh, orc, saha):
     """The C5-shaped sub-domain with the RK2 dense-output ghosts (the
     compiled table-EOS, point-mass, dense-ghost kind): one LAT window against
     the oracle, and a visible difference from the linear ghosts."""
-    cfg, mesh, U = W.debris_stream_c5(saha, regions=(4, 3, 2), n_split=6, dxr=1.0)
+    cfg, mesh, U = _c5_reduced(saha)
     cfg = dataclasses.replace(cfg, ghost_dense=1)
-    ctx = tdh.Context(cfg, mesh, U, table=saha, inv_mode=2)
-    dtb, dt0, lev, L = ctx.reduce_dt()
-    assert L > 0
-    ctx.run_window(dt0 * 2 ** L, batched=True)
-    g = ctx.get_state()
-    ctx.close()
-    o, _ = orc.lat_window(cfg, mesh, U, lev, dt0, table=saha)
-    err = rel_err(6, mesh, g, o)
-    lin, _ = orc.lat_window(dataclasses.replace(cfg, ghost_dense=0), mesh, U, lev, dt0, table=saha)
-    print("C5-shaped dense-ghost window rel err", err, "levels", np.bincount(lev),
-          "max |dense - linear|", np.max(np.abs(o - lin)))
-    assert np.all(err <= TOL)
+    g, g_info, _ = _gpu_lat_windows(tdh, cfg, mesh, U, 1, table=saha, inv_mode=2, graph=False)
+    assert g_info[0][3] > 0
+    o, o_info, _, _ = orc.run_lat(cfg, mesh, U, 1, table=saha)
+    _check_windows(g_info, o_info)
+    with orc.interp_rounding(True):
+        o2, _, _, _ = orc.run_lat(cfg, mesh, U, 1, table=saha)
+    ok, rep = point_mass_bar(6, mesh, g, o, o2)
+    lin, _, _, _ = orc.run_lat(dataclasses.replace(cfg, ghost_dense=0), mesh, U, 1, table=saha)
+    print("C5-shaped dense-ghost window:", rep, "max |dense - linear|", np.max(np.abs(o - lin)))
+    assert ok
     assert not np.array_equal(o, lin)
+
+
+def test_c5_subdomain_512_learned_form_two_windows(tdh, orc, saha, seed_params):
+    """The benchmark's headline form on the 512-block sub-domain of the
+    production-shaped run (112 x 32^3 + 400 x 16^3, Saha table, dual energy,
+    moving point mass, N_LAT = 3, merge_frac 0.01): network-started seed
+    passes (mode 4, network trained on the GPU), batched launches replayed from
+    a graph, two windows with the library's own CFL steps and levels, against
+    the oracle's two windows from its own."""
+    cfg, mesh, U = W.debris_stream_c5(saha, box=W.C5_SUBDOMAIN_512)
+    cfg = dataclasses.replace(cfg, merge_frac=0.01)
+    g, g_info, st = _gpu_lat_windows(tdh, cfg, mesh, U, 2, table=saha, inv_mode=4, seed_params=seed_params)
+    o, o_info, bu, cu = orc.run_lat(cfg, mesh, U, 2, table=saha)
+    _check_windows(g_info, o_info)
+    assert st["block_updates"] == bu
+    with orc.interp_rounding(True):
+        o2, _, _, _ = orc.run_lat(cfg, mesh, U, 2, table=saha)
+    ok, rep = point_mass_bar(6, mesh, g, o, o2)
+    print("C5 512-block sub-domain, learned form, 2 windows:", rep, "levels", [np.bincount(i[0]) for i in o_info],
+          flush=True)
+    assert ok
 
 
 @pytest.mark.parametrize("case", ["c2_mode2", "c2_mode4_hlle", "c5_sync_point_mass", "c5_lat_point_mass",
@@ -467,9 +551,8 @@ def test_cfl_from_the_second_stage_equals_the_reduction(tdh, orc, saha, case):
         ctx.set_tile(len([t for t in tdh.tile_shapes() if t[0] > 0]))  # the first split form
     for w in range(3):
         dtb, dt0, lev, L = ctx.reduce_dt()
-        if w == 0:
-            g0 = ctx.get_state()
-            dto = orc.cfl(cfg, mesh, g0, table=table, phi=phi, t=ctx.time)
+        if w == 0:  # the initial state at t = 0
+            dto = orc.cfl(cfg, mesh, U, table=table, phi=phi, t=0.0)
             assert np.all(np.abs(dtb / dto - 1) < 1e-13)
         ctx.run_window(dt0 * 2 ** L, batched=True)
         cells_after = ctx.seed_cells() if table is not None else None
@@ -510,22 +593,18 @@ def test_c5_full_size_lat_window(tdh, orc, saha):
     """The production-shaped workload at full size (4096 blocks, 65.2 M cells,
     Saha table, dual energy, moving point mass with excision, N_LAT = 3,
     merge_frac 0.01) in the benchmark's launch configuration (batched launches
-    replayed from a captured graph): the levels from the library's CFL equal
-    the oracle's assignment bit for bit, and one window equals the oracle's
-    within 1e-11 per cell."""
+    replayed from a captured graph): the library's dt_b and levels equal the
+    oracle's own, and one window meets the point-mass bar."""
     import time
     cfg, mesh, U = W.debris_stream_c5(saha)
     cfg = dataclasses.replace(cfg, merge_frac=0.01)
-    ctx = tdh.Context(cfg, mesh, U, table=saha, inv_mode=2)
-    dtb, dt0, lev, L = ctx.reduce_dt()
-    lev_o, L_o, dt0_o = orc.lat_assign(cfg, mesh, dtb)
-    assert np.array_equal(lev, lev_o) and L == L_o and dt0 == dt0_o
-    ctx.run_window(dt0 * 2 ** L, batched=True, graph=True)
-    g = ctx.get_state()
-    ctx.close()
+    g, g_info, _ = _gpu_lat_windows(tdh, cfg, mesh, U, 1, table=saha, inv_mode=2)
     t0 = time.perf_counter()
-    o, _ = orc.lat_window(cfg, mesh, U, lev, dt0, table=saha)
-    err = rel_err(6, mesh, g, o)
-    print("C5 full-size window: levels", np.bincount(lev), "oracle seconds", round(time.perf_counter() - t0, 1),
-          "rel err", err, flush=True)
-    assert np.all(err <= TOL)
+    o, o_info, _, _ = orc.run_lat(cfg, mesh, U, 1, table=saha)
+    secs = time.perf_counter() - t0
+    _check_windows(g_info, o_info)
+    with orc.interp_rounding(True):
+        o2, _, _, _ = orc.run_lat(cfg, mesh, U, 1, table=saha)
+    ok, rep = point_mass_bar(6, mesh, g, o, o2)
+    print("C5 full-size window: levels", np.bincount(o_info[0][0]), "oracle seconds", round(secs, 1), rep, flush=True)
+    assert ok
