@@ -224,7 +224,13 @@ tdh_status tdh_gravity_solve(tdh_ctx *ctx, void *dev_work, size_t bytes, double 
  * src's current state onto dst's mesh, and dst's time src's.  Per target cell:
  * inside dst's excision sphere at that time (grav_kind 2), the sink state
  * (rho_floor, 0, U_floor); centre outside src's domain along a non-periodic
- * axis, the floor state; target grid coincident with the source grid (equal
+ * axis, the floor state; within two source cells inside a source face beyond
+ * which dst's domain extends (non-periodic axes), the value below blended
+ * toward the floor state, density, momentum and thermal energy density each
+ * as s q + (1 - s) q_floor, s = 3u^2 - 2u^3 with u the distance to the
+ * nearest such face in units of two source cells (so density and pressure
+ * reach the floor smoothly at the old domain's edge); target grid coincident
+ * with the source grid (equal
  * spacings, origins a whole number of cells apart), the source cell copied;
  * otherwise the mean over the eight sub-cell midpoints (+-1/4 cell per axis)
  * of the trilinear interpolant of the source density, momentum and thermal

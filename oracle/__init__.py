@@ -344,16 +344,18 @@ def run_lat(cfg, mesh, U, windows, table=None, phi=None, t0=0.0):
 
 
 class interp_rounding:
-    """Context in which the table interpolation (1 - w) x + w y is evaluated as
-    one fused multiply-add (fused=True) instead of two rounded products and a
-    rounded sum: an equally valid rounding, used only to measure how strongly a
-    workload amplifies rounding differences."""
+    """Context in which the oracle rounds differently, used only to measure how
+    strongly a workload amplifies rounding differences: fused=True evaluates
+    the table interpolation (1 - w) x + w y as one fused multiply-add instead of
+    two rounded products and a rounded sum; long_math=True evaluates the EOS's
+    base-10 logarithms and powers in long double, rounded once.  Each is an
+    equally valid evaluation, one rounding away from the default."""
 
-    def __init__(self, fused: bool):
-        self.fused = fused
+    def __init__(self, fused: bool = True, long_math: bool = False):
+        self.mode = (1 if fused else 0) | (2 if long_math else 0)
 
     def __enter__(self):
-        lib().orc_set_interp_rounding(1 if self.fused else 0)
+        lib().orc_set_interp_rounding(self.mode)
         return self
 
     def __exit__(self, *exc):

@@ -182,13 +182,21 @@ static void table_rho_cell(const orc_table *T, double lr, int *i, double *w) {
   *i = ii; *w = x - ii;
 }
 
-/* Rounding of the linear interpolation (1 - w) x + w y: 0 (default) rounds
- * both products and the sum; 1 takes w y + (1 - w) x as one fused
- * multiply-add.  Both are exact evaluations of the same formula up to one
- * rounding; mode 1 exists only so that the tests can measure how strongly a
- * workload amplifies such a difference (the conditioning of the comparison). */
-static int g_interp_fused = 0;
-void orc_set_interp_rounding(int fused) { g_interp_fused = fused ? 1 : 0; }
+/* Alternative roundings, for the tests only (they measure how strongly a
+ * workload amplifies rounding differences: the conditioning of a comparison).
+ * Bit 0: the linear interpolation (1 - w) x + w y is taken as one fused
+ * multiply-add w y + (1 - w) x instead of two rounded products and a rounded
+ * sum.  Bit 1: the EOS's base-10 logarithms and powers are evaluated in long
+ * double and rounded once to double instead of by the double-precision
+ * library routines.  Each is an equally valid evaluation of the same formula,
+ * one rounding apart; the default (0) is the plain definition. */
+static int g_interp_fused = 0, g_math_long = 0;
+void orc_set_interp_rounding(int mode) {
+  g_interp_fused = mode & 1;
+  g_math_long = (mode >> 1) & 1;
+}
+static double log10_e(double x) { return g_math_long ? (double)log10l((long double)x) : log10(x); }
+static double pow10_e(double y) { return g_math_long ? (double)powl(10.0L, (long double)y) : pow(10.0, y); }
 
 static double lerp(double w, double x, double y) {
   return g_interp_fused ? fma(w, y, (1.0 - w) * x) : (1.0 - w) * x + w * y;
@@ -236,10 +244,10 @@ static void eos_pc(const orc_cfg *c, const orc_table *T, double rho, double U, d
   double Ue = U;
   double uf = u_floor(c, rho);
   if (Ue < uf) Ue = uf; /* keeps the logarithm defined; the inversion clamps into the table */
-  table_rho_cell(T, log10(rho), &i, &w);
-  table_invert(T, i, w, log10(Ue / rho), &j, &wT);
-  *P = pow(10.0, tbil(T->lP, T->nT, i, w, j, wT));
-  *cs = pow(10.0, 0.5 * tbil(T->lc2, T->nT, i, w, j, wT));
+  table_rho_cell(T, log10_e(rho), &i, &w);
+  table_invert(T, i, w, log10_e(Ue / rho), &j, &wT);
+  *P = pow10_e(tbil(T->lP, T->nT, i, w, j, wT));
+  *cs = pow10_e(0.5 * tbil(T->lc2, T->nT, i, w, j, wT));
 }
 
 /* ------------------------------------------------------------------ */

@@ -10,8 +10,17 @@
  *   - inside the BH excision sphere at time t (point-mass configurations):
  *     the sink state (rho_floor, 0, U_floor), as the hydro update's reset;
  *   - centre outside the source domain along a non-periodic axis: the floor
- *     state (the paper blends density and pressure across a band of the
- *     atmosphere; that blend is not part of this oracle);
+ *     state (rho_floor, 0, U_floor);
+ *   - centre inside the source domain but within BAND source cells of a
+ *     source face beyond which the target domain extends (a non-periodic axis
+ *     whose target extent passes that face): the remapped state below blended
+ *     toward the floor state, density, momentum and thermal energy density
+ *     each as s q + (1 - s) q_floor with s = 3 u^2 - 2 u^3, u = the distance
+ *     to the nearest such face in units of BAND source cells (clamped to
+ *     [0, 1]); total energy rebuilt from the blended values.  The floor state
+ *     is at rest, and for the ideal gas the thermal energy density is the
+ *     pressure over (gamma - 1), so density and pressure go smoothly to the
+ *     floor across the band (the band sits in the old domain's atmosphere);
  *   - target grid coincident with the source grid (same spacing, origin an
  *     integer number of cells away): the source cell's conserved values,
  *     copied (a remap onto the same grid is the identity);
@@ -98,6 +107,27 @@ static double *gather(const orc_rmesh *m, int nv, const double *U) {
   return g;
 }
 
+#define BAND 2.0 /* width of the blending band in source cells */
+
+/* Blending weight of a target centre c inside the source domain: 1 away from
+   the source faces the target domain extends beyond, falling smoothly to 0 at
+   them (section header). */
+static double band_weight(const orc_rmesh *s, const orc_rmesh *d, const double *c) {
+  int Ns[3] = {s->nx, s->ny, s->nz}, Nd[3] = {d->nx, d->ny, d->nz};
+  double u = 1.0;
+  for (int a = 0; a < 3; a++) {
+    if (s->bc[a] == 0) continue;
+    double lo = s->x0[a], hi = s->x0[a] + Ns[a] * s->dx[a];
+    double dlo = d->x0[a], dhi = d->x0[a] + Nd[a] * d->dx[a];
+    double w = BAND * s->dx[a];
+    if (dlo < lo) { double v = (c[a] - lo) / w; if (v < u) u = v; }
+    if (dhi > hi) { double v = (hi - c[a]) / w; if (v < u) u = v; }
+  }
+  if (u <= 0.0) return 0.0;
+  if (u >= 1.0) return 1.0;
+  return u * u * (3.0 - 2.0 * u);
+}
+
 static int src_index(int i, int n, int periodic) {
   if (periodic) return ((i % n) + n) % n;
   return i < 0 ? 0 : (i >= n ? n - 1 : i);
@@ -149,7 +179,7 @@ int orc_remap(const orc_rcfg *cfg, const orc_rmesh *src, const double *Us, const
           int gi[3] = {dst->blk[4 * b + 1] + i, dst->blk[4 * b + 2] + j, dst->blk[4 * b + 3] + k};
           double c[3];
           for (int d = 0; d < 3; d++) c[d] = dst->x0[d] + (gi[d] + 0.5) * dst->dx[d];
-          double q[6];
+          double q[6], uth0 = 0.0; /* conserved state; its thermal energy density */
           int outside = 0;
           for (int d = 0; d < 3; d++) {
             double lo = src->x0[d], hi = src->x0[d] + Ns3[d] * src->dx[d];
@@ -163,6 +193,7 @@ int orc_remap(const orc_rcfg *cfg, const orc_rmesh *src, const double *Us, const
             for (int d = 0; d < 3; d++) si[d] = src_index(gi[d] + shift[d], Ns3[d], src->bc[d] == 0);
             size_t p = ((size_t)si[2] * src->ny + si[1]) * src->nx + si[0];
             for (int v = 0; v < 6; v++) q[v] = g[v * Ns + p];
+            uth0 = g[6 * Ns + p];
           } else {
             double acc[5] = {0, 0, 0, 0, 0}; /* rho, mx, my, mz, U */
             for (int sz = 0; sz < 2; sz++)
@@ -180,6 +211,19 @@ int orc_remap(const orc_rcfg *cfg, const orc_rmesh *src, const double *Us, const
             q[0] = acc[0]; q[1] = acc[1]; q[2] = acc[2]; q[3] = acc[3];
             q[4] = acc[4] + 0.5 * (acc[1] * acc[1] + acc[2] * acc[2] + acc[3] * acc[3]) / acc[0];
             q[5] = acc[4];
+            uth0 = acc[4];
+          }
+          if (!excised_at(cfg, c, t) && !outside) {
+            double w = band_weight(src, dst, c);
+            if (w < 1.0) {
+              double uf = u_floor_r(cfg, cfg->rho_floor);
+              double rho = w * q[0] + (1.0 - w) * cfg->rho_floor;
+              double m[3] = {w * q[1], w * q[2], w * q[3]};
+              double uth = w * uth0 + (1.0 - w) * uf;
+              q[0] = rho; q[1] = m[0]; q[2] = m[1]; q[3] = m[2];
+              q[4] = uth + 0.5 * (m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) / rho;
+              q[5] = uth;
+            }
           }
           size_t l = ((size_t)k * n + j) * n + i;
           for (int v = 0; v < nv; v++) Ud[off + v * n3 + l] = q[v];

@@ -5,7 +5,12 @@
 //
 // Remap: one thread per target cell.  A target cell inside the excision
 // sphere takes the sink state and one whose centre lies outside the source
-// domain along a non-periodic axis the floor state; on a target grid that
+// domain along a non-periodic axis the floor state; within kBand source cells
+// inside a source face beyond which the target domain extends, the remapped
+// density, momentum and thermal energy density are blended toward the floor
+// state (at rest) with the weight s = 3u^2 - 2u^3 of the distance u to the
+// nearest such face in band widths, so density and pressure reach the floor
+// smoothly at the old domain's edge; on a target grid that
 // coincides with the source grid (same spacing, origin a whole number of
 // cells away) the source cell's conserved values are copied; otherwise the
 // cell averages the trilinear interpolant of the source density, momentum and
@@ -117,6 +122,28 @@ __device__ __forceinline__ bool excised_at(const Phys &p, const double *r, doubl
 __device__ __forceinline__ double u_floor_of(const Phys &p, double rho) {
   return p.eos_kind == 0 ? p.p_floor / (p.gamma - 1.0) : rho * p.e_floor;
 }
+
+constexpr double kBand = 2.0;  // width of the blending band in source cells
+
+// blending weight of target centre c (inside the source domain): 1 away from the
+// source faces the target domain extends beyond, falling smoothly to 0 at them
+__device__ __forceinline__ double band_weight(const MeshDev &S, const MeshDev &D, const double *c) {
+#pragma clang fp contract(off)
+  const int NS[3] = {S.nx, S.ny, S.nz}, ND[3] = {D.nx, D.ny, D.nz};
+  double u = 1.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (S.bc[a] == 0) continue;
+    const double lo = S.x0[a], hi = S.x0[a] + NS[a] * S.dx[a];
+    const double dlo = D.x0[a], dhi = D.x0[a] + ND[a] * D.dx[a];
+    const double w = kBand * S.dx[a];
+    if (dlo < lo) u = fmin(u, (c[a] - lo) / w);
+    if (dhi > hi) u = fmin(u, (hi - c[a]) / w);
+  }
+  if (u <= 0.0) return 0.0;
+  if (u >= 1.0) return 1.0;
+  return u * u * (3.0 - 2.0 * u);
+}
 }  // namespace
 
 template <int NV>
@@ -135,8 +162,9 @@ __global__ __launch_bounds__(kRmThreads) void remap_kernel(SrcView S, MeshDev D,
       const double lo = S.m.x0[d], hi = S.m.x0[d] + NS[d] * S.m.dx[d];
       if (S.m.bc[d] != 0 && (c[d] < lo || c[d] >= hi)) outside = true;
     }
-    double q[6];
-    if (excised_at(p, c, t) || outside) {
+    double q[6], uth0 = 0.0;  // conserved state; its thermal energy density
+    const bool sink = excised_at(p, c, t);
+    if (sink || outside) {
       const double uf = u_floor_of(p, p.rho_floor);
       q[0] = p.rho_floor;
       q[1] = q[2] = q[3] = 0.0;
@@ -148,6 +176,7 @@ __global__ __launch_bounds__(kRmThreads) void remap_kernel(SrcView S, MeshDev D,
 #pragma unroll
       for (int d = 0; d < 3; ++d) si[d] = src_axis(gi[d] + sh[d], NS[d], S.m.bc[d] == 0);
       src_cell<NV>(S, si[0], si[1], si[2], q);
+      uth0 = NV > 5 ? q[5] : q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0];
     } else {
 #pragma clang fp contract(off)
       double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -169,6 +198,23 @@ __global__ __launch_bounds__(kRmThreads) void remap_kernel(SrcView S, MeshDev D,
       q[3] = acc[3];
       q[4] = acc[4] + 0.5 * (acc[1] * acc[1] + acc[2] * acc[2] + acc[3] * acc[3]) / acc[0];
       q[5] = acc[4];
+      uth0 = acc[4];
+    }
+    if (!sink && !outside) {
+#pragma clang fp contract(off)
+      const double w = band_weight(S.m, D, c);
+      if (w < 1.0) {
+        const double uf = u_floor_of(p, p.rho_floor);
+        const double rho = w * q[0] + (1.0 - w) * p.rho_floor;
+        const double m0 = w * q[1], m1 = w * q[2], m2 = w * q[3];
+        const double uth = w * uth0 + (1.0 - w) * uf;
+        q[0] = rho;
+        q[1] = m0;
+        q[2] = m1;
+        q[3] = m2;
+        q[4] = uth + 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho;
+        q[5] = uth;
+      }
     }
     const int b = D.lmap[((gi[2] >> D.lat_shift) * D.ly + (gi[1] >> D.lat_shift)) * D.lx + (gi[0] >> D.lat_shift)];
     const BlockInfo B = D.blocks[b];

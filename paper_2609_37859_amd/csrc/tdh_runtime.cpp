@@ -619,22 +619,25 @@ static tdh_status require_window_boundary(tdh_ctx *c) {
   return TDH_OK;
 }
 
-extern "C" tdh_status tdh_reduce_dt(tdh_ctx *c, double *host_dtb, double *host_dt0, int8_t *host_levels,
-                                    int *host_lmax) {
-  CHECK_CTX(c);
+// The CFL reduction of tdh_reduce_dt: per-item
+// partial minima into part, per-block steps into dtb (device), then the level
+// assignment on the host.  stage_minima: take the minima the last window's
+// second stages left, where they hold this state's (the same values).
+static tdh_status reduce_dt_impl(tdh_ctx *c, double *part, double *dtb_dev, bool stage_minima, double *host_dtb,
+                                 double *host_dt0, int8_t *host_levels, int *host_lmax) {
   tdh_status s;
   if ((s = ready(c)) || (s = require_window_boundary(c))) return s;
   StageArgs a = base_args(c);
-  if (c->cfl_parts) {  // the last window's second stages left the tile minima of this state
-    HIPCHK(c, launch_cfl_blocks(c->d_cfl_part, c->nb, c->d_cfl_block_start, c->cfg.cfl, c->d_dtb, c->stream));
+  if (stage_minima && c->cfl_parts) {  // the last window's second stages left the tile minima of this state
+    HIPCHK(c, launch_cfl_blocks(c->d_cfl_part, c->nb, c->d_cfl_block_start, c->cfg.cfl, dtb_dev, c->stream));
     c->stats.kernel_launches += 1;
   } else {
-    HIPCHK(c, launch_cfl(a, c->cfg.cfl, c->t, c->d_cfl_item_block, c->cfl_nitems, c->d_cfl_part, c->nb,
-                         c->d_cfl_block_start, c->d_dtb, c->stream));
+    HIPCHK(c, launch_cfl(a, c->cfg.cfl, c->t, c->d_cfl_item_block, c->cfl_nitems, part, c->nb,
+                         c->d_cfl_block_start, dtb_dev, c->stream));
     c->stats.kernel_launches += 2;
     c->cfl_seeds = c->cfg.eos_kind == 1 && (c->cfg.inv_mode == 2 || c->cfg.inv_mode == 4);
   }
-  HIPCHK(c, hipMemcpyAsync(c->h_dtb, c->d_dtb, c->nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->h_dtb, dtb_dev, c->nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   std::vector<double> dtb(c->h_dtb, c->h_dtb + c->nb);
   double dt0;
@@ -651,6 +654,12 @@ extern "C" tdh_status tdh_reduce_dt(tdh_ctx *c, double *host_dtb, double *host_d
     for (int b = 0; b < c->nb; ++b) host_levels[b] = (int8_t)lev[b];
   if (host_lmax) *host_lmax = c->Lmax;
   return TDH_OK;
+}
+
+extern "C" tdh_status tdh_reduce_dt(tdh_ctx *c, double *host_dtb, double *host_dt0, int8_t *host_levels,
+                                    int *host_lmax) {
+  CHECK_CTX(c);
+  return reduce_dt_impl(c, c->d_cfl_part, c->d_dtb, true, host_dtb, host_dt0, host_levels, host_lmax);
 }
 
 extern "C" tdh_status tdh_set_levels(tdh_ctx *c, const int8_t *host_levels) {

@@ -202,13 +202,14 @@ class Context:
                     "tdh_set_eos_table")
 
     def reduce_dt(self):
+        """CFL reduction and level assignment: (dt_block, dt0, levels, Lmax)."""
         nb = self.mesh.nblocks
         dtb = np.zeros(nb)
         lev = np.zeros(nb, dtype=np.int8)
         dt0 = C.c_double()
         lmax = C.c_int()
-        self._check(self.L.tdh_reduce_dt(self.ctx, _dp(dtb), C.byref(dt0),
-                                         lev.ctypes.data_as(C.POINTER(C.c_int8)), C.byref(lmax)), "tdh_reduce_dt")
+        fn, name = self.L.tdh_reduce_dt, "tdh_reduce_dt"
+        self._check(fn(self.ctx, _dp(dtb), C.byref(dt0), lev.ctypes.data_as(C.POINTER(C.c_int8)), C.byref(lmax)), name)
         return dtb, dt0.value, lev.astype(np.int32), lmax.value
 
     def set_levels(self, levels):

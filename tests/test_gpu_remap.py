@@ -32,7 +32,7 @@ def _remap_gpu(T, cfg, src, U, dst, t=0.0):
     return out
 
 
-@pytest.mark.parametrize("case", ["identity", "refine_shifted", "coarsen", "outside_excision"])
+@pytest.mark.parametrize("case", ["identity", "refine_shifted", "coarsen", "outside_excision", "band_both_sides"])
 def test_remap_matches_the_oracle(tdh, orc, case):
     if case == "identity":
         cfg = W.Config(dual=1)
@@ -47,6 +47,11 @@ def test_remap_matches_the_oracle(tdh, orc, case):
     elif case == "coarsen":
         cfg = W.Config()
         src, dst = W.uniform_mesh(2, 2, 2, 16, 1.0 / 32), W.uniform_mesh(2, 2, 2, 8, 1.0 / 16)
+        t = 0.0
+    elif case == "band_both_sides":  # larger target on both x faces and the high y face, finer, table-free
+        cfg = W.Config(dual=1, rho_floor=1e-6, p_floor=1e-8)
+        src = W.uniform_mesh(2, 2, 2, 8, 1.0 / 16, bc=(1, 1, 0))
+        dst = W.uniform_mesh(5, 3, 2, 8, 1.0 / 24, x0=(-0.3, 0.1, 0.0), bc=(1, 1, 0))
         t = 0.0
     else:
         cfg = W.Config(dual=1, grav_kind=2, gm_bh=1.0, r_soft=0.01, r_exc=0.1, bh_x0=(0.5, 0.5, 0.5),

@@ -108,7 +108,46 @@ def test_remap_outside_and_excision(orc):
     inside = (X - (0.5 - 0.2 * t)) ** 2 + (Y - 0.5) ** 2 + (Z - 0.5) ** 2 < 0.01
     assert inside.sum() > 0
     assert np.all(G[0][:, :, :16][inside] == cfg.rho_floor) and np.all(G[1][:, :, :16][inside] == 0.0)
-    assert np.array_equal(G[:, :, :, :16][:, ~inside], W.to_global(src, 6, U)[:, ~inside])
+    # the coincident grid copies every other cell but those of the band inside
+    # the face the target extends beyond (x = 1: two source cells, 14 and 15)
+    keep = ~inside
+    keep[:, :, 14:] = False
+    assert np.array_equal(G[:, :, :, :16][:, keep], W.to_global(src, 6, U)[:, keep])
+
+
+def test_remap_blends_into_the_floor_across_a_band(orc):
+    """Target domain larger than the source on both sides of x (outflow): the
+    remapped state reaches the floor state smoothly.  Along x, density and
+    thermal pressure fall monotonically from the source values to the floor
+    values over the band inside each extended face and are unchanged beyond
+    it; density and pressure move by the same fraction of their way to the
+    floor (one blending weight); the velocity goes to rest; and where the
+    target does not extend past a face (y, z) nothing is blended."""
+    cfg = W.Config(rho_floor=1e-6, p_floor=1e-8)
+    src = W.uniform_mesh(2, 2, 2, 8, 1.0 / 16, bc=(1, 1, 1))
+    dst = W.uniform_mesh(4, 2, 2, 8, 1.0 / 16, x0=(-0.5, 0.0, 0.0), bc=(1, 1, 1))
+    rho0, P0, v0 = 2.0, 0.5, 0.3
+
+    def fn(x, y, z):
+        return W.ideal_conserved(rho0 + 0 * x, v0 + 0 * x, 0 * x, 0 * x, P0 + 0 * x, cfg.gamma, False)
+    U = W.pack_state(src, 5, fn)
+    G = W.to_global(dst, 5, orc.remap(cfg, src, U, dst))
+    rho = G[0]
+    P = (cfg.gamma - 1) * (G[4] - 0.5 * (G[1] ** 2 + G[2] ** 2 + G[3] ** 2) / G[0])
+    for a in (rho, P, G[1]):                       # uniform across y and z
+        assert np.all(a == a[:1, :1, :])
+    r, p, m = rho[0, 0], P[0, 0], G[1][0, 0]
+    # x cells 0..7 and 24..31 lie outside the source: floor; 8..23 inside
+    assert np.all(r[:8] == cfg.rho_floor) and np.all(r[24:] == cfg.rho_floor) and np.all(m[:8] == 0)
+    assert np.all(r[10:22] == rho0) and np.allclose(p[10:22], P0, rtol=1e-14)      # beyond the band
+    band = np.r_[8:10, 22:24]
+    assert np.all((r[band] > cfg.rho_floor) & (r[band] < rho0))
+    assert r[8] < r[9] and r[23] < r[22]                                       # rising into the domain
+    fr = (r[band] - cfg.rho_floor) / (rho0 - cfg.rho_floor)
+    fp = (p[band] - cfg.p_floor) / (P0 - cfg.p_floor)
+    assert np.allclose(fr, fp, rtol=1e-12)
+    assert np.allclose(m[band], fr * rho0 * v0, rtol=1e-12)                   # velocity brought to rest the same way
+    assert np.allclose(fr[:2], fr[2:][::-1], rtol=1e-12)                       # symmetric faces
 
 
 def test_galilean_boost(orc):
