@@ -565,6 +565,38 @@ __device__ __forceinline__ ItemRange xcd_items(int i0, int i1) {
   return r;
 }
 
+// Work items of a launch over levels Llo..Lhi (blocks sorted finest level
+// first, item prefix `start` over that order), level by level from the finest,
+// each level's items shared among the XCDs as by xcd_items: every XCD gets its
+// share of every level, so a launch that mixes levels is balanced across the
+// XCDs as separate per-level launches would be.
+struct LevelItems {
+  const int *cnt_ge, *start;
+  int L, Llo, item;
+  ItemRange R;
+  __device__ __forceinline__ LevelItems(const StageArgs &a, const int *st) : cnt_ge(a.cnt_ge), start(st) {
+    Llo = a.Llo;
+    L = min(a.Lhi, a.lmax) + 1;
+    item = 0;
+    R.first = R.end = R.step = 0;
+    advance_level();
+  }
+  __device__ __forceinline__ void advance_level() {
+    while (--L >= Llo) {
+      const int b0 = cnt_ge[L + 1], b1 = cnt_ge[L];
+      if (b1 <= b0) continue;
+      R = xcd_items(start[b0], start[b1]);
+      item = R.first;
+      if (item < R.end) return;
+    }
+  }
+  __device__ __forceinline__ bool valid() const { return L >= Llo; }
+  __device__ __forceinline__ void next() {
+    item += R.step;
+    if (item >= R.end) advance_level();
+  }
+};
+
 struct TileCtx {
   int b;
   BlockInfo B;
@@ -590,20 +622,21 @@ __device__ __forceinline__ void plm_face(double q0, double q1, double q2, double
 // flux or the time-integrated impulse.  Gf receives the fluxes in conserved
 // order (slots 0..NV-1) and the face velocity (slot 6).
 //   fr: local coordinates of the cell right of the face; nbo: block owning the
-//   cell across a block face (-1 beyond an outflow edge); seedl: seed cell of
-//   the left state (-1: none).
+//   cell across a block face (-1 beyond an outflow edge); seedl, seedr: seed
+//   cells of the left and right states (-1: none).  The two seeds come from
+//   the cells' centre states, so the two EOS evaluations do not wait on each
+//   other.
 template <int NV, int D, int PK = 0>
 __device__ __forceinline__ void face_flux(const StageArgs &a, const BlockInfo &B, int fb, double t, double dtb,
-                                          const int *fr, const double *wl, const double *wr, int seedl, int nbo,
-                                          double *Gf, int excl = -1, int excr = -1) {
+                                          const int *fr, const double *wl, const double *wr, int seedl, int seedr,
+                                          int nbo, double *Gf, int excl = -1, int excr = -1) {
   constexpr int PN = 1 + D, P1 = 1 + (D + 1) % 3, P2 = 1 + (D + 2) % 3;
   const Phys &p = a.p;
   const MeshDev &m = a.m;
   const int n = B.n;
   double pl, cl, pr, cr;
-  int jl = -1;
-  eos_pc<PK>(p, a.t, wl[0], wl[4], seedl, pl, cl, &jl);
-  eos_pc<PK>(p, a.t, wr[0], wr[4], p.inv_mode == 0 ? -1 : jl, pr, cr);
+  eos_pc<PK>(p, a.t, wl[0], wl[4], seedl, pl, cl);
+  eos_pc<PK>(p, a.t, wr[0], wr[4], seedr, pr, cr);
   double F[5];
   if (k_riemann<PK>(p) == 1) hlle(wl, pl, cl, wr, pr, cr, F);
   else hllc(wl, pl, cl, wr, pr, cr, F);
@@ -876,13 +909,15 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
       const double *col = sW + perm[vv] * SW;
       plm_face(col[sl[0]], col[sl[1]], col[sl[2]], col[sl[3]], wl[vv], wr[vv]);
     }
-    int seedl = -1;
+    int seedl = -1, seedr = -1;
     if (k_eos<PK>(p) == 1 && p.inv_mode != 0) {
-      // seed the left state from the table cell of the adjacent tile cell's centre
-      int tc[3] = {fc[0], fc[1], fc[2]};
-      if (tc[D] > 0) tc[D] -= 1;
-      if (tc[D] >= TD) tc[D] -= 1;
-      seedl = sJc[tc[0] + TX * (tc[1] + TY * tc[2])];
+      // seed each state from the table cell of its cell's centre (the nearest
+      // tile cell where its cell is a halo cell)
+      int tl[3] = {fc[0], fc[1], fc[2]}, tr[3] = {fc[0], fc[1], fc[2]};
+      if (tl[D] > 0) tl[D] -= 1;
+      if (tr[D] >= TD) tr[D] = TD - 1;
+      seedl = sJc[tl[0] + TX * (tl[1] + TY * tl[2])];
+      seedr = sJc[tr[0] + TX * (tr[1] + TY * tr[2])];
     }
     const int fr[3] = {T.to[0] + fc[0], T.to[1] + fc[1], T.to[2] + fc[2]};  // cell right of the face
     const int side = fr[D] == T.B.n;
@@ -890,9 +925,9 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
     const int nbo = (fr[D] == 0 || side) ? sB[(side ? sl[2] : sl[1]) - G::TV] : T.b;
     double Gf[7];
     if constexpr (k_gcache<PK>())
-      face_flux<NV, D, PK>(a, T.B, T.fb, T.t, T.dtb, fr, wl, wr, seedl, nbo, Gf, sExc[sl[1]], sExc[sl[2]]);
+      face_flux<NV, D, PK>(a, T.B, T.fb, T.t, T.dtb, fr, wl, wr, seedl, seedr, nbo, Gf, sExc[sl[1]], sExc[sl[2]]);
     else
-      face_flux<NV, D, PK>(a, T.B, T.fb, T.t, T.dtb, fr, wl, wr, seedl, nbo, Gf);
+      face_flux<NV, D, PK>(a, T.B, T.fb, T.t, T.dtb, fr, wl, wr, seedl, seedr, nbo, Gf);
 #pragma unroll
     for (int v = 0; v < NV; ++v) sF[v * G::NF + f] = Gf[v];
     sF[6 * G::NF + f] = Gf[6];
@@ -949,13 +984,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) 
   __shared__ unsigned char sExc[GC];   // their excision flags
   const Phys &p = a.p;
   const MeshDev &m = a.m;
-  const int a0 = a.cnt_ge[a.Lhi + 1], a1 = a.cnt_ge[a.Llo];
-  if (a1 <= a0) return;
-  const int i0 = a.item_start[a0], i1 = a.item_start[a1];
   const double dt0 = a.win[1];
   const double tk = a.win[0] + a.k * dt0;
-  const ItemRange R = xcd_items(i0, i1);
-  for (int item = R.first; item < R.end; item += R.step) {
+  for (LevelItems it(a, a.item_start); it.valid(); it.next()) {
+    const int item = it.item;
     const int tid = item_tid();
     const int2 bt = a.item_bt[item];
     TileCtx T;
@@ -1076,17 +1108,19 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
 #pragma unroll
     for (int vv = 0; vv < NV; ++vv)
       plm_face(W[0][perm[vv]], W[1][perm[vv]], W[2][perm[vv]], W[3][perm[vv]], wl[vv], wr[vv]);
-    int seedl = -1;
+    int seedl = -1, seedr = -1;
     if (p.eos_kind == 1 && p.inv_mode != 0) {
-      // seed the left state from the table cell of the nearest own cell left of the face
-      int tc[3] = {fr[0], fr[1], fr[2]};
-      if (tc[D] > 0) tc[D] -= 1;
-      if (tc[D] >= n) tc[D] = n - 1;
+      // seed each state from the table cell of the nearest own cell on its side of the face
+      int tl[3] = {fr[0], fr[1], fr[2]}, tr[3] = {fr[0], fr[1], fr[2]};
+      if (tl[D] > 0) tl[D] -= 1;
+      if (tr[D] >= n) tr[D] = n - 1;
       const int parb = uni(a.par[b]);
-      seedl = a.jc[jseg_in(a, parb) * a.jn + B.off / NV + ((long long)tc[2] * n + tc[1]) * n + tc[0]];
+      const long long base = jseg_in(a, parb) * a.jn + B.off / NV;
+      seedl = a.jc[base + ((long long)tl[2] * n + tl[1]) * n + tl[0]];
+      seedr = a.jc[base + ((long long)tr[2] * n + tr[1]) * n + tr[0]];
     }
     double Gf[7];
-    face_flux<NV, D>(a, B, fb, t, dtb, fr, wl, wr, seedl, nbo, Gf);
+    face_flux<NV, D>(a, B, fb, t, dtb, fr, wl, wr, seedl, seedr, nbo, Gf);
     double *F = a.flx + D * a.fstride + (NV + 1) * B.foff;
 #pragma unroll
     for (int v = 0; v < NV; ++v) F[v * nf + f] = Gf[v];
@@ -1180,9 +1214,7 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
 // multiple of 256 cells, so every wave is full when it calls the network.
 template <int NV>
 __global__ __launch_bounds__(kChunk) void seed_kernel(StageArgs a) {
-  const int a0 = a.cnt_ge[a.Lhi + 1], a1 = a.cnt_ge[a.Llo];
-  if (a1 <= a0) return;
-  const int i0 = a.item_start[a0], i1 = a.item_start[a1];
+  if (a.cnt_ge[a.Llo] <= a.cnt_ge[a.Lhi + 1]) return;
   const Phys &p = a.p;
   const int nv = NV;
   const bool net = (p.inv_mode == 1 || p.inv_mode == 4) && a.s.enabled;
@@ -1208,9 +1240,8 @@ __global__ __launch_bounds__(kChunk) void seed_kernel(StageArgs a) {
     else if (t == 56) s_b[128] = a.s.w.b3[0];
     __syncthreads();
   }
-  const ItemRange R = xcd_items(i0, i1);
-  for (int item = R.first; item < R.end; item += R.step) {
-    const int2 bt = a.item_bt[item];
+  for (LevelItems li(a, a.item_start); li.valid(); li.next()) {
+    const int2 bt = a.item_bt[li.item];
     const int b = uni(bt.x);
     const BlockInfo B = uni(a.m.blocks[b]);
     const long long n3 = (long long)B.n * B.n * B.n;
