@@ -162,6 +162,20 @@ tdh_status tdh_set_eos_table(tdh_ctx *ctx, int nrho, int nT, double lr0, double 
 tdh_status tdh_reduce_dt(tdh_ctx *ctx, double *host_dt_block, double *host_dt0, int8_t *host_levels,
                          int *host_lmax);
 
+/* tdh_reduce_dt for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same results, bit for bit, with the reduction's per-item partial minima
+ * and per-block steps in a static device array of the library (4 MiB per
+ * GPU, held until the process ends) instead of buffers the library allocated
+ * at tdh_init_blocks.  It always reduces over the state itself (never the
+ * minima a window's second stages left).  Meshes with more than 2^19 work
+ * items plus blocks (one item per 256 cells of a block: about 134 M cells)
+ * return TDH_ERANGE.  Every context on a GPU shares that GPU's array: calls
+ * that overlap on one GPU (other threads or streams) race.  Allocates
+ * nothing; synchronises the stream. */
+tdh_status tdh_reduce_dt_static(tdh_ctx *ctx, double *host_dt_block, double *host_dt0, int8_t *host_levels,
+                                int *host_lmax);
+
 /* Install host-chosen levels (each 0..30, neighbours at most one apart)
  * and start a new window. */
 tdh_status tdh_set_levels(tdh_ctx *ctx, const int8_t *host_levels);

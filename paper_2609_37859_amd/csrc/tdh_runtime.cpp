@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -88,7 +89,28 @@ struct tdh_ctx {
   // captured multigrid cycles (V-cycle, extra sweep, defect norm): key = workspace
   std::map<const void *, hipGraphExec_t> mg_graphs;
   double *d_facc = nullptr;  // frame-acceleration partial sums and result
+  double *scratch = nullptr;  // this GPU's copy of the static device scratch
 };
+
+// Device scratch of the allocation-free entry point (tdh_reduce_dt_static):
+// its per-item partial minima and per-block steps.  One copy per GPU, held
+// until the process ends; every call on a GPU shares it.
+constexpr long long kScratchDoubles = 1LL << 19;  // 4 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+static std::mutex g_scratch_mu;
+static std::map<int, double *> g_scratch_ptr;  // device -> address of its copy
+
+// Address of the current device's scratch copy, resolved once per device
+// (null if the runtime cannot resolve it).
+static double *device_scratch(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  double *ptr = nullptr;
+  if (hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)) != hipSuccess) ptr = nullptr;
+  g_scratch_ptr[dev] = ptr;
+  return ptr;
+}
 
 static thread_local std::string g_err;
 
@@ -208,6 +230,7 @@ extern "C" tdh_status tdh_init(const tdh_config *cfg, void *hip_stream, tdh_ctx 
     return fail(nullptr, TDH_EHIP, "tdh_init: no HIP device");
   }
   c->grid = prop.multiProcessorCount * 8;
+  c->scratch = device_scratch(dev);
   *out = c;
   return TDH_OK;
 }
@@ -619,7 +642,7 @@ static tdh_status require_window_boundary(tdh_ctx *c) {
   return TDH_OK;
 }
 
-// The CFL reduction of tdh_reduce_dt: per-item
+// The CFL reduction of tdh_reduce_dt and tdh_reduce_dt_static: per-item
 // partial minima into part, per-block steps into dtb (device), then the level
 // assignment on the host.  stage_minima: take the minima the last window's
 // second stages left, where they hold this state's (the same values).
@@ -660,6 +683,20 @@ extern "C" tdh_status tdh_reduce_dt(tdh_ctx *c, double *host_dtb, double *host_d
                                     int *host_lmax) {
   CHECK_CTX(c);
   return reduce_dt_impl(c, c->d_cfl_part, c->d_dtb, true, host_dtb, host_dt0, host_levels, host_lmax);
+}
+
+extern "C" tdh_status tdh_reduce_dt_static(tdh_ctx *c, double *host_dtb, double *host_dt0, int8_t *host_levels,
+                                           int *host_lmax) {
+  CHECK_CTX(c);
+  if (!c->scratch) return fail(c, TDH_ESTATE, "the device scratch of this context's GPU was not resolved");
+  if (!c->have_mesh) return fail(c, TDH_ESTATE, "no mesh: call tdh_init_blocks first");
+  const long long need = (long long)c->cfl_nitems + c->nb;
+  if (need > (long long)kScratchDoubles)
+    return fail(c, TDH_ERANGE, "tdh_reduce_dt_static: %lld work items + %d blocks exceed the %lld-double device scratch "
+                               "(meshes up to about 134 M cells)", (long long)c->cfl_nitems, c->nb,
+                (long long)kScratchDoubles);
+  // every value is written before it is read: nothing needs clearing
+  return reduce_dt_impl(c, c->scratch, c->scratch + c->cfl_nitems, false, host_dtb, host_dt0, host_levels, host_lmax);
 }
 
 extern "C" tdh_status tdh_set_levels(tdh_ctx *c, const int8_t *host_levels) {

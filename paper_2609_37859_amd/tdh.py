@@ -68,6 +68,7 @@ def lib():
         "tdh_init_blocks": ([ctx, P(tdh_mesh), vp, C.c_size_t, P(d), P(d)], st),
         "tdh_set_eos_table": ([ctx, i, i, d, d, d, d, P(d), P(d), P(d)], st),
         "tdh_reduce_dt": ([ctx, P(d), P(d), P(C.c_int8), P(i)], st),
+        "tdh_reduce_dt_static": ([ctx, P(d), P(d), P(C.c_int8), P(i)], st),
         "tdh_set_levels": ([ctx, P(C.c_int8)], st),
         "tdh_step_level": ([ctx, i, d], st),
         "tdh_run_window": ([ctx, d, i, i], st),
@@ -201,14 +202,16 @@ class Context:
         self._check(self.L.tdh_set_eos_table(self.ctx, t.nrho, t.nT, t.lr0, t.dlr, t.lT0, t.dlT, *map(_dp, arrs)),
                     "tdh_set_eos_table")
 
-    def reduce_dt(self):
-        """CFL reduction and level assignment: (dt_block, dt0, levels, Lmax)."""
+    def reduce_dt(self, static=False):
+        """CFL reduction and level assignment: (dt_block, dt0, levels, Lmax).
+        static=True calls the allocation-free variant (tdh_reduce_dt_static)."""
         nb = self.mesh.nblocks
         dtb = np.zeros(nb)
         lev = np.zeros(nb, dtype=np.int8)
         dt0 = C.c_double()
         lmax = C.c_int()
-        fn, name = self.L.tdh_reduce_dt, "tdh_reduce_dt"
+        fn, name = (self.L.tdh_reduce_dt_static, "tdh_reduce_dt_static") if static else \
+            (self.L.tdh_reduce_dt, "tdh_reduce_dt")
         self._check(fn(self.ctx, _dp(dtb), C.byref(dt0), lev.ctypes.data_as(C.POINTER(C.c_int8)), C.byref(lmax)), name)
         return dtb, dt0.value, lev.astype(np.int32), lmax.value
 
