@@ -178,15 +178,19 @@ def run_form(T, W, cfg, mesh, U, table, steps, warmup, inv_mode, batched, seed_p
 
 
 def run_lat(T, W, cfg, mesh, U, windows, warmup, inv_mode=0, batched=True, graph=False, table=None, phi=None,
-            seed_params=None):
+            seed_params=None, tile=-1):
     """LAT windows (reduce_dt, level assignment, one window of 2^Lmax sub-cycles)
-    timed end to end; returns rates from the library's own update counters."""
+    timed end to end; returns rates from the library's own update counters.
+    tile < 0: the autotuner picks the stage variant (its id is returned)."""
     import torch
     ctx = T.Context(cfg, mesh, U, phi=phi, table=table, inv_mode=inv_mode)
     if seed_params is not None:
         ctx.mlp_init(seed_params, W.seed_ranges(table))
         ctx.mlp_enable_seed(True)
-    ctx.autotune(reps=3)
+    if tile >= 0:
+        ctx.set_tile(tile)
+    else:
+        ctx.autotune(reps=3)
     for _ in range(warmup):
         _, dt0, lev, L = ctx.reduce_dt()
         ctx.run_window(dt0 * 2 ** L, batched=batched, graph=graph)
@@ -205,14 +209,15 @@ def run_lat(T, W, cfg, mesh, U, windows, warmup, inv_mode=0, batched=True, graph
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     st1 = ctx.stats()
-    tile = T.tile_shapes()[ctx.get_tile()]
+    tile_id = ctx.get_tile()
+    tile = T.tile_shapes()[tile_id]
     ctx.close()
     cu = st1["cell_updates"] - st0["cell_updates"]
     bu = st1["block_updates"] - st0["block_updates"]
     return {"value": cu / el, "sync_equivalent": sync_equiv / el, "ms_per_window": 1e3 * el / windows,
             "windows": windows, "block_updates": int(bu), "block_updates_sync": int(sync_equiv // mesh.ncells *
                                                                                       mesh.nblocks),
-            "levels": [int(v) for v in np.trim_zeros(hist, "b")], "tile": tile}
+            "levels": [int(v) for v in np.trim_zeros(hist, "b")], "tile": tile, "tile_id": tile_id}
 
 
 def lat_section(T, W, windows, warmup):
@@ -220,11 +225,14 @@ def lat_section(T, W, windows, warmup):
     from a graph beside one launch per level."""
     cfg, mesh, U, phi, info = W.polytrope_c3()
     cfg = dataclasses.replace(cfg, merge_frac=0.01)  # performance runs merge sparse top bins
+    batched = run_lat(T, W, cfg, mesh, U, windows, warmup, batched=True, graph=True, phi=phi)
     return {
         "workload": "256^3 as 512 MeshBlocks of 32^3, n=1.5 polytrope (1 Msun, 1 Rsun) in a 1e-10 atmosphere, fixed "
                     "potential, ideal gas, N_LAT=3, merge_frac 0.01, outflow",
-        "batched_graph": run_lat(T, W, cfg, mesh, U, windows, warmup, batched=True, graph=True, phi=phi),
-        "plain": run_lat(T, W, cfg, mesh, U, windows, warmup, batched=False, graph=False, phi=phi)}
+        "note": "both forms use the stage variant the autotuner picked for the batched form",
+        "batched_graph": batched,
+        "plain": run_lat(T, W, cfg, mesh, U, windows, warmup, batched=False, graph=False, phi=phi,
+                         tile=batched["tile_id"])}
 
 
 C5_WORKLOAD = ("production-shaped: 4096 MeshBlocks (1688 x 32^3 + 2408 x 16^3, 65.2M cells), Saha H/He table EOS "
@@ -617,7 +625,7 @@ def main():
     ap.add_argument("--oracle-windows", type=int, default=2, help="windows of the oracle on the 512-block sub-domain")
     ap.add_argument("--no-single-thread", action="store_true", help="skip the single-thread oracle window")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps of the c2 accuracy check (0: skip)")
-    ap.add_argument("--lat-windows", type=int, default=5, help="timed windows per form on the polytrope")
+    ap.add_argument("--lat-windows", type=int, default=10, help="timed windows per form on the polytrope")
     ap.add_argument("--gravity-cycles", type=int, default=10, help="timed multigrid V-cycles on the 256^3 Jeans wave")
     ap.add_argument("--gravity-steps", type=int, default=10, help="timed coupled steps on the 256^3 Jeans wave")
     ap.add_argument("--remap-reps", type=int, default=5, help="timed restart remaps")

@@ -1203,15 +1203,19 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
   }
 }
 
-// Table cell of every active cell's stage-input centre state.  Modes 1 and 4
-// start the search from the learned network's prediction (its hidden layer on
-// the matrix cores), modes 2 and 3 bisect; all end at the same, exact cell,
-// which seeds the stage kernel's face and compression queries.  Modes 1 and 3
-// run it once after a state upload; afterwards each stage leaves the cells of
-// its output for the next.  Modes 2 and 4 run it before every stage except a
-// window's first when the CFL pass has recorded (bisected) the cells of its
-// state.  Blocks hold a
-// multiple of 256 cells, so every wave is full when it calls the network.
+// Table cell of every active cell's stage-input centre state, which seeds the
+// stage kernel's face and compression queries; every start ends at the same,
+// exact cell.  Modes 1 and 3 run it once after a state upload (afterwards each
+// stage leaves the cells of its output for the next): mode 1 starts every
+// search from the learned network's prediction (all three layers on the matrix
+// cores), mode 3 bisects.  Modes 2 and 4 run it before every stage except a
+// window's first when the CFL pass has recorded the cells of its state: a cell
+// first tries the cell held for its previous state (for a second stage the
+// stage input's, for a first stage the last stage-1 state's) and keeps it if it
+// brackets; where it does not, or none is held, mode 2 bisects and mode 4
+// searches from the network's prediction, which a wave evaluates when any of
+// its cells needs it.  Blocks hold a multiple of 256 cells, so every wave is
+// full when it calls the network.
 template <int NV>
 __global__ __launch_bounds__(kChunk) void seed_kernel(StageArgs a) {
   if (a.cnt_ge[a.Llo] <= a.cnt_ge[a.Lhi + 1]) return;
@@ -1254,11 +1258,26 @@ __global__ __launch_bounds__(kChunk) void seed_kernel(StageArgs a) {
     c2p(p, q, w);
     const double Ue = fmax(w[4], w[0] * p.e_floor);
     const double lr = log10_tab(a.t.lg, w[0]), le = log10_tab(a.t.lg, Ue / w[0]);
-    const int seed = net ? seed_cell_wave<true>(sd, a.t, lr, le) : -1;
-    int i, j, it;
+    int i, j = -1, it;
     double wr, wT;
     table_rho(a.t, lr, i, wr);
-    table_invert(a.t, i, wr, le, seed, p.newton_max_iter, j, wT, it);
+    if (p.inv_mode == 2 || p.inv_mode == 4) {
+      // the cell held for the previous state: a second stage's input follows
+      // the stage input's (segment of the block's current state), a first
+      // stage's the last stage-1 state's (segment 2)
+      const int prev = a.jc[(a.phase == 2 ? (long long)parb : 2LL) * a.jn + B.off / nv + cell];
+      if (prev >= 0) {
+        const int jj = min(prev, a.t.nT - 2);
+        double lP, lc2;
+        if (table_record(a.t, i, wr, le, jj, wT, lP, lc2)) j = jj;
+      }
+    }
+    if (!net || (p.inv_mode == 4 && __ballot(j < 0) == 0)) {
+      if (j < 0) table_invert(a.t, i, wr, le, -1, p.newton_max_iter, j, wT, it);
+    } else {
+      const int seed = seed_cell_wave<true>(sd, a.t, lr, le);  // the whole wave
+      if (j < 0) table_invert(a.t, i, wr, le, seed, p.newton_max_iter, j, wT, it);
+    }
     a.jc[jseg_in(a, parb) * a.jn + B.off / nv + cell] = j;
   }
 }
