@@ -137,6 +137,9 @@ def main():
     ap.add_argument("--kernel", default="stage_tiled")
     ap.add_argument("--sq", action="append", default=[], help="directory of a --pmc run of SQ counters (repeatable)")
     ap.add_argument("--cells", type=float, default=0.0, help="cells one launch of the kernel updates (per-cell rates)")
+    ap.add_argument("--windows", type=int, default=0, help="LAT windows in the run: list every kernel per window")
+    ap.add_argument("--alg-bytes", type=float, default=0.0,
+                    help="algorithmic HBM bytes of all the kernel's launches in the counter runs")
     ap.add_argument("--cmd", action="append", default=[], help="command that produced the inputs (repeatable)")
     ap.add_argument("--title", default="stage kernel")
     ap.add_argument("--out", required=True)
@@ -160,6 +163,15 @@ def main():
                      f"{float(r['MinNs']) / 1e6:.4f} | {float(r['MaxNs']) / 1e6:.4f} |")
     lines += ["", f"Variant used after tuning: `{used['Name']}`, average {float(used['AverageNs']) / 1e6:.4f} ms "
                   f"over {used['Calls']} launches.", ""]
+    if args.windows > 0:
+        allrows = [r for r in csv.DictReader(open(_one(args.stats, "*kernel_stats.csv"))) if "tdh::" in r["Name"]]
+        allrows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+        lines += [f"Every library kernel of the run, per window ({args.windows} windows; the network's training "
+                  "kernels ran once before them):", "", "| kernel | calls | ms per window |", "|---|---|---|"]
+        for r in allrows:
+            nm = r["Name"].split("(")[0]
+            lines.append(f"| `{nm}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6 / args.windows:.3f} |")
+        lines.append("")
     out = {"kernel": used["Name"], "avg_launch_ms": float(used["AverageNs"]) / 1e6, "kernel_hash": kernel_source_hash()}
     if args.fetch and args.write and args.copy_fetch and args.copy_write:
         f_k = copy_factor(args.copy_fetch, "FETCH_SIZE", args.copy_bytes)
@@ -175,6 +187,11 @@ def main():
                   f"- total {(fb + wb) / 1e6:.2f} MB per launch", ""]
         out.update({"hbm_read_bytes_per_launch": fb, "hbm_write_bytes_per_launch": wb,
                     "hbm_bytes_per_launch": fb + wb, "fetch_factor": f_k, "write_factor": w_k})
+        if args.alg_bytes > 0:
+            ratio = (fb + wb) * len(fv) / args.alg_bytes
+            lines += [f"- against the algorithmic bytes of those launches ({args.alg_bytes / 1e9:.1f} GB): "
+                      f"{ratio:.2f} x", ""]
+            out["traffic_over_algorithmic"] = ratio
     for d in args.sq:
         tab = counter_table(d, used["Name"])
         if not tab:
