@@ -46,7 +46,7 @@ class _Cfg(C.Structure):
 class _Mesh(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("bc", C.c_int * 3),
                 ("x0", C.c_double * 3), ("dx", C.c_double * 3), ("nblocks", C.c_int),
-                ("blk", C.POINTER(C.c_int))]
+                ("blk", C.POINTER(C.c_int)), ("rlev", C.POINTER(C.c_int))]
 
 
 class _Table(C.Structure):
@@ -74,6 +74,8 @@ def lib():
         _lib.orc_lat_assign.restype = i
         _lib.orc_lat_window.argtypes = [P(_Cfg), P(_Mesh), P(_Table), P(d), P(d), P(i), d, d]
         _lib.orc_lat_window.restype = C.c_int64
+        _lib.orc_ghost_fill.argtypes = [P(_Cfg), P(_Mesh), P(d), i, P(d)]
+        _lib.orc_ghost_fill.restype = i
         _lib.orc_eos_eval.argtypes = [P(_Cfg), P(_Table), C.c_int64, P(d), P(d), P(d), P(d)]
         _lib.orc_eos_eval.restype = None
         _lib.orc_table_invert.argtypes = [P(_Table), C.c_int64, P(d), P(d), P(i), P(d), P(d)]
@@ -142,6 +144,11 @@ class _Keep:
             m.dx[:] = list(mesh.dx)
             m.nblocks = mesh.nblocks
             m.blk = _ip(self.blk)
+            if getattr(mesh, "rlev", None) is not None:
+                self.rlev = np.ascontiguousarray(mesh.rlev, dtype=np.int32)
+                if self.rlev.shape != (mesh.nblocks,):
+                    raise ValueError("rlev needs one refinement level per block")
+                m.rlev = _ip(self.rlev)
             self.mesh = m
         self.table = None
         if table is not None:
@@ -258,11 +265,20 @@ def mg_levels(nx, ny, nz):
     return [tuple(int(v) for v in dims[3 * l:3 * l + 3]) for l in range(n)]
 
 
+def _single_level(*meshes):
+    """Self-gravity, the restart remap and the frame estimators work on one
+    refinement level."""
+    for m in meshes:
+        if getattr(m, "refined", False):
+            raise ValueError("this oracle routine needs a single-level mesh")
+
+
 def mg_solve(mesh, nv, U, four_pi_G, max_cycles, tol=0.0, phi_global=None):
     """Self-gravity potential of state U by multigrid V-cycles (periodic).
     Returns (phi_global [nz, ny, nx], phi_blocks (per block (n+2)^3), cycles,
     rms defects before and after each cycle).  phi_global, if given, is the
     warm start."""
+    _single_level(mesh)
     k = _Keep(_DummyCfg(), mesh, None)
     U = np.ascontiguousarray(U, dtype=np.float64)
     warm = phi_global is not None
@@ -279,6 +295,7 @@ def mg_solve(mesh, nv, U, four_pi_G, max_cycles, tol=0.0, phi_global=None):
 def remap(cfg, mesh_src, U_src, mesh_dst, t=0.0):
     """Restart remap of the state U_src on mesh_src onto mesh_dst (cfg: floors,
     dual energy and excision of the target run).  Returns the target state."""
+    _single_level(mesh_src, mesh_dst)
     ks = _Keep(cfg, mesh_src, None, need_table=False)
     kd = _Keep(cfg, mesh_dst, None, need_table=False)
     U_src = np.ascontiguousarray(U_src, dtype=np.float64)
@@ -288,6 +305,7 @@ def remap(cfg, mesh_src, U_src, mesh_dst, t=0.0):
 
 
 def galilean_boost(cfg, mesh, U, V, rho_skip):
+    _single_level(mesh)
     k = _Keep(cfg, mesh, None, need_table=False)
     U = np.ascontiguousarray(U, dtype=np.float64).copy()
     Va = np.ascontiguousarray(V, dtype=np.float64)
@@ -296,6 +314,7 @@ def galilean_boost(cfg, mesh, U, V, rho_skip):
 
 
 def frame_acceleration(cfg, mesh, U, rho_min, t=0.0):
+    _single_level(mesh)
     k = _Keep(cfg, mesh, None, need_table=False)
     U = np.ascontiguousarray(U, dtype=np.float64)
     A = np.zeros(3)
@@ -321,6 +340,18 @@ class threads:
     def __exit__(self, *exc):
         lib().orc_set_num_threads(self.prev)
         return False
+
+
+def ghost_fill(cfg, mesh, U, b):
+    """Padded stage input [nv, n+4, n+4, n+4] (index [v, k, j, i], two ghost
+    layers) of block b when every stored history equals U."""
+    k = _Keep(cfg, mesh, None, need_table=False)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    n = int(mesh.blk[b, 0])
+    out = np.zeros(cfg.nv * (n + 4) ** 3)
+    if lib().orc_ghost_fill(C.byref(k.cfg), C.byref(k.mesh), _dp(U), int(b), _dp(out)) != 0:
+        raise ValueError("oracle ghost_fill rejected its input")
+    return out.reshape(cfg.nv, n + 4, n + 4, n + 4)
 
 
 def run_lat(cfg, mesh, U, windows, table=None, phi=None, t0=0.0):

@@ -28,6 +28,14 @@
  *     interpolation, reflux with gravity work                  (Sec. LAT method; eqs lat-base-dt,
  *                                                              lat-factor, lat-flux-impulse,
  *                                                              lat-mass-impulse-mismatch, lat-grav-reflux)
+ *   - two refinement levels under LAT: the coarse-fine factor
+ *     rule, ghost states restricted from finer histories,
+ *     interpolated in time and prolonged into finer ghosts,
+ *     and the coarse side's flux correction at coarse-fine
+ *     faces                                                    (Sec. LAT method)
+ * Prolongation is piecewise linear with minmod-limited slopes on the
+ * conserved variables, restriction the mean of the 2x2x2 children: the
+ * paper names the operations and their order, not the operators.
  * The Riemann solver is HLLC (Toro, Riemann Solvers and Numerical Methods for
  * Fluid Dynamics, 3rd ed., Sec. 10.4, with Davis wave-speed estimates) or, by
  * configuration, the HLLE solver of the paper's production runs (Table 1;
@@ -64,11 +72,13 @@ typedef struct {
 } orc_cfg;
 
 typedef struct {
-  int nx, ny, nz;  /* global cells */
+  int nx, ny, nz;  /* global cells of refinement level 0 */
   int bc[3];       /* 0 periodic, 1 outflow (zero gradient) */
-  double x0[3], dx[3];
+  double x0[3], dx[3]; /* cell widths of refinement level 0 */
   int nblocks;
-  const int *blk;  /* [nblocks][4] = n, ox, oy, oz (global cell origin) */
+  const int *blk;  /* [nblocks][4] = n, ox, oy, oz (global cell origin at the block's level) */
+  const int *rlev; /* [nblocks] refinement level of each block (0 or 1; NULL: all 0); level r has
+                      cell widths dx / 2^r and global extents (nx, ny, nz) * 2^r */
 } orc_mesh;
 
 typedef struct {
@@ -85,8 +95,10 @@ typedef struct {
   const orc_mesh *m;
   const orc_table *tab;
   int nv;
-  int lat, lx, ly, lz;
+  int lat, lx, ly, lz; /* lattice edge in level-0 cells, lattice cells per axis */
   int *lmap;     /* lattice cell -> block */
+  int *rl;       /* refinement level of each block */
+  int rmax;      /* largest refinement level */
   size_t *off;   /* state offset of each block (doubles) */
   size_t *poff;  /* potential offset of each block */
   size_t *ioff;  /* impulse offset of each block */
@@ -94,19 +106,30 @@ typedef struct {
 } mesh_t;
 
 static void mesh_free(mesh_t *M) {
-  free(M->lmap); free(M->off); free(M->poff); free(M->ioff);
+  free(M->lmap); free(M->rl); free(M->off); free(M->poff); free(M->ioff);
   memset(M, 0, sizeof *M);
 }
+
+/* cell width along d of refinement level r (exact: a power-of-two scaling) */
+static double dx_r(const orc_mesh *m, int r, int d) { return ldexp(m->dx[d], -r); }
 
 static int mesh_build(mesh_t *M, const orc_cfg *cfg, const orc_mesh *m, const orc_table *tab) {
   memset(M, 0, sizeof *M);
   M->cfg = cfg; M->m = m; M->tab = tab;
   M->nv = cfg->dual ? 6 : 5;
   if (m->nblocks <= 0) return -1;
+  M->rl = malloc(m->nblocks * sizeof(int));
+  /* lattice edge: the smallest block extent in level-0 cells */
   int lat = 1 << 30;
-  for (int b = 0; b < m->nblocks; b++) if (m->blk[4 * b] < lat) lat = m->blk[4 * b];
-  if (lat < 2) return -1;
-  if (m->nx % lat || m->ny % lat || m->nz % lat) return -1;
+  for (int b = 0; b < m->nblocks; b++) {
+    int r = m->rlev ? m->rlev[b] : 0;
+    int n = m->blk[4 * b];
+    if (r < 0 || r > 1 || n % (1 << r)) { free(M->rl); M->rl = NULL; return -1; }
+    M->rl[b] = r;
+    if (r > M->rmax) M->rmax = r;
+    if ((n >> r) < lat) lat = n >> r;
+  }
+  if (lat < 2 || m->nx % lat || m->ny % lat || m->nz % lat) { mesh_free(M); return -1; }
   M->lat = lat; M->lx = m->nx / lat; M->ly = m->ny / lat; M->lz = m->nz / lat;
   size_t nl = (size_t)M->lx * M->ly * M->lz;
   M->lmap = malloc(nl * sizeof(int));
@@ -116,12 +139,16 @@ static int mesh_build(mesh_t *M, const orc_cfg *cfg, const orc_mesh *m, const or
   for (size_t i = 0; i < nl; i++) M->lmap[i] = -1;
   size_t o = 0, po = 0, io = 0;
   for (int b = 0; b < m->nblocks; b++) {
+    int r = M->rl[b];
     int n = m->blk[4 * b], ox = m->blk[4 * b + 1], oy = m->blk[4 * b + 2], oz = m->blk[4 * b + 3];
-    if (n % lat || ox % lat || oy % lat || oz % lat) { mesh_free(M); return -1; }
-    if (ox < 0 || oy < 0 || oz < 0 || ox + n > m->nx || oy + n > m->ny || oz + n > m->nz) { mesh_free(M); return -1; }
-    for (int c = oz / lat; c < (oz + n) / lat; c++)
-      for (int bb = oy / lat; bb < (oy + n) / lat; bb++)
-        for (int a = ox / lat; a < (ox + n) / lat; a++) {
+    int L = lat << r; /* lattice edge in this block's cells */
+    if (n % L || ox % L || oy % L || oz % L) { mesh_free(M); return -1; }
+    if (ox < 0 || oy < 0 || oz < 0 || ox + n > (m->nx << r) || oy + n > (m->ny << r) || oz + n > (m->nz << r)) {
+      mesh_free(M); return -1;
+    }
+    for (int c = oz / L; c < (oz + n) / L; c++)
+      for (int bb = oy / L; bb < (oy + n) / L; bb++)
+        for (int a = ox / L; a < (ox + n) / L; a++) {
           size_t li = ((size_t)c * M->ly + bb) * M->lx + a;
           if (M->lmap[li] != -1) { mesh_free(M); return -1; }
           M->lmap[li] = b;
@@ -145,17 +172,29 @@ static int wrap_axis(int g, int N, int bc) {
   return g;
 }
 
-/* global cell -> owning block and local index */
-static void locate(const mesh_t *M, int gx, int gy, int gz, int *b, int *i, int *j, int *k) {
+/* Block covering global cell (gx, gy, gz) of refinement level r (indices
+ * already inside the level's extents); its level may differ from r. */
+static int covering_block(const mesh_t *M, int r, int gx, int gy, int gz) {
+  int L = M->lat << r;
+  return M->lmap[((size_t)(gz / L) * M->ly + gy / L) * M->lx + gx / L];
+}
+
+/* global cell of level r -> owning block and local index, for a cell whose
+ * covering block is on level r (every cell of a single-level mesh) */
+static void locate_r(const mesh_t *M, int r, int gx, int gy, int gz, int *b, int *i, int *j, int *k) {
   const orc_mesh *m = M->m;
-  gx = wrap_axis(gx, m->nx, m->bc[0]);
-  gy = wrap_axis(gy, m->ny, m->bc[1]);
-  gz = wrap_axis(gz, m->nz, m->bc[2]);
-  int bb = M->lmap[((size_t)(gz / M->lat) * M->ly + gy / M->lat) * M->lx + gx / M->lat];
+  gx = wrap_axis(gx, m->nx << r, m->bc[0]);
+  gy = wrap_axis(gy, m->ny << r, m->bc[1]);
+  gz = wrap_axis(gz, m->nz << r, m->bc[2]);
+  int bb = covering_block(M, r, gx, gy, gz);
   *b = bb;
   *i = gx - m->blk[4 * bb + 1];
   *j = gy - m->blk[4 * bb + 2];
   *k = gz - m->blk[4 * bb + 3];
+}
+
+static void locate(const mesh_t *M, int gx, int gy, int gz, int *b, int *i, int *j, int *k) {
+  locate_r(M, 0, gx, gy, gz, b, i, j, k);
 }
 
 /* whether the neighbour across a face is a real cell (not beyond an outflow edge) */
@@ -327,23 +366,24 @@ static void hlle(const double *wl, double pl, double cl, const double *wr, doubl
 /* ------------------------------------------------------------------ */
 /* gravity and excision geometry                                       */
 /* ------------------------------------------------------------------ */
-static double cell_x(const orc_mesh *m, int d, int g) { return m->x0[d] + (g + 0.5) * m->dx[d]; }
+/* centre of global cell g (level r) along d */
+static double cell_x(const orc_mesh *m, int r, int d, int g) { return m->x0[d] + (g + 0.5) * dx_r(m, r, d); }
 
 static double bh_pos(const orc_cfg *c, int d, double t) { return c->bh_x0[d] - c->v_frame[d] * t; }
 
 /* softened point-mass potential at a cell centre (eq bh-softened-gravity) */
-static double phi_point(const orc_cfg *c, const orc_mesh *m, int gx, int gy, int gz, double t) {
-  double dx = cell_x(m, 0, gx) - bh_pos(c, 0, t);
-  double dy = cell_x(m, 1, gy) - bh_pos(c, 1, t);
-  double dz = cell_x(m, 2, gz) - bh_pos(c, 2, t);
+static double phi_point(const orc_cfg *c, const orc_mesh *m, int r, int gx, int gy, int gz, double t) {
+  double dx = cell_x(m, r, 0, gx) - bh_pos(c, 0, t);
+  double dy = cell_x(m, r, 1, gy) - bh_pos(c, 1, t);
+  double dz = cell_x(m, r, 2, gz) - bh_pos(c, 2, t);
   return -c->gm_bh / sqrt(dx * dx + dy * dy + dz * dz + c->r_soft * c->r_soft);
 }
 
-static int excised(const orc_cfg *c, const orc_mesh *m, int gx, int gy, int gz, double t) {
+static int excised(const orc_cfg *c, const orc_mesh *m, int r, int gx, int gy, int gz, double t) {
   if (c->grav_kind != 2 || !(c->r_exc > 0.0)) return 0;
-  double dx = cell_x(m, 0, gx) - bh_pos(c, 0, t);
-  double dy = cell_x(m, 1, gy) - bh_pos(c, 1, t);
-  double dz = cell_x(m, 2, gz) - bh_pos(c, 2, t);
+  double dx = cell_x(m, r, 0, gx) - bh_pos(c, 0, t);
+  double dy = cell_x(m, r, 1, gy) - bh_pos(c, 1, t);
+  double dz = cell_x(m, r, 2, gz) - bh_pos(c, 2, t);
   return dx * dx + dy * dy + dz * dz < c->r_exc * c->r_exc;
 }
 
@@ -355,7 +395,7 @@ static double phi_at(const mesh_t *M, const double *phi, int b, int i, int j, in
     int np = n + 2;
     return phi[M->poff[b] + ((size_t)(k + 1) * np + (j + 1)) * np + (i + 1)];
   }
-  return phi_point(M->cfg, m, m->blk[4 * b + 1] + i, m->blk[4 * b + 2] + j, m->blk[4 * b + 3] + k, t);
+  return phi_point(M->cfg, m, M->rl[b], m->blk[4 * b + 1] + i, m->blk[4 * b + 2] + j, m->blk[4 * b + 3] + k, t);
 }
 
 /* ------------------------------------------------------------------ */
@@ -388,6 +428,7 @@ static void block_stage(const mesh_t *M, const double *phi, int b, const double 
   const size_t np3 = (size_t)PADX(n) * PADX(n) * PADX(n);
   const size_t n3 = (size_t)n * n * n;
   const size_t nf = (size_t)(n + 1) * n * n; /* faces per direction */
+  const double dxb[3] = {dx_r(m, M->rl[b], 0), dx_r(m, M->rl[b], 1), dx_r(m, M->rl[b], 2)};
 
   double *W = malloc(np3 * nv * sizeof(double));
   double *F = malloc(3 * nf * (nv + 1) * sizeof(double)); /* fluxes + face velocity */
@@ -404,7 +445,7 @@ static void block_stage(const mesh_t *M, const double *phi, int b, const double 
     for (int k = -2; k < n + 2; k++)
       for (int j = -2; j < n + 2; j++)
         for (int i = -2; i < n + 2; i++)
-          exm[pidx(n, i, j, k)] = (unsigned char)excised(c, m, o[0] + i, o[1] + j, o[2] + k, t);
+          exm[pidx(n, i, j, k)] = (unsigned char)excised(c, m, M->rl[b], o[0] + i, o[1] + j, o[2] + k, t);
   }
 
   /* face fluxes: direction d, face index a in [0, n] between cells a-1 and a */
@@ -500,10 +541,10 @@ static void block_stage(const mesh_t *M, const double *phi, int b, const double 
           size_t fp = fm + 1;
           for (int v = 0; v < nv; v++) {
             const double *Fv = F + ((size_t)d * (nv + 1) + v) * nf;
-            rhs[v] -= (Fv[fp] - Fv[fm]) / m->dx[d];
+            rhs[v] -= (Fv[fp] - Fv[fm]) / dxb[d];
           }
           const double *Vf = F + ((size_t)d * (nv + 1) + nv) * nf;
-          divv += (Vf[fp] - Vf[fm]) / m->dx[d];
+          divv += (Vf[fp] - Vf[fm]) / dxb[d];
           if (c->grav_kind) {
             int im[3] = {i, j, k}, ip[3] = {i, j, k};
             im[d] -= 1; ip[d] += 1;
@@ -511,9 +552,9 @@ static void block_stage(const mesh_t *M, const double *phi, int b, const double 
             double p0 = phi_at(M, phi, b, i, j, k, t);
             double pp = phi_at(M, phi, b, ip[0], ip[1], ip[2], t);
             double rho_i = qpad[IDN * np3 + p];
-            rhs[IM1 + d] -= rho_i * (pp - pm) / (2.0 * m->dx[d]);
+            rhs[IM1 + d] -= rho_i * (pp - pm) / (2.0 * dxb[d]);
             const double *Fr = F + ((size_t)d * (nv + 1) + IDN) * nf;
-            rhs[IEN] -= (Fr[fp] * (pp - p0) + Fr[fm] * (p0 - pm)) / (2.0 * m->dx[d]);
+            rhs[IEN] -= (Fr[fp] * (pp - p0) + Fr[fm] * (p0 - pm)) / (2.0 * dxb[d]);
           }
         }
         double qn[6];
@@ -576,7 +617,7 @@ static void excise_reset(const mesh_t *M, int b, double *q, double t) {
   for (int k = 0; k < n; k++)
     for (int j = 0; j < n; j++)
       for (int i = 0; i < n; i++) {
-        if (!excised(c, m, m->blk[4 * b + 1] + i, m->blk[4 * b + 2] + j, m->blk[4 * b + 3] + k, t)) continue;
+        if (!excised(c, m, M->rl[b], m->blk[4 * b + 1] + i, m->blk[4 * b + 2] + j, m->blk[4 * b + 3] + k, t)) continue;
         size_t p = cidx(n, i, j, k);
         double uf = u_floor(c, c->rho_floor);
         q[IDN * n3 + p] = c->rho_floor;
@@ -603,7 +644,7 @@ int orc_cfl(const orc_cfg *cfg, const orc_mesh *m, const orc_table *tab, const d
     for (int k = 0; k < n; k++)
       for (int j = 0; j < n; j++)
         for (int i = 0; i < n; i++) {
-          if (excised(cfg, m, m->blk[4 * b + 1] + i, m->blk[4 * b + 2] + j, m->blk[4 * b + 3] + k, t)) continue;
+          if (excised(cfg, m, M.rl[b], m->blk[4 * b + 1] + i, m->blk[4 * b + 2] + j, m->blk[4 * b + 3] + k, t)) continue;
           size_t p = cidx(n, i, j, k);
           double qq[6], w[6];
           for (int v = 0; v < M.nv; v++) qq[v] = q[v * n3 + p];
@@ -611,7 +652,7 @@ int orc_cfl(const orc_cfg *cfg, const orc_mesh *m, const orc_table *tab, const d
           double P, cs;
           eos_pc(cfg, tab, w[0], w[4], &P, &cs);
           for (int d = 0; d < 3; d++) {
-            double s = m->dx[d] / (fabs(w[1 + d]) + cs);
+            double s = dx_r(m, M.rl[b], d) / (fabs(w[1 + d]) + cs);
             if (s < best) best = s;
           }
           /* source-term limit: the gravitational acceleration may move the gas
@@ -622,10 +663,10 @@ int orc_cfl(const orc_cfg *cfg, const orc_mesh *m, const orc_table *tab, const d
               int ip[3] = {i, j, k}, im[3] = {i, j, k};
               ip[d] += 1; im[d] -= 1;
               double gd = (phi_at(&M, phi, b, ip[0], ip[1], ip[2], t) - phi_at(&M, phi, b, im[0], im[1], im[2], t)) /
-                          (2.0 * m->dx[d]);
+                          (2.0 * dx_r(m, M.rl[b], d));
               g2 += gd * gd;
             }
-            double dmin = fmin(m->dx[0], fmin(m->dx[1], m->dx[2]));
+            double dmin = fmin(dx_r(m, M.rl[b], 0), fmin(dx_r(m, M.rl[b], 1), dx_r(m, M.rl[b], 2)));
             if (g2 > 0.0) {
               double s = sqrt(dmin / sqrt(g2));
               if (s < best) best = s;
@@ -642,26 +683,32 @@ int orc_cfl(const orc_cfg *cfg, const orc_mesh *m, const orc_table *tab, const d
 /* LAT level assignment (eq lat-factor, bin merging, neighbour limit)  */
 /* ------------------------------------------------------------------ */
 
-/* blocks sharing a face, edge or corner (periodic wrap; nothing beyond outflow edges) */
+/* blocks sharing a face, edge or corner (periodic wrap; nothing beyond outflow
+ * edges), whatever their refinement level: the lattice cells (level-0 units)
+ * around the block's extent */
 static int *adjacency(const mesh_t *M, int *deg_out_max) {
   const orc_mesh *m = M->m;
   int nb = m->nblocks, maxd = 64;
   int *adj = malloc((size_t)nb * maxd * sizeof(int));
+  int N[3] = {m->nx, m->ny, m->nz};
   for (int b = 0; b < nb; b++) {
     int cnt = 0;
-    int n = m->blk[4 * b], L = M->lat;
-    int o[3] = {m->blk[4 * b + 1], m->blk[4 * b + 2], m->blk[4 * b + 3]};
-    for (int cz = o[2] - L; cz < o[2] + n + L; cz += L)
-      for (int cy = o[1] - L; cy < o[1] + n + L; cy += L)
-        for (int cx = o[0] - L; cx < o[0] + n + L; cx += L) {
-          if (!inside_axis(cx, m->nx, m->bc[0]) || !inside_axis(cy, m->ny, m->bc[1]) ||
-              !inside_axis(cz, m->nz, m->bc[2]))
-            continue;
-          int nb2, i, j, k;
-          locate(M, cx, cy, cz, &nb2, &i, &j, &k);
+    int r = M->rl[b], L = M->lat;
+    int n0 = m->blk[4 * b] >> r; /* extent in level-0 cells */
+    int o[3] = {m->blk[4 * b + 1] >> r, m->blk[4 * b + 2] >> r, m->blk[4 * b + 3] >> r};
+    for (int cz = o[2] - L; cz < o[2] + n0 + L; cz += L)
+      for (int cy = o[1] - L; cy < o[1] + n0 + L; cy += L)
+        for (int cx = o[0] - L; cx < o[0] + n0 + L; cx += L) {
+          int g[3] = {cx, cy, cz}, ok = 1;
+          for (int d = 0; d < 3; d++) {
+            if (!inside_axis(g[d], N[d], m->bc[d])) ok = 0;
+            else g[d] = wrap_axis(g[d], N[d], m->bc[d]);
+          }
+          if (!ok) continue;
+          int nb2 = covering_block(M, 0, g[0], g[1], g[2]);
           if (nb2 == b) continue;
           int seen = 0;
-          for (int s = 0; s < cnt; s++) if (adj[b * maxd + s] == nb2) seen = 1;
+          for (int s2 = 0; s2 < cnt; s2++) if (adj[b * maxd + s2] == nb2) seen = 1;
           if (!seen && cnt < maxd - 1) adj[b * maxd + cnt++] = nb2;
         }
     adj[b * maxd + cnt] = -1;
@@ -670,11 +717,24 @@ static int *adjacency(const mesh_t *M, int *deg_out_max) {
   return adj;
 }
 
+/* Admissible pair of LAT exponents e (factor 2^e) for adjacent blocks b, c:
+ * on the same refinement level at most one apart; across a coarse-fine
+ * interface f_fine <= f_coarse <= 2 f_fine (Sec. LAT method). */
+static int exps_admissible(const mesh_t *M, int b, int c, int eb, int ec) {
+  int rb = M->rl[b], rc = M->rl[c];
+  if (rb == rc) return abs(eb - ec) <= 1;
+  if (rb > rc) return eb <= ec && ec <= eb + 1; /* b fine, c coarse */
+  return ec <= eb && eb <= ec + 1;               /* b coarse, c fine */
+}
+
 /*
  * dt_block -> levels.  exps[b] = min(N_LAT, floor(log2(dt_b / dt0))) is taken
  * with ilogb (exact), bins are merged from the top while they hold fewer than
- * merge_frac * N blocks, then neighbours are limited to one exponent apart by
- * relaxation to the fixed point.  Output level = Lmax - exponent, so level 0
+ * merge_frac * N blocks, then neighbours are limited by relaxation to the
+ * fixed point: one exponent apart on one refinement level, and
+ * f_fine <= f_coarse <= 2 f_fine across refinement levels (Sec. LAT method).
+ * The relaxation only lowers exponents, so it ends at the greatest admissible
+ * assignment below the CFL bins.  Output level = Lmax - exponent, so level 0
  * is the coarsest (largest step) and Lmax the finest.  Returns Lmax.
  */
 int orc_lat_assign(const orc_cfg *cfg, const orc_mesh *m, const double *dt_block, int *levels, double *dt0_out) {
@@ -700,7 +760,9 @@ int orc_lat_assign(const orc_cfg *cfg, const orc_mesh *m, const double *dt_block
     if ((double)cnt >= cfg->merge_frac * nb) break;
     for (int b = 0; b < nb; b++) if (e[b] == top) e[b] = top - 1;
   }
-  /* neighbour limit: e_b <= e_c + 1 for every neighbour c */
+  /* neighbour limit, relaxed to its fixed point: e_b <= e_c + 1 for every
+   * neighbour c on the same refinement level or a finer one, and e_b <= e_c
+   * for a fine block b next to a coarser c (f_fine <= f_coarse <= 2 f_fine) */
   int maxd;
   int *adj = adjacency(&M, &maxd);
   for (int changed = 1; changed;) {
@@ -708,7 +770,8 @@ int orc_lat_assign(const orc_cfg *cfg, const orc_mesh *m, const double *dt_block
     for (int b = 0; b < nb; b++)
       for (int s = 0; adj[b * maxd + s] >= 0; s++) {
         int cN = adj[b * maxd + s];
-        if (e[b] > e[cN] + 1) { e[b] = e[cN] + 1; changed = 1; }
+        int cap = M.rl[b] > M.rl[cN] ? e[cN] : e[cN] + 1;
+        if (e[b] > cap) { e[b] = cap; changed = 1; }
       }
   }
   int Lmax = 0;
@@ -741,35 +804,113 @@ static double dense_value(double qn, double q1, double qe, double th) {
   return (1.0 - th) * qn + th * (1.0 - th) * q1 + th * th * qe;
 }
 
-/* conserved value of variable v at global cell of block nb, as seen at
- * sub-cycle k by a reader with factor fb in phase ph (1 or 2).  A neighbour
- * that is mid-step at the reader's stage time has its start, stage-1 and end
- * states stored: with ghost_dense its RK2 dense output is used there, else
- * the linear interpolation of start and end (Sec. LAT method). */
-static double ghost_value(const lat_t *L, int reader, int nbk, size_t cell, int v, int k, int ph) {
-  const mesh_t *M = L->M;
-  int n = M->m->blk[4 * nbk];
-  size_t n3 = (size_t)n * n * n;
-  size_t o = M->off[nbk] + v * n3 + cell;
+/* Value at the reader's stage time of a neighbour quantity whose stored
+ * history is qs (start of the neighbour's step), q1 (its stage-1 output) and
+ * qe (its latest state): the reader nbk-neighbour relation at sub-cycle k in
+ * phase ph (1 or 2) with factors fb (reader) and fn (neighbour).  A neighbour
+ * that is mid-step at the reader's stage time uses its RK2 dense output with
+ * ghost_dense, else the linear interpolation of start and end (Sec. LAT
+ * method). */
+static double hist_interp(const lat_t *L, int reader, int nbk, double qs, double q1, double qe, int k, int ph) {
   int fb = L->f[reader], fn = L->f[nbk];
   int act = (k % fn) == 0;
-  const int dense = M->cfg->ghost_dense;
+  const int dense = L->M->cfg->ghost_dense;
   if (ph == 1) {
-    if (act) return L->Qend[o];
+    if (act) return qe;
     int t0 = k - k % fn;
     double w = (double)(k - t0) / fn;
-    if (dense) return dense_value(L->Qstart[o], L->Q1[o], L->Qend[o], w);
-    return (1.0 - w) * L->Qstart[o] + w * L->Qend[o];
+    if (dense) return dense_value(qs, q1, qe, w);
+    return (1.0 - w) * qs + w * qe;
   }
   if (act) {
-    if (fn <= fb) return L->Q1[o];
+    if (fn <= fb) return q1;
     double w = (double)fb / fn;
-    return (1.0 - w) * L->Qend[o] + w * L->Q1[o];
+    return (1.0 - w) * qe + w * q1;
   }
   int t0 = k - k % fn;
   double w = (double)(k + fb - t0) / fn;
-  if (dense) return dense_value(L->Qstart[o], L->Q1[o], L->Qend[o], w);
-  return (1.0 - w) * L->Qstart[o] + w * L->Qend[o];
+  if (dense) return dense_value(qs, q1, qe, w);
+  return (1.0 - w) * qs + w * qe;
+}
+
+/* conserved value of variable v at a cell of block nbk, as the reader sees it */
+static double ghost_value(const lat_t *L, int reader, int nbk, size_t cell, int v, int k, int ph) {
+  const mesh_t *M = L->M;
+  int n = M->m->blk[4 * nbk];
+  size_t o = M->off[nbk] + v * (size_t)n * n * n + cell;
+  return hist_interp(L, reader, nbk, L->Qstart[o], L->Q1[o], L->Qend[o], k, ph);
+}
+
+/* global cell index g of level r along axis d mapped into the level's extents
+ * (periodic wrap, or the nearest cell beyond an outflow edge) */
+static int level_axis(const mesh_t *M, int r, int d, int g) {
+  const orc_mesh *m = M->m;
+  int N[3] = {m->nx, m->ny, m->nz};
+  return wrap_axis(g, N[d] << r, m->bc[d]);
+}
+
+/*
+ * Conserved state q[nv] of global cell G (level r, any index: it is wrapped
+ * here) as the reader sees it at sub-cycle k, phase ph, whatever the level of
+ * the block covering it (Sec. LAT method, coarse-fine interfaces):
+ *  - covered on level r: the owner's history at the reader's stage time;
+ *  - covered by a finer block: the owner's stored histories (start, stage 1,
+ *    latest) are each restricted to the cell (mean of its 2x2x2 children,
+ *    summed in k, j, i order), then interpolated in time;
+ *  - covered by a coarser block: prolongation of the coarse cell containing G
+ *    from level r-1 values taken at the same stage time, q_c + sum_d s_d d_d/4
+ *    (axes in x, y, z order), with d_d the minmod of the two one-sided coarse
+ *    differences along d and s_d = +1 for the upper child, -1 for the lower.
+ */
+static void cell_state(const lat_t *L, int reader, int r, const int G[3], int k, int ph, double *q) {
+  const mesh_t *M = L->M;
+  const orc_mesh *m = M->m;
+  const int nv = M->nv;
+  int g[3];
+  for (int d = 0; d < 3; d++) g[d] = level_axis(M, r, d, G[d]);
+  int c = covering_block(M, r, g[0], g[1], g[2]);
+  int rc = M->rl[c];
+  int n = m->blk[4 * c];
+  size_t n3 = (size_t)n * n * n;
+  if (rc == r) {
+    size_t cell = cidx(n, g[0] - m->blk[4 * c + 1], g[1] - m->blk[4 * c + 2], g[2] - m->blk[4 * c + 3]);
+    for (int v = 0; v < nv; v++) q[v] = ghost_value(L, reader, c, cell, v, k, ph);
+    return;
+  }
+  if (rc == r + 1) {
+    int base[3] = {2 * g[0] - m->blk[4 * c + 1], 2 * g[1] - m->blk[4 * c + 2], 2 * g[2] - m->blk[4 * c + 3]};
+    for (int v = 0; v < nv; v++) {
+      double hs = 0.0, h1 = 0.0, he = 0.0;
+      for (int kz = 0; kz < 2; kz++)
+        for (int jy = 0; jy < 2; jy++)
+          for (int ix = 0; ix < 2; ix++) {
+            size_t o = M->off[c] + v * n3 + cidx(n, base[0] + ix, base[1] + jy, base[2] + kz);
+            hs += L->Qstart[o]; h1 += L->Q1[o]; he += L->Qend[o];
+          }
+      q[v] = hist_interp(L, reader, c, 0.125 * hs, 0.125 * h1, 0.125 * he, k, ph);
+    }
+    return;
+  }
+  /* rc == r - 1: prolongation from the coarse level */
+  int gc[3] = {g[0] >> 1, g[1] >> 1, g[2] >> 1};
+  double qc[6], qm[3][6], qp[3][6];
+  cell_state(L, reader, r - 1, gc, k, ph, qc);
+  for (int d = 0; d < 3; d++) {
+    int a[3] = {gc[0], gc[1], gc[2]}, b2[3] = {gc[0], gc[1], gc[2]};
+    a[d] -= 1; b2[d] += 1;
+    cell_state(L, reader, r - 1, a, k, ph, qm[d]);
+    cell_state(L, reader, r - 1, b2, k, ph, qp[d]);
+  }
+  for (int v = 0; v < nv; v++) {
+    double val = qc[v];
+    for (int d = 0; d < 3; d++) {
+      double dl = qc[v] - qm[d][v], dr = qp[d][v] - qc[v];
+      double mm = dl * dr <= 0.0 ? 0.0 : (fabs(dl) < fabs(dr) ? dl : dr);
+      double s = (g[d] & 1) ? 0.25 : -0.25;
+      val += s * mm;
+    }
+    q[v] = val;
+  }
 }
 
 /* dense output of one value, for pins */
@@ -778,24 +919,26 @@ double orc_dense_value(double qn, double q1, double qe, double th) { return dens
 static void fill_pad(const lat_t *L, int b, int k, int ph, double *qpad) {
   const mesh_t *M = L->M;
   const orc_mesh *m = M->m;
-  int n = m->blk[4 * b];
+  int n = m->blk[4 * b], r = M->rl[b];
   size_t np3 = (size_t)PADX(n) * PADX(n) * PADX(n);
   for (int kk = -2; kk < n + 2; kk++)
     for (int jj = -2; jj < n + 2; jj++)
       for (int ii = -2; ii < n + 2; ii++) {
-        int nbk, li, lj, lk;
-        locate(M, m->blk[4 * b + 1] + ii, m->blk[4 * b + 2] + jj, m->blk[4 * b + 3] + kk, &nbk, &li, &lj, &lk);
-        int nn = m->blk[4 * nbk];
-        size_t cell = cidx(nn, li, lj, lk);
-        for (int v = 0; v < M->nv; v++) qpad[v * np3 + pidx(n, ii, jj, kk)] = ghost_value(L, b, nbk, cell, v, k, ph);
+        int G[3] = {m->blk[4 * b + 1] + ii, m->blk[4 * b + 2] + jj, m->blk[4 * b + 3] + kk};
+        double q[6];
+        cell_state(L, b, r, G, k, ph, q);
+        for (int v = 0; v < M->nv; v++) qpad[v * np3 + pidx(n, ii, jj, kk)] = q[v];
       }
 }
 
-/* neighbour across face (d, side) of local face cell (u0,u1): returns block or -1 */
-static int face_neighbor(const mesh_t *M, int b, int d, int side, int u0, int u1, int *cell_nb, int *u0n, int *u1n,
-                         int *ci) {
+/* Neighbour across face (d, side) of local face cell (u0,u1) of block b:
+ * returns the block covering the cell across, or -1 beyond an outflow edge.
+ * (*u0n, *u1n) index the neighbour's face cell on its opposite face: the
+ * coarse cell containing the one across for a coarser neighbour, the first
+ * (lowest-index) of the 2x2 fine face cells for a finer one. */
+static int face_neighbor(const mesh_t *M, int b, int d, int side, int u0, int u1, int *u0n, int *u1n, int *ci) {
   const orc_mesh *m = M->m;
-  int n = m->blk[4 * b];
+  int n = m->blk[4 * b], r = M->rl[b];
   int loc[3];
   if (d == 0) { loc[1] = u0; loc[2] = u1; }
   if (d == 1) { loc[0] = u0; loc[2] = u1; }
@@ -804,13 +947,18 @@ static int face_neighbor(const mesh_t *M, int b, int d, int side, int u0, int u1
   int g[3] = {m->blk[4 * b + 1] + loc[0], m->blk[4 * b + 2] + loc[1], m->blk[4 * b + 3] + loc[2]};
   *ci = (int)cidx(n, loc[0], loc[1], loc[2]);
   g[d] += side ? 1 : -1;
-  int N[3] = {m->nx, m->ny, m->nz};
+  int N[3] = {m->nx << r, m->ny << r, m->nz << r};
   if (!inside_axis(g[d], N[d], m->bc[d])) return -1;
-  int nbk, i, j, k;
-  locate(M, g[0], g[1], g[2], &nbk, &i, &j, &k);
-  int nn = m->blk[4 * nbk];
-  *cell_nb = (int)cidx(nn, i, j, k);
-  int ln[3] = {i, j, k};
+  for (int a = 0; a < 3; a++) g[a] = wrap_axis(g[a], N[a], m->bc[a]);
+  int nbk = covering_block(M, r, g[0], g[1], g[2]);
+  int rn = M->rl[nbk];
+  int h[3];
+  for (int a = 0; a < 3; a++) {
+    if (rn == r) h[a] = g[a];
+    else if (rn < r) h[a] = g[a] >> 1;
+    else h[a] = a == d ? 2 * g[a] + (side ? 0 : 1) : 2 * g[a];
+  }
+  int ln[3] = {h[0] - m->blk[4 * nbk + 1], h[1] - m->blk[4 * nbk + 2], h[2] - m->blk[4 * nbk + 3]};
   *u0n = d == 0 ? ln[1] : ln[0];
   *u1n = d == 2 ? ln[1] : ln[2];
   return nbk;
@@ -831,20 +979,23 @@ int64_t orc_lat_window(const orc_cfg *cfg, const orc_mesh *m, const orc_table *t
     if (levels[b] < 0 || levels[b] > 30) { mesh_free(&M); return -1; }
     if (levels[b] > Lmax) Lmax = levels[b];
   }
-  /* neighbour levels must differ by at most one */
+  /* neighbour levels must be admissible (exponent = Lmax - level) */
   {
     int maxd;
     int *adj = adjacency(&M, &maxd);
     for (int b = 0; b < nb; b++)
-      for (int s = 0; adj[b * maxd + s] >= 0; s++)
-        if (abs(levels[b] - levels[adj[b * maxd + s]]) > 1) { free(adj); mesh_free(&M); return -1; }
+      for (int s = 0; adj[b * maxd + s] >= 0; s++) {
+        int c = adj[b * maxd + s];
+        if (!exps_admissible(&M, b, c, Lmax - levels[b], Lmax - levels[c])) { free(adj); mesh_free(&M); return -1; }
+        if (abs(M.rl[b] - M.rl[c]) > 1) { free(adj); mesh_free(&M); return -1; }
+      }
     free(adj);
   }
   lat_t L;
   L.M = &M; L.phi = phi;
   L.Qend = U;
   L.Qstart = malloc(M.total * sizeof(double));
-  L.Q1 = malloc(M.total * sizeof(double));
+  L.Q1 = calloc(M.total, sizeof(double));
   L.Qnew = malloc(M.total * sizeof(double));
   L.imp = calloc(M.itotal, sizeof(double));
   L.bf1 = calloc(M.itotal, sizeof(double));
@@ -887,12 +1038,12 @@ int64_t orc_lat_window(const orc_cfg *cfg, const orc_mesh *m, const orc_table *t
       int n = m->blk[4 * b];
       double dtb = L.f[b] * dt0;
       for (int d = 0; d < 3; d++) {
-        double area = m->dx[(d + 1) % 3] * m->dx[(d + 2) % 3];
+        double area = dx_r(m, M.rl[b], (d + 1) % 3) * dx_r(m, M.rl[b], (d + 2) % 3);
         for (int side = 0; side < 2; side++)
           for (int u1 = 0; u1 < n; u1++)
             for (int u0 = 0; u0 < n; u0++) {
-              int cnb, u0n, u1n, ci;
-              int nbk = face_neighbor(&M, b, d, side, u0, u1, &cnb, &u0n, &u1n, &ci);
+              int u0n, u1n, ci;
+              int nbk = face_neighbor(&M, b, d, side, u0, u1, &u0n, &u1n, &ci);
               if (nbk < 0) continue;
               int fw = L.f[b] > L.f[nbk] ? L.f[b] : L.f[nbk];
               int overwrite = (k % fw) == 0;
@@ -913,14 +1064,19 @@ int64_t orc_lat_window(const orc_cfg *cfg, const orc_mesh *m, const orc_table *t
       memcpy(L.Qend + M.off[b], L.Qnew + M.off[b], sz * sizeof(double));
       updates++;
     }
-    /* reflux for blocks completing at k+1 against finer neighbours */
+    /* Flux corrections (eq lat-flux-impulse and the reflux after it) for
+     * blocks completing at k+1: against neighbours on the same refinement
+     * level that update more often, and against every finer neighbour, whose
+     * 2x2 face impulses (summed in u1, u0 order) replace the coarse face's own;
+     * a block never corrects against a coarser neighbour. */
     double tc = t0 + (k + 1) * dt0;
 #pragma omp parallel for schedule(dynamic)
     for (int b = 0; b < nb; b++) {
       if ((k + 1) % L.f[b]) continue;
       int n = m->blk[4 * b];
       size_t n3 = (size_t)n * n * n;
-      double vol = m->dx[0] * m->dx[1] * m->dx[2];
+      int r = M.rl[b];
+      double vol = dx_r(m, r, 0) * dx_r(m, r, 1) * dx_r(m, r, 2);
       /* cells in increasing index order, faces in order x-, x+, y-, y+, z-, z+ */
       for (int kk = 0; kk < n; kk++)
         for (int jj = 0; jj < n; jj++)
@@ -931,16 +1087,22 @@ int64_t orc_lat_window(const orc_cfg *cfg, const orc_mesh *m, const orc_table *t
                 if (lc[d] != (side ? n - 1 : 0)) continue;
                 int u0 = d == 0 ? jj : ii;
                 int u1 = d == 2 ? jj : kk;
-                int cnb, u0n, u1n, ci;
-                int nbk = face_neighbor(&M, b, d, side, u0, u1, &cnb, &u0n, &u1n, &ci);
-                if (nbk < 0 || L.f[nbk] >= L.f[b]) continue;
+                int u0n, u1n, ci;
+                int nbk = face_neighbor(&M, b, d, side, u0, u1, &u0n, &u1n, &ci);
+                if (nbk < 0) continue;
+                int rn = M.rl[nbk];
+                if (rn < r || (rn == r && L.f[nbk] >= L.f[b])) continue;
                 int nn = m->blk[4 * nbk];
+                int w = rn > r ? 2 : 1;
                 double sg = side ? 1.0 : -1.0;
                 double dI[6];
                 for (int v = 0; v < nv; v++) {
                   size_t ib = M.ioff[b] + ((size_t)(2 * d + side) * nv + v) * n * n + fidx(n, u0, u1);
-                  size_t in = M.ioff[nbk] + ((size_t)(2 * d + (1 - side)) * nv + v) * nn * nn + fidx(nn, u0n, u1n);
-                  dI[v] = L.imp[ib] - L.imp[in];
+                  size_t in = M.ioff[nbk] + ((size_t)(2 * d + (1 - side)) * nv + v) * nn * nn;
+                  double In = 0.0;
+                  for (int e1 = 0; e1 < w; e1++)
+                    for (int e0 = 0; e0 < w; e0++) In += L.imp[in + fidx(nn, u0n + e0, u1n + e1)];
+                  dI[v] = L.imp[ib] - In;
                 }
                 size_t p = cidx(n, ii, jj, kk);
                 double *q = L.Qend + M.off[b];
@@ -1034,4 +1196,27 @@ void orc_set_num_threads(int n) {
 #else
   (void)n;
 #endif
+}
+
+/*
+ * Ghost fill of block b with every stored history equal to U (a state at rest
+ * in time, every block on one LAT level), for pins of the coarse-fine spatial
+ * operators (restriction and prolongation).  out: [nv][(n+4)^3], the padded
+ * block in the layout the stage update reads.  Returns 0, or -1 on invalid
+ * input.
+ */
+int orc_ghost_fill(const orc_cfg *cfg, const orc_mesh *m, const double *U, int b, double *out) {
+  mesh_t M;
+  if (mesh_build(&M, cfg, m, NULL)) return -1;
+  if (b < 0 || b >= m->nblocks) { mesh_free(&M); return -1; }
+  lat_t L;
+  memset(&L, 0, sizeof L);
+  L.M = &M;
+  L.Qstart = L.Q1 = L.Qend = (double *)U;
+  L.f = malloc(m->nblocks * sizeof(int));
+  for (int i = 0; i < m->nblocks; i++) L.f[i] = 1;
+  fill_pad(&L, b, 0, 1, out);
+  free(L.f);
+  mesh_free(&M);
+  return 0;
 }

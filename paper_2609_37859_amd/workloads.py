@@ -66,7 +66,10 @@ class Config:
 
 @dataclasses.dataclass
 class Mesh:
-    """Uniform-spacing mesh of cubic blocks aligned to a lattice of the smallest edge."""
+    """Cubic blocks aligned to a lattice of the smallest block edge (in cells
+    of refinement level 0).  A block on refinement level r has cell widths
+    dx / 2^r and its origin counted in level-r cells; nx, ny, nz and dx are
+    level 0's."""
     nx: int
     ny: int
     nz: int
@@ -74,10 +77,18 @@ class Mesh:
     x0: tuple
     dx: tuple
     blk: np.ndarray            # int32 [nblocks, 4] = n, ox, oy, oz
+    rlev: np.ndarray = None    # int32 [nblocks] refinement level (0 or 1); None: all on level 0
 
     @property
     def nblocks(self) -> int:
         return int(self.blk.shape[0])
+
+    @property
+    def refined(self) -> bool:
+        return self.rlev is not None and bool(np.any(self.rlev != 0))
+
+    def level(self, b: int) -> int:
+        return 0 if self.rlev is None else int(self.rlev[b])
 
     def block_cells(self) -> np.ndarray:
         return self.blk[:, 0].astype(np.int64) ** 3
@@ -143,14 +154,46 @@ def mixed_mesh(regions, rn, split, dx, x0=(0.0, 0.0, 0.0), bc=(1, 1, 1)) -> Mesh
                 np.asarray(blk, dtype=np.int32))
 
 
+def amr_mesh(nb, n, dx, refine, x0=(0.0, 0.0, 0.0), bc=(0, 0, 0)) -> Mesh:
+    """Two refinement levels.  Level 0 is a (nbx, nby, nbz) grid of regions of
+    n^3 cells of width dx; a region flagged in ``refine`` (bool array
+    [nbz, nby, nbx]) is covered instead by eight level-1 blocks of n^3 cells
+    of width dx/2.  Every block holds n^3 cells; blocks are listed region by
+    region (x fastest), a refined region's eight in x-fastest order."""
+    nbx, nby, nbz = nb
+    blk, lev = [], []
+    for cz in range(nbz):
+        for cy in range(nby):
+            for cx in range(nbx):
+                if refine[cz, cy, cx]:
+                    for sz in range(2):
+                        for sy in range(2):
+                            for sx in range(2):
+                                blk.append((n, 2 * cx * n + sx * n, 2 * cy * n + sy * n, 2 * cz * n + sz * n))
+                                lev.append(1)
+                else:
+                    blk.append((n, cx * n, cy * n, cz * n))
+                    lev.append(0)
+    if np.isscalar(dx):
+        dx = (dx, dx, dx)
+    return Mesh(nbx * n, nby * n, nbz * n, tuple(bc), tuple(map(float, x0)), tuple(map(float, dx)),
+                np.asarray(blk, dtype=np.int32), np.asarray(lev, dtype=np.int32))
+
+
+def block_volume(mesh: Mesh, b: int) -> float:
+    """Cell volume of block b."""
+    return float(np.prod([np.ldexp(d, -mesh.level(b)) for d in mesh.dx]))
+
+
 def cell_centres(mesh: Mesh, b: int, ghost: int = 0):
     """Cell-centre coordinates of block b (optionally with ghost layers), as
     3-D arrays indexed [k, j, i]."""
     n, ox, oy, oz = (int(v) for v in mesh.blk[b])
     r = np.arange(-ghost, n + ghost, dtype=np.float64)
-    xs = mesh.x0[0] + (ox + r + 0.5) * mesh.dx[0]
-    ys = mesh.x0[1] + (oy + r + 0.5) * mesh.dx[1]
-    zs = mesh.x0[2] + (oz + r + 0.5) * mesh.dx[2]
+    h = [np.ldexp(d, -mesh.level(b)) for d in mesh.dx]
+    xs = mesh.x0[0] + (ox + r + 0.5) * h[0]
+    ys = mesh.x0[1] + (oy + r + 0.5) * h[1]
+    zs = mesh.x0[2] + (oz + r + 0.5) * h[2]
     z, y, x = np.meshgrid(zs, ys, xs, indexing="ij")
     return x, y, z
 
@@ -172,7 +215,10 @@ def unpack_block(mesh: Mesh, nv: int, U: np.ndarray, b: int) -> np.ndarray:
 
 
 def to_global(mesh: Mesh, nv: int, U: np.ndarray) -> np.ndarray:
-    """Assemble the block-ordered state into a [nv, nz, ny, nx] array."""
+    """Assemble the block-ordered state of a single-level mesh into a
+    [nv, nz, ny, nx] array."""
+    if mesh.refined:
+        raise ValueError("to_global needs a single-level mesh")
     g = np.empty((nv, mesh.nz, mesh.ny, mesh.nx))
     for b in range(mesh.nblocks):
         n, ox, oy, oz = (int(v) for v in mesh.blk[b])
