@@ -97,20 +97,28 @@ typedef struct {
                      runs (Table 1): the HLL flux with the same Davis wave-speed bounds */
   int ghost_dense; /* LAT ghosts of a neighbour that is mid-step at the stage time
                      (Sec. LAT method): 0 linear interpolation in time of its start and
-                     end states; 1 the dense output of its RK2 step where that state is
-                     admissible (positive density and internal energy), linear otherwise */
+                     end states; 1 the dense output of its RK2 step, a convex combination
+                     of its start, stage-1 and end states (admissible where they are) */
 } tdh_config;
 
-/* Mesh: uniform spacing dx; cubic blocks whose edge n is a power of two in
- * [8, 256], with origins on the lattice of the smallest edge, covering the
- * domain exactly once. */
+/* Mesh: cubic blocks whose edge n is a power of two in [8, 256], covering the
+ * domain exactly once, on up to two refinement levels (Sec. LAT method,
+ * coarse-fine interfaces).  A block on level r has cell widths dx / 2^r and
+ * its origin counted in level-r cells; every origin lies on the lattice of the
+ * smallest block extent measured in level-0 cells.  Ghost states across a
+ * coarse-fine interface are the coarse histories restricted (mean of the 2x2x2
+ * fine children), interpolated in time and prolonged (minmod-limited linear);
+ * the coarse side takes the flux correction at every coarse-fine face.  Runs
+ * with a refined block support neither tdh_gravity_solve, tdh_remap nor
+ * tdh_frame_acceleration (TDH_EINVAL). */
 typedef struct {
-  int nx, ny, nz;   /* global cells per axis */
+  int nx, ny, nz;   /* global cells per axis of level 0 */
   int bc[3];        /* per axis: 0 periodic, 1 outflow (zero gradient) */
   double x0[3];     /* lower domain corner */
-  double dx[3];     /* cell widths */
+  double dx[3];     /* cell widths of level 0 */
   int nblocks;
-  const int *blk;   /* host [nblocks][4] = n, ox, oy, oz (global cell origin) */
+  const int *blk;   /* host [nblocks][4] = n, ox, oy, oz (origin in cells of the block's level) */
+  const int *rlev;  /* host [nblocks] refinement level of each block, 0 or 1 (NULL: all 0) */
 } tdh_mesh;
 
 /* Counters since tdh_init_blocks. */
@@ -149,8 +157,9 @@ tdh_status tdh_set_eos_table(tdh_ctx *ctx, int nrho, int nT, double lr0, double 
 /* Per-block CFL step dt_b = cfl * min over cells of min over axes of
  * dx/(|v|+c_s) and, with gravity, sqrt(dx_min/|g|) (g the centred potential
  * gradient; excised cells skipped), its minimum dt0 (eq lat-base-dt) and the LAT
- * levels of eq lat-factor after bin merging and the one-level neighbour
- * limit; level = Lmax - log2(f_b), level 0 coarsest.  The levels are
+ * levels of eq lat-factor after bin merging and the neighbour limits (one
+ * level apart on one refinement level, f_fine <= f_coarse <= 2 f_fine across
+ * refinement levels); level = Lmax - log2(f_b), level 0 coarsest.  The levels are
  * installed and start a new window.  host_dt_block [nblocks] and
  * host_levels [nblocks] may be NULL.  With the table EOS in inv_mode 2 or 4
  * it also records every cell's table cell as the seeds of the next window's
@@ -176,8 +185,9 @@ tdh_status tdh_reduce_dt(tdh_ctx *ctx, double *host_dt_block, double *host_dt0, 
 tdh_status tdh_reduce_dt_static(tdh_ctx *ctx, double *host_dt_block, double *host_dt0, int8_t *host_levels,
                                 int *host_lmax);
 
-/* Install host-chosen levels (each 0..30, neighbours at most one apart)
- * and start a new window. */
+/* Install host-chosen levels (each 0..30; neighbours on one refinement level
+ * at most one apart; across refinement levels f_fine <= f_coarse <= 2 f_fine
+ * with f = 2^(Lmax - level)) and start a new window. */
 tdh_status tdh_set_levels(tdh_ctx *ctx, const int8_t *host_levels);
 
 /* One LAT sub-cycle: every block whose level is >= level takes one RK2
@@ -296,7 +306,8 @@ tdh_status tdh_eos_eval_batch(tdh_ctx *ctx, const double *dev_rho, const double 
  *   split form (a face-flux kernel per axis writing the faces of every active
  *     block to HBM, then a per-cell update kernel; fits every mesh):
  *     (0, waves per SIMD of the face kernels, of the update kernel, 0).
- * Every variant gives bit-identical results.
+ * Every variant gives bit-identical results.  Meshes with a refined block
+ * run one fused variant of their own (8 x 8 x 4 cells) whatever is chosen.
  * tdh_autotune times one stage over all blocks reps times per fitting shape
  * (state unchanged), keeps the fastest, returns its id and per-shape
  * milliseconds (host_ms [tdh_num_tiles()], -1 where a shape does not fit;

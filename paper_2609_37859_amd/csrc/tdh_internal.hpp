@@ -14,7 +14,8 @@ constexpr int kCntSlots = 33;     // cnt_ge[0..32]
 
 // One MeshBlock as the kernels see it.
 struct BlockInfo {
-  int n, ox, oy, oz;
+  int n, ox, oy, oz;  // edge and origin, in cells of the block's refinement level
+  int lev, pad_;      // refinement level (0 or 1: cell widths dx / 2^lev)
   long long off;   // offset (doubles) of the block in every state buffer
   long long poff;  // offset of its (n+2)^3 potential
   long long ioff;  // offset of its [6][nv][n^2] face arrays
@@ -22,10 +23,11 @@ struct BlockInfo {
 };
 
 struct MeshDev {
-  int nx, ny, nz;
+  int nx, ny, nz;                  // cells of refinement level 0 (level r: 2^r times as many)
   int bc[3];
-  double x0[3], dx[3], inv_dx[3];
-  int lat, lat_shift, lx, ly, lz;  // lattice edge (a power of two) and its log2
+  double x0[3], dx[3], inv_dx[3];  // level 0's cell widths
+  int lat, lat_shift, lx, ly, lz;  // lattice edge in level-0 cells (a power of two) and its log2
+  int amr;                         // some block is on refinement level 1
   int nv;
   const int *lmap;          // lattice cell -> block
   const BlockInfo *blocks;

@@ -40,24 +40,40 @@ __device__ __forceinline__ int block_of(const MeshDev &m, int gx, int gy, int gz
   return m.lmap[((gz >> m.lat_shift) * m.ly + (gy >> m.lat_shift)) * m.lx + (gx >> m.lat_shift)];
 }
 
+// block covering global cell (gx, gy, gz) of refinement level r (inside the
+// level's extents); its own level may be r, r + 1 or r - 1
+__device__ __forceinline__ int block_of(const MeshDev &m, int r, int gx, int gy, int gz) {
+  const int sh = m.lat_shift + r;
+  return m.lmap[((gz >> sh) * m.ly + (gy >> sh)) * m.lx + (gx >> sh)];
+}
+
 // Physics switches of the stage path.  PK = 0 reads them from Phys at run time;
-// otherwise they are fixed at compile time, PK = physics_code(p), so the
-// compiler drops the other paths and the registers they would hold.  multi = 0
-// marks a window without levels: every neighbour is on the reader's schedule,
-// so ghosts need no time interpolation and faces no impulses.
+// PK = kPkAmr reads them at run time too and adds ghosts across refinement
+// levels (the only kernels that take meshes with a refined block); otherwise
+// they are fixed at compile time, PK = physics_code(p), so the compiler drops
+// the other paths and the registers they would hold.  multi = 0 marks a window
+// without levels: every neighbour is on the reader's schedule, so ghosts need
+// no time interpolation and faces no impulses.
 __host__ __device__ constexpr int physics_code(int eos, int dual, int grav, int riemann, int dense, int multi) {
   return 1 + eos + 2 * dual + 4 * grav + 16 * riemann + 32 * dense + 64 * multi;
 }
-template <int PK> __device__ __forceinline__ int k_eos(const Phys &p) { return PK ? (PK - 1) & 1 : p.eos_kind; }
-template <int PK> __device__ __forceinline__ int k_dual(const Phys &p) { return PK ? ((PK - 1) >> 1) & 1 : p.dual; }
-template <int PK> __device__ __forceinline__ int k_grav(const Phys &p) { return PK ? ((PK - 1) >> 2) & 3 : p.grav_kind; }
-template <int PK> __device__ __forceinline__ int k_riemann(const Phys &p) { return PK ? ((PK - 1) >> 4) & 1 : p.riemann; }
-template <int PK> __device__ __forceinline__ int k_dense(const Phys &p) { return PK ? ((PK - 1) >> 5) & 1 : p.ghost_dense; }
-template <int PK> __host__ __device__ constexpr bool k_multi() { return PK ? ((PK - 1) >> 6) & 1 : true; }
+constexpr int kPkAmr = -1;
+template <int PK> __device__ __forceinline__ int k_eos(const Phys &p) { return PK > 0 ? (PK - 1) & 1 : p.eos_kind; }
+template <int PK> __device__ __forceinline__ int k_dual(const Phys &p) { return PK > 0 ? ((PK - 1) >> 1) & 1 : p.dual; }
+template <int PK> __device__ __forceinline__ int k_grav(const Phys &p) { return PK > 0 ? ((PK - 1) >> 2) & 3 : p.grav_kind; }
+template <int PK> __device__ __forceinline__ int k_riemann(const Phys &p) { return PK > 0 ? ((PK - 1) >> 4) & 1 : p.riemann; }
+template <int PK> __device__ __forceinline__ int k_dense(const Phys &p) { return PK > 0 ? ((PK - 1) >> 5) & 1 : p.ghost_dense; }
+template <int PK> __host__ __device__ constexpr bool k_multi() { return PK > 0 ? ((PK - 1) >> 6) & 1 : true; }
+// ghosts across refinement levels (kPkAmr only; every other kind assumes one level)
+template <int PK> __host__ __device__ constexpr bool k_amr() { return PK == kPkAmr; }
+template <int PK> __device__ __forceinline__ int lev_of(const BlockInfo &B) { return k_amr<PK>() ? B.lev : 0; }
+// cell width and its inverse along d on refinement level r (exact: powers of two)
+__device__ __forceinline__ double dx_lev(const MeshDev &m, int d, int r) { return r ? 0.5 * m.dx[d] : m.dx[d]; }
+__device__ __forceinline__ double inv_dx_lev(const MeshDev &m, int d, int r) { return r ? 2.0 * m.inv_dx[d] : m.inv_dx[d]; }
 // compiled point-mass kinds keep each staged cell's potential and excision
 // flag in LDS: every cell's value serves its own and its neighbours' terms
 // (a stored potential is one cached load, not worth the LDS)
-template <int PK> __host__ __device__ constexpr bool k_gcache() { return PK && (((PK - 1) >> 2) & 3) == 2; }
+template <int PK> __host__ __device__ constexpr bool k_gcache() { return PK > 0 && (((PK - 1) >> 2) & 3) == 2; }
 
 // Where a reader with factor fb finds block nb's conserved state at its stage time.
 struct Src {
@@ -414,21 +430,26 @@ __device__ __forceinline__ void hlle(const double *wl, double pl, double cl, con
 // ---------------------------------------------------------------------------
 // gravity / excision geometry
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double cell_x(const MeshDev &m, int d, int g) { return m.x0[d] + (g + 0.5) * m.dx[d]; }
+// centre of global cell g (refinement level r) along d
+__device__ __forceinline__ double cell_x(const MeshDev &m, int d, int g, int r = 0) {
+  return m.x0[d] + (g + 0.5) * dx_lev(m, d, r);
+}
 
-__device__ __forceinline__ double phi_point(const Phys &p, const MeshDev &m, int gx, int gy, int gz, double t) {
-  const double dx = cell_x(m, 0, gx) - (p.bh_x0[0] - p.v_frame[0] * t);
-  const double dy = cell_x(m, 1, gy) - (p.bh_x0[1] - p.v_frame[1] * t);
-  const double dz = cell_x(m, 2, gz) - (p.bh_x0[2] - p.v_frame[2] * t);
+__device__ __forceinline__ double phi_point(const Phys &p, const MeshDev &m, int gx, int gy, int gz, double t,
+                                            int r = 0) {
+  const double dx = cell_x(m, 0, gx, r) - (p.bh_x0[0] - p.v_frame[0] * t);
+  const double dy = cell_x(m, 1, gy, r) - (p.bh_x0[1] - p.v_frame[1] * t);
+  const double dz = cell_x(m, 2, gz, r) - (p.bh_x0[2] - p.v_frame[2] * t);
   return -p.gm_bh / sqrt(dx * dx + dy * dy + dz * dz + p.r_soft * p.r_soft);
 }
 
 template <int PK = 0>
-__device__ __forceinline__ bool excised(const Phys &p, const MeshDev &m, int gx, int gy, int gz, double t) {
+__device__ __forceinline__ bool excised(const Phys &p, const MeshDev &m, int gx, int gy, int gz, double t,
+                                        int r = 0) {
   if (k_grav<PK>(p) != 2 || !(p.r_exc > 0.0)) return false;
-  const double dx = cell_x(m, 0, gx) - (p.bh_x0[0] - p.v_frame[0] * t);
-  const double dy = cell_x(m, 1, gy) - (p.bh_x0[1] - p.v_frame[1] * t);
-  const double dz = cell_x(m, 2, gz) - (p.bh_x0[2] - p.v_frame[2] * t);
+  const double dx = cell_x(m, 0, gx, r) - (p.bh_x0[0] - p.v_frame[0] * t);
+  const double dy = cell_x(m, 1, gy, r) - (p.bh_x0[1] - p.v_frame[1] * t);
+  const double dz = cell_x(m, 2, gz, r) - (p.bh_x0[2] - p.v_frame[2] * t);
   return dx * dx + dy * dy + dz * dz < p.r_exc * p.r_exc;
 }
 
@@ -439,7 +460,7 @@ __device__ __forceinline__ double phi_at(const StageArgs &a, const BlockInfo &B,
     const int np = B.n + 2;
     return a.phi[B.poff + ((long long)(k + 1) * np + (j + 1)) * np + (i + 1)];
   }
-  return phi_point(a.p, a.m, B.ox + i, B.oy + j, B.oz + k, t);
+  return phi_point(a.p, a.m, B.ox + i, B.oy + j, B.oz + k, t, lev_of<PK>(B));
 }
 
 // ---------------------------------------------------------------------------
@@ -451,14 +472,99 @@ struct Nbr {
   int u0, u1;    // its face-cell coordinates (transverse, increasing axis order)
 };
 
+// Src's combination of three stored values (start or latest A, end or stage-1
+// B, stage-1 C of a dense output), as src_val takes it from the buffers.
+__device__ __forceinline__ double src_combine(const Src &s, double A, double B, double C) {
+  if (s.w == 0.0) return A;
+  if (s.C) return (1.0 - s.w) * A + s.w * (1.0 - s.w) * C + s.w * s.w * B;
+  if (s.w == 1.0) return B;
+  return (1.0 - s.w) * A + s.w * B;
+}
+
+// Conserved state of a cell of a finer block Bn (source s) as the reader sees
+// it: each stored history of the 2x2x2 children from local cell (i0, j0, k0)
+// is restricted to their mean (summed in k, j, i order), then interpolated in
+// time (Sec. LAT method, coarse-fine interfaces).
+template <int NV>
+__device__ __forceinline__ void restricted(const BlockInfo &Bn, const Src &s, int i0, int j0, int k0, double *q) {
+  const long long n = Bn.n, n3 = n * n * n;
+  const long long c0 = Bn.off + (k0 * n + j0) * n + i0;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double hA = 0.0, hB = 0.0, hC = 0.0;
+    for (int kz = 0; kz < 2; ++kz)
+      for (int jy = 0; jy < 2; ++jy)
+        for (int ix = 0; ix < 2; ++ix) {
+          const long long o = c0 + v * n3 + (kz * n + jy) * n + ix;
+          hA += s.A[o];
+          hB += s.B[o];
+          if (s.C) hC += s.C[o];
+        }
+    q[v] = src_combine(s, 0.125 * hA, 0.125 * hB, 0.125 * hC);
+  }
+}
+
+// Conserved state of global cell g of level r (any index: wrapped here) when
+// the block covering it is on level r or r + 1.
+template <int NV, int PK>
+__device__ __forceinline__ void level_state(const StageArgs &a, int fb, int r, int gx, int gy, int gz, double *q) {
+  const MeshDev &m = a.m;
+  gx = wrap_axis(gx, m.nx << r, m.bc[0]);
+  gy = wrap_axis(gy, m.ny << r, m.bc[1]);
+  gz = wrap_axis(gz, m.nz << r, m.bc[2]);
+  const int nb = block_of(m, r, gx, gy, gz);
+  const BlockInfo Bn = m.blocks[nb];
+  const Src s = source_of<PK>(a, fb, nb);
+  if (Bn.lev != r) {
+    restricted<NV>(Bn, s, 2 * gx - Bn.ox, 2 * gy - Bn.oy, 2 * gz - Bn.oz, q);
+    return;
+  }
+  const long long n = Bn.n, n3 = n * n * n;
+  const long long idx = ((long long)(gz - Bn.oz) * n + (gy - Bn.oy)) * n + (gx - Bn.ox);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) q[v] = src_val(s, Bn.off + v * n3 + idx);
+}
+
+// Ghost state of fine cell g (level r = 1, inside the extents) covered by a
+// coarser block: prolongation of the coarse cell containing it from coarse
+// values at the reader's stage time, q_c + sum_d s_d minmod(q_c - q_-d,
+// q_+d - q_c) / 4 in x, y, z order, s_d = +1 for the upper child, -1 for the
+// lower (coarse neighbours covered by fine blocks enter restricted).
+template <int NV, int PK>
+__device__ __forceinline__ void prolonged(const StageArgs &a, int fb, int r, int gx, int gy, int gz, double *q) {
+  const int c[3] = {gx >> 1, gy >> 1, gz >> 1};
+  const int g[3] = {gx, gy, gz};
+  double qc[6];
+  level_state<NV, PK>(a, fb, r - 1, c[0], c[1], c[2], qc);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) q[v] = qc[v];
+#pragma unroll 1
+  for (int d = 0; d < 3; ++d) {
+    int cm[3] = {c[0], c[1], c[2]}, cp[3] = {c[0], c[1], c[2]};
+    cm[d] -= 1;
+    cp[d] += 1;
+    double qm[6], qp[6];
+    level_state<NV, PK>(a, fb, r - 1, cm[0], cm[1], cm[2], qm);
+    level_state<NV, PK>(a, fb, r - 1, cp[0], cp[1], cp[2], qp);
+    const double sgn = (g[d] & 1) ? 0.25 : -0.25;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double dl = qc[v] - qm[v], dr = qp[v] - qc[v];
+      const double mm = dl * dr <= 0.0 ? 0.0 : (fabs(dl) < fabs(dr) ? dl : dr);
+      q[v] += sgn * mm;
+    }
+  }
+}
+
 // load conserved state of global cell g (stage view of the reader), return block info
 template <int NV, int PK = 0>
 __device__ __forceinline__ void load_q(const StageArgs &a, int b, const BlockInfo &B, const Src &own, int fb,
                                        int gx, int gy, int gz, double *q, int *nb_out, long long *idx_out) {
   const MeshDev &m = a.m;
-  gx = wrap_axis(gx, m.nx, m.bc[0]);
-  gy = wrap_axis(gy, m.ny, m.bc[1]);
-  gz = wrap_axis(gz, m.nz, m.bc[2]);
+  const int r = lev_of<PK>(B);
+  gx = wrap_axis(gx, m.nx << r, m.bc[0]);
+  gy = wrap_axis(gy, m.ny << r, m.bc[1]);
+  gz = wrap_axis(gz, m.nz << r, m.bc[2]);
   const int lx = gx - B.ox, ly = gy - B.oy, lz = gz - B.oz;
   if ((unsigned)lx < (unsigned)B.n && (unsigned)ly < (unsigned)B.n && (unsigned)lz < (unsigned)B.n) {
     const long long n3 = (long long)B.n * B.n * B.n;
@@ -467,8 +573,18 @@ __device__ __forceinline__ void load_q(const StageArgs &a, int b, const BlockInf
     if (nb_out) { *nb_out = b; *idx_out = idx; }
     return;
   }
-  const int nb = block_of(m, gx, gy, gz);
+  const int nb = k_amr<PK>() ? block_of(m, r, gx, gy, gz) : block_of(m, gx, gy, gz);
   const BlockInfo Bn = m.blocks[nb];
+  if (k_amr<PK>() && Bn.lev != r) {  // a block on the other refinement level
+    if (Bn.lev > r) {
+      const Src s = source_of<PK>(a, fb, nb);
+      restricted<NV>(Bn, s, 2 * gx - Bn.ox, 2 * gy - Bn.oy, 2 * gz - Bn.oz, q);
+    } else {
+      prolonged<NV, PK>(a, fb, r, gx, gy, gz, q);
+    }
+    if (nb_out) { *nb_out = nb; *idx_out = -1; }
+    return;
+  }
   const Src s = source_of<PK>(a, fb, nb);
   const long long n3 = (long long)Bn.n * Bn.n * Bn.n;
   const long long idx = ((long long)(gz - Bn.oz) * Bn.n + (gy - Bn.oy)) * Bn.n + (gx - Bn.ox);
@@ -531,6 +647,7 @@ __device__ __forceinline__ long long uni(long long x) {
 __device__ __forceinline__ BlockInfo uni(const BlockInfo &b) {
   BlockInfo r;
   r.n = uni(b.n); r.ox = uni(b.ox); r.oy = uni(b.oy); r.oz = uni(b.oz);
+  r.lev = uni(b.lev); r.pad_ = 0;
   r.off = uni(b.off); r.poff = uni(b.poff); r.ioff = uni(b.ioff); r.foff = uni(b.foff);
   return r;
 }
@@ -649,9 +766,9 @@ __device__ __forceinline__ void face_flux(const StageArgs &a, const BlockInfo &B
   }
   if (k_grav<PK>(p) == 2 && p.r_exc > 0.0) {
     int gl[3] = {B.ox + fr[0], B.oy + fr[1], B.oz + fr[2]};
-    const bool eR = excr >= 0 ? excr != 0 : excised<PK>(p, m, gl[0], gl[1], gl[2], t);
+    const bool eR = excr >= 0 ? excr != 0 : excised<PK>(p, m, gl[0], gl[1], gl[2], t, lev_of<PK>(B));
     gl[D] -= 1;
-    const bool eL = excl >= 0 ? excl != 0 : excised<PK>(p, m, gl[0], gl[1], gl[2], t);
+    const bool eL = excl >= 0 ? excl != 0 : excised<PK>(p, m, gl[0], gl[1], gl[2], t, lev_of<PK>(B));
     if (eL != eR) {
       const bool into = eR ? (F[0] >= 0.0) : (F[0] <= 0.0);
       if (!into) {
@@ -677,14 +794,17 @@ __device__ __forceinline__ void face_flux(const StageArgs &a, const BlockInfo &B
     const int u1 = D == 2 ? fr[1] : fr[2];
     const long long nn2 = (long long)n * n;
     const long long base = B.ioff + (long long)(2 * D + side) * NV * nn2 + (long long)u1 * n + u0;
-    // only faces towards a block on another schedule take part in the reflux
+    // only faces towards a block on another schedule, or on another
+    // refinement level, take part in the reflux
     const int fn = nbo >= 0 ? a.fac[nbo] : fb;
-    if (fn == fb) {
+    const bool other_level = k_amr<PK>() && nbo >= 0 && m.blocks[nbo].lev != B.lev;
+    if (fn == fb && !other_level) {
     } else if (a.phase == 1) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) a.bf1[base + v * nn2] = Gf[v];
     } else {
-      const double area = m.dx[(D + 1) % 3] * m.dx[(D + 2) % 3];
+      const int r = lev_of<PK>(B);
+      const double area = dx_lev(m, (D + 1) % 3, r) * dx_lev(m, (D + 2) % 3, r);
       const int fw = fb > fn ? fb : fn;
       const bool overwrite = (a.k & (fw - 1)) == 0;
 #pragma unroll
@@ -708,7 +828,8 @@ __device__ __forceinline__ void axis_update(const StageArgs &a, const BlockInfo 
   constexpr int PN = 1 + D;
   const Phys &p = a.p;
   const MeshDev &m = a.m;
-  const double idx = m.inv_dx[D];
+  const double idx = inv_dx_lev(m, D, lev_of<PK>(B));
+  const double hd = dx_lev(m, D, lev_of<PK>(B));
 #pragma unroll
   for (int v = 0; v < NV; ++v) rhs[v] -= (Fhi[v] - Flo[v]) * idx;
   divv += (Fhi[6] - Flo[6]) * idx;
@@ -720,8 +841,8 @@ __device__ __forceinline__ void axis_update(const StageArgs &a, const BlockInfo 
     const double pm = phis ? phis[0] : phi_at<PK>(a, B, im[0], im[1], im[2], t);
     const double p0 = phis ? phis[1] : phi_at<PK>(a, B, lc[0], lc[1], lc[2], t);
     const double pp = phis ? phis[2] : phi_at<PK>(a, B, ip[0], ip[1], ip[2], t);
-    rhs[PN] -= rho * (pp - pm) / (2.0 * m.dx[D]);
-    rhs[IEN] -= (Fhi[IDN] * (pp - p0) + Flo[IDN] * (p0 - pm)) / (2.0 * m.dx[D]);
+    rhs[PN] -= rho * (pp - pm) / (2.0 * hd);
+    rhs[IEN] -= (Fhi[IDN] * (pp - p0) + Flo[IDN] * (p0 - pm)) / (2.0 * hd);
   }
   // Pin the sums here: otherwise the compiler may sink this axis's arithmetic
   // to the final use and keep its inputs live through the remaining axes.
@@ -786,7 +907,7 @@ __device__ __forceinline__ void finish_cell(const StageArgs &a, const BlockInfo 
     if (Uc > 0.0 && Uc > p.eta2 * emax) qn[IAX] = Uc;
   }
   if (a.phase == 2 && k_grav<PK>(p) == 2 && p.r_exc > 0.0) {
-    if (excised<PK>(p, m, B.ox + lc[0], B.oy + lc[1], B.oz + lc[2], tk + dtb)) {
+    if (excised<PK>(p, m, B.ox + lc[0], B.oy + lc[1], B.oz + lc[2], tk + dtb, lev_of<PK>(B))) {
       const double uf = u_floor<PK>(p, p.rho_floor);
       qn[IDN] = p.rho_floor;
       qn[IM1] = qn[IM2] = qn[IM3] = 0.0;
@@ -821,7 +942,8 @@ __device__ __forceinline__ void finish_cell(const StageArgs &a, const BlockInfo 
     int jo = -1;
     eos_pc<PK>(p, a.t, w[0], w[4], (k_eos<PK>(p) == 1 && p.inv_mode != 0) ? jcell : -1, P, cs, &jo);
     double best = INFINITY;
-    for (int d = 0; d < 3; ++d) best = fmin(best, m.dx[d] / (fabs(w[1 + d]) + cs));
+    const int r = lev_of<PK>(B);
+    for (int d = 0; d < 3; ++d) best = fmin(best, dx_lev(m, d, r) / (fabs(w[1 + d]) + cs));
     if (k_grav<PK>(p)) {
       const double t = tk + dtb;
       double g2 = 0.0;
@@ -830,10 +952,10 @@ __device__ __forceinline__ void finish_cell(const StageArgs &a, const BlockInfo 
         ip[d] += 1;
         im[d] -= 1;
         const double gd = (phi_at<PK>(a, B, ip[0], ip[1], ip[2], t) - phi_at<PK>(a, B, im[0], im[1], im[2], t)) /
-                          (2.0 * m.dx[d]);
+                          (2.0 * dx_lev(m, d, r));
         g2 += gd * gd;
       }
-      const double dmin = fmin(m.dx[0], fmin(m.dx[1], m.dx[2]));
+      const double dmin = fmin(dx_lev(m, 0, r), fmin(dx_lev(m, 1, r), dx_lev(m, 2, r)));
       if (g2 > 0.0) best = fmin(best, sqrt(dmin / sqrt(g2)));
     }
     *cflv = best;
@@ -862,7 +984,7 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
   const MeshDev &m = a.m;
   const int tid = item_tid();
   const int cc[3] = {tid % TX, (tid / TX) % TY, tid / (TX * TY)};  // own cell in the tile
-  const int Nd = D == 0 ? m.nx : (D == 1 ? m.ny : m.nz);
+  const int Nd = (D == 0 ? m.nx : (D == 1 ? m.ny : m.nz)) << lev_of<PK>(T.B);
   // stage the halo along D (the tile's own cells were staged at the item start)
   if (tid < 4 * A) {
     const int layer = tid / A, u = tid % A;
@@ -886,7 +1008,7 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
       if (layer == 1 || layer == 2) {  // the cells next to the tile: the only halo the terms need
         const int l0 = T.to[0] + c[0], l1 = T.to[1] + c[1], l2 = T.to[2] + c[2];
         sPhi[slot] = phi_at<PK>(a, T.B, l0, l1, l2, T.t);
-        sExc[slot] = excised<PK>(p, m, g[0], g[1], g[2], T.t) ? 1 : 0;
+        sExc[slot] = excised<PK>(p, m, g[0], g[1], g[2], T.t, lev_of<PK>(T.B)) ? 1 : 0;
       }
     }
   }
@@ -1019,7 +1141,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) 
       sW[6 * SW + tid] = q[IEN];
       if constexpr (k_gcache<PK>()) {
         sPhi[tid] = phi_at<PK>(a, T.B, lc[0], lc[1], lc[2], T.t);
-        sExc[tid] = excised<PK>(p, m, T.B.ox + lc[0], T.B.oy + lc[1], T.B.oz + lc[2], T.t) ? 1 : 0;
+        sExc[tid] = excised<PK>(p, m, T.B.ox + lc[0], T.B.oy + lc[1], T.B.oz + lc[2], T.t, lev_of<PK>(T.B)) ? 1 : 0;
       }
     }
     double rhs[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -1054,6 +1176,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) 
 // split form: a kernel per axis computes every face flux of the active blocks
 // into the flux arrays (one face per thread, no LDS, no barriers), then one
 // kernel per cell sums them.  Same arithmetic as the fused form, bit for bit.
+// Single-level meshes only (refined meshes run the fused form's kPkAmr kind).
 // ---------------------------------------------------------------------------
 // face (fi, fj, fk) of axis D: the D-th coordinate in [0, n], the others in
 // [0, n), x fastest
@@ -1302,17 +1425,18 @@ __global__ void commit_kernel(const int *order, const int *cnt_ge, int lmin, int
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) par[order[i]] ^= 1;
 }
 
-// Delayed flux correction for blocks completing now against finer neighbours
-// (eqs lat-mass-impulse-mismatch, lat-grav-reflux); one launch per axis so a
-// cell touched by several faces is corrected in axis order without races.
+// Delayed flux correction for blocks completing now (eqs lat-flux-impulse,
+// lat-mass-impulse-mismatch, lat-grav-reflux): against neighbours on the same
+// refinement level that update more often, and against every finer neighbour,
+// whose 2x2 face impulses (summed in u1, u0 order) replace the coarse face's
+// own; never against a coarser neighbour.  One launch per axis so a cell
+// touched by several faces is corrected in axis order without races.
 __global__ void reflux_kernel(StageArgs a, int lc, int dir, int nmax) {
   const MeshDev &m = a.m;
   const int nv = m.nv;
   const int nc = a.cnt_ge[lc];
   const long long per = 2LL * nmax * nmax;
   const long long total = (long long)nc * per;
-  const int N[3] = {m.nx, m.ny, m.nz};
-  const double vol = m.dx[0] * m.dx[1] * m.dx[2];
   const double tc = a.win[0] + a.k * a.win[1];  // completion time
   for (long long it = (long long)blockIdx.x * blockDim.x + threadIdx.x; it < total;
        it += (long long)gridDim.x * blockDim.x) {
@@ -1330,25 +1454,32 @@ __global__ void reflux_kernel(StageArgs a, int lc, int dir, int nmax) {
     if (dir == 1) { loc[0] = u0; loc[2] = u1; }
     if (dir == 2) { loc[0] = u0; loc[1] = u1; }
     loc[dir] = side ? n - 1 : 0;
+    const int r = B.lev;
+    const int N[3] = {m.nx << r, m.ny << r, m.nz << r};
     int gg[3] = {B.ox + loc[0], B.oy + loc[1], B.oz + loc[2]};
     gg[dir] += side ? 1 : -1;
     if (m.bc[dir] != 0 && (gg[dir] < 0 || gg[dir] >= N[dir])) continue;
-    gg[0] = wrap_axis(gg[0], m.nx, m.bc[0]);
-    gg[1] = wrap_axis(gg[1], m.ny, m.bc[1]);
-    gg[2] = wrap_axis(gg[2], m.nz, m.bc[2]);
-    const int nb = block_of(m, gg[0], gg[1], gg[2]);
-    if (a.fac[nb] >= a.fac[b]) continue;
+    for (int d = 0; d < 3; ++d) gg[d] = wrap_axis(gg[d], N[d], m.bc[d]);
+    const int nb = block_of(m, r, gg[0], gg[1], gg[2]);
     const BlockInfo Bn = m.blocks[nb];
-    const int ln[3] = {gg[0] - Bn.ox, gg[1] - Bn.oy, gg[2] - Bn.oz};
+    if (Bn.lev < r || (Bn.lev == r && a.fac[nb] >= a.fac[b])) continue;
+    const int w = Bn.lev > r ? 2 : 1;
+    int h[3];  // the cell across (the first of the 2x2 fine face cells for a finer neighbour)
+    for (int d = 0; d < 3; ++d) h[d] = w == 1 ? gg[d] : (d == dir ? 2 * gg[d] + (side ? 0 : 1) : 2 * gg[d]);
+    const int ln[3] = {h[0] - Bn.ox, h[1] - Bn.oy, h[2] - Bn.oz};
     const int v0 = dir == 0 ? ln[1] : ln[0];
     const int v1 = dir == 2 ? ln[1] : ln[2];
     const int nn = Bn.n;
     double dI[6];
     for (int v = 0; v < nv; ++v) {
       const long long ib = B.ioff + ((long long)(2 * dir + side) * nv + v) * n * n + (long long)u1 * n + u0;
-      const long long in = Bn.ioff + ((long long)(2 * dir + 1 - side) * nv + v) * nn * nn + (long long)v1 * nn + v0;
-      dI[v] = a.imp[ib] - a.imp[in];
+      const long long in = Bn.ioff + ((long long)(2 * dir + 1 - side) * nv + v) * nn * nn;
+      double In = 0.0;
+      for (int e1 = 0; e1 < w; ++e1)
+        for (int e0 = 0; e0 < w; ++e0) In += a.imp[in + (long long)(v1 + e1) * nn + (v0 + e0)];
+      dI[v] = a.imp[ib] - In;
     }
+    const double vol = dx_lev(m, 0, r) * dx_lev(m, 1, r) * dx_lev(m, 2, r);
     const double sg = side ? 1.0 : -1.0;
     double *q = a.par[b] ? a.Qb : a.Qa;
     const long long n3 = (long long)n * n * n;
@@ -1403,9 +1534,10 @@ __global__ __launch_bounds__(kChunk) void cfl_items_kernel(StageArgs a, double t
     if (rec && inside) a.jc[js] = j;
     double best = INFINITY;
     const int ci = (int)(cq % n), cj = (int)((cq / n) % n), ck = (int)(cq / ((long long)n * n));
-    const bool exc = p.grav_kind == 2 && p.r_exc > 0.0 && excised(p, m, B.ox + ci, B.oy + cj, B.oz + ck, t);
+    const int r = B.lev;
+    const bool exc = p.grav_kind == 2 && p.r_exc > 0.0 && excised(p, m, B.ox + ci, B.oy + cj, B.oz + ck, t, r);
     if (inside && !exc) {
-      for (int d = 0; d < 3; ++d) best = fmin(best, m.dx[d] / (fabs(w[1 + d]) + cs));
+      for (int d = 0; d < 3; ++d) best = fmin(best, dx_lev(m, d, r) / (fabs(w[1 + d]) + cs));
       // source-term limit: sqrt(dx_min / |g|) with g the centred potential gradient
       if (p.grav_kind) {
         double g2 = 0.0;
@@ -1415,10 +1547,10 @@ __global__ __launch_bounds__(kChunk) void cfl_items_kernel(StageArgs a, double t
           ip[d] += 1;
           im[d] -= 1;
           const double gd = (phi_at(a, B, ip[0], ip[1], ip[2], t) - phi_at(a, B, im[0], im[1], im[2], t)) /
-                            (2.0 * m.dx[d]);
+                            (2.0 * dx_lev(m, d, r));
           g2 += gd * gd;
         }
-        const double dmin = fmin(m.dx[0], fmin(m.dx[1], m.dx[2]));
+        const double dmin = fmin(dx_lev(m, 0, r), fmin(dx_lev(m, 1, r), dx_lev(m, 2, r)));
         if (g2 > 0.0) best = fmin(best, sqrt(dmin / sqrt(g2)));
       }
     }
@@ -1562,6 +1694,18 @@ hipError_t launch_stage(const StageArgs &a, int tile, int grid, hipStream_t s) {
   int i = 0;
   // the network variant when it starts the searches (table EOS, mode 1, network on)
   const bool net = a.p.eos_kind == 1 && a.p.inv_mode == 1 && a.s.enabled;
+  if (a.m.amr) {
+    // Meshes with a refined block: one variant (8 x 8 x 4 cells, two waves per
+    // SIMD: the cross-level ghost path needs the registers), whatever the tile.
+    if (a.m.nv == 6) {
+      if (net) hipLaunchKernelGGL((stage_tiled<8, 8, 4, 6, 2, true, 256, kPkAmr>), dim3(grid), dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((stage_tiled<8, 8, 4, 6, 2, false, 256, kPkAmr>), dim3(grid), dim3(256), 0, s, a);
+    } else {
+      if (net) hipLaunchKernelGGL((stage_tiled<8, 8, 4, 5, 2, true, 256, kPkAmr>), dim3(grid), dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((stage_tiled<8, 8, 4, 5, 2, false, 256, kPkAmr>), dim3(grid), dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+  }
   const int code = a.m.nv != 5 + (a.p.dual ? 1 : 0)
                        ? 0
                        : physics_code(a.p.eos_kind, a.p.dual ? 1 : 0, a.p.grav_kind, a.p.riemann, a.p.ghost_dense,

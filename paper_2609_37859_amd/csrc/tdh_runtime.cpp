@@ -30,6 +30,8 @@ struct tdh_ctx {
   double x0[3] = {0, 0, 0}, dx[3] = {1, 1, 1};
   int nb = 0, nv = 5, lat = 0, lx = 0, ly = 0, lz = 0, nmax = 0;
   std::vector<int> blk;                 // [nb][4]
+  std::vector<int> rl;                  // refinement level of each block (0 or 1)
+  bool amr = false;                     // some block is on level 1
   std::vector<int> lmap;
   std::vector<BlockInfo> binfo;
   std::vector<std::vector<int>> adj;    // face/edge/corner neighbours
@@ -153,10 +155,13 @@ static const char *mesh_layout(const tdh_config *cfg, const tdh_mesh *m, Layout 
   int lat = 1 << 30, nmax = 0;
   for (int b = 0; b < m->nblocks; ++b) {
     const int n = m->blk[4 * b];
+    const int r = m->rlev ? m->rlev[b] : 0;
     if (!is_pow2(n) || n < 2 || n > 256) return "block edge must be a power of two in [2, 256]";
-    lat = std::min(lat, n);
+    if (r < 0 || r > 1) return "refinement level must be 0 or 1";
+    lat = std::min(lat, n >> r);  // the lattice counts level-0 cells
     nmax = std::max(nmax, n);
   }
+  if (lat < 1) return "a level-1 block must span at least one level-0 cell";
   if (m->nx <= 0 || m->ny <= 0 || m->nz <= 0 || m->nx % lat || m->ny % lat || m->nz % lat)
     return "domain size must be a positive multiple of the smallest block edge";
   for (int d = 0; d < 3; ++d) {
@@ -296,7 +301,7 @@ static Phys make_phys(const tdh_config &g) {
 // extra work, and the point mass's term moves with time (the reduction takes
 // the host's time).
 static bool stage_cfl(const tdh_ctx *c) {
-  return c->cfg.eos_kind == 1 && c->cfg.n_lat == 0 && c->Lmax == 0 && c->cfg.grav_kind != 2;
+  return c->cfg.eos_kind == 1 && c->cfg.n_lat == 0 && c->Lmax == 0 && c->cfg.grav_kind != 2 && !c->amr;
 }
 
 static StageArgs base_args(tdh_ctx *c) {
@@ -315,6 +320,7 @@ static StageArgs base_args(tdh_ctx *c) {
   a.m.lx = c->lx;
   a.m.ly = c->ly;
   a.m.lz = c->lz;
+  a.m.amr = c->amr ? 1 : 0;
   a.m.nv = c->nv;
   a.m.lmap = c->d_lmap;
   a.m.blocks = c->d_blocks;
@@ -346,14 +352,17 @@ static StageArgs base_args(tdh_ctx *c) {
   return a;
 }
 
-// face/edge/corner adjacency through the lattice (periodic wrap, nothing beyond outflow edges)
+// face/edge/corner adjacency through the lattice (periodic wrap, nothing beyond
+// outflow edges), whatever the refinement levels: the lattice cells (level-0
+// units) around each block's extent
 static void build_adjacency(tdh_ctx *c) {
   c->adj.assign(c->nb, {});
   const int L = c->lat;
   const int N[3] = {c->nx, c->ny, c->nz};
   for (int b = 0; b < c->nb; ++b) {
-    const int n = c->blk[4 * b];
-    const int o[3] = {c->blk[4 * b + 1], c->blk[4 * b + 2], c->blk[4 * b + 3]};
+    const int r = c->rl[b];
+    const int n = c->blk[4 * b] >> r;
+    const int o[3] = {c->blk[4 * b + 1] >> r, c->blk[4 * b + 2] >> r, c->blk[4 * b + 3] >> r};
     std::vector<int> &A = c->adj[b];
     for (int cz = o[2] - L; cz < o[2] + n + L; cz += L)
       for (int cy = o[1] - L; cy < o[1] + n + L; cy += L)
@@ -436,18 +445,22 @@ extern "C" tdh_status tdh_init_blocks(tdh_ctx *c, const tdh_mesh *m, void *dev_a
   for (int d = 0; d < 3; ++d) { c->bc[d] = m->bc[d]; c->x0[d] = m->x0[d]; c->dx[d] = m->dx[d]; }
   c->nb = m->nblocks;
   c->blk.assign(m->blk, m->blk + 4 * m->nblocks);
+  c->rl.assign(c->nb, 0);
+  if (m->rlev) c->rl.assign(m->rlev, m->rlev + c->nb);
+  c->amr = std::any_of(c->rl.begin(), c->rl.end(), [](int r) { return r != 0; });
   c->lat = L.lat;
   c->nmax = L.nmax;
   c->lx = c->nx / c->lat; c->ly = c->ny / c->lat; c->lz = c->nz / c->lat;
   c->lmap.assign((size_t)c->lx * c->ly * c->lz, -1);
   for (int b = 0; b < c->nb; ++b) {
     const int n = c->blk[4 * b], ox = c->blk[4 * b + 1], oy = c->blk[4 * b + 2], oz = c->blk[4 * b + 3];
-    if (ox % c->lat || oy % c->lat || oz % c->lat || ox < 0 || oy < 0 || oz < 0 || ox + n > c->nx ||
-        oy + n > c->ny || oz + n > c->nz)
+    const int r = c->rl[b], Lr = c->lat << r;  // lattice edge in this block's cells
+    if (ox % Lr || oy % Lr || oz % Lr || ox < 0 || oy < 0 || oz < 0 || ox + n > (c->nx << r) ||
+        oy + n > (c->ny << r) || oz + n > (c->nz << r))
       return fail(c, TDH_EINVAL, "block %d is not aligned to the lattice or leaves the domain", b);
-    for (int z = oz / c->lat; z < (oz + n) / c->lat; ++z)
-      for (int y = oy / c->lat; y < (oy + n) / c->lat; ++y)
-        for (int x = ox / c->lat; x < (ox + n) / c->lat; ++x) {
+    for (int z = oz / Lr; z < (oz + n) / Lr; ++z)
+      for (int y = oy / Lr; y < (oy + n) / Lr; ++y)
+        for (int x = ox / Lr; x < (ox + n) / Lr; ++x) {
           int &slot = c->lmap[((size_t)z * c->ly + y) * c->lx + x];
           if (slot != -1) return fail(c, TDH_EINVAL, "blocks %d and %d overlap", slot, b);
           slot = b;
@@ -459,6 +472,8 @@ extern "C" tdh_status tdh_init_blocks(tdh_ctx *c, const tdh_mesh *m, void *dev_a
   for (int b = 0; b < c->nb; ++b) {
     BlockInfo &B = c->binfo[b];
     B.n = c->blk[4 * b]; B.ox = c->blk[4 * b + 1]; B.oy = c->blk[4 * b + 2]; B.oz = c->blk[4 * b + 3];
+    B.lev = c->rl[b];
+    B.pad_ = 0;
     B.off = L.off[b]; B.poff = L.poff[b]; B.ioff = L.ioff[b]; B.foff = L.foff[b];
   }
   c->total = L.total; c->ptotal = L.ptotal; c->itotal = L.itotal; c->ncells = L.ncells;
@@ -514,7 +529,8 @@ extern "C" tdh_status tdh_init_blocks(tdh_ctx *c, const tdh_mesh *m, void *dev_a
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipHostMalloc((void **)&c->h_dtb, c->nb * sizeof(double), hipHostMallocDefault));
   build_adjacency(c);
-  if (c->lat < 8) return fail(c, TDH_EINVAL, "blocks must have an edge of at least 8 cells");
+  for (int b = 0; b < c->nb; ++b)
+    if (c->blk[4 * b] < 8) return fail(c, TDH_EINVAL, "blocks must have an edge of at least 8 cells");
   c->tile = 0;
   while (c->tile < num_tiles() && !tile_fits(c, c->tile)) c->tile++;
   c->have_mesh = true;
@@ -624,12 +640,17 @@ static std::vector<int> assign_levels(const tdh_ctx *c, const std::vector<double
     for (int &v : e)
       if (v == top) v = top - 1;
   }
-  // neighbours differ by at most one exponent: relax to the fixed point
+  // neighbour limits, relaxed to their fixed point (the greatest admissible
+  // exponents below the CFL bins): one exponent apart on one refinement level;
+  // across levels f_fine <= f_coarse <= 2 f_fine, i.e. a fine block's exponent
+  // at most its coarse neighbour's, a coarse block's at most one above
   for (bool changed = true; changed;) {
     changed = false;
     for (int b = 0; b < nb; ++b)
-      for (int n : c->adj[b])
-        if (e[b] > e[n] + 1) { e[b] = e[n] + 1; changed = true; }
+      for (int n : c->adj[b]) {
+        const int cap = c->rl[b] > c->rl[n] ? e[n] : e[n] + 1;
+        if (e[b] > cap) { e[b] = cap; changed = true; }
+      }
   }
   const int L = *std::max_element(e.begin(), e.end());
   std::vector<int> lev(nb);
@@ -710,8 +731,13 @@ extern "C" tdh_status tdh_set_levels(tdh_ctx *c, const int8_t *host_levels) {
     if (lev[b] < 0 || lev[b] > kMaxLevel) return fail(c, TDH_EINVAL, "level of block %d outside [0, 30]", b);
   }
   for (int b = 0; b < c->nb; ++b)
-    for (int n : c->adj[b])
-      if (std::abs(lev[b] - lev[n]) > 1) return fail(c, TDH_EINVAL, "neighbours %d and %d differ by more than one level", b, n);
+    for (int n : c->adj[b]) {
+      if (std::abs(lev[b] - lev[n]) > 1)
+        return fail(c, TDH_EINVAL, "neighbours %d and %d differ by more than one level", b, n);
+      // a finer block never takes a longer step than its coarser neighbour
+      if (c->rl[b] > c->rl[n] && lev[b] < lev[n])
+        return fail(c, TDH_EINVAL, "block %d (refined) steps longer than its coarser neighbour %d", b, n);
+    }
   return install_levels(c, lev);
 }
 
@@ -803,7 +829,7 @@ static tdh_status enqueue_subcycle(tdh_ctx *c, int k, bool batched) {
   }
   HIPCHK(c, launch_commit(c->d_order, c->d_cnt_ge, lmin, c->d_par, c->stream));
   c->stats.kernel_launches++;
-  if (c->Lmax > 0) {
+  if (c->Lmax > 0 || c->amr) {  // coarse-fine faces are corrected on every coarse step
     const int fmax = 1 << c->Lmax;
     const int lc = (k + 1 == fmax) ? 0 : c->Lmax - ctz(k + 1);
     a.k = k + 1;
@@ -1015,6 +1041,7 @@ extern "C" tdh_status tdh_gravity_workspace_bytes(tdh_ctx *c, size_t *host_bytes
   tdh_status st;
   if ((st = ready(c))) return st;
   if (!host_bytes) return fail(c, TDH_EINVAL, "null output");
+  if (c->amr) return fail(c, TDH_EINVAL, "the self-gravity solve needs a single-level mesh");
   MgPlan P;
   if ((st = mg_plan(c, nullptr, &P))) return st;
   *host_bytes = P.bytes;
@@ -1027,6 +1054,7 @@ extern "C" tdh_status tdh_gravity_solve(tdh_ctx *c, void *dev_work, size_t bytes
   tdh_status st;
   if ((st = ready(c)) || (st = require_window_boundary(c))) return st;
   if (!dev_work) return fail(c, TDH_EINVAL, "null workspace");
+  if (c->amr) return fail(c, TDH_EINVAL, "the self-gravity solve needs a single-level mesh");
   if (!std::isfinite(four_pi_G) || !(tol >= 0.0) || max_cycles < 0 || max_cycles > 1000)
     return fail(c, TDH_EINVAL, "four_pi_G must be finite, tol >= 0 and max_cycles in [0, 1000]");
   MgPlan P;
@@ -1104,6 +1132,7 @@ extern "C" tdh_status tdh_remap(tdh_ctx *dst, tdh_ctx *src) {
   if ((st = ready(dst)) || (st = require_window_boundary(dst))) return st;
   if ((st = ready(src)) || (st = require_window_boundary(src))) return fail(dst, TDH_ESTATE, "source: %s", g_err.c_str());
   if (dst == src) return fail(dst, TDH_EINVAL, "source and target are the same context");
+  if (dst->amr || src->amr) return fail(dst, TDH_EINVAL, "the remap needs single-level meshes");
   if (dst->nv != src->nv) return fail(dst, TDH_EINVAL, "source and target differ in dual energy (%d vs %d variables)",
                                       src->nv, dst->nv);
   // the target grid coincides with the source grid if the spacings are equal and
@@ -1152,6 +1181,7 @@ extern "C" tdh_status tdh_frame_acceleration(tdh_ctx *c, double rho_min, double 
   if ((st = ready(c)) || (st = require_window_boundary(c))) return st;
   if (!host_A) return fail(c, TDH_EINVAL, "null output");
   if (c->cfg.grav_kind != 2) return fail(c, TDH_ESTATE, "the frame acceleration needs the point mass (grav_kind 2)");
+  if (c->amr) return fail(c, TDH_EINVAL, "the frame acceleration needs a single-level mesh");
   const StageArgs a = base_args(c);
   double *part = c->d_facc, *out = c->d_facc + 4 * frame_acceleration_parts();
   HIPCHK(c, launch_frame_acceleration(a.m, c->d_par, c->Qa, c->Qb, a.p, c->t, rho_min, part, out, c->stream));

@@ -34,7 +34,7 @@ class tdh_config(C.Structure):
 class tdh_mesh(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("bc", C.c_int * 3),
                 ("x0", C.c_double * 3), ("dx", C.c_double * 3), ("nblocks", C.c_int),
-                ("blk", C.POINTER(C.c_int))]
+                ("blk", C.POINTER(C.c_int)), ("rlev", C.POINTER(C.c_int))]
 
 
 class tdh_stats(C.Structure):
@@ -131,6 +131,7 @@ def make_config(cfg, inv_mode=0, newton_max_iter=4) -> tdh_config:
 
 
 def make_mesh(mesh):
+    """tdh_mesh of a workloads.Mesh, and the arrays it points into (keep them alive)."""
     blk = np.ascontiguousarray(mesh.blk, dtype=np.int32)
     m = tdh_mesh()
     m.nx, m.ny, m.nz = mesh.nx, mesh.ny, mesh.nz
@@ -139,7 +140,12 @@ def make_mesh(mesh):
     m.dx[:] = list(mesh.dx)
     m.nblocks = mesh.nblocks
     m.blk = blk.ctypes.data_as(C.POINTER(C.c_int))
-    return m, blk
+    keep = [blk]
+    if getattr(mesh, "rlev", None) is not None:
+        rlev = np.ascontiguousarray(mesh.rlev, dtype=np.int32)
+        m.rlev = rlev.ctypes.data_as(C.POINTER(C.c_int))
+        keep.append(rlev)
+    return m, keep
 
 
 class Context:

@@ -576,6 +576,43 @@ def random_smooth_state(mesh: Mesh, cfg: Config, seed: int, amp=0.2, modes=3):
 # ---------------------------------------------------------------------------
 # learned EOS seed: training samples, initial parameters, normalisation
 # ---------------------------------------------------------------------------
+def amr_blast(nb=(4, 4, 4), n=8, refined=((1, 1, 1), (2, 1, 1), (1, 2, 1), (2, 2, 2)), seed=5, amp=0.2,
+              hot=30.0, dual=1, n_lat=2, ghost_dense=0, riemann=0):
+    """Two-level workload of the coarse-fine LAT: a periodic unit-length box
+    (along x) of nb level-0 regions of n^3 cells, the listed regions (x, y, z
+    region indices) refined into eight level-1 blocks of n^3 cells.  Ideal
+    gas (gamma 5/3) with a smooth random perturbation of amplitude amp
+    (random_smooth_state) and an over-pressured Gaussian (peak pressure
+    1 + hot, width one level-0 region / 4) at the centre of the first refined
+    region: its sound speed and the halved fine cells give the refined blocks
+    the smallest CFL steps, so a LAT window mixes factors across refinement
+    levels and on each level.  Returns (cfg, mesh, U)."""
+    cfg = Config(dual=dual, gamma=5.0 / 3.0, cfl=0.3, n_lat=n_lat, rho_floor=1e-10, p_floor=1e-12,
+                 ghost_dense=ghost_dense, riemann=riemann)
+    ref = np.zeros(nb[::-1], dtype=bool)
+    for cx, cy, cz in refined:
+        ref[cz, cy, cx] = True
+    dx = 1.0 / (nb[0] * n)
+    mesh = amr_mesh(nb, n, dx, ref, bc=(0, 0, 0))
+    base = random_smooth_state(mesh, dataclasses.replace(cfg, dual=0), seed=seed, amp=amp)
+    cx, cy, cz = refined[0]
+    c = [(cx + 0.5) * n * dx, (cy + 0.5) * n * dx, (cz + 0.5) * n * dx]
+    w = 0.25 * n * dx
+    out = []
+    off = mesh.offsets(5)
+    for b in range(mesh.nblocks):
+        x, y, z = cell_centres(mesh, b)
+        q = base[off[b]:off[b + 1]].reshape(5, *x.shape)
+        rho = q[0]
+        K = 0.5 * (q[1] ** 2 + q[2] ** 2 + q[3] ** 2) / rho
+        P = (q[4] - K) * (cfg.gamma - 1.0)
+        P = P + hot * np.exp(-((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2) / (2 * w * w))
+        U = P / (cfg.gamma - 1.0)
+        blk = [q[0], q[1], q[2], q[3], U + K] + ([U] if dual else [])
+        out.append(np.stack(blk).ravel())
+    return cfg, mesh, np.ascontiguousarray(np.concatenate(out))
+
+
 def seed_ranges(table: EosTable):
     """(log rho lo, hi, log e lo, hi, log T lo, hi) used to normalise to [-1, 1]."""
     return (table.lr0, table.lr0 + (table.nrho - 1) * table.dlr, float(table.le.min()), float(table.le.max()),

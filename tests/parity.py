@@ -80,12 +80,23 @@ def _stencil_max(c, bc):
     return s
 
 
+def _by_variable(nv, mesh, U):
+    """[nv, ncells] view of a block-ordered state (every block's cells, in
+    block order): the strict form is per cell, so it needs no global grid and
+    serves meshes on several refinement levels."""
+    from paper_2609_37859_amd.workloads import unpack_block
+    return np.concatenate([unpack_block(mesh, nv, U, b).reshape(nv, -1) for b in range(mesh.nblocks)], axis=1)
+
+
 def rel_err(nv, mesh, a, b, with_counts=False, stencil=False):
     if not (np.all(np.isfinite(a)) and np.all(np.isfinite(b))):
         errs = np.full(nv, np.inf)  # a non-finite state never passes
         return (errs, 0) if with_counts else errs
-    from paper_2609_37859_amd.workloads import to_global
-    A, B = to_global(mesh, nv, a), to_global(mesh, nv, b)
+    if stencil:
+        from paper_2609_37859_amd.workloads import to_global
+        A, B = to_global(mesh, nv, a), to_global(mesh, nv, b)
+    else:
+        A, B = _by_variable(nv, mesh, a), _by_variable(nv, mesh, b)
     c, ill = _cell_scales(nv, B)
     s = _stencil_max(c, mesh.bc) if stencil else c
     d = np.abs(A - B)

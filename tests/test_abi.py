@@ -3,6 +3,7 @@
 import ctypes
 import os
 
+import numpy as np
 import pytest
 
 from paper_2609_37859_amd import tdh as T
@@ -39,3 +40,13 @@ def test_arena_size_and_mesh_validation_without_gpu():
     bad = W.uniform_mesh(2, 1, 1, 12, 0.1)  # 12 is not a power of two
     m2, keep2 = T.make_mesh(bad)
     assert L.tdh_arena_bytes(ctypes.byref(c), ctypes.byref(m2)) == 0
+    # two refinement levels: levels 0 and 1 accepted, anything else refused
+    ref = np.zeros((2, 2, 2), dtype=bool)
+    ref[1, 0, 1] = True
+    amr = W.amr_mesh((2, 2, 2), 8, 0.1, ref)
+    m3, keep3 = T.make_mesh(amr)
+    assert L.tdh_arena_bytes(ctypes.byref(c), ctypes.byref(m3)) >= 3 * 6 * 8 ** 3 * 8 * amr.nblocks
+    amr.rlev = amr.rlev.copy()
+    amr.rlev[0] = 2
+    m4, keep4 = T.make_mesh(amr)
+    assert L.tdh_arena_bytes(ctypes.byref(c), ctypes.byref(m4)) == 0
