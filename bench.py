@@ -35,7 +35,9 @@ level) in six inversion forms with its own stage-kernel roofline, "lat" the
 256^3 polytrope (ideal gas, fixed potential, LAT) batched beside per-level,
 "learned_seed" the network's training and evaluation, "gravity" the
 self-gravity multigrid on the 256^3 Jeans wave, "remap" the restart remap of
-the 128^3 stream onto 256^3.
+the 128^3 stream onto 256^3, "amr" the production-shaped run on two refinement
+levels (134.2 M cells) with its stage kernel's roofline and the oracle on a
+sub-domain.
 """
 import argparse
 import dataclasses
@@ -310,6 +312,84 @@ def c5_section(T, W, table, params, forms, windows, warmup, repeats, tile):
                                 "stage_launches": int(launches), "ms_per_window": 1e3 * el2 / windows}
         ctx.close()
         out[name] = r
+    return out
+
+
+AMR_WORKLOAD = ("production-shaped run on two refinement levels: the 301 flagged regions refined into eight "
+                "level-1 blocks each, 1688 level-0 + 2408 level-1 MeshBlocks of 32^3 (134.2M cells), Saha H/He "
+                "table EOS 256x256, dual energy, 1e3 Msun point mass with excision in a moving frame, debris "
+                "stream, LAT N_LAT=3, merge_frac 0.01, CFL 0.3, outflow")
+
+
+def amr_section(T, W, table, params, windows, warmup, oracle_windows):
+    """The two-level (coarse-fine) LAT run in the learned form (its own stage
+    kernel kind), with the stage kernel's launch timing from a pass without
+    graph replay, and on the region sub-domain AMR_SUBDOMAIN the oracle
+    (timed on the host's threads) against the same form."""
+    import oracle
+    from tests.parity import rel_err
+    cfg, mesh, U = W.debris_stream_amr(table)
+    cfg = dataclasses.replace(cfg, merge_frac=0.01)
+    ctx = T.Context(cfg, mesh, U, table=table, inv_mode=4)
+    ctx.mlp_init(params, W.seed_ranges(table))
+    ctx.mlp_enable_seed(True)
+    for _ in range(warmup):
+        _, dt0, lev, L = ctx.reduce_dt()
+        ctx.run_window(dt0 * 2 ** L, batched=True, graph=True)
+    ctx.sync()
+    el, cu, bu, se, hist = _timed_windows(ctx, windows, graph=True)
+    ctx.set_timing(True)
+    el2, cu2, _, _, _ = _timed_windows(ctx, windows, graph=False)
+    stage_ms, launches = ctx.stage_time()
+    ctx.close()
+    del U
+    bpc = 5 * 6 * 8
+    launch_ms = stage_ms / max(launches, 1)
+    alg = bpc * cu2 / max(launches, 1)
+    achieved = alg / (launch_ms * 1e-3) / 1e9
+    out = {"workload": AMR_WORKLOAD, "cells": int(mesh.ncells), "blocks": int(mesh.nblocks),
+           "value": cu / el, "unit": "cell-updates/s", "ms_per_window": 1e3 * el / windows, "windows": windows,
+           "sync_equivalent": se / el, "block_updates": int(bu), "levels": [int(v) for v in np.trim_zeros(hist, "b")],
+           "form": "learned (mode 4, network, batched, graph); stage kernel kind of its own with cross-level ghosts",
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "stage_tiled (kPkAmr)",
+                        "avg_launch_ms": launch_ms, "launches": int(launches),
+                        "algorithmic_bytes_per_launch": alg, "algorithmic_bytes_per_cell_update": bpc}}
+    if oracle_windows > 0:
+        cfg_s, mesh_s, U_s = W.debris_stream_amr(table, box=W.AMR_SUBDOMAIN)
+        cfg_s = dataclasses.replace(cfg_s, merge_frac=0.01)
+        t0 = time.perf_counter()
+        o, info, obu, ocu = oracle.run_lat(cfg_s, mesh_s, U_s, oracle_windows, table=table)
+        cpu_s = time.perf_counter() - t0
+        ctx = T.Context(cfg_s, mesh_s, U_s, table=table, inv_mode=4)
+        ctx.mlp_init(params, W.seed_ranges(table))
+        ctx.mlp_enable_seed(True)
+        lev_equal = True
+        for w in range(oracle_windows):
+            _, dt0, lev, L = ctx.reduce_dt()
+            lev_equal &= bool(np.array_equal(lev, info[w][0])) and L == info[w][1]
+            ctx.run_window(dt0 * 2 ** L, batched=True, graph=True)
+        g = ctx.get_state()
+        ctx.close()
+        strict = rel_err(cfg_s.nv, mesh_s, g, o)
+        spread = []
+        for kw in ({"fused": True}, {"fused": False, "long_math": True}):
+            with oracle.interp_rounding(**kw):
+                spread.append(rel_err(cfg_s.nv, mesh_s, oracle.run_lat(cfg_s, mesh_s, U_s, oracle_windows,
+                                                                       table=table)[0], o))
+        spread = np.max(spread, axis=0)
+        out["cpu_baseline"] = {"value": ocu / cpu_s, "unit": "cell-updates/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "host_cpu": host_cpu_model(),
+                               "sample": f"{oracle_windows} LAT windows of the sub-domain {W.AMR_SUBDOMAIN} "
+                                         f"({mesh_s.ncells} cells, {mesh_s.nblocks} blocks, "
+                                         f"{int(mesh_s.rlev.sum())} refined; {ocu} cell-updates), own CFL steps "
+                                         f"and levels, {cpu_s:.1f} s"}
+        out["accuracy"] = {"max_rel_err_vs_oracle_strict": float(np.max(strict)),
+                           "per_variable_strict": [float(v) for v in strict],
+                           "oracle_spread_strict": [float(v) for v in spread],
+                           "bar": "strict <= max(1e-11, 4 x the oracle's own spread) (the point-mass bar)",
+                           "levels_bit_exact": lev_equal,
+                           "case": f"sub-domain {W.AMR_SUBDOMAIN}, {oracle_windows} windows, learned form"}
     return out
 
 
@@ -605,7 +685,7 @@ def c2_section(T, W, table, params, forms, steps, warmup, repeats, tile, cpu_ste
     return out
 
 
-SECTIONS = "c5,c5_oracle,c2,lat,seed_eval,gravity,remap"
+SECTIONS = "c5,c5_oracle,c2,lat,seed_eval,gravity,remap,amr"
 
 
 def main():
@@ -629,6 +709,9 @@ def main():
     ap.add_argument("--gravity-cycles", type=int, default=10, help="timed multigrid V-cycles on the 256^3 Jeans wave")
     ap.add_argument("--gravity-steps", type=int, default=10, help="timed coupled steps on the 256^3 Jeans wave")
     ap.add_argument("--remap-reps", type=int, default=5, help="timed restart remaps")
+    ap.add_argument("--amr-windows", type=int, default=3, help="timed windows of the two-level run")
+    ap.add_argument("--amr-oracle-windows", type=int, default=1,
+                    help="windows of the oracle on the two-level sub-domain (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -673,6 +756,9 @@ def main():
     grav = gravity_section(T, W, args.gravity_cycles, args.gravity_steps) \
         if "gravity" in sections and args.gravity_cycles > 0 else None
     remap = remap_section(T, W, table, args.remap_reps) if "remap" in sections and args.remap_reps > 0 else None
+    amr = amr_section(T, W, table, params, args.amr_windows, 1, args.amr_oracle_windows) \
+        if "amr" in sections and args.amr_windows > 0 else None
+    note("two-level run done")
 
     head = c5.get("learned")
     plain = c5.get("plain")
@@ -722,6 +808,7 @@ def main():
         "lat": lat,
         "gravity": grav,
         "remap": remap,
+        "amr": amr,
     }
     print(json.dumps(out), flush=True)
 

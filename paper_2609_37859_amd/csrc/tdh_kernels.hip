@@ -463,6 +463,13 @@ __device__ __forceinline__ double phi_at(const StageArgs &a, const BlockInfo &B,
   return phi_point(a.p, a.m, B.ox + i, B.oy + j, B.oz + k, t, lev_of<PK>(B));
 }
 
+// phi_at for the kernels that serve every mesh (CFL reduction, flux
+// correction): the block's own refinement level, whatever the kind
+__device__ __forceinline__ double phi_at_block(const StageArgs &a, const BlockInfo &B, int i, int j, int k, double t) {
+  if (a.p.grav_kind == 1) return phi_at<0>(a, B, i, j, k, t);
+  return phi_point(a.p, a.m, B.ox + i, B.oy + j, B.oz + k, t, B.lev);
+}
+
 // ---------------------------------------------------------------------------
 // stage kernel
 // ---------------------------------------------------------------------------
@@ -1487,8 +1494,8 @@ __global__ void reflux_kernel(StageArgs a, int lc, int dir, int nmax) {
     if (a.p.grav_kind) {
       int lnb[3] = {loc[0], loc[1], loc[2]};
       lnb[dir] += side ? 1 : -1;
-      const double pn = phi_at(a, B, lnb[0], lnb[1], lnb[2], tc);
-      const double pi = phi_at(a, B, loc[0], loc[1], loc[2], tc);
+      const double pn = phi_at_block(a, B, lnb[0], lnb[1], lnb[2], tc);
+      const double pi = phi_at_block(a, B, loc[0], loc[1], loc[2], tc);
       q[B.off + IEN * n3 + cidx] += sg / (2.0 * vol) * dI[IDN] * (pn - pi);
     }
     for (int v = 0; v < nv; ++v) q[B.off + v * n3 + cidx] += sg * dI[v] / vol;
@@ -1546,7 +1553,7 @@ __global__ __launch_bounds__(kChunk) void cfl_items_kernel(StageArgs a, double t
           int ip[3] = {lc[0], lc[1], lc[2]}, im[3] = {lc[0], lc[1], lc[2]};
           ip[d] += 1;
           im[d] -= 1;
-          const double gd = (phi_at(a, B, ip[0], ip[1], ip[2], t) - phi_at(a, B, im[0], im[1], im[2], t)) /
+          const double gd = (phi_at_block(a, B, ip[0], ip[1], ip[2], t) - phi_at_block(a, B, im[0], im[1], im[2], t)) /
                             (2.0 * dx_lev(m, d, r));
           g2 += gd * gd;
         }

@@ -650,44 +650,29 @@ def mlp_init_params(seed: int) -> np.ndarray:
 # at y = 11 regions) and the two x regions about the centre.  Its timing sample
 # for the CPU oracle and its parity case.
 C5_SUBDOMAIN_512 = (5, 7, 4, 13, 0, 9)
+# region box of the two-level run that holds coarse and refined regions across
+# the stream's lower edge (14 level-0 + 80 level-1 blocks of 32^3, 3.1 M cells)
+AMR_SUBDOMAIN = (4, 7, 5, 9, 2, 4)
 
 
-def debris_stream_c5(table: EosTable, regions=(13, 17, 9), rn=32, n_split=301, dxr=0.25, vfr=1e8, dv=3e7,
-                     rho_pk=1e-3, T=1e4, stream_frac=0.3, sig_cells=8.0, box=None):
-    """Production-shaped run: 13 x 17 x 9 regions of 32^3 cells at dx = 0.25 Rsun;
-    the 301 regions nearest the stream axis and the black-hole path are split
-    into eight 16^3 blocks (1688 x 32^3 + 2408 x 16^3 = 4096 blocks, 65.2 M
-    cells).  A tidally stretched n = 1.5 stream (ellipsoid with semi-axes
-    0.3 L_x, 8 dx, 8 dx; rho = rho_pk theta^1.5, T = 1e4 K) with a linear
-    velocity spread v_x = dV (x - x_c) / (0.3 L_x) lies in a 1e-10 rho_pk
-    background at rest; a 1e3 Msun point mass starts 20 Rsun from the stream
-    centre and moves at -V_fr along x (uniform frame velocity V_fr); excision
-    radius 4 dx, softening 0.1 dx; outflow boundaries.
-
-    box = (x0, x1, y0, y1, z0, z1) keeps only those regions of the region grid
-    (the same cells, split decisions, coordinates and initial data as in the
-    whole run), with outflow boundaries at the box faces."""
+def _debris_setup(table: EosTable, regions, rn, n_split, dxr, vfr, dv, rho_pk, T, stream_frac, sig_cells):
+    """Region selection, run parameters and initial data of the debris-stream
+    runs: (dx, flagged regions [rz, ry, rx], cfg, fn(x, y, z) -> conserved)."""
     dx = dxr * R_SUN
     rx, ry, rz = regions
     L = np.array([rx, ry, rz]) * rn * dx
     c = 0.5 * L
     bh0 = np.array([c[0], c[1] + 20.0 * R_SUN, c[2]])
-    # split the regions whose centres are nearest the stream axis or the BH path
+    # flag the regions whose centres are nearest the stream axis or the BH path
     cz, cy, cx = np.meshgrid(np.arange(rz), np.arange(ry), np.arange(rx), indexing="ij")
     pc = np.stack([(cx + 0.5) * rn * dx, (cy + 0.5) * rn * dx, (cz + 0.5) * rn * dx], -1)
     d_axis = np.hypot(pc[..., 1] - c[1], pc[..., 2] - c[2]) + np.maximum(np.abs(pc[..., 0] - c[0]) - stream_frac * L[0], 0)
     d_bh = np.hypot(pc[..., 1] - bh0[1], pc[..., 2] - bh0[2])
     score = np.minimum(d_axis, d_bh) + 1e-6 * (cx + rx * (cy + ry * cz))  # deterministic ties
     order = np.argsort(score.ravel(), kind="stable")
-    split = np.zeros(rx * ry * rz, dtype=bool)
-    split[order[:n_split]] = True
-    split = split.reshape(rz, ry, rx)
-    if box is None:
-        mesh = mixed_mesh(regions, rn, split, dx, bc=(1, 1, 1))
-    else:
-        x0, x1, y0, y1, z0, z1 = box
-        mesh = mixed_mesh((x1 - x0, y1 - y0, z1 - z0), rn, split[z0:z1, y0:y1, x0:x1], dx,
-                          x0=(x0 * rn * dx, y0 * rn * dx, z0 * rn * dx), bc=(1, 1, 1))
+    flag = np.zeros(rx * ry * rz, dtype=bool)
+    flag[order[:n_split]] = True
+    flag = flag.reshape(rz, ry, rx)
     cfg = Config(eos_kind=1, dual=1, grav_kind=2, n_lat=3, cfl=0.3, eta1=1e-3, eta2=1e-4,
                  rho_floor=1e-10 * rho_pk * 0.5, p_floor=0.0, e_floor=table.e_floor, merge_frac=0.0,
                  gm_bh=G_NEWTON * 1e3 * M_SUN, r_soft=0.1 * dx, r_exc=4.0 * dx, bh_x0=tuple(bh0),
@@ -708,4 +693,46 @@ def debris_stream_c5(table: EosTable, regions=(13, 17, 9), rn=32, n_split=301, d
         vx = np.where(inside, dv * (x - c[0]) / a_s, 0.0)
         return [rho, rho * vx, 0 * x, 0 * x, U + 0.5 * rho * vx * vx, U]
 
+    return dx, flag, cfg, fn
+
+
+def debris_stream_c5(table: EosTable, regions=(13, 17, 9), rn=32, n_split=301, dxr=0.25, vfr=1e8, dv=3e7,
+                     rho_pk=1e-3, T=1e4, stream_frac=0.3, sig_cells=8.0, box=None):
+    """Production-shaped run: 13 x 17 x 9 regions of 32^3 cells at dx = 0.25 Rsun;
+    the 301 regions nearest the stream axis and the black-hole path are split
+    into eight 16^3 blocks (1688 x 32^3 + 2408 x 16^3 = 4096 blocks, 65.2 M
+    cells).  A tidally stretched n = 1.5 stream (ellipsoid with semi-axes
+    0.3 L_x, 8 dx, 8 dx; rho = rho_pk theta^1.5, T = 1e4 K) with a linear
+    velocity spread v_x = dV (x - x_c) / (0.3 L_x) lies in a 1e-10 rho_pk
+    background at rest; a 1e3 Msun point mass starts 20 Rsun from the stream
+    centre and moves at -V_fr along x (uniform frame velocity V_fr); excision
+    radius 4 dx, softening 0.1 dx; outflow boundaries.
+
+    box = (x0, x1, y0, y1, z0, z1) keeps only those regions of the region grid
+    (the same cells, split decisions, coordinates and initial data as in the
+    whole run), with outflow boundaries at the box faces."""
+    dx, split, cfg, fn = _debris_setup(table, regions, rn, n_split, dxr, vfr, dv, rho_pk, T, stream_frac, sig_cells)
+    if box is None:
+        mesh = mixed_mesh(regions, rn, split, dx, bc=(1, 1, 1))
+    else:
+        x0, x1, y0, y1, z0, z1 = box
+        mesh = mixed_mesh((x1 - x0, y1 - y0, z1 - z0), rn, split[z0:z1, y0:y1, x0:x1], dx,
+                          x0=(x0 * rn * dx, y0 * rn * dx, z0 * rn * dx), bc=(1, 1, 1))
+    return cfg, mesh, pack_state(mesh, cfg.nv, fn)
+
+
+def debris_stream_amr(table: EosTable, regions=(13, 17, 9), rn=32, n_refine=301, dxr=0.25, vfr=1e8, dv=3e7,
+                      rho_pk=1e-3, T=1e4, stream_frac=0.3, sig_cells=8.0, box=None):
+    """The production-shaped run on two refinement levels: the 301 regions of
+    debris_stream_c5 that it splits are refined instead, each into eight
+    level-1 blocks of 32^3 cells at dx / 2 (1688 level-0 + 2408 level-1 blocks,
+    all 32^3: 4096 blocks, 134.2 M cells); stream, point mass, frame,
+    excision radius (4 level-0 cells) and boundaries as there.  box as there."""
+    dx, ref, cfg, fn = _debris_setup(table, regions, rn, n_refine, dxr, vfr, dv, rho_pk, T, stream_frac, sig_cells)
+    if box is None:
+        mesh = amr_mesh(regions, rn, dx, ref, bc=(1, 1, 1))
+    else:
+        x0, x1, y0, y1, z0, z1 = box
+        mesh = amr_mesh((x1 - x0, y1 - y0, z1 - z0), rn, dx, ref[z0:z1, y0:y1, x0:x1],
+                        x0=(x0 * rn * dx, y0 * rn * dx, z0 * rn * dx), bc=(1, 1, 1))
     return cfg, mesh, pack_state(mesh, cfg.nv, fn)

@@ -153,7 +153,7 @@ def test_amr_point_mass_excision(tdh, orc, saha):
     bar as the other point-mass workloads, in the strict form: within four
     times the oracle's own spread under alternative roundings, at least 1e-11."""
     import oracle
-    cfg0, mesh, U = W.amr_blast(dual=1, hot=2.0)
+    cfg0, mesh, U = W.amr_blast(dual=1)
     h = mesh.dx[0]
     cx, cy, cz = (1 + 0.5) * 8 * h, (1 + 0.5) * 8 * h, (1 + 0.5) * 8 * h
     cfg = dataclasses.replace(cfg0, grav_kind=2, gm_bh=2e-3, r_soft=0.1 * h, r_exc=1.5 * h,
@@ -161,6 +161,9 @@ def test_amr_point_mass_excision(tdh, orc, saha):
     g, g_info, _ = _windows_gpu(tdh, cfg, mesh, U, 1)
     o, o_info, _, _ = orc.run_lat(cfg, mesh, U, 1)
     _check_levels(g_info, o_info)
+    lev, L = o_info[0][0], o_info[0][1]
+    fine = mesh.rlev == 1
+    assert L == 2 and len(set(lev[fine])) > 1  # fine blocks on several factors: fine-fine corrections too
     alts = []
     for fused, long_math in ((True, False), (False, True)):
         with oracle.interp_rounding(fused=fused, long_math=long_math):
@@ -187,3 +190,53 @@ def test_amr_mesh_rejections(tdh):
     with pytest.raises(tdh.TdhError, match="single-level"):
         ctx.frame_acceleration(1e-3)
     ctx.close()
+
+
+def test_amr_production_shaped_subdomain(tdh, orc, saha, seed_params_amr):
+    """The production-shaped two-level run (debris_stream_amr) on its region
+    sub-domain: 14 level-0 and 80 level-1 blocks of 32^3 across the stream's
+    lower edge, Saha table, dual energy, the point mass, LAT N_LAT = 3, in the
+    bench's learned form (mode 4 with the GPU-trained network, batched,
+    graph) over two windows.  Levels bit for bit; the point-mass bar in the
+    strict form (within four times the oracle's own spread, at least 1e-11)."""
+    import oracle
+    cfg, mesh, U = W.debris_stream_amr(saha, box=W.AMR_SUBDOMAIN)
+    cfg = dataclasses.replace(cfg, merge_frac=0.01)
+    assert 0 < int(mesh.rlev.sum()) < mesh.nblocks
+    ctx = tdh.Context(cfg, mesh, U, table=saha, inv_mode=4)
+    ctx.mlp_init(seed_params_amr, W.seed_ranges(saha))
+    ctx.mlp_enable_seed(True)
+    info = []
+    for _ in range(2):
+        dtb, dt0, lev, L = ctx.reduce_dt()
+        info.append((dtb, dt0, lev, L))
+        ctx.run_window(dt0 * 2 ** L, batched=True, graph=True)
+    g = ctx.get_state()
+    ctx.close()
+    o, o_info, _, _ = orc.run_lat(cfg, mesh, U, 2, table=saha)
+    _check_levels(info, o_info)
+    assert max(L for _, _, _, L in info) >= 1
+    alts = []
+    for kw in ({"fused": True}, {"fused": False, "long_math": True}):
+        with oracle.interp_rounding(**kw):
+            alts.append(orc.run_lat(cfg, mesh, U, 2, table=saha)[0])
+    strict = rel_err(cfg.nv, mesh, g, o)
+    spread = np.max([rel_err(cfg.nv, mesh, a, o) for a in alts], axis=0)
+    print("AMR production-shaped strict", strict, "oracle spread", spread)
+    assert np.all(strict <= np.maximum(TOL, 4.0 * spread))
+
+
+@pytest.fixture(scope="module")
+def seed_params_amr(tdh, saha):
+    """The learned seed trained on the GPU by the library's kernels (600 Adam steps)."""
+    import torch
+    cfg = W.Config(eos_kind=1, e_floor=saha.e_floor)
+    mesh = W.uniform_mesh(1, 1, 1, 8, 1.0)
+    ctx = tdh.Context(cfg, mesh, W.uniform_state(mesh, W.Config()), table=saha)
+    x = torch.from_numpy(W.seed_training_samples(saha, 1 << 20, 1)).cuda()
+    lT, _, _ = ctx.eos_invert(x[:, 0].contiguous(), x[:, 1].contiguous(), mode=0)
+    ctx.mlp_init(W.mlp_init_params(2), W.seed_ranges(saha))
+    ctx.mlp_train(x, lT, steps=600, batch=4096, lr=1e-3, seed=1)
+    p = ctx.mlp_params()
+    ctx.close()
+    return p
