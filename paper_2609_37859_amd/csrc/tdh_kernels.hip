@@ -54,8 +54,9 @@ __device__ __forceinline__ int block_of(const MeshDev &m, int r, int gx, int gy,
 // the other paths and the registers they would hold.  multi = 0 marks a window
 // without levels: every neighbour is on the reader's schedule, so ghosts need
 // no time interpolation and faces no impulses.
-__host__ __device__ constexpr int physics_code(int eos, int dual, int grav, int riemann, int dense, int multi) {
-  return 1 + eos + 2 * dual + 4 * grav + 16 * riemann + 32 * dense + 64 * multi;
+__host__ __device__ constexpr int physics_code(int eos, int dual, int grav, int riemann, int dense, int multi,
+                                               int amr = 0) {
+  return 1 + eos + 2 * dual + 4 * grav + 16 * riemann + 32 * dense + 64 * multi + 128 * amr;
 }
 constexpr int kPkAmr = -1;
 template <int PK> __device__ __forceinline__ int k_eos(const Phys &p) { return PK > 0 ? (PK - 1) & 1 : p.eos_kind; }
@@ -64,8 +65,9 @@ template <int PK> __device__ __forceinline__ int k_grav(const Phys &p) { return 
 template <int PK> __device__ __forceinline__ int k_riemann(const Phys &p) { return PK > 0 ? ((PK - 1) >> 4) & 1 : p.riemann; }
 template <int PK> __device__ __forceinline__ int k_dense(const Phys &p) { return PK > 0 ? ((PK - 1) >> 5) & 1 : p.ghost_dense; }
 template <int PK> __host__ __device__ constexpr bool k_multi() { return PK > 0 ? ((PK - 1) >> 6) & 1 : true; }
-// ghosts across refinement levels (kPkAmr only; every other kind assumes one level)
-template <int PK> __host__ __device__ constexpr bool k_amr() { return PK == kPkAmr; }
+// ghosts across refinement levels (kPkAmr and the compiled kinds with the amr
+// bit; every other kind assumes one level)
+template <int PK> __host__ __device__ constexpr bool k_amr() { return PK == kPkAmr || (PK > 0 && (((PK - 1) >> 7) & 1)); }
 template <int PK> __device__ __forceinline__ int lev_of(const BlockInfo &B) { return k_amr<PK>() ? B.lev : 0; }
 // cell width and its inverse along d on refinement level r (exact: powers of two)
 __device__ __forceinline__ double dx_lev(const MeshDev &m, int d, int r) { return r ? 0.5 * m.dx[d] : m.dx[d]; }
@@ -74,6 +76,21 @@ __device__ __forceinline__ double inv_dx_lev(const MeshDev &m, int d, int r) { r
 // flag in LDS: every cell's value serves its own and its neighbours' terms
 // (a stored potential is one cached load, not worth the LDS)
 template <int PK> __host__ __device__ constexpr bool k_gcache() { return PK > 0 && (((PK - 1) >> 2) & 3) == 2; }
+
+// The stage kernel's arguments read again from the kernel-argument segment
+// (scalar loads) at the start of each work item: the pointer passes through an
+// empty volatile asm, so loads through it can neither be hoisted above that
+// point nor merged with earlier ones.  It bounds the live ranges of the many
+// uniform fields, which the scalar register file cannot hold for the whole
+// kernel (the compiler would park them in vector-register lanes and restore
+// them a lane at a time: on the point-mass kind 1176 such restores in the
+// code, 55 with the re-read).  Valid in kernels whose one argument is the
+// StageArgs, passed by value, first.
+__device__ __forceinline__ const StageArgs &kargs() {
+  auto p = (const __attribute__((address_space(4))) StageArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(p));
+  return *(const StageArgs *)p;
+}
 
 // Where a reader with factor fb finds block nb's conserved state at its stage time.
 struct Src {
@@ -772,10 +789,16 @@ __device__ __forceinline__ void face_flux(const StageArgs &a, const BlockInfo &B
     vf = F[0] / ru;
   }
   if (k_grav<PK>(p) == 2 && p.r_exc > 0.0) {
-    int gl[3] = {B.ox + fr[0], B.oy + fr[1], B.oz + fr[2]};
-    const bool eR = excr >= 0 ? excr != 0 : excised<PK>(p, m, gl[0], gl[1], gl[2], t, lev_of<PK>(B));
-    gl[D] -= 1;
-    const bool eL = excl >= 0 ? excl != 0 : excised<PK>(p, m, gl[0], gl[1], gl[2], t, lev_of<PK>(B));
+    bool eR, eL;
+    if constexpr (k_gcache<PK>()) {  // the flags staged in LDS
+      eR = excr != 0;
+      eL = excl != 0;
+    } else {
+      int gl[3] = {B.ox + fr[0], B.oy + fr[1], B.oz + fr[2]};
+      eR = excr >= 0 ? excr != 0 : excised<PK>(p, m, gl[0], gl[1], gl[2], t, lev_of<PK>(B));
+      gl[D] -= 1;
+      eL = excl >= 0 ? excl != 0 : excised<PK>(p, m, gl[0], gl[1], gl[2], t, lev_of<PK>(B));
+    }
     if (eL != eR) {
       const bool into = eR ? (F[0] >= 0.0) : (F[0] <= 0.0);
       if (!into) {
@@ -1098,7 +1121,7 @@ __device__ __forceinline__ void tile_axis(const StageArgs &a, const TileCtx &T, 
 // NT: threads per workgroup, 256 (one per cell) or 320 (every axis's faces in
 // one round; the last wave only stages and computes faces).
 template <int TX, int TY, int TZ, int NV, int OCC, bool NET, int NT, int PK>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void stage_tiled(StageArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void stage_tiled(StageArgs a_in) {
   using G = TileGeom<TX, TY, TZ>;
   static_assert(G::TV == kChunk, "one cell per thread");
   static_assert(NT == kChunk || NT >= G::NF, "a wide workgroup covers every axis's faces in one round");
@@ -1111,11 +1134,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) 
   constexpr int GC = k_gcache<PK>() ? SW : 1;
   __shared__ double sPhi[GC];          // potential of the staged cells (compiled gravity kinds)
   __shared__ unsigned char sExc[GC];   // their excision flags
-  const Phys &p = a.p;
-  const MeshDev &m = a.m;
-  const double dt0 = a.win[1];
-  const double tk = a.win[0] + a.k * dt0;
-  for (LevelItems it(a, a.item_start); it.valid(); it.next()) {
+  const double dt0 = a_in.win[1];
+  const double tk = a_in.win[0] + a_in.k * dt0;
+  for (LevelItems it(a_in, a_in.item_start); it.valid(); it.next()) {
+    // re-read per item on the kinds whose uniform values overflow the scalar
+    // registers (the table EOS and the run-time kinds; measured: the
+    // point-mass kind's stage 2.21 -> 2.16 ms, the ideal-gas kind 2.7 % slower)
+    const StageArgs &a = (PK <= 0 || k_eos<PK>(a_in.p) == 1) ? kargs() : a_in;
+    const Phys &p = a.p;
+    const MeshDev &m = a.m;
     const int item = it.item;
     const int tid = item_tid();
     const int2 bt = a.item_bt[item];
@@ -1194,18 +1221,19 @@ __device__ __forceinline__ long long face_index(int n, int i, int j, int k) {
 }
 
 template <int NV, int D, int OCC>
-__global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void face_kernel(StageArgs a) {
+__global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void face_kernel(StageArgs a_in) {
   constexpr int PN = 1 + D, P1 = 1 + (D + 1) % 3, P2 = 1 + (D + 2) % 3;
-  const Phys &p = a.p;
-  const MeshDev &m = a.m;
-  const int a0 = a.cnt_ge[a.Lhi + 1], a1 = a.cnt_ge[a.Llo];
+      const int a0 = a_in.cnt_ge[a_in.Lhi + 1], a1 = a_in.cnt_ge[a_in.Llo];
   if (a1 <= a0) return;
-  const int i0 = a.fitem_start[a0], i1 = a.fitem_start[a1];
-  const double dt0 = a.win[1];
-  const double tk = a.win[0] + a.k * dt0;
-  const int Nd = D == 0 ? m.nx : (D == 1 ? m.ny : m.nz);
+  const int i0 = a_in.fitem_start[a0], i1 = a_in.fitem_start[a1];
+  const double dt0 = a_in.win[1];
+  const double tk = a_in.win[0] + a_in.k * dt0;
+  const int Nd = D == 0 ? a_in.m.nx : (D == 1 ? a_in.m.ny : a_in.m.nz);
   const ItemRange R = xcd_items(i0, i1);
   for (int item = R.first; item < R.end; item += R.step) {
+    const StageArgs &a = kargs();  // re-read per item (as in stage_tiled)
+    const Phys &p = a.p;
+    const MeshDev &m = a.m;
     const int2 bt = a.fitem_bt[item];
     const int b = uni(bt.x);
     const BlockInfo B = uni(m.blocks[b]);
@@ -1278,16 +1306,17 @@ __device__ __forceinline__ double load_E(const StageArgs &a, int b, const BlockI
 }
 
 template <int NV, bool NET, int OCC>
-__global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void update_kernel(StageArgs a) {
-  const Phys &p = a.p;
-  const MeshDev &m = a.m;
-  const int a0 = a.cnt_ge[a.Lhi + 1], a1 = a.cnt_ge[a.Llo];
+__global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void update_kernel(StageArgs a_in) {
+      const int a0 = a_in.cnt_ge[a_in.Lhi + 1], a1 = a_in.cnt_ge[a_in.Llo];
   if (a1 <= a0) return;
-  const int i0 = a.item_start[a0], i1 = a.item_start[a1];
-  const double dt0 = a.win[1];
-  const double tk = a.win[0] + a.k * dt0;
+  const int i0 = a_in.item_start[a0], i1 = a_in.item_start[a1];
+  const double dt0 = a_in.win[1];
+  const double tk = a_in.win[0] + a_in.k * dt0;
   const ItemRange R = xcd_items(i0, i1);
   for (int item = R.first; item < R.end; item += R.step) {
+    const StageArgs &a = kargs();  // re-read per item (as in stage_tiled)
+    const Phys &p = a.p;
+    const MeshDev &m = a.m;
     const int2 bt = a.item_bt[item];
     const int b = uni(bt.x);
     const BlockInfo B = uni(m.blocks[b]);
@@ -1347,16 +1376,15 @@ __global__ __launch_bounds__(kChunk) __attribute__((amdgpu_waves_per_eu(OCC, OCC
 // its cells needs it.  Blocks hold a multiple of 256 cells, so every wave is
 // full when it calls the network.
 template <int NV>
-__global__ __launch_bounds__(kChunk) void seed_kernel(StageArgs a) {
-  if (a.cnt_ge[a.Llo] <= a.cnt_ge[a.Lhi + 1]) return;
-  const Phys &p = a.p;
+__global__ __launch_bounds__(kChunk) void seed_kernel(StageArgs a_in) {
+  if (a_in.cnt_ge[a_in.Llo] <= a_in.cnt_ge[a_in.Lhi + 1]) return;
   const int nv = NV;
-  const bool net = (p.inv_mode == 1 || p.inv_mode == 4) && a.s.enabled;
+  const bool net = (a_in.p.inv_mode == 1 || a_in.p.inv_mode == 4) && a_in.s.enabled;
   // the network's weights, staged once per workgroup for all its items
   __shared__ __align__(16) short s_w2[64 * 64];
   __shared__ __align__(16) short s_w13[128 + 64];
   __shared__ __align__(16) float s_b[128 + 4];
-  Seed sd = a.s;
+  Seed sd = a_in.s;
   sd.w.w2b = s_w2;
   sd.w.w1b = s_w13;
   sd.w.w3b = s_w13 + 128;
@@ -1365,16 +1393,18 @@ __global__ __launch_bounds__(kChunk) void seed_kernel(StageArgs a) {
   sd.w.b3 = s_b + 128;
   if (net) {
     const int t = threadIdx.x;
-    const uint4 *w2 = (const uint4 *)a.s.w.w2b;
+    const uint4 *w2 = (const uint4 *)a_in.s.w.w2b;
     for (int k = t; k < 512; k += kChunk) ((uint4 *)s_w2)[k] = w2[k];
-    if (t < 16) ((uint4 *)s_w13)[t] = ((const uint4 *)a.s.w.w1b)[t];
-    else if (t < 24) ((uint4 *)s_w13)[t] = ((const uint4 *)a.s.w.w3b)[t - 16];
-    else if (t < 40) ((uint4 *)s_b)[t - 24] = ((const uint4 *)a.s.w.b1)[t - 24];
-    else if (t < 56) ((uint4 *)s_b)[t - 24] = ((const uint4 *)a.s.w.b2)[t - 40];
-    else if (t == 56) s_b[128] = a.s.w.b3[0];
+    if (t < 16) ((uint4 *)s_w13)[t] = ((const uint4 *)a_in.s.w.w1b)[t];
+    else if (t < 24) ((uint4 *)s_w13)[t] = ((const uint4 *)a_in.s.w.w3b)[t - 16];
+    else if (t < 40) ((uint4 *)s_b)[t - 24] = ((const uint4 *)a_in.s.w.b1)[t - 24];
+    else if (t < 56) ((uint4 *)s_b)[t - 24] = ((const uint4 *)a_in.s.w.b2)[t - 40];
+    else if (t == 56) s_b[128] = a_in.s.w.b3[0];
     __syncthreads();
   }
-  for (LevelItems li(a, a.item_start); li.valid(); li.next()) {
+  for (LevelItems li(a_in, a_in.item_start); li.valid(); li.next()) {
+    const StageArgs &a = kargs();  // re-read per item (as in stage_tiled)
+    const Phys &p = a.p;
     const int2 bt = a.item_bt[li.item];
     const int b = uni(bt.x);
     const BlockInfo B = uni(a.m.blocks[b]);
@@ -1510,14 +1540,15 @@ __global__ void reflux_kernel(StageArgs a, int lc, int dir, int nmax) {
 // its block's current segment: the seeds of the window's first stage, so no
 // seed pass runs before it.
 template <int NV>
-__global__ __launch_bounds__(kChunk) void cfl_items_kernel(StageArgs a, double t, const int *item_block,
+__global__ __launch_bounds__(kChunk) void cfl_items_kernel(StageArgs a_in, double t, const int *item_block,
                                                            const int *block_item_start, int nitems, double *part) {
   __shared__ double red[kChunk / 64];
-  const MeshDev &m = a.m;
-  const Phys &p = a.p;
   const int nv = NV;
-  const bool rec = p.eos_kind == 1 && (p.inv_mode == 2 || p.inv_mode == 4) && a.jc != nullptr;
   for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const StageArgs &a = kargs();  // re-read per item (as in stage_tiled; the StageArgs is the first argument)
+    const MeshDev &m = a.m;
+    const Phys &p = a.p;
+    const bool rec = p.eos_kind == 1 && (p.inv_mode == 2 || p.inv_mode == 4) && a.jc != nullptr;
     const int b = uni(item_block[item]);
     const BlockInfo B = uni(m.blocks[b]);
     const int n = B.n;
@@ -1702,8 +1733,19 @@ hipError_t launch_stage(const StageArgs &a, int tile, int grid, hipStream_t s) {
   // the network variant when it starts the searches (table EOS, mode 1, network on)
   const bool net = a.p.eos_kind == 1 && a.p.inv_mode == 1 && a.s.enabled;
   if (a.m.amr) {
-    // Meshes with a refined block: one variant (8 x 8 x 4 cells, two waves per
-    // SIMD: the cross-level ghost path needs the registers), whatever the tile.
+    // Meshes with a refined block: one variant (8 x 8 x 4 cells), whatever the
+    // tile; the production physics (table EOS, dual energy, point mass, levels,
+    // linear ghosts) has a kind of its own, the rest read the switches (two
+    // waves per SIMD: the cross-level ghost path needs the registers).
+    constexpr int kAmrProd = physics_code(1, 1, 2, 0, 0, 1, 1);  // 3 waves per SIMD, as the single-level kind
+    const int acode = a.m.nv != 5 + (a.p.dual ? 1 : 0)
+                          ? 0
+                          : physics_code(a.p.eos_kind, a.p.dual ? 1 : 0, a.p.grav_kind, a.p.riemann, a.p.ghost_dense,
+                                         1, 1);
+    if (!net && acode == kAmrProd) {
+      hipLaunchKernelGGL((stage_tiled<8, 8, 4, 6, 3, false, 256, kAmrProd>), dim3(grid), dim3(256), 0, s, a);
+      return hipGetLastError();
+    }
     if (a.m.nv == 6) {
       if (net) hipLaunchKernelGGL((stage_tiled<8, 8, 4, 6, 2, true, 256, kPkAmr>), dim3(grid), dim3(256), 0, s, a);
       else hipLaunchKernelGGL((stage_tiled<8, 8, 4, 6, 2, false, 256, kPkAmr>), dim3(grid), dim3(256), 0, s, a);
