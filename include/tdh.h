@@ -26,10 +26,16 @@
  *     owns them and keeps them alive while the context uses them.
  *   - All device work is enqueued on the stream given to tdh_init; calls that
  *     return host data synchronise that stream first.
- *   - Only tdh_init, tdh_init_blocks, tdh_set_eos_table and tdh_mlp_init
- *     allocate device memory (small metadata only: block tables, lattice
- *     map, EOS table, network weights).  The state lives in the caller's
- *     arena.  Stepping calls allocate nothing.
+ *   - The library allocates no device memory.  Everything a context uses on
+ *     the device lives in buffers the caller owns: the arena of
+ *     tdh_init_blocks (state, impulses, potential, block and work-item
+ *     tables, reduction partials, the learned seed's weights and moments),
+ *     the EOS table buffer of tdh_set_eos_table and the workspace of
+ *     tdh_gravity_solve; tdh_reduce_dt_static uses a static per-GPU array
+ *     of the library.  Captured windows and V-cycles are HIP graph objects,
+ *     which the HIP runtime instantiates (tdh_run_window with use_graph,
+ *     tdh_gravity_solve); every other call enqueues plain kernel launches
+ *     and copies.
  *
  * State layout (host and device): blocks one after another in the order of
  * the block list; block b holds nv arrays of n_b^3 doubles, x fastest, with
@@ -130,9 +136,11 @@ typedef struct {
   int64_t kernel_launches;
 } tdh_stats;
 
-/* Device bytes the state arena must hold for this configuration and mesh
- * (two state copies, the stage-1 state, the potential, face impulses).
- * Returns 0 for an invalid mesh. */
+/* Device bytes the arena must hold for this configuration and mesh (two
+ * state copies, the stage-1 state, the potential, face impulses, seed cells,
+ * split-form fluxes, block and work-item tables, reduction partials, and with
+ * the table EOS the learned seed's buffers, about 22 MB).  Returns 0 for an
+ * invalid mesh. */
 size_t tdh_arena_bytes(const tdh_config *cfg, const tdh_mesh *mesh);
 
 /* Create a context on the current HIP device; hip_stream is a hipStream_t
@@ -147,12 +155,21 @@ tdh_status tdh_init(const tdh_config *cfg, void *hip_stream, tdh_ctx **out);
 tdh_status tdh_init_blocks(tdh_ctx *ctx, const tdh_mesh *mesh, void *dev_arena, size_t arena_bytes,
                            const double *host_state, const double *host_phi);
 
+/* Device bytes the packed EOS table of nrho x nT nodes needs (0 outside
+ * 2 <= nrho, nT <= 4096). */
+size_t tdh_table_bytes(int nrho, int nT);
+
 /* Tabulated EOS (Sec. Tabulated EOS construction): node (i, j) at
  * log10 rho = lr0 + i*dlr, log10 T = lT0 + j*dlT; host arrays [nrho][nT],
  * T contiguous, of log10 P, log10 e (specific internal energy, strictly
- * increasing in T on every row) and log10 c_s^2.  2 <= nrho, nT <= 4096. */
+ * increasing in T on every row) and log10 c_s^2.  2 <= nrho, nT <= 4096.
+ * dev_table: caller-owned device buffer of at least tdh_table_bytes(nrho, nT)
+ * bytes, 256-byte aligned, that the context reads until the next call of this
+ * function or tdh_destroy (TDH_ENOMEM if smaller, TDH_EINVAL if null or
+ * misaligned). */
 tdh_status tdh_set_eos_table(tdh_ctx *ctx, int nrho, int nT, double lr0, double dlr, double lT0, double dlT,
-                             const double *host_logP, const double *host_loge, const double *host_logcs2);
+                             const double *host_logP, const double *host_loge, const double *host_logcs2,
+                             void *dev_table, size_t table_bytes);
 
 /* Per-block CFL step dt_b = cfl * min over cells of min over axes of
  * dx/(|v|+c_s) and, with gravity, sqrt(dx_min/|g|) (g the centred potential

@@ -38,7 +38,7 @@ struct tdh_ctx {
   long long total = 0, ptotal = 0, itotal = 0;
   long long ncells = 0;
 
-  // device memory: state in the caller's arena, metadata owned here
+  // device memory: all in the caller's arena and buffers (the library allocates none)
   double *Qa = nullptr, *Qb = nullptr, *Qs = nullptr, *imp = nullptr, *bf1 = nullptr, *phi = nullptr;
   int *jc = nullptr;  // seed table cells: a segment of ncells per state buffer (Qa, Qb, Qs)
   double *flx = nullptr;  // face fluxes of the split stage form (3 axes)
@@ -52,8 +52,7 @@ struct tdh_ctx {
   int2 *d_item_bt = nullptr, *d_fitem_bt = nullptr;  // per work item: block, item within the block
   double *d_cfl_part = nullptr, *d_dtb = nullptr, *d_win = nullptr;
   int cfl_nitems = 0;
-  double *h_dtb = nullptr;  // pinned host copy of the per-block steps
-  std::vector<void *> owned;
+  std::vector<double> h_dtb;  // host copy of the per-block steps
 
   // EOS table
   bool have_table = false;
@@ -140,11 +139,16 @@ static tdh_status hip_fail(tdh_ctx *c, hipError_t e, const char *what) {
 
 static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+static constexpr int kMlpMaxBatch = 65536;
+static constexpr int kMlpMaxSteps = 1 << 20;
+
 // ---------------------------------------------------------------------------
 // mesh validation and layout
 // ---------------------------------------------------------------------------
 struct Layout {
   long long total = 0, ptotal = 0, itotal = 0, ncells = 0, ftotal = 0;
+  long long nitems = 0;   // 256-cell work items over all blocks
+  long long lcells = 0;   // lattice cells
   std::vector<long long> off, poff, ioff, foff;
   int lat = 0, nmax = 0;
 };
@@ -183,30 +187,87 @@ static const char *mesh_layout(const tdh_config *cfg, const tdh_mesh *m, Layout 
     L.foff[b] = L.ftotal;
     L.ftotal += (n + 1) * n * n;
     L.ncells += n * n * n;
+    L.nitems += (n * n * n + kChunk - 1) / kChunk;
   }
   L.lat = lat;
   L.nmax = nmax;
+  L.lcells = (long long)(m->nx / lat) * (m->ny / lat) * (m->nz / lat);
   return nullptr;
 }
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 static int nv_of(const tdh_config *cfg) { return cfg->dual ? 6 : 5; }
 
-static size_t arena_need(const tdh_config *cfg, const Layout &L) {
-  size_t s = 0;
-  s += 3 * align256(L.total * sizeof(double));   // Qa, Qb, Qs
-  s += 2 * align256(L.itotal * sizeof(double));  // impulses, stage-1 boundary fluxes
-  if (cfg->grav_kind == 1) s += align256(L.ptotal * sizeof(double));
-  if (cfg->eos_kind == 1) s += align256(3 * L.ncells * sizeof(int));  // seed cells of Qa, Qb, Qs
-  s += align256(3 * (nv_of(cfg) + 1) * L.ftotal * sizeof(double));  // face fluxes of the split stage form
-  return s;
+// The arena's regions in order: every device byte a context uses lives in
+// the caller's arena (state, impulses, potential, seeds, split-form fluxes,
+// the block and work-item tables, the reduction's partials, and with the
+// table EOS the learned seed's weights, moments, gradients and partial
+// sums), except the EOS table (tdh_set_eos_table) and the self-gravity
+// workspace (tdh_gravity_solve), which are the caller's buffers too.  With
+// c == nullptr only the total size.
+static size_t arena_regions(const tdh_config *cfg, const Layout &L, int nb, char *base, tdh_ctx *c) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char * {
+    char *r = base ? base + off : nullptr;
+    off += align256(bytes);
+    return r;
+  };
+  const int nv = nv_of(cfg);
+  const long long fitems = (L.ftotal + (long long)nb * (kChunk - 1)) / kChunk;
+  char *Qa = take(L.total * sizeof(double)), *Qb = take(L.total * sizeof(double));
+  char *Qs = take(L.total * sizeof(double));
+  char *imp = take(L.itotal * sizeof(double)), *bf1 = take(L.itotal * sizeof(double));
+  char *phi = cfg->grav_kind == 1 ? take(L.ptotal * sizeof(double)) : nullptr;
+  char *jc = cfg->eos_kind == 1 ? take(3 * L.ncells * sizeof(int)) : nullptr;  // seed cells of Qa, Qb, Qs
+  char *flx = take(3 * (nv + 1) * L.ftotal * sizeof(double));
+  char *blocks = take(nb * sizeof(BlockInfo)), *lmap = take(L.lcells * sizeof(int));
+  char *fac = take(nb * sizeof(int)), *par = take(nb * sizeof(int)), *order = take(nb * sizeof(int));
+  char *item_start = take((nb + 1) * sizeof(int)), *fitem_start = take((nb + 1) * sizeof(int));
+  char *item_bt = take(L.nitems * sizeof(int2)), *fitem_bt = take(fitems * sizeof(int2));
+  char *cnt_ge = take(kCntSlots * sizeof(int)), *dtb = take(nb * sizeof(double)), *win = take(2 * sizeof(double));
+  char *cfl_block_start = take((nb + 1) * sizeof(int)), *cfl_item_block = take(L.nitems * sizeof(int));
+  char *cfl_part = take(L.nitems * sizeof(double));
+  char *facc = take((4 * frame_acceleration_parts() + 4) * sizeof(double));
+  char *mw = nullptr, *mm = nullptr, *mv = nullptr, *mgrad = nullptr, *mpart = nullptr, *mloss_part = nullptr;
+  char *mloss = nullptr, *mb = nullptr, *mwb = nullptr;
+  if (cfg->eos_kind == 1) {  // the learned seed of the table inversion
+    mw = take(kMlpParams * sizeof(float));
+    mm = take(kMlpParams * sizeof(float));
+    mv = take(kMlpParams * sizeof(float));
+    mgrad = take(kMlpParams * sizeof(float));
+    mpart = take((size_t)(kMlpMaxBatch / 64) * kMlpParams * sizeof(float));
+    mloss_part = take((kMlpMaxBatch / 64) * sizeof(float));
+    mloss = take(kMlpMaxSteps * sizeof(float));
+    mb = take((64 + 64 + 1) * sizeof(float));
+    mwb = take((128 + 4096 + 4096 + 64) * sizeof(short));
+  }
+  if (c) {
+    c->Qa = (double *)Qa; c->Qb = (double *)Qb; c->Qs = (double *)Qs;
+    c->imp = (double *)imp; c->bf1 = (double *)bf1; c->phi = (double *)phi; c->jc = (int *)jc;
+    c->flx = (double *)flx;
+    c->d_blocks = (BlockInfo *)blocks; c->d_lmap = (int *)lmap;
+    c->d_fac = (int *)fac; c->d_par = (int *)par; c->d_order = (int *)order;
+    c->d_item_start = (int *)item_start; c->d_fitem_start = (int *)fitem_start;
+    c->d_item_bt = (int2 *)item_bt; c->d_fitem_bt = (int2 *)fitem_bt;
+    c->d_cnt_ge = (int *)cnt_ge; c->d_dtb = (double *)dtb; c->d_win = (double *)win;
+    c->d_cfl_block_start = (int *)cfl_block_start; c->d_cfl_item_block = (int *)cfl_item_block;
+    c->d_cfl_part = (double *)cfl_part; c->d_facc = (double *)facc;
+    c->d_mw = (float *)mw; c->d_mm = (float *)mm; c->d_mv = (float *)mv; c->d_mgrad = (float *)mgrad;
+    c->d_mpart = (float *)mpart; c->d_mloss_part = (float *)mloss_part; c->d_mloss = (float *)mloss;
+    c->d_mb = (float *)mb; c->d_mwb = (short *)mwb;
+  }
+  return off;
+}
+
+static size_t arena_need(const tdh_config *cfg, const Layout &L, int nb) {
+  return arena_regions(cfg, L, nb, nullptr, nullptr);
 }
 
 extern "C" size_t tdh_arena_bytes(const tdh_config *cfg, const tdh_mesh *mesh) {
   if (!cfg) return 0;
   Layout L;
   if (mesh_layout(cfg, mesh, L)) return 0;
-  return arena_need(cfg, L);
+  return arena_need(cfg, L, mesh->nblocks);
 }
 
 // ---------------------------------------------------------------------------
@@ -243,10 +304,8 @@ extern "C" tdh_status tdh_init(const tdh_config *cfg, void *hip_stream, tdh_ctx 
 extern "C" void tdh_destroy(tdh_ctx *c) {
   if (!c) return;
   for (hipEvent_t e : c->ev) hipEventDestroy(e);
-  if (c->h_dtb) hipHostFree(c->h_dtb);
   for (auto &g : c->graphs) hipGraphExecDestroy(g.second);
   for (auto &g : c->mg_graphs) hipGraphExecDestroy(g.second);
-  for (void *p : c->owned) hipFree(p);
   delete c;
 }
 
@@ -258,16 +317,6 @@ extern "C" const char *tdh_last_error(const tdh_ctx *c) { return c ? c->err.c_st
     if ((c)->poisoned) return fail((c), TDH_ESTATE, "context poisoned by a HIP error"); \
   } while (0)
 
-template <class T>
-static tdh_status dev_alloc(tdh_ctx *c, T **p, size_t count) {
-  void *q = nullptr;
-  if (count == 0) count = 1;
-  hipError_t e = hipMalloc(&q, count * sizeof(T));
-  if (e != hipSuccess) return fail(c, TDH_ENOMEM, "hipMalloc of %zu bytes failed", count * sizeof(T));
-  c->owned.push_back(q);
-  *p = (T *)q;
-  return TDH_OK;
-}
 
 static Phys make_phys(const tdh_config &g) {
   Phys p{};
@@ -437,8 +486,8 @@ extern "C" tdh_status tdh_init_blocks(tdh_ctx *c, const tdh_mesh *m, void *dev_a
   Layout L;
   if (const char *why = mesh_layout(&c->cfg, m, L)) return fail(c, TDH_EINVAL, "tdh_init_blocks: %s", why);
   if (!dev_arena || ((uintptr_t)dev_arena & 255)) return fail(c, TDH_EINVAL, "arena must be non-null, 256-byte aligned");
-  if (arena_bytes < arena_need(&c->cfg, L)) return fail(c, TDH_ENOMEM, "arena holds %zu bytes, %zu needed", arena_bytes,
-                                                        arena_need(&c->cfg, L));
+  if (arena_bytes < arena_need(&c->cfg, L, m->nblocks))
+    return fail(c, TDH_ENOMEM, "arena holds %zu bytes, %zu needed", arena_bytes, arena_need(&c->cfg, L, m->nblocks));
   if (!host_state) return fail(c, TDH_EINVAL, "host_state is null");
   if (c->cfg.grav_kind == 1 && !host_phi) return fail(c, TDH_EINVAL, "grav_kind 1 needs host_phi");
   c->nx = m->nx; c->ny = m->ny; c->nz = m->nz;
@@ -477,31 +526,9 @@ extern "C" tdh_status tdh_init_blocks(tdh_ctx *c, const tdh_mesh *m, void *dev_a
     B.off = L.off[b]; B.poff = L.poff[b]; B.ioff = L.ioff[b]; B.foff = L.foff[b];
   }
   c->total = L.total; c->ptotal = L.ptotal; c->itotal = L.itotal; c->ncells = L.ncells;
-  // carve the arena
-  char *p = (char *)dev_arena;
-  auto take = [&](size_t bytes) { char *r = p; p += align256(bytes); return r; };
-  c->Qa = (double *)take(L.total * sizeof(double));
-  c->Qb = (double *)take(L.total * sizeof(double));
-  c->Qs = (double *)take(L.total * sizeof(double));
-  c->imp = (double *)take(L.itotal * sizeof(double));
-  c->bf1 = (double *)take(L.itotal * sizeof(double));
-  if (c->cfg.grav_kind == 1) c->phi = (double *)take(L.ptotal * sizeof(double));
-  if (c->cfg.eos_kind == 1) c->jc = (int *)take(3 * L.ncells * sizeof(int));
+  // carve the arena: the library allocates no device memory
+  arena_regions(&c->cfg, L, c->nb, (char *)dev_arena, c);
   c->ftotal = L.ftotal;
-  c->flx = (double *)take(3 * (c->nv + 1) * L.ftotal * sizeof(double));
-  // metadata
-  tdh_status s;
-  if ((s = dev_alloc(c, &c->d_blocks, c->nb)) || (s = dev_alloc(c, &c->d_lmap, c->lmap.size())) ||
-      (s = dev_alloc(c, &c->d_fac, c->nb)) || (s = dev_alloc(c, &c->d_par, c->nb)) ||
-      (s = dev_alloc(c, &c->d_order, c->nb)) || (s = dev_alloc(c, &c->d_item_start, c->nb + 1)) ||
-      (s = dev_alloc(c, &c->d_fitem_start, c->nb + 1)) ||
-      (s = dev_alloc(c, &c->d_item_bt, (size_t)(L.ncells / kChunk))) ||
-      (s = dev_alloc(c, &c->d_fitem_bt, (size_t)((L.ftotal + (long long)c->nb * (kChunk - 1)) / kChunk))) ||
-      (s = dev_alloc(c, &c->d_cnt_ge, kCntSlots)) || (s = dev_alloc(c, &c->d_dtb, c->nb)) ||
-      (s = dev_alloc(c, &c->d_win, 2)) ||
-      (s = dev_alloc(c, &c->d_cfl_block_start, c->nb + 1)) ||
-      (s = dev_alloc(c, &c->d_facc, (size_t)(4 * frame_acceleration_parts() + 4))))
-    return s;
   std::vector<int> cstart(c->nb + 1, 0), citem;
   for (int b = 0; b < c->nb; ++b) {
     const long long n = c->blk[4 * b];
@@ -510,8 +537,6 @@ extern "C" tdh_status tdh_init_blocks(tdh_ctx *c, const tdh_mesh *m, void *dev_a
     for (int i = 0; i < ni; ++i) citem.push_back(b);
   }
   c->cfl_nitems = cstart[c->nb];
-  if ((s = dev_alloc(c, &c->d_cfl_item_block, citem.size())) || (s = dev_alloc(c, &c->d_cfl_part, citem.size())))
-    return s;
   HIPCHK(c, hipMemcpyAsync(c->d_blocks, c->binfo.data(), c->nb * sizeof(BlockInfo), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_lmap, c->lmap.data(), c->lmap.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_cfl_block_start, cstart.data(), cstart.size() * sizeof(int), hipMemcpyHostToDevice,
@@ -527,7 +552,7 @@ extern "C" tdh_status tdh_init_blocks(tdh_ctx *c, const tdh_mesh *m, void *dev_a
   c->cfl_parts = false;
   if (c->phi) HIPCHK(c, hipMemcpyAsync(c->phi, host_phi, L.ptotal * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  HIPCHK(c, hipHostMalloc((void **)&c->h_dtb, c->nb * sizeof(double), hipHostMallocDefault));
+  c->h_dtb.assign(c->nb, 0.0);
   build_adjacency(c);
   for (int b = 0; b < c->nb; ++b)
     if (c->blk[4 * b] < 8) return fail(c, TDH_EINVAL, "blocks must have an edge of at least 8 cells");
@@ -537,23 +562,47 @@ extern "C" tdh_status tdh_init_blocks(tdh_ctx *c, const tdh_mesh *m, void *dev_a
   return install_levels(c, std::vector<int>(c->nb, 0));
 }
 
+// Packed EOS table (see Table in tdh_internal.hpp), in doubles: density-row
+// pairs of log e, then of (log P, log c_s^2), then the 128-byte cell records,
+// then the log10 and 10^x function tables.
+struct TableLayout {
+  size_t pc_off, rec_off, fn_off, total;
+};
+static TableLayout table_layout(int nrho, int nT) {
+  TableLayout t;
+  const size_t np = (size_t)(nrho - 1) * nT;
+  t.pc_off = (2 * np + 3) & ~(size_t)3;              // 32-byte alignment of the double4 records
+  t.rec_off = (t.pc_off + 4 * np + 15) & ~(size_t)15;  // 128-byte cell records
+  const size_t nrec = (size_t)(nrho - 1) * (nT - 1);
+  t.fn_off = t.rec_off + 16 * nrec;                    // 128-byte aligned
+  t.total = t.fn_off + 2 * 128 + 64;
+  return t;
+}
+
+extern "C" size_t tdh_table_bytes(int nrho, int nT) {
+  if (nrho < 2 || nT < 2 || nrho > 4096 || nT > 4096) return 0;
+  return table_layout(nrho, nT).total * sizeof(double);
+}
+
 extern "C" tdh_status tdh_set_eos_table(tdh_ctx *c, int nrho, int nT, double lr0, double dlr, double lT0, double dlT,
-                                        const double *lP, const double *le, const double *lc2) {
+                                        const double *lP, const double *le, const double *lc2, void *dev_table,
+                                        size_t table_bytes) {
   CHECK_CTX(c);
   if (nrho < 2 || nT < 2 || nrho > 4096 || nT > 4096) return fail(c, TDH_ERANGE, "table dimensions out of range");
   if (!lP || !le || !lc2) return fail(c, TDH_EINVAL, "null table array");
+  if (!dev_table || ((uintptr_t)dev_table & 255))
+    return fail(c, TDH_EINVAL, "table buffer must be non-null, 256-byte aligned");
+  if (table_bytes < tdh_table_bytes(nrho, nT))
+    return fail(c, TDH_ENOMEM, "table buffer holds %zu bytes, %zu needed", table_bytes, tdh_table_bytes(nrho, nT));
   if (!(dlr > 0.0) || !(dlT > 0.0)) return fail(c, TDH_EINVAL, "table spacings must be positive");
   for (int i = 0; i < nrho; ++i)
     for (int j = 0; j + 1 < nT; ++j)
       if (!(le[(size_t)i * nT + j + 1] > le[(size_t)i * nT + j]))
         return fail(c, TDH_EINVAL, "log e is not increasing in T on row %d", i);
-  // pack by density-row pairs (see Table in tdh_internal.hpp)
-  const size_t np = (size_t)(nrho - 1) * nT;
-  const size_t pc_off = (2 * np + 3) & ~(size_t)3;  // 32-byte alignment of the double4 records
-  const size_t rec_off = (pc_off + 4 * np + 15) & ~(size_t)15;  // 128-byte cell records
-  const size_t nrec = (size_t)(nrho - 1) * (nT - 1);
-  const size_t fn_off = rec_off + 16 * nrec;  // 128-byte aligned
-  std::vector<double> packed(fn_off + 2 * 128 + 64, 0.0);
+  // pack by density-row pairs
+  const TableLayout TL = table_layout(nrho, nT);
+  const size_t pc_off = TL.pc_off, rec_off = TL.rec_off, fn_off = TL.fn_off;
+  std::vector<double> packed(TL.total, 0.0);
   // log10 and 10^x tables, from the host's extended-precision library
   for (int i = 0; i < 128; ++i) {
     const double ci = 1.0 / (1.0 + (i + 0.5) / 128.0);
@@ -585,10 +634,7 @@ extern "C" tdh_status tdh_set_eos_table(tdh_ctx *c, int nrho, int nT, double lr0
         r[8 + v] = packed[pc_off + 4 * (q + 1) + v];
       }
     }
-  if (!c->d_table || c->tab.nrho != nrho || c->tab.nT != nT) {
-    tdh_status s = dev_alloc(c, &c->d_table, packed.size());
-    if (s) return s;
-  }
+  c->d_table = (double *)dev_table;
   HIPCHK(c, hipMemcpyAsync(c->d_table, packed.data(), packed.size() * sizeof(double), hipMemcpyHostToDevice,
                            c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -681,9 +727,9 @@ static tdh_status reduce_dt_impl(tdh_ctx *c, double *part, double *dtb_dev, bool
     c->stats.kernel_launches += 2;
     c->cfl_seeds = c->cfg.eos_kind == 1 && (c->cfg.inv_mode == 2 || c->cfg.inv_mode == 4);
   }
-  HIPCHK(c, hipMemcpyAsync(c->h_dtb, dtb_dev, c->nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->h_dtb.data(), dtb_dev, c->nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  std::vector<double> dtb(c->h_dtb, c->h_dtb + c->nb);
+  std::vector<double> dtb(c->h_dtb.begin(), c->h_dtb.end());
   double dt0;
   std::vector<int> lev = c->cfg.n_lat > 0 ? assign_levels(c, dtb, dt0) : std::vector<int>(c->nb, 0);
   if (c->cfg.n_lat == 0) {
@@ -1378,8 +1424,6 @@ extern "C" tdh_status tdh_get_stage_time(tdh_ctx *c, double *host_ms, int64_t *h
 // ---------------------------------------------------------------------------
 // learned EOS seed network
 // ---------------------------------------------------------------------------
-static constexpr int kMlpMaxBatch = 65536;
-static constexpr int kMlpMaxSteps = 1 << 20;
 
 static void invalidate_graphs(tdh_ctx *c) {
   for (auto &g : c->graphs) hipGraphExecDestroy(g.second);
@@ -1391,15 +1435,8 @@ extern "C" tdh_status tdh_mlp_init(tdh_ctx *c, const float *host_params, double 
   CHECK_CTX(c);
   if (!host_params) return fail(c, TDH_EINVAL, "null parameters");
   if (!(lr_hi > lr_lo) || !(le_hi > le_lo) || !(lt_hi > lt_lo)) return fail(c, TDH_EINVAL, "empty normalisation range");
-  tdh_status s;
-  if (!c->have_mlp) {
-    if ((s = dev_alloc(c, &c->d_mw, kMlpParams)) || (s = dev_alloc(c, &c->d_mm, kMlpParams)) ||
-        (s = dev_alloc(c, &c->d_mv, kMlpParams)) || (s = dev_alloc(c, &c->d_mgrad, kMlpParams)) ||
-        (s = dev_alloc(c, &c->d_mpart, (size_t)(kMlpMaxBatch / 64) * kMlpParams)) ||
-        (s = dev_alloc(c, &c->d_mloss_part, kMlpMaxBatch / 64)) || (s = dev_alloc(c, &c->d_mloss, kMlpMaxSteps)) ||
-        (s = dev_alloc(c, &c->d_mb, 64 + 64 + 1)) || (s = dev_alloc(c, &c->d_mwb, 128 + 4096 + 4096 + 64)))
-      return s;
-  }
+  if (!c->have_mesh) return fail(c, TDH_ESTATE, "no mesh: the network's buffers are in the arena (tdh_init_blocks)");
+  if (!c->d_mw) return fail(c, TDH_ESTATE, "the learned seed serves the table EOS: a context with eos_kind 1");
   std::vector<float> zero(kMlpParams, 0.0f);
   HIPCHK(c, hipMemcpyAsync(c->d_mw, host_params, kMlpParams * sizeof(float), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_mm, zero.data(), kMlpParams * sizeof(float), hipMemcpyHostToDevice, c->stream));

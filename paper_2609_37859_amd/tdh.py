@@ -66,7 +66,8 @@ def lib():
         "tdh_arena_bytes": ([P(tdh_config), P(tdh_mesh)], C.c_size_t),
         "tdh_init": ([P(tdh_config), vp, P(ctx)], st),
         "tdh_init_blocks": ([ctx, P(tdh_mesh), vp, C.c_size_t, P(d), P(d)], st),
-        "tdh_set_eos_table": ([ctx, i, i, d, d, d, d, P(d), P(d), P(d)], st),
+        "tdh_set_eos_table": ([ctx, i, i, d, d, d, d, P(d), P(d), P(d), vp, C.c_size_t], st),
+        "tdh_table_bytes": ([i, i], C.c_size_t),
         "tdh_reduce_dt": ([ctx, P(d), P(d), P(C.c_int8), P(i)], st),
         "tdh_reduce_dt_static": ([ctx, P(d), P(d), P(C.c_int8), P(i)], st),
         "tdh_set_levels": ([ctx, P(C.c_int8)], st),
@@ -204,9 +205,21 @@ class Context:
             raise TdhError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")
 
     def set_eos_table(self, t):
+        """Install the table; its packed device copy lives in a torch buffer
+        owned here (the library allocates no device memory)."""
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (t.lP, t.le, t.lc2)]
-        self._check(self.L.tdh_set_eos_table(self.ctx, t.nrho, t.nT, t.lr0, t.dlr, t.lT0, t.dlT, *map(_dp, arrs)),
-                    "tdh_set_eos_table")
+        nbytes = self.L.tdh_table_bytes(t.nrho, t.nT)
+        if nbytes == 0:
+            raise TdhError("tdh_table_bytes rejected the table dimensions")
+        buf = self.torch.empty(nbytes + 256, dtype=self.torch.uint8, device=self.device)
+        buf.record_stream(self.stream)
+        ptr = (buf.data_ptr() + 255) & ~255
+        self._check(self.L.tdh_set_eos_table(self.ctx, t.nrho, t.nT, t.lr0, t.dlr, t.lT0, t.dlT, *map(_dp, arrs),
+                                             C.c_void_p(ptr), nbytes), "tdh_set_eos_table")
+        old = getattr(self, "_table_buf", None)
+        if old is not None:
+            old.record_stream(self.stream)  # queued work may still read it
+        self._table_buf = buf
 
     def reduce_dt(self, static=False):
         """CFL reduction and level assignment: (dt_block, dt0, levels, Lmax).

@@ -50,3 +50,20 @@ def test_arena_size_and_mesh_validation_without_gpu():
     amr.rlev[0] = 2
     m4, keep4 = T.make_mesh(amr)
     assert L.tdh_arena_bytes(ctypes.byref(c), ctypes.byref(m4)) == 0
+
+
+def test_library_allocates_no_device_memory():
+    """Every device byte a context uses is the caller's (arena, table buffer,
+    gravity workspace) or the static per-GPU array of the allocation-free
+    reduction: no source of the library calls a device allocator."""
+    import re
+    csrc = os.path.join(os.path.dirname(T.__file__), "csrc")
+    pat = re.compile(r"\bhip(Malloc|MallocAsync|MallocManaged|ExtMallocWithFlags|MallocPitch|Malloc3D|HostMalloc|"
+                     r"MallocFromPoolAsync|Free|FreeAsync|HostFree)\s*\(")
+    hits = []
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".cpp", ".hpp")):
+            for n, line in enumerate(open(os.path.join(csrc, f)), 1):
+                if pat.search(line):
+                    hits.append(f"{f}:{n}: {line.strip()}")
+    assert not hits, hits
