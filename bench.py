@@ -352,7 +352,7 @@ def amr_section(T, W, table, params, windows, warmup, oracle_windows):
            "sync_equivalent": se / el, "block_updates": int(bu), "levels": [int(v) for v in np.trim_zeros(hist, "b")],
            "form": "learned (mode 4, network, batched, graph); stage kernel kind of its own with cross-level ghosts",
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "stage_tiled (kPkAmr)",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "stage_tiled (two-level kind)",
                         "avg_launch_ms": launch_ms, "launches": int(launches),
                         "algorithmic_bytes_per_launch": alg, "algorithmic_bytes_per_cell_update": bpc}}
     if oracle_windows > 0:
