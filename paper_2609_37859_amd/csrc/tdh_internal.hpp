@@ -151,8 +151,9 @@ int frame_acceleration_parts();
 
 int num_tiles();
 void tile_shape(int id, int *dims);  // x, y, z edges and waves per SIMD of variant id (x = 0: split form)
-hipError_t launch_stage(const StageArgs &a, int tile, int grid, hipStream_t s);
-hipError_t launch_seed(const StageArgs &a, int grid, hipStream_t s);
+// persistent launches: cus = compute units of the device (the launchers size the grid)
+hipError_t launch_stage(const StageArgs &a, int tile, int cus, hipStream_t s);
+hipError_t launch_seed(const StageArgs &a, int cus, hipStream_t s);
 hipError_t launch_set_window(double *win, double t, double dt0, hipStream_t s);
 hipError_t launch_commit(const int *order, const int *cnt_ge, int lmin, int *par, hipStream_t s);
 hipError_t launch_reflux(const StageArgs &a, int lc, int dir, int nmax, int grid, hipStream_t s);  // a.k = completing index
@@ -160,7 +161,7 @@ hipError_t launch_cfl_blocks(const double *part, int nblocks, const int *block_i
                              hipStream_t s);
 bool tile_is_fused(int id);
 hipError_t launch_cfl(const StageArgs &a, double cfl, double t, const int *item_block, int nitems,
-                      double *part, int nblocks, const int *block_item_start, double *dtb, hipStream_t s);
+                      double *part, int nblocks, const int *block_item_start, double *dtb, int cus, hipStream_t s);
 hipError_t launch_eos_invert(const Table &t, const Seed &s, int newton_max_iter, const double *lr, const double *le,
                              double *lT, int32_t *j, int32_t *iters, int64_t n, int mode, hipStream_t st);
 hipError_t launch_eos_eval(const Phys &p, const Table &t, const double *rho, const double *U, double *P,

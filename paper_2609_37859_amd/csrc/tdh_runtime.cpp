@@ -73,7 +73,7 @@ struct tdh_ctx {
   int k = 0;                 // next sub-cycle
   double dt_coarse = 0.0, dt0 = 0.0;
   double t = 0.0;            // time of the last synchronised state
-  int grid = 2048;           // persistent grid of the stage kernel
+  int cus = 256;             // compute units (the persistent launches size their grids from it)
   int tile = 0;              // stage tile shape (launch_stage id)
   tdh_stats stats{};
 
@@ -295,7 +295,7 @@ extern "C" tdh_status tdh_init(const tdh_config *cfg, void *hip_stream, tdh_ctx 
     delete c;
     return fail(nullptr, TDH_EHIP, "tdh_init: no HIP device");
   }
-  c->grid = prop.multiProcessorCount * 8;
+  c->cus = prop.multiProcessorCount;
   c->scratch = device_scratch(dev);
   *out = c;
   return TDH_OK;
@@ -723,7 +723,7 @@ static tdh_status reduce_dt_impl(tdh_ctx *c, double *part, double *dtb_dev, bool
     c->stats.kernel_launches += 1;
   } else {
     HIPCHK(c, launch_cfl(a, c->cfg.cfl, c->t, c->d_cfl_item_block, c->cfl_nitems, part, c->nb,
-                         c->d_cfl_block_start, dtb_dev, c->stream));
+                         c->d_cfl_block_start, dtb_dev, c->cus, c->stream));
     c->stats.kernel_launches += 2;
     c->cfl_seeds = c->cfg.eos_kind == 1 && (c->cfg.inv_mode == 2 || c->cfg.inv_mode == 4);
   }
@@ -811,13 +811,13 @@ static tdh_status timed_stage(tdh_ctx *c, const StageArgs &a) {
   const bool t = c->timing && !c->capturing;
   tdh_status s;
   if (c->cfg.eos_kind == 1 && (c->cfg.inv_mode == 2 || c->cfg.inv_mode == 4) && !(a.k == 0 && a.phase == 1)) {
-    HIPCHK(c, launch_seed(a, c->grid, c->stream));
+    HIPCHK(c, launch_seed(a, c->cus, c->stream));
     c->stats.kernel_launches++;
   }
   if (t && 2 * (c->ev_used + 1) > c->ev.size())
     if ((s = collect_timing(c))) return s;
   if (t) HIPCHK(c, hipEventRecord(c->ev[2 * c->ev_used], c->stream));
-  HIPCHK(c, launch_stage(a, c->tile, c->grid, c->stream));
+  HIPCHK(c, launch_stage(a, c->tile, c->cus, c->stream));
   if (t) {
     HIPCHK(c, hipEventRecord(c->ev[2 * c->ev_used + 1], c->stream));
     c->ev_used++;
@@ -845,7 +845,7 @@ static tdh_status ensure_seeds(tdh_ctx *c) {
   a.phase = 1;
   a.Llo = 0;
   a.Lhi = kCntSlots - 2;
-  HIPCHK(c, launch_seed(a, c->grid, c->stream));
+  HIPCHK(c, launch_seed(a, c->cus, c->stream));
   c->stats.kernel_launches++;
   if (carried) c->seeds_held = true;
   c->cfl_seeds = false;
@@ -1368,9 +1368,9 @@ extern "C" tdh_status tdh_autotune(tdh_ctx *c, int reps, int *host_best, float *
   for (int id = 0; id < num_tiles(); ++id) {
     float ms = -1.0f;
     if (tile_fits(c, id)) {
-      HIPCHK(c, launch_stage(a, id, c->grid, c->stream));  // warm-up
+      HIPCHK(c, launch_stage(a, id, c->cus, c->stream));  // warm-up
       HIPCHK(c, hipEventRecord(e0, c->stream));
-      for (int r = 0; r < reps; ++r) HIPCHK(c, launch_stage(a, id, c->grid, c->stream));
+      for (int r = 0; r < reps; ++r) HIPCHK(c, launch_stage(a, id, c->cus, c->stream));
       HIPCHK(c, hipEventRecord(e1, c->stream));
       HIPCHK(c, hipEventSynchronize(e1));
       HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
