@@ -156,6 +156,8 @@ hipError_t launch_stage(const StageArgs &a, int tile, int cus, hipStream_t s);
 hipError_t launch_seed(const StageArgs &a, int cus, hipStream_t s);
 hipError_t launch_set_window(double *win, double t, double dt0, hipStream_t s);
 hipError_t launch_commit(const int *order, const int *cnt_ge, int lmin, int *par, hipStream_t s);
+// per work item (block, item within the block) of the level-sorted list order / start (nb blocks)
+hipError_t launch_expand_items(const int *order, const int *start, int nb, int2 *bt, hipStream_t s);
 hipError_t launch_reflux(const StageArgs &a, int lc, int dir, int nmax, int grid, hipStream_t s);  // a.k = completing index
 hipError_t launch_cfl_blocks(const double *part, int nblocks, const int *block_item_start, double cfl, double *dtb,
                              hipStream_t s);

@@ -1460,6 +1460,16 @@ __global__ void set_window_kernel(double *win, double t, double dt0) {
   }
 }
 
+// (block, index of the item within the block) of every work item of a
+// level-sorted block list: position i of the list owns the items
+// start[i] .. start[i+1]-1
+__global__ void expand_items_kernel(const int *order, const int *start, int nb, int2 *bt) {
+  for (int i = blockIdx.x; i < nb; i += gridDim.x) {
+    const int b = order[i], s0 = start[i], s1 = start[i + 1];
+    for (int t = s0 + (int)threadIdx.x; t < s1; t += (int)blockDim.x) bt[t] = make_int2(b, t - s0);
+  }
+}
+
 __global__ void commit_kernel(const int *order, const int *cnt_ge, int lmin, int *par) {
   const int na = cnt_ge[lmin];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) par[order[i]] ^= 1;
@@ -1835,6 +1845,12 @@ bool tile_is_fused(int id) {
 
 hipError_t launch_set_window(double *win, double t, double dt0, hipStream_t s) {
   hipLaunchKernelGGL(set_window_kernel, dim3(1), dim3(64), 0, s, win, t, dt0);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_items(const int *order, const int *start, int nb, int2 *bt, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(expand_items_kernel, dim3(nb < 4096 ? nb : 4096), dim3(256), 0, s, order, start, nb, bt);
   return hipGetLastError();
 }
 

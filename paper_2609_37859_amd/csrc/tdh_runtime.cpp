@@ -68,7 +68,6 @@ struct tdh_ctx {
 
   // LAT window state
   std::vector<int> levels, fac, par, order, item_start, fitem_start, cnt_ge;
-  std::vector<int2> item_bt, fitem_bt;
   int Lmax = 0;
   int k = 0;                 // next sub-cycle
   double dt_coarse = 0.0, dt0 = 0.0;
@@ -462,17 +461,10 @@ static tdh_status install_levels(tdh_ctx *c, const std::vector<int> &lev) {
                            c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_fitem_start, c->fitem_start.data(), (c->nb + 1) * sizeof(int),
                            hipMemcpyHostToDevice, c->stream));
-  c->item_bt.resize(c->item_start[c->nb]);
-  c->fitem_bt.resize(c->fitem_start[c->nb]);
-  for (int i = 0; i < c->nb; ++i) {
-    for (int t = c->item_start[i]; t < c->item_start[i + 1]; ++t) c->item_bt[t] = make_int2(c->order[i], t - c->item_start[i]);
-    for (int t = c->fitem_start[i]; t < c->fitem_start[i + 1]; ++t)
-      c->fitem_bt[t] = make_int2(c->order[i], t - c->fitem_start[i]);
-  }
-  HIPCHK(c, hipMemcpyAsync(c->d_item_bt, c->item_bt.data(), c->item_bt.size() * sizeof(int2), hipMemcpyHostToDevice,
-                           c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->d_fitem_bt, c->fitem_bt.data(), c->fitem_bt.size() * sizeof(int2),
-                           hipMemcpyHostToDevice, c->stream));
+  // the per-item tables (block, item within the block) are expanded on the
+  // device from the lists just uploaded
+  HIPCHK(c, launch_expand_items(c->d_order, c->d_item_start, c->nb, c->d_item_bt, c->stream));
+  HIPCHK(c, launch_expand_items(c->d_order, c->d_fitem_start, c->nb, c->d_fitem_bt, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_cnt_ge, c->cnt_ge.data(), kCntSlots * sizeof(int), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->k = 0;
