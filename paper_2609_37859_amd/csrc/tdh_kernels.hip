@@ -1722,26 +1722,27 @@ void tile_shape(int id, int *dims) {
 // round, 1.91 at 16 and 1.89 at 24 on the production-shaped LAT run).
 constexpr int kRounds = 16;
 
-static int resident_grid(const void *kernel, int threads, int cus) {
+static int resident_grid(const void *kernel, int threads, int cus, int rounds = kRounds) {
   static std::mutex mu;
   static std::unordered_map<const void *, int> per_cu;
   std::lock_guard<std::mutex> lock(mu);
   const auto it = per_cu.find(kernel);
-  if (it != per_cu.end()) return cus * it->second;
+  if (it != per_cu.end()) return cus * it->second * rounds;
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, 0) != hipSuccess || n < 1)
-    return cus * kRounds;  // one workgroup per CU assumed (not kept: the query is tried again)
-  per_cu.emplace(kernel, n * kRounds);
-  return cus * n * kRounds;
+    return cus * rounds;  // one workgroup per CU assumed (not kept: the query is tried again)
+  per_cu.emplace(kernel, n);
+  return cus * n * rounds;
 }
 
 // persistent launch of a kernel whose one argument is the StageArgs
 template <typename K>
-static hipError_t launch_persistent(K kernel, int threads, int cus, hipStream_t s, const StageArgs &a) {
+static hipError_t launch_persistent(K kernel, int threads, int cus, hipStream_t s, const StageArgs &a,
+                                    int rounds = kRounds) {
   const void *k = reinterpret_cast<const void *>(kernel);
   StageArgs arg = a;
   void *argv[] = {&arg};
-  return hipLaunchKernel(k, dim3(resident_grid(k, threads, cus)), dim3(threads), argv, 0, s);
+  return hipLaunchKernel(k, dim3(resident_grid(k, threads, cus, rounds)), dim3(threads), argv, 0, s);
 }
 
 template <int NV, int OF, int OU>
@@ -1754,9 +1755,15 @@ static hipError_t launch_split(const StageArgs &a, bool net, int cus, hipStream_
   return launch_persistent(update_kernel<NV, false, OU>, kChunk, cus, s, a);
 }
 
+// The seed pass takes 4 rounds: each of its workgroups first stages the
+// network's weights (9 KB) in LDS, which more rounds repeat (measured on the
+// production-shaped run: 2.29 ms of seed passes per window at 4 rounds, 2.51
+// at 16).
+constexpr int kSeedRounds = 4;
+
 hipError_t launch_seed(const StageArgs &a, int cus, hipStream_t s) {
-  if (a.m.nv == 6) return launch_persistent(seed_kernel<6>, kChunk, cus, s, a);
-  return launch_persistent(seed_kernel<5>, kChunk, cus, s, a);
+  if (a.m.nv == 6) return launch_persistent(seed_kernel<6>, kChunk, cus, s, a, kSeedRounds);
+  return launch_persistent(seed_kernel<5>, kChunk, cus, s, a, kSeedRounds);
 }
 
 // Configurations with a stage kernel of their own (physics_code): the table
