@@ -52,6 +52,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -694,7 +695,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20, help="timed LAT windows per run of the headline forms "
                                                           "(timed steps per run of the c2 forms)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--repeats", type=int, default=3,
+    ap.add_argument("--repeats", type=int, default=5,
                     help="timed runs of --steps windows per form; each form reports the median run")
     ap.add_argument("--sections", default=SECTIONS, help=f"comma list out of {SECTIONS}")
     ap.add_argument("--forms", default="learned,plain,temporal,chained,learned_hlle,learned_inkernel",
@@ -770,14 +771,27 @@ def main():
         alg_per_launch = bpc * tp["cell_updates"] / max(tp["stage_launches"], 1)
         achieved = alg_per_launch / (launch_ms * 1e-3) / 1e9
         prof = counters_from_profiles("c5")
-        valu = prof.get("sq", {}).get("SQ_INSTS_VALU")
+        sq = prof.get("sq", {})
+        valu = sq.get("SQ_INSTS_VALU")
+        # instruction and FLOP rates over the profiled launches' own mean duration
+        # (the counters' launches, not this run's timing pass)
+        pms = prof.get("avg_launch_ms")
+        f64 = None
+        if pms and "SQ_INSTS_VALU_FMA_F64" in sq:
+            flop = 64 * (sq["SQ_INSTS_VALU_ADD_F64"] + sq["SQ_INSTS_VALU_MUL_F64"] + sq["SQ_INSTS_VALU_TRANS_F64"]
+                         + 2 * sq["SQ_INSTS_VALU_FMA_F64"])
+            tf = flop / (pms * 1e-3) / 1e12
+            f64 = {"flop_per_launch": flop, "achieved": tf, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                   "frac": tf / FP64_VECTOR_PEAK_TFLOPS, "profiled_launch_ms": pms}
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": prof.get("hbm_bytes_per_launch"),
                 "kernel": "stage_tiled", "avg_launch_ms": launch_ms, "launches": tp["stage_launches"],
                 "algorithmic_bytes_per_launch": alg_per_launch, "algorithmic_bytes_per_cell_update": bpc,
-                "valu_issue": ({"wave_insts_per_launch": valu, "achieved": valu / (launch_ms * 1e-3),
+                "valu_issue": ({"wave_insts_per_launch": valu, "achieved": valu / (pms * 1e-3),
                                 "peak": VALU_PEAK_WAVE_INSTS, "unit": "wave64 VALU instructions/s",
-                                "frac": valu / (launch_ms * 1e-3) / VALU_PEAK_WAVE_INSTS} if valu else None)}
+                                "frac": valu / (pms * 1e-3) / VALU_PEAK_WAVE_INSTS,
+                                "profiled_launch_ms": pms} if valu and pms else None),
+                "fp64": f64}
     value = head["value"] if head else None
     out = {
         "metric": "FP64 cell-updates/s (LAT-batched+MLP-EOS vs plain) at <=1e-11 rel err; % HBM roof",
