@@ -98,21 +98,37 @@ def kernel_stats(d, kernel):
     return rows
 
 
-def counter_per_dispatch(d, name_exact, counter):
-    vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(_one(d, "*counter_collection.csv")))
+def _tail(vals, last):
+    return vals[-last:] if last > 0 else vals
+
+
+def trace_durations(d, name_exact):
+    """Durations (ms) of the dispatches of one kernel in dispatch order, from
+    the kernel trace."""
+    rows = [r for r in csv.DictReader(open(_one(d, "*kernel_trace.csv"))) if r["Kernel_Name"] == name_exact]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in rows]
+
+
+def counter_per_dispatch(d, name_exact, counter, last=0):
+    rows = [r for r in csv.DictReader(open(_one(d, "*counter_collection.csv")))
             if r["Kernel_Name"] == name_exact and r["Counter_Name"] == counter]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    vals = _tail([float(r["Counter_Value"]) for r in rows], last)
     if not vals:
         raise SystemExit(f"no {counter} for {name_exact} under {d}")
     return vals
 
 
-def counter_table(d, kernel):
-    """{counter: [values per dispatch]} for the dispatches of `kernel`."""
+def counter_table(d, kernel, last=0):
+    """{counter: [values per dispatch]} for the dispatches of `kernel` (the
+    last `last` of them if last > 0), in dispatch order."""
+    rows = [r for r in csv.DictReader(open(_one(d, "*counter_collection.csv"))) if r["Kernel_Name"] == kernel]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
     out = {}
-    for r in csv.DictReader(open(_one(d, "*counter_collection.csv"))):
-        if r["Kernel_Name"] == kernel:
-            out.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
-    return out
+    for r in rows:
+        out.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return {k: _tail(v, last) for k, v in out.items()}
 
 
 def copy_factor(d, counter, nbytes):
@@ -139,7 +155,7 @@ def main():
     ap.add_argument("--cells", type=float, default=0.0, help="cells one launch of the kernel updates (per-cell rates)")
     ap.add_argument("--windows", type=int, default=0, help="LAT windows in the run: list every kernel per window")
     ap.add_argument("--alg-bytes", type=float, default=0.0,
-                    help="algorithmic HBM bytes of all the kernel's launches in the counter runs")
+                    help="algorithmic HBM bytes of the kernel's launches the figures cover (all, or --last N)")
     ap.add_argument("--cmd", action="append", default=[], help="command that produced the inputs (repeatable)")
     ap.add_argument("--title", default="stage kernel")
     ap.add_argument("--out", required=True)
@@ -147,6 +163,9 @@ def main():
     ap.add_argument("--family", help="summarise every kernel whose name contains this (instead of one kernel)")
     ap.add_argument("--units", type=int, default=1, help="units of work in the run (family mode)")
     ap.add_argument("--unit-name", default="units")
+    ap.add_argument("--last", type=int, default=0,
+                    help="per-launch figures over the kernel's last N dispatches only (a timed pass at the end "
+                         "of the run); 0: every dispatch")
     args = ap.parse_args()
     if args.family:
         family_summary(args)
@@ -173,11 +192,19 @@ def main():
             lines.append(f"| `{nm}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6 / args.windows:.3f} |")
         lines.append("")
     out = {"kernel": used["Name"], "avg_launch_ms": float(used["AverageNs"]) / 1e6, "kernel_hash": kernel_source_hash()}
+    if args.last > 0:
+        dur = _tail(trace_durations(args.stats, used["Name"]), args.last)
+        lines += [f"Timed launches (the last {len(dur)} dispatches of `{used['Name']}`, the run's HIP-event "
+                  f"pass): average {statistics.mean(dur):.4f} ms, min {min(dur):.4f}, max {max(dur):.4f}, "
+                  f"sum {sum(dur):.2f} ms", ""]
+        out["avg_launch_ms_all"] = out["avg_launch_ms"]
+        out["avg_launch_ms"] = statistics.mean(dur)
+        out["launches"] = len(dur)
     if args.fetch and args.write and args.copy_fetch and args.copy_write:
         f_k = copy_factor(args.copy_fetch, "FETCH_SIZE", args.copy_bytes)
         w_k = copy_factor(args.copy_write, "WRITE_SIZE", args.copy_bytes)
-        fv = counter_per_dispatch(args.fetch, used["Name"], "FETCH_SIZE")
-        wv = counter_per_dispatch(args.write, used["Name"], "WRITE_SIZE")
+        fv = counter_per_dispatch(args.fetch, used["Name"], "FETCH_SIZE", args.last)
+        wv = counter_per_dispatch(args.write, used["Name"], "WRITE_SIZE", args.last)
         fb, wb = statistics.mean(fv) * f_k, statistics.mean(wv) * w_k
         lines += ["HBM traffic per launch (counter runs of the same command, copy-calibrated):", "",
                   f"- FETCH_SIZE: mean {statistics.mean(fv):.1f} KiB over {len(fv)} launches; copy factor "
@@ -193,7 +220,7 @@ def main():
                       f"{ratio:.2f} x", ""]
             out["traffic_over_algorithmic"] = ratio
     for d in args.sq:
-        tab = counter_table(d, used["Name"])
+        tab = counter_table(d, used["Name"], args.last)
         if not tab:
             continue
         lines += [f"SQ counters per launch ({d.rstrip('/').split('/')[-1]}):", ""]
