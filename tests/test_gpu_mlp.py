@@ -161,6 +161,38 @@ def test_training_on_gpu_reduces_loss_and_seeds_the_inversion(gctx, saha):
     gctx.mlp_enable_seed(False)
 
 
+def test_what_the_trained_network_gains_over_bisection(gctx, saha):
+    """What the network gains: on queries of its training distribution with no
+    history, its prediction starts the table search next to the answer, so the
+    search reads far fewer table columns than the plain bisection does, and
+    the answer is the same.  Column reads beyond the two end nodes both forms
+    read: bisection one per halving (log2 of the node intervals, 8 on 256
+    nodes) plus the right neighbour when the last halving left it unread;
+    seeded, two per secant try (the cell's two nodes), and where the seed
+    misses after newton_max_iter steps the same bisection on top."""
+    import torch
+    _train_seed(gctx, saha)  # the C4 recipe: 2000 steps
+    gctx.mlp_enable_seed(True)
+    xq = torch.from_numpy(W.seed_training_samples(saha, 1 << 16, 5)).cuda()
+    lT0, j0, it0 = gctx.eos_invert(xq[:, 0].contiguous(), xq[:, 1].contiguous(), mode=0)
+    lT1, j1, it1 = gctx.eos_invert(xq[:, 0].contiguous(), xq[:, 1].contiguous(), mode=1)
+    torch.cuda.synchronize()
+    gctx.mlp_enable_seed(False)
+    assert torch.equal(j0, j1) and torch.equal(lT0, lT1)
+    it0, it1 = it0.cpu().numpy(), it1.cpu().numpy()
+    assert np.all(it0 == -1)                                 # mode 0: bisection every time
+    halvings = int(np.ceil(np.log2(saha.nT - 1)))
+    bisect_reads = halvings + 0.5                            # the right neighbour about half the time
+    maxit = 4                                                # the context's newton_max_iter
+    seeded = np.where(it1 >= 0, 2.0 * (it1 + 1), 2.0 * (maxit + 1) + bisect_reads)
+    fallback = float(np.mean(it1 < 0))
+    hist = np.bincount(it1[it1 >= 0], minlength=maxit + 1)
+    print(f"column reads per query: bisection {bisect_reads:.1f}, network-seeded {seeded.mean():.2f}; "
+          f"secant steps {hist.tolist()}, fallback rate {fallback:.2e}")
+    assert fallback < 1e-3
+    assert seeded.mean() < 0.5 * bisect_reads
+
+
 def test_corrupted_network_changes_nothing(gctx, saha):
     """A broken seed (garbage weights) makes every query fall back; the
     inversion results are unchanged bit for bit."""
