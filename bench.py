@@ -317,21 +317,33 @@ def c5_section(T, W, table, params, forms, windows, warmup, repeats, tile):
             return c
 
         ctx = make_ctx()
+        t_tune = time.perf_counter()
         if tile >= 0:
             ctx.set_tile(tile)
         else:
             ctx.autotune(reps=3)
+        ctx.sync()
+        t_tune = time.perf_counter() - t_tune
         for _ in range(warmup):
             _, dt0, lev, L = ctx.reduce_dt()
             ctx.run_window(dt0 * 2 ** L, batched=batched, graph=graph)
         ctx.sync()
+        st_before = ctx.stats()
         runs = sorted((_timed_windows(ctx, windows, graph, batched) for _ in range(repeats)), key=lambda r: r[0])
+        st_after = ctx.stats()
         el, cu, bu, se, hist = runs[len(runs) // 2]
         r = {"value": cu / el, "ms_per_window": 1e3 * el / windows, "windows": windows, "repeats": repeats,
              "sync_equivalent": se / el, "block_updates": int(bu),
              "block_updates_sync": int(se // mesh.ncells * mesh.nblocks),
              "levels": [int(v) for v in np.trim_zeros(hist, "b")], "tile": T.tile_shapes()[ctx.get_tile()],
-             "form": C5_FORMS[name]}
+             "form": C5_FORMS[name],
+             # outside the timed windows: the autotuner, and the graph captures of the warm-up (a window
+             # whose Lmax has no graph yet is captured inside a timed window: counted here)
+             "autotune_s": t_tune if tile < 0 else None,
+             "graph_captures_warmup": int(st_before["graph_captures"]),
+             "capture_ms_warmup": st_before["capture_ms"],
+             "graph_captures_in_timed_runs": int(st_after["graph_captures"] - st_before["graph_captures"]),
+             "capture_ms_in_timed_runs": st_after["capture_ms"] - st_before["capture_ms"]}
         used_tile = ctx.get_tile()
         ctx.close()
         if name == "learned":

@@ -134,6 +134,8 @@ typedef struct {
   int64_t windows;        /* completed LAT windows */
   int64_t sub_cycles;     /* step_level calls */
   int64_t kernel_launches;
+  int64_t graph_captures; /* window graphs captured and instantiated (one per new Lmax and launch form) */
+  double capture_ms;      /* host time those captures and instantiations took */
 } tdh_stats;
 
 /* Device bytes the arena must hold for this configuration and mesh (two

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -947,6 +948,7 @@ extern "C" tdh_status tdh_run_window(tdh_ctx *c, double dt_coarse, int batched, 
       return TDH_OK;
     }
     hipGraph_t g;
+    const auto t_cap = std::chrono::steady_clock::now();
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     c->capturing = true;
     for (int k = 0; k < nsub; ++k) {
@@ -963,6 +965,8 @@ extern "C" tdh_status tdh_run_window(tdh_ctx *c, double dt_coarse, int batched, 
     HIPCHK(c, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
     hipGraphDestroy(g);
     c->graphs[key] = ge;
+    c->stats.graph_captures++;
+    c->stats.capture_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_cap).count();
     HIPCHK(c, hipGraphLaunch(ge, c->stream));
   } else {
     for (int k = 0; k < nsub; ++k)

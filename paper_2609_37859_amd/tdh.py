@@ -39,7 +39,8 @@ class tdh_mesh(C.Structure):
 
 class tdh_stats(C.Structure):
     _fields_ = [("block_updates", C.c_int64), ("cell_updates", C.c_int64), ("windows", C.c_int64),
-                ("sub_cycles", C.c_int64), ("kernel_launches", C.c_int64)]
+                ("sub_cycles", C.c_int64), ("kernel_launches", C.c_int64), ("graph_captures", C.c_int64),
+                ("capture_ms", C.c_double)]
 
 
 _lib = None
