@@ -87,3 +87,28 @@ def test_remap_between_different_variable_sets(tdh):
         b.remap_from(a)
     a.close()
     b.close()
+
+
+def test_window_graphs_are_captured_once_per_lmax(tdh):
+    """A window replayed from a graph is captured the first time its Lmax (and
+    launch form) occurs and replayed afterwards; tdh_stats counts the captures
+    and their host time."""
+    big = W.uniform_mesh(3, 1, 1, 8, 1.0 / 24, bc=(1, 1, 1))
+    cfg = W.Config(n_lat=2)
+    ctx = tdh.Context(cfg, big, W.uniform_state(big, cfg))
+    _, dt0, _, _ = ctx.reduce_dt()
+    assert ctx.stats()["graph_captures"] == 0
+    ctx.set_levels(np.array([0, 1, 2], dtype=np.int8))      # Lmax 2
+    for _ in range(2):
+        ctx.run_window(dt0, batched=True, graph=True)
+    st = ctx.stats()
+    assert st["graph_captures"] == 1 and st["capture_ms"] > 0.0 and st["windows"] == 2
+    ctx.set_levels(np.array([0, 0, 0], dtype=np.int8))      # Lmax 0: a graph of its own
+    for _ in range(2):
+        ctx.run_window(dt0, batched=True, graph=True)
+    ctx.set_levels(np.array([0, 1, 2], dtype=np.int8))      # Lmax 2 again: replayed
+    ctx.run_window(dt0, batched=True, graph=True)
+    ctx.run_window(dt0, batched=True, graph=False)          # no graph: nothing captured
+    st = ctx.stats()
+    assert st["graph_captures"] == 2 and st["windows"] == 6
+    ctx.close()
